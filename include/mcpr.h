@@ -1,0 +1,226 @@
+/*
+ * mcpr.h -- C ABI of the MI355X fine propagator and MC-moments Parareal driver
+ * (Bossuyt, Vandewalle, Samaey, "Monte-Carlo/Moments micro-macro Parareal
+ * method for unimodal and bimodal scalar McKean-Vlasov SDEs", arXiv 2310.11365).
+ *
+ * Conventions shared by every call
+ *   - Device pointers (particle arrays, statistics, maps) are owned by the
+ *     caller; the library never frees them.  Host pointers are read or written
+ *     only for the duration of the call.
+ *   - Calls taking a stream are asynchronous on that stream (a hipStream_t;
+ *     NULL is the null stream) unless stated otherwise.  Kernels of one call
+ *     run in stream order; a context must not be used from two host threads or
+ *     two streams at once (it owns the reduction scratch).
+ *   - Particle arrays hold n_particles values of type double (MCPR_FP64) or
+ *     float (MCPR_FP32) and must be 16-byte aligned.
+ *   - Every call validates its arguments before launching anything and
+ *     returns MCPR_E_INVALID_ARG (nothing launched) on a bad argument;
+ *     mcpr_last_error() then describes it.  HIP failures give MCPR_E_DEVICE.
+ *   - Random numbers: Philox4x32-10 with key = (seed low word, seed high
+ *     word) and counter = (p / 4, step or boundary index, instance, tag);
+ *     particle p takes word p % 4, Box-Muller pairs words (0,1) and (2,3).
+ *     Tags: 0 Euler-Maruyama, 1 initial normal, 2 initial mixture pick,
+ *     3 matching resample.  The numbers depend on the particle, the global step
+ *     and the instance only, so every Parareal iteration and the serial run see
+ *     the same numbers (Property "Exactness of MC-moments Parareal").
+ */
+#ifndef MCPR_H
+#define MCPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mcpr_ctx mcpr_ctx;
+typedef struct mcpr_parareal mcpr_parareal;
+typedef void *mcpr_stream; /* hipStream_t */
+
+typedef enum {
+    MCPR_OK = 0,
+    MCPR_E_INVALID_ARG = -1,
+    MCPR_E_OOM = -2,
+    MCPR_E_DEVICE = -3,
+    MCPR_E_NONFINITE = -4,
+    MCPR_E_UNSUPPORTED = -5
+} mcpr_status;
+
+enum { MCPR_FP64 = 0, MCPR_FP32 = 1 }; /* FP32: fp32 particles, fp64 reductions and matching */
+enum { MCPR_P0_NORMAL = 0, MCPR_P0_MIXTURE = 1, MCPR_P0_DELTA = 2 };
+enum { MCPR_MAP_KEEP = 0, MCPR_MAP_AFFINE = 1, MCPR_MAP_RESAMPLE = 2 };
+enum { MCPR_MAX_REGIONS = 8 };
+
+/* Drift and diffusion of the scalar McKean-Vlasov SDE (Sec. 1.1, eq.
+ * general_McKean_Vlasov) in the class the build supports: polynomial in the
+ * particle position, affine in the ensemble's mean m and variance v.
+ *   a(x, m, v) = a0 + a1 x + a2 x^2 + a3 x^3 + am m + av v
+ *   b(x, m, v) = b0 + b1 x + bm m + bv v                                    */
+typedef struct {
+    double a0, a1, a2, a3, am, av;
+    double b0, b1, bm, bv;
+} mcpr_coef;
+
+/* One problem: coefficients, initial law p0, time grid, regions of
+ * attraction (Sec. 2.2: D_i = [split_{i-1}, split_i), split_0 = -inf,
+ * split_I = +inf; a particle on a boundary belongs to the upper region).    */
+typedef struct {
+    mcpr_coef coef;
+    int32_t p0_kind;   /* MCPR_P0_*: N(mu1, sd1^2); w N(mu1,sd1^2) + (1-w) N(mu2,sd2^2); point mass at mu1 */
+    int32_t precision; /* MCPR_FP64 or MCPR_FP32 */
+    double p0_w, p0_mu1, p0_sd1, p0_mu2, p0_sd2;
+    double dt;               /* Euler-Maruyama step; a slice is steps_per_slice steps */
+    int32_t steps_per_slice; /* m >= 1 */
+    int32_t n_slices;        /* N >= 1 */
+    int32_t n_regions;       /* I, 1..MCPR_MAX_REGIONS */
+    int32_t coarse_substeps; /* RK4 steps per slice of the coarse propagator, >= 1 */
+    double split[MCPR_MAX_REGIONS - 1]; /* I-1 increasing boundaries */
+    uint64_t seed;
+} mcpr_problem;
+
+/* One particle ensemble (a micro state u in R^P, Sec. 3.4). */
+typedef struct {
+    void *x;             /* device, n_particles values, 16-byte aligned          */
+    int64_t n_particles; /* P >= 1                                              */
+    int32_t instance;    /* RNG stream (counter word 2), >= 0                    */
+    int32_t slice;       /* slice index n: step j draws at global step n*m + j   */
+    int32_t problem;     /* index into the problems[] array of the call          */
+    int32_t reserved;
+} mcpr_ensemble;
+
+/* Restriction record of one region (eq. multimodal_R): particle count,
+ * population mean and variance (weights 1/n), min and max.  n == 0: mean,
+ * var are 0.  If all particles of the region coincide, var is exactly 0 and
+ * mean is that value.  nonfinite != 0 if any particle was NaN or Inf.      */
+typedef struct {
+    int64_t n;
+    double mean, var, min, max;
+    int32_t nonfinite;
+    int32_t reserved;
+} mcpr_region_stats;
+
+/* Matching of the particles of one region (eq. multimodal_M):
+ *   MCPR_MAP_KEEP      x' = x
+ *   MCPR_MAP_AFFINE    x' = fma(scale, x - from, to)     (sqrt(sigma/V[u]) (u - E[u]) + mu)
+ *   MCPR_MAP_RESAMPLE  x' = fma(scale, xi, to)           (sqrt(sigma) xi + mu, V[u] = 0)
+ * xi: tag-3 normals at counter word 1 = boundary.  In MCPR_FP32 the map is
+ * evaluated in fp64 and rounded once to fp32.                              */
+typedef struct {
+    double from, scale, to;
+    int32_t mode;
+    int32_t boundary;
+} mcpr_region_map;
+
+/* ---- context ------------------------------------------------------------ */
+/* Creates a context on a HIP device; it owns reduction scratch, staging and
+ * per-call tables, grown on demand and reused (no allocation once warm). */
+mcpr_status mcpr_create(mcpr_ctx **ctx, int32_t device);
+void mcpr_destroy(mcpr_ctx *ctx);
+const char *mcpr_last_error(const mcpr_ctx *ctx);
+const char *mcpr_version(void);
+
+/* Measurement: when enabled, mcpr_fine_propagate brackets each of its
+ * Euler-Maruyama step launches with a pair of HIP events on the call's
+ * stream, waits for the last one and accumulates the launches' elapsed time,
+ * their number and the particle-steps done (the call then blocks the host). */
+mcpr_status mcpr_profile_enable(mcpr_ctx *ctx, int32_t on);
+mcpr_status mcpr_profile_read(mcpr_ctx *ctx, double *em_ms, int64_t *em_launches, int64_t *particle_steps,
+                              int32_t reset);
+
+/* ---- hot-path calls ------------------------------------------------------ */
+/* Initial law p0 (Sec. 1.1) sampled into each ensemble (tags 1 and 2). */
+mcpr_status mcpr_init_particles(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems,
+                                const mcpr_ensemble *ens, int32_t n_ens, mcpr_stream stream);
+
+/* Restriction R (eq. multimodal_R; S of Sec. 3.4 when I = 1).
+ * stats: device, [n_ens][n_regions + 1]; entry n_regions is the whole ensemble.
+ * Ensembles of one call must share n_regions. */
+mcpr_status mcpr_moments(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems,
+                         const mcpr_ensemble *ens, int32_t n_ens, mcpr_region_stats *stats,
+                         mcpr_stream stream);
+
+/* Fine propagator F_n (eq. Euler_Maruyama, with the X_n term of the standard
+ * scheme): steps_per_slice Euler-Maruyama steps of every ensemble, in place,
+ * all ensembles batched into each step's launch.  Step j of ensemble e uses
+ * the population mean and variance of e at the start of the step (the
+ * empirical measure of eq. general_equation) and normals at global step
+ * slice*m + j.  Ensembles of one call must share steps_per_slice, precision
+ * and n_regions; their coefficients and sizes may differ.
+ * stats (device, may be NULL): [n_ens][n_regions + 1] restriction of the
+ *   final state.
+ * trace (device, may be NULL): [n_ens][steps_per_slice][2] the (mean,
+ *   variance) each step used.                                              */
+mcpr_status mcpr_fine_propagate(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems,
+                                const mcpr_ensemble *ens, int32_t n_ens, mcpr_region_stats *stats,
+                                double *trace, mcpr_stream stream);
+
+/* Matching T per region (eq. multimodal_M), in place.  maps: device,
+ * [n_ens][n_regions].  dry_run != 0: nothing is written; probe (device,
+ * [n_ens][n_regions + 1]) receives the restriction of the transformed values
+ * grouped by the region each particle came from (min and max decide whether
+ * a region stays inside its domain, Remark on particle fractions).         */
+mcpr_status mcpr_match(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems,
+                       const mcpr_ensemble *ens, int32_t n_ens, const mcpr_region_map *maps,
+                       int32_t dry_run, mcpr_region_stats *probe, mcpr_stream stream);
+
+/* ---- Parareal driver ----------------------------------------------------- */
+/* One Parareal instance: an independent problem with its own particle count
+ * and ring of n_slices + 1 ensemble slots (caller-owned device memory of
+ * (n_slices + 1) * slot_stride values; slot_stride >= n_particles and a
+ * multiple of 4).  Slice n of iteration k lives in slot (n - k) mod (N + 1).*/
+typedef struct {
+    int32_t problem;  /* index into problems[] */
+    int32_t instance; /* RNG stream */
+    int64_t n_particles;
+    int64_t slot_stride;
+    void *ring;
+} mcpr_instance;
+
+/* Generalised micro-macro Parareal (eq. mM_parareal_other_k_NEW) with the
+ * MC-moments iterator (unimodal and multimodal definitions of Sec. 3.4;
+ * alpha = (a - c) + R(b)), lifting by T of u0, coarse propagator = Taylor
+ * moment model (eq. moment_model_class_1 per region, eq.
+ * moment_model_Taylor_multimodal) with fractions frozen, RK4.  learning != 0:
+ * the particle-fraction model of Sec. 3.6 (two regions).  All instances of
+ * one driver share steps_per_slice, n_slices, n_regions and precision.  The
+ * problems array is copied.  An instance stops iterating once its delta
+ * (below) is <= tol, or after n_slices iterations (every slice exact).      */
+mcpr_status mcpr_parareal_create(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems,
+                                 const mcpr_instance *inst, int32_t n_inst, int32_t learning, double tol,
+                                 mcpr_parareal **out);
+void mcpr_parareal_destroy(mcpr_parareal *pr);
+
+/* Iteration 0: if sample_u0, draw u0 from p0 into slot 0 (else slot 0 must
+ * hold u0); rho_0 = R(u0); rho^0_{n+1} = C_n(rho^0_n); u^0_n = T(rho^0_n, u0)
+ * per region.  Synchronises the stream. */
+mcpr_status mcpr_parareal_init(mcpr_parareal *pr, int32_t sample_u0, mcpr_stream stream);
+
+/* One iteration k -> k+1 for every instance that has not stopped: F on the
+ * slices n >= k of all instances in one batched sweep, sequential coarse
+ * sweep with the iterator on the host, matching on the device.  delta_out
+ * (host, may be NULL): [n_inst] max over n of the change of the global mean
+ * and variance.  Synchronises the stream. */
+mcpr_status mcpr_parareal_iterate(mcpr_parareal *pr, double *delta_out, mcpr_stream stream);
+
+/* Number of iterations done (k). */
+int32_t mcpr_parareal_iteration(const mcpr_parareal *pr);
+
+/* Macro state of instance i (host arrays): rho [(N+1)][I][3] = (fraction,
+ * mean, variance) per region; glob [(N+1)][2] = mixture mean and variance
+ * (eq. mixture_of_distributions_mean_variance).  Either may be NULL. */
+mcpr_status mcpr_parareal_macro(const mcpr_parareal *pr, int32_t inst, double *rho, double *glob);
+
+/* Iterator outcome of the last iteration, [N][I] (host): 0 short cut
+ * I(a,b,a) = (R(b), b), 1 matched, 2 negative variance, 3 would leave its
+ * region, 4 empty region. */
+mcpr_status mcpr_parareal_flags(const mcpr_parareal *pr, int32_t inst, int32_t *flags);
+
+/* Device pointer of u^k_n (slice-start state n of the current iteration k). */
+mcpr_status mcpr_parareal_slot(const mcpr_parareal *pr, int32_t inst, int32_t n, void **x);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCPR_H */

@@ -1,0 +1,998 @@
+// api.hip -- host side of the C ABI (include/mcpr.h): context, argument
+// validation, work tables, the launch sequence of each call, and the
+// MC-moments Parareal driver.
+//
+// Every sum over particles is formed on the device in the canonical order of
+// common.hpp; the host only combines per-slice macro quantities (the coarse
+// propagator and the Parareal iterator work on a few doubles per slice).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "launch.hpp"
+#include "mcpr.h"
+
+static_assert(sizeof(mcpr_region_stats) == sizeof(mcpr::RegionStats), "record layout");
+static_assert(sizeof(mcpr_region_map) == sizeof(mcpr::RegionMap), "map layout");
+static_assert(sizeof(mcpr_region_stats) == 48, "record size");
+
+using mcpr::RegionMap;
+using mcpr::RegionPartial;
+using mcpr::RegionStats;
+using mcpr::WorkItem;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+struct HostBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+} // namespace
+
+struct mcpr_ctx {
+    int device = 0;
+    std::string err;
+    DevBuf items, blocks, part[2], shift[2], rpart, rshift[2], maps, recs;
+    HostBuf staging;
+    hipEvent_t staged = nullptr; // the last upload from staging has completed
+    // profiling of the Euler-Maruyama step launches (off unless enabled)
+    bool profile = false;
+    std::vector<hipEvent_t> prof0, prof1; // one pair per step launch
+    double prof_ms = 0.0;
+    int64_t prof_launches = 0;
+    int64_t prof_particle_steps = 0;
+};
+
+namespace {
+
+mcpr_status fail(mcpr_ctx *ctx, mcpr_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                                          \
+    do {                                                                                                       \
+        hipError_t e_ = (expr);                                                                                \
+        if (e_ != hipSuccess) return fail(ctx, MCPR_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+mcpr_status ensure(mcpr_ctx *ctx, DevBuf &b, size_t bytes) {
+    if (bytes <= b.cap) return MCPR_OK;
+    size_t want = std::max(bytes, b.cap * 3 / 2);
+    want = (want + 255) & ~(size_t)255;
+    if (b.p) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(b.p));
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        b.p = nullptr;
+        return fail(ctx, MCPR_E_OOM, "device allocation of %zu bytes failed", want);
+    }
+    b.cap = want;
+    return MCPR_OK;
+}
+
+// Host staging of the per-call tables (pinned, reused once its last upload is done).
+mcpr_status stage(mcpr_ctx *ctx, size_t bytes, char **out) {
+    HIP_TRY(hipEventSynchronize(ctx->staged));
+    if (bytes > ctx->staging.cap) {
+        if (ctx->staging.p) HIP_TRY(hipHostFree(ctx->staging.p));
+        ctx->staging.p = nullptr;
+        size_t want = std::max(bytes, (size_t)1 << 16);
+        if (hipHostMalloc(&ctx->staging.p, want, hipHostMallocDefault) != hipSuccess) {
+            ctx->staging.cap = 0;
+            return fail(ctx, MCPR_E_OOM, "pinned allocation of %zu bytes failed", want);
+        }
+        ctx->staging.cap = want;
+    }
+    *out = (char *)ctx->staging.p;
+    return MCPR_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// ----------------------------------------------------------------------------
+// validation
+// ----------------------------------------------------------------------------
+mcpr_status check_problem(mcpr_ctx *ctx, const mcpr_problem &p, int idx) {
+    if (p.precision != MCPR_FP64 && p.precision != MCPR_FP32)
+        return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: precision %d", idx, p.precision);
+    if (!(p.dt > 0.0) || !std::isfinite(p.dt)) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: dt must be > 0", idx);
+    if (p.steps_per_slice < 1) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: steps_per_slice < 1", idx);
+    if (p.n_slices < 1) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: n_slices < 1", idx);
+    if ((int64_t)p.n_slices * p.steps_per_slice > 0x7fffffffLL)
+        return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: too many steps", idx);
+    if (p.n_regions < 1 || p.n_regions > MCPR_MAX_REGIONS)
+        return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: n_regions must be in 1..%d", idx, MCPR_MAX_REGIONS);
+    for (int i = 0; i + 1 < p.n_regions; ++i) {
+        if (!std::isfinite(p.split[i])) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: split %d", idx, i);
+        if (i > 0 && !(p.split[i] > p.split[i - 1]))
+            return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: splits must increase", idx);
+    }
+    if (p.coarse_substeps < 1) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: coarse_substeps < 1", idx);
+    if (p.p0_kind < 0 || p.p0_kind > 2) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: p0_kind", idx);
+    const double *c = &p.coef.a0;
+    for (int i = 0; i < 10; ++i)
+        if (!std::isfinite(c[i])) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: coefficient %d not finite", idx, i);
+    return MCPR_OK;
+}
+
+bool same_layout(const mcpr_problem &a, const mcpr_problem &b) {
+    if (a.precision != b.precision || a.steps_per_slice != b.steps_per_slice || a.n_regions != b.n_regions)
+        return false;
+    for (int i = 0; i + 1 < a.n_regions; ++i)
+        if (a.split[i] != b.split[i]) return false;
+    return true;
+}
+
+mcpr_status check_call(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems, const mcpr_ensemble *ens,
+                       int32_t n_ens) {
+    if (!ctx) return MCPR_E_INVALID_ARG;
+    if (!problems || n_problems < 1) return fail(ctx, MCPR_E_INVALID_ARG, "no problems");
+    if (!ens || n_ens < 1) return fail(ctx, MCPR_E_INVALID_ARG, "no ensembles");
+    for (int i = 0; i < n_problems; ++i) {
+        mcpr_status st = check_problem(ctx, problems[i], i);
+        if (st != MCPR_OK) return st;
+    }
+    const mcpr_problem *first = &problems[ens[0].problem >= 0 && ens[0].problem < n_problems ? ens[0].problem : 0];
+    int64_t total_sc = 0;
+    for (int e = 0; e < n_ens; ++e) {
+        const mcpr_ensemble &E = ens[e];
+        if (E.problem < 0 || E.problem >= n_problems)
+            return fail(ctx, MCPR_E_INVALID_ARG, "ensemble %d: problem index %d", e, E.problem);
+        if (!same_layout(problems[E.problem], *first))
+            return fail(ctx, MCPR_E_INVALID_ARG,
+                        "ensemble %d: precision, steps_per_slice and regions must agree within a call", e);
+        if (!E.x) return fail(ctx, MCPR_E_INVALID_ARG, "ensemble %d: null particle pointer", e);
+        if (((uintptr_t)E.x & 15) != 0) return fail(ctx, MCPR_E_INVALID_ARG, "ensemble %d: pointer not 16-byte aligned", e);
+        if (E.n_particles < 1 || E.n_particles > ((int64_t)1 << 34))
+            return fail(ctx, MCPR_E_INVALID_ARG, "ensemble %d: n_particles %lld", e, (long long)E.n_particles);
+        if (E.instance < 0) return fail(ctx, MCPR_E_INVALID_ARG, "ensemble %d: instance < 0", e);
+        if (E.slice < 0 || (int64_t)(E.slice + 1) * problems[E.problem].steps_per_slice > 0x7fffffffLL)
+            return fail(ctx, MCPR_E_INVALID_ARG, "ensemble %d: slice %d", e, E.slice);
+        total_sc += mcpr::superchunks(E.n_particles, mcpr::canonical_quads_per_thread(E.n_particles));
+    }
+    if (total_sc > 0x7fffffffLL) return fail(ctx, MCPR_E_INVALID_ARG, "too many particles in one call");
+    return MCPR_OK;
+}
+
+// ----------------------------------------------------------------------------
+// work tables
+// ----------------------------------------------------------------------------
+struct Tables {
+    std::vector<WorkItem> items;
+    std::vector<int2> blocks;
+    int total_sc = 0;
+};
+
+void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_t n_ens, Tables &t) {
+    t.items.resize(n_ens);
+    t.blocks.clear();
+    int off = 0;
+    for (int e = 0; e < n_ens; ++e) {
+        const mcpr_ensemble &E = ens[e];
+        const mcpr_problem &p = problems[E.problem];
+        WorkItem &w = t.items[e];
+        std::memset(&w, 0, sizeof w);
+        w.x = E.x;
+        w.P = E.n_particles;
+        w.inst = E.instance;
+        w.step0 = E.slice * p.steps_per_slice;
+        w.R = mcpr::canonical_quads_per_thread(E.n_particles);
+        w.nsc = (int32_t)mcpr::superchunks(E.n_particles, w.R);
+        w.part_off = off;
+        w.p0_kind = p.p0_kind;
+        w.key0 = (uint32_t)(p.seed & 0xffffffffu);
+        w.key1 = (uint32_t)(p.seed >> 32);
+        const double *c = &p.coef.a0;
+        for (int i = 0; i < 10; ++i) w.c[i] = c[i];
+        w.dt = p.dt;
+        w.sdt = std::sqrt(p.dt);
+        w.p0[0] = p.p0_w;
+        w.p0[1] = p.p0_mu1;
+        w.p0[2] = p.p0_sd1;
+        w.p0[3] = p.p0_mu2;
+        w.p0[4] = p.p0_sd2;
+        for (int s = 0; s < w.nsc; ++s) t.blocks.push_back(make_int2(e, s));
+        off += w.nsc;
+    }
+    t.total_sc = off;
+}
+
+// Upload items and blocks (and optionally maps) through the pinned staging buffer.
+mcpr_status upload(mcpr_ctx *ctx, const Tables &t, const void *maps, size_t map_bytes, hipStream_t s) {
+    const size_t ib = t.items.size() * sizeof(WorkItem), bb = t.blocks.size() * sizeof(int2);
+    mcpr_status st;
+    if ((st = ensure(ctx, ctx->items, ib)) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->blocks, bb)) != MCPR_OK) return st;
+    if (map_bytes && (st = ensure(ctx, ctx->maps, map_bytes)) != MCPR_OK) return st;
+    char *h;
+    if ((st = stage(ctx, align256(ib) + align256(bb) + align256(map_bytes), &h)) != MCPR_OK) return st;
+    std::memcpy(h, t.items.data(), ib);
+    std::memcpy(h + align256(ib), t.blocks.data(), bb);
+    HIP_TRY(hipMemcpyAsync(ctx->items.p, h, ib, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ctx->blocks.p, h + align256(ib), bb, hipMemcpyHostToDevice, s));
+    if (map_bytes) {
+        std::memcpy(h + align256(ib) + align256(bb), maps, map_bytes);
+        HIP_TRY(hipMemcpyAsync(ctx->maps.p, h + align256(ib) + align256(bb), map_bytes, hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(hipEventRecord(ctx->staged, s));
+    return MCPR_OK;
+}
+
+mcpr::Splits splits_of(const mcpr_problem &p) {
+    mcpr::Splits sp;
+    for (int i = 0; i < mcpr::kMaxRegions - 1; ++i) sp.s[i] = (i + 1 < p.n_regions) ? p.split[i] : 0.0;
+    return sp;
+}
+
+// Restriction records of the ensembles in the tables.  shift: per-item shift of
+// the first pass (NULL: x[0]).  Two passes when the ensemble is split into
+// regions, so that each region's sums are taken about that region's mean.
+mcpr_status records(mcpr_ctx *ctx, const Tables &t, int prec, int nreg, const mcpr::Splits &sp, const double *shift,
+                    bool two_pass, int mode, const RegionMap *maps, RegionStats *out, hipStream_t s) {
+    const int nr = nreg + 1, n = (int)t.items.size();
+    mcpr_status st;
+    if ((st = ensure(ctx, ctx->rpart, (size_t)t.total_sc * nr * sizeof(RegionPartial))) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->rshift[0], (size_t)n * nr * sizeof(double))) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->rshift[1], (size_t)n * nr * sizeof(double))) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->recs, (size_t)n * nr * sizeof(RegionStats))) != MCPR_OK) return st;
+    const WorkItem *items = (const WorkItem *)ctx->items.p;
+    const int2 *blocks = (const int2 *)ctx->blocks.p;
+    const int nb = (int)t.blocks.size();
+    double *rs0 = (double *)ctx->rshift[0].p, *rs1 = (double *)ctx->rshift[1].p;
+    RegionPartial *rp = (RegionPartial *)ctx->rpart.p;
+    HIP_TRY(mcpr::launch_fill_shift(prec, nr, items, n, shift, rs0, s));
+    HIP_TRY(mcpr::launch_region_partials(prec, nr, mode, items, blocks, nb, rs0, sp, maps, rp, s));
+    if (two_pass) {
+        HIP_TRY(mcpr::launch_region_combine(nr, items, n, rp, rs0, (RegionStats *)ctx->recs.p, rs1, s));
+        HIP_TRY(mcpr::launch_region_partials(prec, nr, mode, items, blocks, nb, rs1, sp, maps, rp, s));
+        HIP_TRY(mcpr::launch_region_combine(nr, items, n, rp, rs1, out, nullptr, s));
+    } else {
+        HIP_TRY(mcpr::launch_region_combine(nr, items, n, rp, rs0, out, nullptr, s));
+    }
+    return MCPR_OK;
+}
+
+// The step sequence of the fine propagator on already uploaded tables.
+mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int nreg, const mcpr::Splits &sp,
+                          RegionStats *stats, double2 *trace, hipStream_t s) {
+    const int n = (int)t.items.size();
+    mcpr_status st;
+    for (int b = 0; b < 2; ++b) {
+        if ((st = ensure(ctx, ctx->part[b], (size_t)t.total_sc * sizeof(double2))) != MCPR_OK) return st;
+        if ((st = ensure(ctx, ctx->shift[b], (size_t)n * sizeof(double))) != MCPR_OK) return st;
+    }
+    const WorkItem *items = (const WorkItem *)ctx->items.p;
+    const int2 *blocks = (const int2 *)ctx->blocks.p;
+    const int nb = (int)t.blocks.size();
+    double2 *part[2] = {(double2 *)ctx->part[0].p, (double2 *)ctx->part[1].p};
+    double *shift[2] = {(double *)ctx->shift[0].p, (double *)ctx->shift[1].p};
+    HIP_TRY(mcpr::launch_sum_init(prec, items, blocks, nb, part[0], shift[0], s));
+    if (ctx->profile) {
+        while ((int)ctx->prof0.size() < m) {
+            hipEvent_t e0, e1;
+            HIP_TRY(hipEventCreate(&e0));
+            HIP_TRY(hipEventCreate(&e1));
+            ctx->prof0.push_back(e0);
+            ctx->prof1.push_back(e1);
+        }
+    }
+    for (int j = 0; j < m; ++j) {
+        const int a = j & 1, b = a ^ 1;
+        if (ctx->profile) HIP_TRY(hipEventRecord(ctx->prof0[j], s));
+        HIP_TRY(mcpr::launch_em_step(prec, items, blocks, nb, j, part[a], shift[a], part[b], shift[b], trace, m, s));
+        if (ctx->profile) HIP_TRY(hipEventRecord(ctx->prof1[j], s));
+    }
+    if (ctx->profile) {
+        HIP_TRY(hipEventSynchronize(ctx->prof1[m - 1]));
+        for (int j = 0; j < m; ++j) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, ctx->prof0[j], ctx->prof1[j]));
+            ctx->prof_ms += ms;
+        }
+        ctx->prof_launches += m;
+        int64_t ps = 0;
+        for (const WorkItem &w : t.items) ps += w.P;
+        ctx->prof_particle_steps += ps * m;
+    }
+    if (stats) {
+        // shift of the record sums: the mean the last step used
+        return records(ctx, t, prec, nreg, sp, shift[m & 1], nreg > 1, 0, nullptr, stats, s);
+    }
+    return MCPR_OK;
+}
+
+} // namespace
+
+// ============================================================================
+// C ABI: context
+// ============================================================================
+extern "C" {
+
+const char *mcpr_version(void) { return "mcpr 0.1 (gfx950)"; }
+
+mcpr_status mcpr_create(mcpr_ctx **out, int32_t device) {
+    if (!out) return MCPR_E_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return MCPR_E_DEVICE;
+    if (device < 0 || device >= count) return MCPR_E_INVALID_ARG;
+    if (hipSetDevice(device) != hipSuccess) return MCPR_E_DEVICE;
+    mcpr_ctx *ctx = new mcpr_ctx();
+    ctx->device = device;
+    if (hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming) != hipSuccess) {
+        delete ctx;
+        return MCPR_E_DEVICE;
+    }
+    *out = ctx;
+    return MCPR_OK;
+}
+
+void mcpr_destroy(mcpr_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    DevBuf *bufs[] = {&ctx->items, &ctx->blocks, &ctx->part[0], &ctx->part[1], &ctx->shift[0], &ctx->shift[1],
+                      &ctx->rpart, &ctx->rshift[0], &ctx->rshift[1], &ctx->maps, &ctx->recs};
+    for (DevBuf *b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (ctx->staging.p) (void)hipHostFree(ctx->staging.p);
+    if (ctx->staged) (void)hipEventDestroy(ctx->staged);
+    for (hipEvent_t e : ctx->prof0) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->prof1) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+const char *mcpr_last_error(const mcpr_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+mcpr_status mcpr_profile_enable(mcpr_ctx *ctx, int32_t on) {
+    if (!ctx) return MCPR_E_INVALID_ARG;
+    HIP_TRY(hipSetDevice(ctx->device));
+    ctx->profile = on != 0;
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_profile_read(mcpr_ctx *ctx, double *em_ms, int64_t *em_launches, int64_t *particle_steps,
+                              int32_t reset) {
+    if (!ctx) return MCPR_E_INVALID_ARG;
+    if (em_ms) *em_ms = ctx->prof_ms;
+    if (em_launches) *em_launches = ctx->prof_launches;
+    if (particle_steps) *particle_steps = ctx->prof_particle_steps;
+    if (reset) {
+        ctx->prof_ms = 0.0;
+        ctx->prof_launches = 0;
+        ctx->prof_particle_steps = 0;
+    }
+    return MCPR_OK;
+}
+
+// ============================================================================
+// C ABI: hot-path calls
+// ============================================================================
+mcpr_status mcpr_init_particles(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems,
+                                const mcpr_ensemble *ens, int32_t n_ens, mcpr_stream stream) {
+    mcpr_status st = check_call(ctx, problems, n_problems, ens, n_ens);
+    if (st != MCPR_OK) return st;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Tables t;
+    build_tables(problems, ens, n_ens, t);
+    if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
+    HIP_TRY(mcpr::launch_init(problems[ens[0].problem].precision, (const WorkItem *)ctx->items.p,
+                              (const int2 *)ctx->blocks.p, (int)t.blocks.size(), s));
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_moments(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems, const mcpr_ensemble *ens,
+                         int32_t n_ens, mcpr_region_stats *stats, mcpr_stream stream) {
+    mcpr_status st = check_call(ctx, problems, n_problems, ens, n_ens);
+    if (st != MCPR_OK) return st;
+    if (!stats) return fail(ctx, MCPR_E_INVALID_ARG, "stats is null");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const mcpr_problem &p = problems[ens[0].problem];
+    Tables t;
+    build_tables(problems, ens, n_ens, t);
+    if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
+    return records(ctx, t, p.precision, p.n_regions, splits_of(p), nullptr, true, 0, nullptr, (RegionStats *)stats, s);
+}
+
+mcpr_status mcpr_fine_propagate(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems,
+                                const mcpr_ensemble *ens, int32_t n_ens, mcpr_region_stats *stats, double *trace,
+                                mcpr_stream stream) {
+    mcpr_status st = check_call(ctx, problems, n_problems, ens, n_ens);
+    if (st != MCPR_OK) return st;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const mcpr_problem &p = problems[ens[0].problem];
+    Tables t;
+    build_tables(problems, ens, n_ens, t);
+    if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
+    return fine_sequence(ctx, t, p.precision, p.steps_per_slice, p.n_regions, splits_of(p), (RegionStats *)stats,
+                         (double2 *)trace, s);
+}
+
+mcpr_status mcpr_match(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems, const mcpr_ensemble *ens,
+                       int32_t n_ens, const mcpr_region_map *maps, int32_t dry_run, mcpr_region_stats *probe,
+                       mcpr_stream stream) {
+    mcpr_status st = check_call(ctx, problems, n_problems, ens, n_ens);
+    if (st != MCPR_OK) return st;
+    if (!maps) return fail(ctx, MCPR_E_INVALID_ARG, "maps is null");
+    if (dry_run && !probe) return fail(ctx, MCPR_E_INVALID_ARG, "dry run needs a probe array");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const mcpr_problem &p = problems[ens[0].problem];
+    Tables t;
+    build_tables(problems, ens, n_ens, t);
+    if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
+    if (dry_run)
+        return records(ctx, t, p.precision, p.n_regions, splits_of(p), nullptr, true, 1, (const RegionMap *)maps,
+                       (RegionStats *)probe, s);
+    HIP_TRY(mcpr::launch_match_apply(p.precision, p.n_regions, (const WorkItem *)ctx->items.p,
+                                     (const int2 *)ctx->blocks.p, (int)t.blocks.size(), splits_of(p),
+                                     (const RegionMap *)maps, s));
+    return MCPR_OK;
+}
+
+} // extern "C"
+
+// ============================================================================
+// MC-moments Parareal driver
+// ============================================================================
+namespace {
+
+// ---- coarse propagator: Taylor moment model per region, fractions frozen ----
+// dM_i/dt = a(M_i, mbar, vbar) + a_xx(M_i) V_i / 2
+// dV_i/dt = (2 a_x(M_i) + b_x(M_i)^2) V_i + b(M_i, mbar, vbar)^2
+// (mbar, vbar) = mixture mean and variance of the regional moments.
+struct Macro {
+    double f[mcpr::kMaxRegions];
+    double M[mcpr::kMaxRegions];
+    double V[mcpr::kMaxRegions];
+};
+
+void mixture(int I, const Macro &r, double &mbar, double &vbar) {
+    double m = 0.0;
+    for (int i = 0; i < I; ++i)
+        if (r.f[i] > 0.0) m += r.f[i] * r.M[i];
+    double v = 0.0;
+    for (int i = 0; i < I; ++i)
+        if (r.f[i] > 0.0) {
+            const double d = r.M[i] - m;
+            v += r.f[i] * (r.V[i] + d * d);
+        }
+    mbar = m;
+    vbar = v;
+}
+
+void moment_rhs(const mcpr_coef &c, int I, const Macro &r, Macro &d) {
+    double mbar, vbar;
+    mixture(I, r, mbar, vbar);
+    for (int i = 0; i < I; ++i) {
+        const double x = r.M[i];
+        const double a = c.a0 + x * (c.a1 + x * (c.a2 + x * c.a3)) + c.am * mbar + c.av * vbar;
+        const double ax = c.a1 + x * (2.0 * c.a2 + 3.0 * c.a3 * x);
+        const double axx = 2.0 * c.a2 + 6.0 * c.a3 * x;
+        const double b = c.b0 + c.b1 * x + c.bm * mbar + c.bv * vbar;
+        const double bx = c.b1;
+        d.M[i] = a + 0.5 * axx * r.V[i];
+        d.V[i] = (2.0 * ax + bx * bx) * r.V[i] + b * b;
+        d.f[i] = 0.0;
+    }
+}
+
+Macro coarse_step(const mcpr_problem &p, const Macro &in) {
+    const int I = p.n_regions;
+    const double h = (p.dt * p.steps_per_slice) / p.coarse_substeps;
+    Macro y = in, k1, k2, k3, k4, tmp;
+    for (int s = 0; s < p.coarse_substeps; ++s) {
+        moment_rhs(p.coef, I, y, k1);
+        tmp = y;
+        for (int i = 0; i < I; ++i) { tmp.M[i] = y.M[i] + 0.5 * h * k1.M[i]; tmp.V[i] = y.V[i] + 0.5 * h * k1.V[i]; }
+        moment_rhs(p.coef, I, tmp, k2);
+        for (int i = 0; i < I; ++i) { tmp.M[i] = y.M[i] + 0.5 * h * k2.M[i]; tmp.V[i] = y.V[i] + 0.5 * h * k2.V[i]; }
+        moment_rhs(p.coef, I, tmp, k3);
+        for (int i = 0; i < I; ++i) { tmp.M[i] = y.M[i] + h * k3.M[i]; tmp.V[i] = y.V[i] + h * k3.V[i]; }
+        moment_rhs(p.coef, I, tmp, k4);
+        for (int i = 0; i < I; ++i) {
+            y.M[i] += (h / 6.0) * (k1.M[i] + 2.0 * k2.M[i] + 2.0 * k3.M[i] + k4.M[i]);
+            y.V[i] += (h / 6.0) * (k1.V[i] + 2.0 * k2.V[i] + 2.0 * k3.V[i] + k4.V[i]);
+        }
+    }
+    return y;
+}
+
+bool bit_equal(const Macro &a, const Macro &b, int I) {
+    return std::memcmp(a.f, b.f, sizeof(double) * I) == 0 && std::memcmp(a.M, b.M, sizeof(double) * I) == 0 &&
+           std::memcmp(a.V, b.V, sizeof(double) * I) == 0;
+}
+
+Macro macro_of(const RegionStats *st, int I, int64_t P) {
+    Macro r;
+    std::memset(&r, 0, sizeof r);
+    for (int i = 0; i < I; ++i) {
+        r.f[i] = (double)st[i].n / (double)P;
+        r.M[i] = st[i].mean;
+        r.V[i] = st[i].var;
+    }
+    return r;
+}
+
+int region_of(const mcpr_problem &p, double x) {
+    int g = 0;
+    for (int i = 0; i + 1 < p.n_regions; ++i) g += (x >= p.split[i]) ? 1 : 0;
+    return g;
+}
+
+// The device's evaluation of an affine map, reproduced on the host.
+double mapped(int prec, const RegionMap &mp, double x) {
+    const double y = std::fma(mp.scale, x - mp.from, mp.to);
+    return prec == MCPR_FP32 ? (double)(float)y : y;
+}
+
+// ---- particle-fraction model (two regions): P1(t) = P* + (P1(0) - P*) e^{-kappa t}
+double frac_model(double y0, double kappa, double pstar, double t) { return pstar + (y0 - pstar) * std::exp(-kappa * t); }
+
+void fit_fractions(const std::vector<double> &t, const std::vector<double> &y, double &kappa, double &pstar) {
+    const int n = (int)t.size();
+    auto sse_of = [&](double k, double p) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double r = frac_model(y[0], k, p, t[j]) - y[j];
+            s += r * r;
+        }
+        return s;
+    };
+    double lam = 1e-3, sse = sse_of(kappa, pstar);
+    for (int it = 0; it < 200; ++it) {
+        double g0 = 0, g1 = 0, h00 = 0, h01 = 0, h11 = 0;
+        for (int j = 0; j < n; ++j) {
+            const double e = std::exp(-kappa * t[j]);
+            const double r = frac_model(y[0], kappa, pstar, t[j]) - y[j];
+            const double dk = -(y[0] - pstar) * t[j] * e, dp = 1.0 - e;
+            g0 += dk * r; g1 += dp * r; h00 += dk * dk; h01 += dk * dp; h11 += dp * dp;
+        }
+        bool improved = false, converged = false;
+        for (int tries = 0; tries < 40 && !improved; ++tries) {
+            const double a00 = h00 * (1.0 + lam), a11 = h11 * (1.0 + lam), det = a00 * a11 - h01 * h01;
+            if (!(det > 0.0) || !std::isfinite(det)) { lam *= 10.0; continue; }
+            double kn = kappa - (a11 * g0 - h01 * g1) / det, pn = pstar - (a00 * g1 - h01 * g0) / det;
+            kn = std::max(kn, 0.0);
+            pn = std::min(std::max(pn, 0.0), 1.0);
+            const double sn = sse_of(kn, pn);
+            if (sn < sse) {
+                converged = std::fabs(kn - kappa) + std::fabs(pn - pstar) <= 1e-14 * (std::fabs(kappa) + std::fabs(pstar));
+                kappa = kn; pstar = pn; sse = sn;
+                lam = std::max(lam / 10.0, 1e-12);
+                improved = true;
+            } else {
+                lam *= 10.0;
+            }
+        }
+        if (!improved || converged) break;
+    }
+}
+
+struct Instance {
+    mcpr_problem pb;
+    int32_t inst;
+    int64_t P, stride;
+    char *ring;
+    std::vector<Macro> rho;          // rho^k_n, n = 0..N
+    std::vector<Macro> cache;        // C_n(rho^k_n), n = 0..N-1
+    std::vector<RegionStats> rec;    // R(F(u^k_{n-1})) at boundary n (n = 1..N), [(N+1)][I+1]
+    std::vector<RegionStats> st0;    // R(u0)
+    std::vector<int32_t> flags;      // [N][I] of the last iteration
+    bool done = false;
+    bool have_fit = false;
+    double kappa = 0.0, pstar = 0.0;
+};
+
+} // namespace
+
+struct mcpr_parareal {
+    mcpr_ctx *ctx;
+    int N, m, I, prec;
+    int k = 0;
+    bool learning;
+    double tol;
+    size_t esize;
+    std::vector<Instance> inst;
+    DevBuf dstats, dmaps;
+    HostBuf hstats;
+};
+
+namespace {
+
+char *slot_ptr(const mcpr_parareal *pr, const Instance &in, int n, int k) {
+    const int N = pr->N;
+    const int idx = ((n - k) % (N + 1) + (N + 1)) % (N + 1);
+    return in.ring + (size_t)idx * in.stride * pr->esize;
+}
+
+mcpr_status pr_fail(mcpr_parareal *pr, mcpr_status st, const char *msg) { return fail(pr->ctx, st, "%s", msg); }
+
+// Fetch device records [n][I+1] into host memory (synchronises the stream).
+mcpr_status fetch(mcpr_parareal *pr, size_t count, std::vector<RegionStats> &out, hipStream_t s) {
+    mcpr_ctx *ctx = pr->ctx;
+    out.resize(count);
+    HIP_TRY(hipMemcpyAsync(out.data(), pr->dstats.p, count * sizeof(RegionStats), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MCPR_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+mcpr_status mcpr_parareal_create(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems,
+                                 const mcpr_instance *inst, int32_t n_inst, int32_t learning, double tol,
+                                 mcpr_parareal **out) {
+    if (!ctx || !out) return MCPR_E_INVALID_ARG;
+    *out = nullptr;
+    if (!problems || n_problems < 1 || !inst || n_inst < 1) return fail(ctx, MCPR_E_INVALID_ARG, "empty driver");
+    for (int i = 0; i < n_problems; ++i) {
+        mcpr_status st = check_problem(ctx, problems[i], i);
+        if (st != MCPR_OK) return st;
+    }
+    const mcpr_problem &p0 = problems[inst[0].problem >= 0 && inst[0].problem < n_problems ? inst[0].problem : 0];
+    for (int i = 0; i < n_inst; ++i) {
+        const mcpr_instance &I = inst[i];
+        if (I.problem < 0 || I.problem >= n_problems) return fail(ctx, MCPR_E_INVALID_ARG, "instance %d: problem", i);
+        const mcpr_problem &p = problems[I.problem];
+        if (!same_layout(p, p0) || p.n_slices != p0.n_slices)
+            return fail(ctx, MCPR_E_INVALID_ARG, "instance %d: layout differs from instance 0", i);
+        if (!I.ring || ((uintptr_t)I.ring & 15)) return fail(ctx, MCPR_E_INVALID_ARG, "instance %d: ring pointer", i);
+        if (I.n_particles < 1 || I.slot_stride < I.n_particles || (I.slot_stride & 3))
+            return fail(ctx, MCPR_E_INVALID_ARG, "instance %d: n_particles / slot_stride", i);
+        if (I.instance < 0) return fail(ctx, MCPR_E_INVALID_ARG, "instance %d: RNG stream", i);
+    }
+    if (learning && p0.n_regions != 2) return fail(ctx, MCPR_E_UNSUPPORTED, "learning needs two regions");
+    if (!(tol >= 0.0)) return fail(ctx, MCPR_E_INVALID_ARG, "tol must be >= 0");
+    mcpr_parareal *pr = new mcpr_parareal();
+    pr->ctx = ctx;
+    pr->N = p0.n_slices;
+    pr->m = p0.steps_per_slice;
+    pr->I = p0.n_regions;
+    pr->prec = p0.precision;
+    pr->learning = learning != 0;
+    pr->tol = tol;
+    pr->esize = pr->prec == MCPR_FP64 ? 8 : 4;
+    pr->inst.resize(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        Instance &in = pr->inst[i];
+        in.pb = problems[inst[i].problem];
+        in.inst = inst[i].instance;
+        in.P = inst[i].n_particles;
+        in.stride = inst[i].slot_stride;
+        in.ring = (char *)inst[i].ring;
+        in.rho.resize(pr->N + 1);
+        in.cache.resize(pr->N);
+        in.rec.resize((size_t)(pr->N + 1) * (pr->I + 1));
+        in.flags.assign((size_t)pr->N * pr->I, 0);
+    }
+    *out = pr;
+    return MCPR_OK;
+}
+
+void mcpr_parareal_destroy(mcpr_parareal *pr) {
+    if (!pr) return;
+    (void)hipDeviceSynchronize();
+    if (pr->dstats.p) (void)hipFree(pr->dstats.p);
+    if (pr->dmaps.p) (void)hipFree(pr->dmaps.p);
+    delete pr;
+}
+
+int32_t mcpr_parareal_iteration(const mcpr_parareal *pr) { return pr ? pr->k : -1; }
+
+mcpr_status mcpr_parareal_init(mcpr_parareal *pr, int32_t sample_u0, mcpr_stream stream) {
+    if (!pr) return MCPR_E_INVALID_ARG;
+    mcpr_ctx *ctx = pr->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int N = pr->N, I = pr->I, n_inst = (int)pr->inst.size();
+    std::vector<mcpr_problem> probs(n_inst);
+    std::vector<mcpr_ensemble> ens(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        Instance &in = pr->inst[i];
+        probs[i] = in.pb;
+        ens[i] = mcpr_ensemble{in.ring, in.P, in.inst, 0, i, 0};
+    }
+    mcpr_status st;
+    if (sample_u0 && (st = mcpr_init_particles(ctx, probs.data(), n_inst, ens.data(), n_inst, stream)) != MCPR_OK)
+        return st;
+    if ((st = ensure(ctx, pr->dstats, (size_t)n_inst * N * (I + 1) * sizeof(RegionStats))) != MCPR_OK) return st;
+    if ((st = mcpr_moments(ctx, probs.data(), n_inst, ens.data(), n_inst, (mcpr_region_stats *)pr->dstats.p, stream)) !=
+        MCPR_OK)
+        return st;
+    std::vector<RegionStats> h;
+    if ((st = fetch(pr, (size_t)n_inst * (I + 1), h, s)) != MCPR_OK) return st;
+
+    // coarse sweep and the lifting maps u^0_n = T(rho^0_n, u0), n = 1..N
+    std::vector<mcpr_ensemble> lens;
+    std::vector<mcpr_problem> lprobs;
+    std::vector<RegionMap> maps;
+    for (int i = 0; i < n_inst; ++i) {
+        Instance &in = pr->inst[i];
+        in.done = false;
+        in.have_fit = false;
+        in.st0.assign(h.begin() + (size_t)i * (I + 1), h.begin() + (size_t)(i + 1) * (I + 1));
+        for (const RegionStats &r : in.st0)
+            if (r.nonfinite) return fail(ctx, MCPR_E_NONFINITE, "instance %d: non-finite initial particles", i);
+        in.rho[0] = macro_of(in.st0.data(), I, in.P);
+        for (int n = 0; n < N; ++n) {
+            in.rho[n + 1] = coarse_step(in.pb, in.rho[n]);
+            in.cache[n] = in.rho[n + 1];
+        }
+        std::fill(in.flags.begin(), in.flags.end(), 0);
+        for (int n = 1; n <= N; ++n) {
+            char *dst = in.ring + (size_t)n * in.stride * pr->esize;
+            HIP_TRY(hipMemcpyAsync(dst, in.ring, (size_t)in.P * pr->esize, hipMemcpyDeviceToDevice, s));
+            lprobs.push_back(in.pb);
+            lens.push_back(mcpr_ensemble{dst, in.P, in.inst, n, (int)lprobs.size() - 1, 0});
+            for (int r = 0; r < I; ++r) {
+                RegionMap mp{0.0, 0.0, 0.0, MCPR_MAP_KEEP, n};
+                const RegionStats &src = in.st0[r];
+                const double mu = in.rho[n].M[r], sig = in.rho[n].V[r];
+                if (src.n > 0 && sig >= 0.0) {
+                    if (src.min == src.max) {
+                        mp.mode = MCPR_MAP_RESAMPLE;
+                        mp.scale = std::sqrt(sig);
+                        mp.to = mu;
+                    } else {
+                        mp.mode = MCPR_MAP_AFFINE;
+                        mp.from = src.mean;
+                        mp.scale = std::sqrt(sig / src.var);
+                        mp.to = mu;
+                    }
+                }
+                maps.push_back(mp);
+            }
+        }
+    }
+    if (!lens.empty()) {
+        if ((st = ensure(ctx, pr->dmaps, maps.size() * sizeof(RegionMap))) != MCPR_OK) return st;
+        HIP_TRY(hipMemcpyAsync(pr->dmaps.p, maps.data(), maps.size() * sizeof(RegionMap), hipMemcpyHostToDevice, s));
+        if ((st = mcpr_match(ctx, lprobs.data(), (int)lprobs.size(), lens.data(), (int)lens.size(),
+                             (const mcpr_region_map *)pr->dmaps.p, 0, nullptr, stream)) != MCPR_OK)
+            return st;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    pr->k = 0;
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_parareal_iterate(mcpr_parareal *pr, double *delta_out, mcpr_stream stream) {
+    if (!pr) return MCPR_E_INVALID_ARG;
+    mcpr_ctx *ctx = pr->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int N = pr->N, I = pr->I, k = pr->k, n_inst = (int)pr->inst.size();
+
+    // 1. fine propagator on every active slice of every running instance
+    std::vector<mcpr_problem> probs;
+    std::vector<mcpr_ensemble> ens;
+    std::vector<std::pair<int, int>> who; // (instance, slice) of each ensemble
+    for (int i = 0; i < n_inst; ++i) {
+        Instance &in = pr->inst[i];
+        if (delta_out) delta_out[i] = 0.0;
+        if (in.done || k >= N) continue;
+        probs.push_back(in.pb);
+        for (int n = k; n < N; ++n) {
+            ens.push_back(mcpr_ensemble{slot_ptr(pr, in, n, k), in.P, in.inst, n, (int)probs.size() - 1, 0});
+            who.emplace_back(i, n);
+        }
+    }
+    if (ens.empty()) return MCPR_OK;
+    mcpr_status st;
+    if ((st = ensure(ctx, pr->dstats, ens.size() * (I + 1) * sizeof(RegionStats))) != MCPR_OK) return st;
+    if ((st = mcpr_fine_propagate(ctx, probs.data(), (int)probs.size(), ens.data(), (int)ens.size(),
+                                  (mcpr_region_stats *)pr->dstats.p, nullptr, stream)) != MCPR_OK)
+        return st;
+    std::vector<RegionStats> h;
+    if ((st = fetch(pr, ens.size() * (I + 1), h, s)) != MCPR_OK) return st;
+    for (size_t e = 0; e < ens.size(); ++e) {
+        Instance &in = pr->inst[who[e].first];
+        const int n = who[e].second;
+        std::memcpy(&in.rec[(size_t)(n + 1) * (I + 1)], &h[e * (I + 1)], sizeof(RegionStats) * (I + 1));
+        for (int r = 0; r <= I; ++r)
+            if (h[e * (I + 1) + r].nonfinite)
+                return fail(ctx, MCPR_E_NONFINITE, "instance %d slice %d: non-finite particles", who[e].first, n);
+    }
+
+    // 2. per instance: learning fit, then the sequential coarse sweep with the iterator
+    std::vector<RegionMap> maps(ens.size() * I);
+    std::vector<char> touched(ens.size(), 0);
+    size_t ebase = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        Instance &in = pr->inst[i];
+        if (in.done || k >= N) continue;
+        const mcpr_problem &p = in.pb;
+        const double dT = p.dt * p.steps_per_slice;
+
+        // particle-fraction model fitted to the exact slices 0..k+1 (Sec. 3.6)
+        std::vector<double> phat(N + 1, -1.0);
+        if (pr->learning) {
+            std::vector<double> tt, yy;
+            for (int n = 0; n <= k + 1 && n <= N; ++n) {
+                tt.push_back(n * dT);
+                yy.push_back(n == 0 ? (double)in.st0[0].n / (double)in.P
+                                    : (double)in.rec[(size_t)n * (I + 1)].n / (double)in.P);
+            }
+            if (tt.size() >= 3) {
+                double kap = in.have_fit ? in.kappa : 1.0 / (N * dT);
+                double pst = in.have_fit ? in.pstar : yy.back();
+                fit_fractions(tt, yy, kap, pst);
+                in.kappa = kap;
+                in.pstar = pst;
+                in.have_fit = true;
+            }
+            if (in.have_fit) {
+                const double tk = (k + 1) * dT, yk = yy.back();
+                for (int n = k + 2; n <= N; ++n) phat[n] = frac_model(yk, in.kappa, in.pstar, n * dT - tk);
+            }
+        }
+
+        std::vector<Macro> nrho(N + 1), ncache(N);
+        nrho[0] = in.rho[0];
+        for (int n = 0; n < N; ++n) {
+            const Macro a = coarse_step(p, nrho[n]);
+            const Macro &c = in.cache[n];
+            ncache[n] = a;
+            const RegionStats *b = &in.rec[(size_t)(n + 1) * (I + 1)];
+            int32_t *fl = &in.flags[(size_t)n * I];
+            Macro &o = nrho[n + 1];
+            // I(a, b, a) = (R(b), b).  Slices below k and their successors are
+            // exact, so their coarse inputs agree bit for bit; n < k can only
+            // take this branch.
+            if (bit_equal(a, c, I) || n < k) {
+                o = macro_of(b, I, in.P);
+                for (int r = 0; r < I; ++r) fl[r] = 0;
+                continue;
+            }
+            const size_t e = ebase + (size_t)(n - k); // this slice's ensemble (n >= k here)
+            std::memset(&o, 0, sizeof o);
+            for (int r = 0; r < I; ++r) {
+                RegionMap &mp = maps[e * I + r];
+                mp = RegionMap{0.0, 0.0, 0.0, MCPR_MAP_KEEP, n + 1};
+                const double fr = (double)b[r].n / (double)in.P;
+                if (b[r].n == 0) {
+                    o.f[r] = 0.0; o.M[r] = a.M[r]; o.V[r] = a.V[r];
+                    fl[r] = 4;
+                    continue;
+                }
+                const double alM = (a.M[r] - c.M[r]) + b[r].mean;
+                const double alV = (a.V[r] - c.V[r]) + b[r].var;
+                if (!(alV >= 0.0)) {
+                    o.f[r] = fr; o.M[r] = b[r].mean; o.V[r] = b[r].var;
+                    fl[r] = 2;
+                    continue;
+                }
+                RegionMap cand{0.0, 0.0, alM, MCPR_MAP_AFFINE, n + 1};
+                bool inside = true;
+                if (b[r].min == b[r].max) {
+                    cand.mode = MCPR_MAP_RESAMPLE;
+                    cand.scale = std::sqrt(alV);
+                    if (I > 1) {
+                        // the resampled particles: check them on the device
+                        std::vector<RegionMap> pm(I, RegionMap{0.0, 0.0, 0.0, MCPR_MAP_KEEP, n + 1});
+                        pm[r] = cand;
+                        if ((st = ensure(ctx, pr->dmaps, I * sizeof(RegionMap))) != MCPR_OK) return st;
+                        HIP_TRY(hipMemcpyAsync(pr->dmaps.p, pm.data(), I * sizeof(RegionMap), hipMemcpyHostToDevice, s));
+                        mcpr_problem one = p;
+                        mcpr_ensemble oe = ens[e];
+                        oe.problem = 0;
+                        if ((st = mcpr_match(ctx, &one, 1, &oe, 1, (const mcpr_region_map *)pr->dmaps.p, 1,
+                                             (mcpr_region_stats *)pr->dstats.p, stream)) != MCPR_OK)
+                            return st;
+                        std::vector<RegionStats> pr_h;
+                        if ((st = fetch(pr, (size_t)(I + 1), pr_h, s)) != MCPR_OK) return st;
+                        inside = region_of(p, pr_h[r].min) == r && region_of(p, pr_h[r].max) == r;
+                    }
+                } else {
+                    cand.from = b[r].mean;
+                    cand.scale = std::sqrt(alV / b[r].var);
+                    if (I > 1)
+                        inside = region_of(p, mapped(pr->prec, cand, b[r].min)) == r &&
+                                 region_of(p, mapped(pr->prec, cand, b[r].max)) == r;
+                }
+                if (!inside) {
+                    o.f[r] = fr; o.M[r] = b[r].mean; o.V[r] = b[r].var;
+                    fl[r] = 3;
+                    continue;
+                }
+                mp = cand;
+                touched[e] = 1;
+                o.f[r] = fr; o.M[r] = alM; o.V[r] = alV;
+                fl[r] = 1;
+            }
+            if (phat[n + 1] >= 0.0) {
+                o.f[0] = phat[n + 1];
+                o.f[1] = 1.0 - phat[n + 1];
+            }
+        }
+
+        // successive-iterate difference of the global moments
+        double d = 0.0;
+        for (int n = 1; n <= N; ++n) {
+            double M0, V0, M1, V1;
+            mixture(I, in.rho[n], M0, V0);
+            mixture(I, nrho[n], M1, V1);
+            d = std::max(d, std::max(std::fabs(M1 - M0), std::fabs(V1 - V0)));
+        }
+        if (delta_out) delta_out[i] = d;
+        in.rho = nrho;
+        in.cache = ncache;
+        if (d <= pr->tol || k + 1 >= N) in.done = true;
+        ebase += (size_t)(N - k);
+    }
+
+    // 3. matching on the device, only ensembles with a moved region
+    std::vector<mcpr_ensemble> mens;
+    std::vector<RegionMap> mmaps;
+    for (size_t e = 0; e < ens.size(); ++e)
+        if (touched[e]) {
+            mens.push_back(ens[e]);
+            mmaps.insert(mmaps.end(), maps.begin() + e * I, maps.begin() + (e + 1) * I);
+        }
+    if (!mens.empty()) {
+        if ((st = ensure(ctx, pr->dmaps, mmaps.size() * sizeof(RegionMap))) != MCPR_OK) return st;
+        HIP_TRY(hipMemcpyAsync(pr->dmaps.p, mmaps.data(), mmaps.size() * sizeof(RegionMap), hipMemcpyHostToDevice, s));
+        if ((st = mcpr_match(ctx, probs.data(), (int)probs.size(), mens.data(), (int)mens.size(),
+                             (const mcpr_region_map *)pr->dmaps.p, 0, nullptr, stream)) != MCPR_OK)
+            return st;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    pr->k = k + 1;
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_parareal_macro(const mcpr_parareal *pr, int32_t inst, double *rho, double *glob) {
+    if (!pr || inst < 0 || inst >= (int)pr->inst.size()) return MCPR_E_INVALID_ARG;
+    const Instance &in = pr->inst[inst];
+    for (int n = 0; n <= pr->N; ++n) {
+        if (rho)
+            for (int r = 0; r < pr->I; ++r) {
+                rho[((size_t)n * pr->I + r) * 3 + 0] = in.rho[n].f[r];
+                rho[((size_t)n * pr->I + r) * 3 + 1] = in.rho[n].M[r];
+                rho[((size_t)n * pr->I + r) * 3 + 2] = in.rho[n].V[r];
+            }
+        if (glob) mixture(pr->I, in.rho[n], glob[2 * n], glob[2 * n + 1]);
+    }
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_parareal_flags(const mcpr_parareal *pr, int32_t inst, int32_t *flags) {
+    if (!pr || !flags || inst < 0 || inst >= (int)pr->inst.size()) return MCPR_E_INVALID_ARG;
+    std::memcpy(flags, pr->inst[inst].flags.data(), pr->inst[inst].flags.size() * sizeof(int32_t));
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_parareal_slot(const mcpr_parareal *pr, int32_t inst, int32_t n, void **x) {
+    if (!pr || !x || inst < 0 || inst >= (int)pr->inst.size() || n < 0 || n > pr->N) return MCPR_E_INVALID_ARG;
+    *x = slot_ptr(pr, pr->inst[inst], n, pr->k);
+    return MCPR_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,80 @@
+// common.hpp -- internal types shared by the host library and its kernels.
+//
+// Canonical reduction order (every sum the library forms over particles):
+//   quad      particles 4q..4q+3:  ((d0 + d1) + (d2 + d3)), absent particles add +0.0
+//   thread    a superchunk is 256 threads x R quads; thread t owns quads
+//             Q = sc*256*R + r*256 + t, r = 0..R-1, and adds them in r order
+//   block     pairwise tree over the 256 thread sums (xor butterfly in each
+//             64-lane wave, then (w0 + w1) + (w2 + w3))
+//   ensemble  thread t adds the superchunk sums s = t, t+256, ... in order,
+//             then the same 256-thread tree.
+// R depends on the particle count only (canonical_quads_per_thread), so the
+// result is a function of the ensemble alone: independent of batching, of the
+// launch shape and of the other ensembles in the call.  This is what lets a
+// Parareal iteration reproduce the serial run bit for bit.
+#pragma once
+
+#include <cstdint>
+
+namespace mcpr {
+
+constexpr int kThreads = 256;        // threads per block; fixed by the canonical tree
+constexpr int kQuadsPerChunk = kThreads; // quads per thread-row of a superchunk
+constexpr int kMaxRegions = 8;
+constexpr int kMaxSuperchunksTarget = 256;
+
+// Quads per thread R of a superchunk (power of two, 1..64): the smallest R
+// with at most kMaxSuperchunksTarget superchunks.
+inline int canonical_quads_per_thread(int64_t P) {
+    int64_t quads = (P + 3) / 4;
+    int R = 1;
+    while (R < 64 && (quads + (int64_t)kThreads * R - 1) / ((int64_t)kThreads * R) > kMaxSuperchunksTarget)
+        R *= 2;
+    return R;
+}
+
+inline int64_t superchunks(int64_t P, int R) {
+    int64_t quads = (P + 3) / 4;
+    return (quads + (int64_t)kThreads * R - 1) / ((int64_t)kThreads * R);
+}
+
+// One ensemble of a launch.
+struct WorkItem {
+    void *x;
+    int64_t P;
+    int32_t inst;
+    int32_t step0;     // global step index of step 0 of this call (slice * m)
+    int32_t nsc;       // superchunks
+    int32_t R;         // quads per thread per superchunk
+    int32_t part_off;  // first superchunk partial of this item
+    int32_t p0_kind;   // initial law (sampling only)
+    uint32_t key0, key1; // Philox key: seed low and high words
+    double c[10];      // a0 a1 a2 a3 am av b0 b1 bm bv
+    double dt, sdt;    // step and its square root
+    double p0[5];      // w, mu1, sd1, mu2, sd2
+};
+
+// Per-superchunk region partial: count, sum d, sum d^2, min, max (d = x - shift).
+struct RegionPartial {
+    double cnt, s1, s2, mn, mx;
+};
+
+// Device-side record; layout identical to mcpr_region_stats.
+struct RegionStats {
+    int64_t n;
+    double mean, var, min, max;
+    int32_t nonfinite;
+    int32_t reserved;
+};
+
+struct RegionMap {
+    double from, scale, to;
+    int32_t mode;
+    int32_t boundary;
+};
+
+struct Splits {
+    double s[kMaxRegions - 1];
+};
+
+} // namespace mcpr

@@ -1,0 +1,694 @@
+// kernels.hip -- CDNA4 (gfx950) kernels of the fine propagator, the restriction
+// and the matching operator.
+//
+// Layout: each ensemble is a contiguous SoA array of P values (fp32 or fp64).
+// A block of 256 threads owns one superchunk of 256*R quads; thread t handles
+// quads Q = sc*256*R + r*256 + t, so every r-row of the block is one fully
+// coalesced 4 KB (fp32) or 8 KB (fp64) read and write.  Philox counters are
+// per quad, so the 4 normals of a quad come from one Philox call in registers.
+//
+// The per-step mean field (population mean and variance, eq. general_equation)
+// is a reduction over the whole ensemble.  Each step kernel writes one fp64
+// partial (sum of x - shift, sum of (x - shift)^2) per superchunk; the next
+// step's blocks combine the partials of their ensemble in a fixed order at
+// start-up (kernel boundaries order the data; no atomics, no fences, no
+// spinning).  The shift of the sums is the previous step's mean, so the
+// one-pass variance does not cancel.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "launch.hpp"
+#include "rng.hpp"
+
+namespace mcpr {
+
+// ----------------------------------------------------------------------------
+// Reductions in the canonical order
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Sum over the 256 threads of a block: butterfly per wave, then (w0+w1)+(w2+w3).
+// lds must hold 4*N doubles.  Every thread receives the result.
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double *lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) lds[wave * N + k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = (lds[k] + lds[N + k]) + (lds[2 * N + k] + lds[3 * N + k]);
+    __syncthreads();
+}
+
+template <int N>
+__device__ __forceinline__ void block_minmax(double (&mn)[N], double (&mx)[N], double *lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        mn[k] = wave_min(mn[k]);
+        mx[k] = wave_max(mx[k]);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            lds[wave * 2 * N + k] = mn[k];
+            lds[wave * 2 * N + N + k] = mx[k];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        mn[k] = fmin(fmin(lds[k], lds[2 * N + k]), fmin(lds[4 * N + k], lds[6 * N + k]));
+        mx[k] = fmax(fmax(lds[N + k], lds[3 * N + k]), fmax(lds[5 * N + k], lds[7 * N + k]));
+    }
+    __syncthreads();
+}
+
+// Mean and variance from shifted sums over n particles.
+__device__ __forceinline__ void finish_moments(double s1, double s2, double shift, double n, double &mean,
+                                               double &var) {
+    const double a = s1 / n;
+    mean = shift + a;
+    var = s2 / n - a * a;
+    if (var < 0.0) var = 0.0;
+}
+
+// Ensemble total of the per-superchunk partials (thread t: s = t, t+256, ...).
+__device__ __forceinline__ void ensemble_sums(const double2 *__restrict__ part, int nsc, double &S1, double &S2,
+                                              double *lds) {
+    double v[2] = {0.0, 0.0};
+    for (int s = threadIdx.x; s < nsc; s += kThreads) {
+        const double2 p = part[s];
+        v[0] += p.x;
+        v[1] += p.y;
+    }
+    block_sum<2>(v, lds);
+    S1 = v[0];
+    S2 = v[1];
+}
+
+// ----------------------------------------------------------------------------
+// Quad load / store (16-byte aligned arrays; the tail quad goes element-wise)
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void load_quad(const float *__restrict__ x, int64_t p, int64_t P, float v[4]) {
+    if (p + 3 < P) {
+        const float4 q = *reinterpret_cast<const float4 *>(x + p);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (p + e < P) ? x[p + e] : 0.0f;
+    }
+}
+__device__ __forceinline__ void load_quad(const double *__restrict__ x, int64_t p, int64_t P, double v[4]) {
+    if (p + 3 < P) {
+        const double2 a = *reinterpret_cast<const double2 *>(x + p);
+        const double2 b = *reinterpret_cast<const double2 *>(x + p + 2);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (p + e < P) ? x[p + e] : 0.0;
+    }
+}
+__device__ __forceinline__ void store_quad(float *__restrict__ x, int64_t p, int64_t P, const float v[4]) {
+    if (p + 3 < P) {
+        *reinterpret_cast<float4 *>(x + p) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (p + e < P) x[p + e] = v[e];
+    }
+}
+__device__ __forceinline__ void store_quad(double *__restrict__ x, int64_t p, int64_t P, const double v[4]) {
+    if (p + 3 < P) {
+        *reinterpret_cast<double2 *>(x + p) = make_double2(v[0], v[1]);
+        *reinterpret_cast<double2 *>(x + p + 2) = make_double2(v[2], v[3]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (p + e < P) x[p + e] = v[e];
+    }
+}
+
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return fma(a, b, c); }
+
+// region index: number of boundaries <= x (ties go to the upper region)
+template <int NREG>
+__device__ __forceinline__ int region_of(double x, const Splits &sp) {
+    int g = 0;
+#pragma unroll
+    for (int i = 0; i < NREG - 1; ++i) g += (x >= sp.s[i]) ? 1 : 0;
+    return g;
+}
+
+// ----------------------------------------------------------------------------
+// Step-0 sums: shift = x[0] (a value of the ensemble itself, so the result
+// depends on the ensemble only)
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sum_init(const WorkItem *__restrict__ items,
+                                                       const int2 *__restrict__ blocks,
+                                                       double2 *__restrict__ part_out,
+                                                       double *__restrict__ shift_out) {
+    __shared__ double lds[8];
+    const int2 bt = blocks[blockIdx.x];
+    const WorkItem &W = items[bt.x];
+    const T *__restrict__ x = reinterpret_cast<const T *>(W.x);
+    const int64_t P = W.P;
+    const int R = W.R;
+    const double shift = (double)x[0];
+    double a1 = 0.0, a2 = 0.0;
+    const int64_t qbase = (int64_t)bt.y * kThreads * R + threadIdx.x;
+    for (int r = 0; r < R; ++r) {
+        const int64_t p = 4 * (qbase + (int64_t)r * kThreads);
+        if (p < P) {
+            T v[4];
+            load_quad(x, p, P, v);
+            double d[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) d[e] = (p + e < P) ? (double)v[e] - shift : 0.0;
+            a1 += (d[0] + d[1]) + (d[2] + d[3]);
+            a2 += (d[0] * d[0] + d[1] * d[1]) + (d[2] * d[2] + d[3] * d[3]);
+        }
+    }
+    double s[2] = {a1, a2};
+    block_sum<2>(s, lds);
+    if (threadIdx.x == 0) {
+        part_out[W.part_off + bt.y] = make_double2(s[0], s[1]);
+        if (bt.y == 0) shift_out[bt.x] = shift;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// One Euler-Maruyama step of every ensemble of the launch (eq. Euler_Maruyama
+// with the X_n term):  x <- x + a(x, m_j, v_j) dt + b(x, m_j, v_j) sqrt(dt) z
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict__ items,
+                                                      const int2 *__restrict__ blocks, int32_t j,
+                                                      const double2 *__restrict__ part_in,
+                                                      const double *__restrict__ shift_in,
+                                                      double2 *__restrict__ part_out,
+                                                      double *__restrict__ shift_out,
+                                                      double2 *__restrict__ trace, int32_t m) {
+    __shared__ double lds[8];
+    const int2 bt = blocks[blockIdx.x];
+    const int item = bt.x, sc = bt.y;
+    const WorkItem &W = items[item];
+    T *__restrict__ x = reinterpret_cast<T *>(W.x);
+    const int64_t P = W.P;
+    const int R = W.R;
+
+    // mean field at the start of the step
+    double S1, S2;
+    ensemble_sums(part_in + W.part_off, W.nsc, S1, S2, lds);
+    double mean, var;
+    finish_moments(S1, S2, shift_in[item], (double)P, mean, var);
+    if (sc == 0 && threadIdx.x == 0) {
+        shift_out[item] = mean;
+        if (trace) trace[(int64_t)item * m + j] = make_double2(mean, var);
+    }
+
+    // step coefficients: drift * dt as a cubic in x, diffusion * sqrt(dt) affine in x
+    const double dt = W.dt, sdt = W.sdt;
+    const T c0 = (T)((W.c[0] + W.c[4] * mean + W.c[5] * var) * dt);
+    const T c1 = (T)(W.c[1] * dt), c2 = (T)(W.c[2] * dt), c3 = (T)(W.c[3] * dt);
+    const T e0 = (T)((W.c[6] + W.c[8] * mean + W.c[9] * var) * sdt);
+    const T e1 = (T)(W.c[7] * sdt);
+    const uint32_t step = (uint32_t)(W.step0 + j);
+    const uint32_t inst = (uint32_t)W.inst;
+    const uint32_t k0 = W.key0, k1 = W.key1;
+
+    double a1 = 0.0, a2 = 0.0;
+    const int64_t qbase = (int64_t)sc * kThreads * R + threadIdx.x;
+    for (int r0 = 0; r0 < R; r0 += 4) {
+        T v[4][4];
+        int64_t pq[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            pq[g] = 4 * (qbase + (int64_t)(r0 + g) * kThreads);
+            if (r0 + g < R && pq[g] < P) load_quad(x, pq[g], P, v[g]);
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            if (r0 + g < R) {
+                const int64_t p = pq[g];
+                if (p < P) {
+                    const Words4 w = philox4x32_10((uint32_t)(p >> 2), step, inst, 0u, k0, k1);
+                    T z[4];
+                    box_muller4(w, z);
+                    double d[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const T xv = v[g][e];
+                        const T drift = fmaT(fmaT(fmaT(c3, xv, c2), xv, c1), xv, c0);
+                        const T diff = fmaT(e1, xv, e0);
+                        const T xn = xv + fmaT(diff, z[e], drift);
+                        v[g][e] = xn;
+                        d[e] = (p + e < P) ? (double)xn - mean : 0.0;
+                    }
+                    store_quad(x, p, P, v[g]);
+                    a1 += (d[0] + d[1]) + (d[2] + d[3]);
+                    a2 += (d[0] * d[0] + d[1] * d[1]) + (d[2] * d[2] + d[3] * d[3]);
+                }
+            }
+        }
+    }
+    double s[2] = {a1, a2};
+    block_sum<2>(s, lds);
+    if (threadIdx.x == 0) part_out[W.part_off + sc] = make_double2(s[0], s[1]);
+}
+
+// ----------------------------------------------------------------------------
+// Region partials (restriction R, eq. multimodal_R).  MODE 0: the values
+// themselves; MODE 1: the values after the matching map of their region (dry
+// run of T), grouped by the region they came from.  NR = regions + 1 (the
+// last entry is the whole ensemble).  Shift per (item, region).
+// ----------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ double apply_map(const RegionMap &mp, T xv, uint32_t q, int e, uint32_t inst,
+                                            uint32_t k0, uint32_t k1);
+
+template <>
+__device__ __forceinline__ double apply_map<float>(const RegionMap &mp, float xv, uint32_t q, int e, uint32_t inst,
+                                                   uint32_t k0, uint32_t k1) {
+    if (mp.mode == 1) return (double)(float)fma(mp.scale, (double)xv - mp.from, mp.to);
+    if (mp.mode == 2) {
+        const Words4 w = philox4x32_10(q, (uint32_t)mp.boundary, inst, 3u, k0, k1);
+        float z[4];
+        box_muller4(w, z);
+        return (double)(float)fma(mp.scale, (double)z[e], mp.to);
+    }
+    return (double)xv;
+}
+template <>
+__device__ __forceinline__ double apply_map<double>(const RegionMap &mp, double xv, uint32_t q, int e, uint32_t inst,
+                                                    uint32_t k0, uint32_t k1) {
+    if (mp.mode == 1) return fma(mp.scale, xv - mp.from, mp.to);
+    if (mp.mode == 2) {
+        const Words4 w = philox4x32_10(q, (uint32_t)mp.boundary, inst, 3u, k0, k1);
+        double z[4];
+        box_muller4(w, z);
+        return fma(mp.scale, z[e], mp.to);
+    }
+    return xv;
+}
+
+template <typename T, int NR, int MODE>
+__global__ __launch_bounds__(kThreads) void k_region_partials(const WorkItem *__restrict__ items,
+                                                              const int2 *__restrict__ blocks,
+                                                              const double *__restrict__ rshift, Splits sp,
+                                                              const RegionMap *__restrict__ maps,
+                                                              RegionPartial *__restrict__ rpart) {
+    constexpr int NREG = NR - 1;
+    __shared__ double lds[4 * 3 * NR + 8 * NR];
+    const int2 bt = blocks[blockIdx.x];
+    const WorkItem &W = items[bt.x];
+    const T *__restrict__ x = reinterpret_cast<const T *>(W.x);
+    const int64_t P = W.P;
+    const int R = W.R;
+    double sh[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) sh[i] = rshift[(int64_t)bt.x * NR + i];
+    RegionMap mp[NREG > 0 ? NREG : 1];
+    if (MODE == 1) {
+#pragma unroll
+        for (int i = 0; i < NREG; ++i) mp[i] = maps[(int64_t)bt.x * NREG + i];
+    }
+    double acc[3 * NR], mn[NR], mx[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        acc[3 * i] = acc[3 * i + 1] = acc[3 * i + 2] = 0.0;
+        mn[i] = __builtin_inf();
+        mx[i] = -__builtin_inf();
+    }
+    const int64_t qbase = (int64_t)bt.y * kThreads * R + threadIdx.x;
+    for (int r = 0; r < R; ++r) {
+        const int64_t Q = qbase + (int64_t)r * kThreads;
+        const int64_t p = 4 * Q;
+        if (p < P) {
+            T v[4];
+            load_quad(x, p, P, v);
+            int g[4];
+            double y[4];
+            bool ok[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                ok[e] = (p + e < P);
+                g[e] = region_of<NREG>((double)v[e], sp);
+                if (MODE == 1) {
+                    RegionMap m0 = mp[0];
+#pragma unroll
+                    for (int i = 1; i < NREG; ++i)
+                        if (g[e] == i) m0 = mp[i];
+                    y[e] = apply_map<T>(m0, v[e], (uint32_t)Q, e, (uint32_t)W.inst, W.key0, W.key1);
+                } else {
+                    y[e] = (double)v[e];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                double d[4], c[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const bool in = ok[e] && (i == NREG || g[e] == i);
+                    d[e] = in ? y[e] - sh[i] : 0.0;
+                    c[e] = in ? 1.0 : 0.0;
+                    if (in) {
+                        mn[i] = fmin(mn[i], y[e]);
+                        mx[i] = fmax(mx[i], y[e]);
+                    }
+                }
+                acc[3 * i] += (c[0] + c[1]) + (c[2] + c[3]);
+                acc[3 * i + 1] += (d[0] + d[1]) + (d[2] + d[3]);
+                acc[3 * i + 2] += (d[0] * d[0] + d[1] * d[1]) + (d[2] * d[2] + d[3] * d[3]);
+            }
+        }
+    }
+    block_sum<3 * NR>(acc, lds);
+    block_minmax<NR>(mn, mx, lds);
+    if (threadIdx.x == 0) {
+        RegionPartial *out = rpart + (int64_t)(W.part_off + bt.y) * NR;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            RegionPartial rp;
+            rp.cnt = acc[3 * i];
+            rp.s1 = acc[3 * i + 1];
+            rp.s2 = acc[3 * i + 2];
+            rp.mn = mn[i];
+            rp.mx = mx[i];
+            out[i] = rp;
+        }
+    }
+}
+
+// One block per item: region partials -> records.  If rshift_next is set it
+// receives the region means (the shifts of a second, better conditioned pass).
+template <int NR>
+__global__ __launch_bounds__(kThreads) void k_region_combine(const WorkItem *__restrict__ items,
+                                                             const RegionPartial *__restrict__ rpart,
+                                                             const double *__restrict__ rshift,
+                                                             RegionStats *__restrict__ out,
+                                                             double *__restrict__ rshift_next) {
+    __shared__ double lds[4 * 3 * NR + 8 * NR];
+    const WorkItem &W = items[blockIdx.x];
+    double acc[3 * NR], mn[NR], mx[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        acc[3 * i] = acc[3 * i + 1] = acc[3 * i + 2] = 0.0;
+        mn[i] = __builtin_inf();
+        mx[i] = -__builtin_inf();
+    }
+    for (int s = threadIdx.x; s < W.nsc; s += kThreads) {
+        const RegionPartial *rp = rpart + (int64_t)(W.part_off + s) * NR;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            acc[3 * i] += rp[i].cnt;
+            acc[3 * i + 1] += rp[i].s1;
+            acc[3 * i + 2] += rp[i].s2;
+            mn[i] = fmin(mn[i], rp[i].mn);
+            mx[i] = fmax(mx[i], rp[i].mx);
+        }
+    }
+    block_sum<3 * NR>(acc, lds);
+    block_minmax<NR>(mn, mx, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const double sh = rshift[(int64_t)blockIdx.x * NR + i];
+            RegionStats st;
+            st.n = (int64_t)acc[3 * i];
+            st.min = mn[i];
+            st.max = mx[i];
+            st.nonfinite = !(isfinite(acc[3 * i + 1]) && isfinite(acc[3 * i + 2]));
+            st.reserved = 0;
+            if (st.n == 0) {
+                st.mean = 0.0;
+                st.var = 0.0;
+            } else if (mn[i] == mx[i]) {
+                st.mean = mn[i];
+                st.var = 0.0;
+            } else {
+                finish_moments(acc[3 * i + 1], acc[3 * i + 2], sh, acc[3 * i], st.mean, st.var);
+            }
+            out[(int64_t)blockIdx.x * NR + i] = st;
+            if (rshift_next)
+                rshift_next[(int64_t)blockIdx.x * NR + i] = (st.n > 0 && isfinite(st.mean)) ? st.mean : sh;
+        }
+    }
+}
+
+// Shifts for the first restriction pass: the value the step sums were shifted
+// by (after a fine step: the last step's mean) or x[0].
+template <typename T, int NR>
+__global__ void k_fill_shift(const WorkItem *__restrict__ items, int n_items, const double *__restrict__ shift,
+                             double *__restrict__ rshift) {
+    const int item = blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= n_items) return;
+    const double s = shift ? shift[item] : (double)reinterpret_cast<const T *>(items[item].x)[0];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) rshift[(int64_t)item * NR + i] = s;
+}
+
+// ----------------------------------------------------------------------------
+// Matching T applied in place, per region (eq. multimodal_M)
+// ----------------------------------------------------------------------------
+template <typename T, int NREG>
+__global__ __launch_bounds__(kThreads) void k_match_apply(const WorkItem *__restrict__ items,
+                                                          const int2 *__restrict__ blocks, Splits sp,
+                                                          const RegionMap *__restrict__ maps) {
+    const int2 bt = blocks[blockIdx.x];
+    const WorkItem &W = items[bt.x];
+    T *__restrict__ x = reinterpret_cast<T *>(W.x);
+    const int64_t P = W.P;
+    const int R = W.R;
+    RegionMap mp[NREG];
+#pragma unroll
+    for (int i = 0; i < NREG; ++i) mp[i] = maps[(int64_t)bt.x * NREG + i];
+    const int64_t qbase = (int64_t)bt.y * kThreads * R + threadIdx.x;
+    for (int r = 0; r < R; ++r) {
+        const int64_t Q = qbase + (int64_t)r * kThreads;
+        const int64_t p = 4 * Q;
+        if (p < P) {
+            T v[4];
+            load_quad(x, p, P, v);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int g = region_of<NREG>((double)v[e], sp);
+                RegionMap m0 = mp[0];
+#pragma unroll
+                for (int i = 1; i < NREG; ++i)
+                    if (g == i) m0 = mp[i];
+                v[e] = (T)apply_map<T>(m0, v[e], (uint32_t)Q, e, (uint32_t)W.inst, W.key0, W.key1);
+            }
+            store_quad(x, p, P, v);
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Initial law p0
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_init(const WorkItem *__restrict__ items,
+                                                   const int2 *__restrict__ blocks) {
+    const int2 bt = blocks[blockIdx.x];
+    const WorkItem &W = items[bt.x];
+    T *__restrict__ x = reinterpret_cast<T *>(W.x);
+    const int64_t P = W.P;
+    const int R = W.R;
+    const int64_t qbase = (int64_t)bt.y * kThreads * R + threadIdx.x;
+    for (int r = 0; r < R; ++r) {
+        const int64_t Q = qbase + (int64_t)r * kThreads;
+        const int64_t p = 4 * Q;
+        if (p >= P) continue;
+        T v[4];
+        if (W.p0_kind == 2) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = (T)W.p0[1];
+        } else {
+            const Words4 w = philox4x32_10((uint32_t)Q, 0u, (uint32_t)W.inst, 1u, W.key0, W.key1);
+            T z[4];
+            box_muller4(w, z);
+            if (W.p0_kind == 0) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = (T)(W.p0[1] + W.p0[2] * (double)z[e]);
+            } else {
+                const Words4 pk = philox4x32_10((uint32_t)Q, 0u, (uint32_t)W.inst, 2u, W.key0, W.key1);
+                const uint32_t pw[4] = {pk.w0, pk.w1, pk.w2, pk.w3};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const bool first = uniform_of(pw[e]) < W.p0[0];
+                    const double mu = first ? W.p0[1] : W.p0[3];
+                    const double sd = first ? W.p0[2] : W.p0[4];
+                    v[e] = (T)(mu + sd * (double)z[e]);
+                }
+            }
+        }
+        store_quad(x, p, P, v);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Launchers
+// ----------------------------------------------------------------------------
+hipError_t launch_sum_init(int prec, const WorkItem *items, const int2 *blocks, int nblocks, double2 *part_out,
+                           double *shift_out, hipStream_t s) {
+    if (prec == 0)
+        hipLaunchKernelGGL(k_sum_init<double>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, part_out, shift_out);
+    else
+        hipLaunchKernelGGL(k_sum_init<float>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, part_out, shift_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_em_step(int prec, const WorkItem *items, const int2 *blocks, int nblocks, int j,
+                          const double2 *part_in, const double *shift_in, double2 *part_out, double *shift_out,
+                          double2 *trace, int m, hipStream_t s) {
+    if (prec == 0)
+        hipLaunchKernelGGL(k_em_step<double>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j, part_in, shift_in,
+                           part_out, shift_out, trace, m);
+    else
+        hipLaunchKernelGGL(k_em_step<float>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j, part_in, shift_in,
+                           part_out, shift_out, trace, m);
+    return hipGetLastError();
+}
+
+template <int NR>
+static void region_partials_nr(int prec, int mode, const WorkItem *items, const int2 *blocks, int nblocks,
+                               const double *rshift, const Splits &sp, const RegionMap *maps, RegionPartial *rpart,
+                               hipStream_t s) {
+    if (prec == 0) {
+        if (mode == 0)
+            hipLaunchKernelGGL((k_region_partials<double, NR, 0>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks,
+                               rshift, sp, maps, rpart);
+        else
+            hipLaunchKernelGGL((k_region_partials<double, NR, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks,
+                               rshift, sp, maps, rpart);
+    } else {
+        if (mode == 0)
+            hipLaunchKernelGGL((k_region_partials<float, NR, 0>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks,
+                               rshift, sp, maps, rpart);
+        else
+            hipLaunchKernelGGL((k_region_partials<float, NR, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks,
+                               rshift, sp, maps, rpart);
+    }
+}
+
+hipError_t launch_region_partials(int prec, int nr, int mode, const WorkItem *items, const int2 *blocks, int nblocks,
+                                  const double *rshift, const Splits &sp, const RegionMap *maps, RegionPartial *rpart,
+                                  hipStream_t s) {
+    switch (nr) {
+    case 2: region_partials_nr<2>(prec, mode, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
+    case 3: region_partials_nr<3>(prec, mode, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
+    case 4: region_partials_nr<4>(prec, mode, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
+    case 5: region_partials_nr<5>(prec, mode, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
+    case 6: region_partials_nr<6>(prec, mode, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
+    case 7: region_partials_nr<7>(prec, mode, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
+    case 8: region_partials_nr<8>(prec, mode, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
+    case 9: region_partials_nr<9>(prec, mode, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int NR>
+static void region_combine_nr(const WorkItem *items, int n_items, const RegionPartial *rpart, const double *rshift,
+                              RegionStats *out, double *rshift_next, hipStream_t s) {
+    hipLaunchKernelGGL((k_region_combine<NR>), dim3(n_items), dim3(kThreads), 0, s, items, rpart, rshift, out,
+                       rshift_next);
+}
+
+hipError_t launch_region_combine(int nr, const WorkItem *items, int n_items, const RegionPartial *rpart,
+                                 const double *rshift, RegionStats *out, double *rshift_next, hipStream_t s) {
+    switch (nr) {
+    case 2: region_combine_nr<2>(items, n_items, rpart, rshift, out, rshift_next, s); break;
+    case 3: region_combine_nr<3>(items, n_items, rpart, rshift, out, rshift_next, s); break;
+    case 4: region_combine_nr<4>(items, n_items, rpart, rshift, out, rshift_next, s); break;
+    case 5: region_combine_nr<5>(items, n_items, rpart, rshift, out, rshift_next, s); break;
+    case 6: region_combine_nr<6>(items, n_items, rpart, rshift, out, rshift_next, s); break;
+    case 7: region_combine_nr<7>(items, n_items, rpart, rshift, out, rshift_next, s); break;
+    case 8: region_combine_nr<8>(items, n_items, rpart, rshift, out, rshift_next, s); break;
+    case 9: region_combine_nr<9>(items, n_items, rpart, rshift, out, rshift_next, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int NR>
+static void fill_shift_nr(int prec, const WorkItem *items, int n_items, const double *shift, double *rshift,
+                          hipStream_t s) {
+    const int nb = (n_items + 255) / 256;
+    if (prec == 0)
+        hipLaunchKernelGGL((k_fill_shift<double, NR>), dim3(nb), dim3(256), 0, s, items, n_items, shift, rshift);
+    else
+        hipLaunchKernelGGL((k_fill_shift<float, NR>), dim3(nb), dim3(256), 0, s, items, n_items, shift, rshift);
+}
+
+hipError_t launch_fill_shift(int prec, int nr, const WorkItem *items, int n_items, const double *shift, double *rshift,
+                             hipStream_t s) {
+    switch (nr) {
+    case 2: fill_shift_nr<2>(prec, items, n_items, shift, rshift, s); break;
+    case 3: fill_shift_nr<3>(prec, items, n_items, shift, rshift, s); break;
+    case 4: fill_shift_nr<4>(prec, items, n_items, shift, rshift, s); break;
+    case 5: fill_shift_nr<5>(prec, items, n_items, shift, rshift, s); break;
+    case 6: fill_shift_nr<6>(prec, items, n_items, shift, rshift, s); break;
+    case 7: fill_shift_nr<7>(prec, items, n_items, shift, rshift, s); break;
+    case 8: fill_shift_nr<8>(prec, items, n_items, shift, rshift, s); break;
+    case 9: fill_shift_nr<9>(prec, items, n_items, shift, rshift, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int NREG>
+static void match_nr(int prec, const WorkItem *items, const int2 *blocks, int nblocks, const Splits &sp,
+                     const RegionMap *maps, hipStream_t s) {
+    if (prec == 0)
+        hipLaunchKernelGGL((k_match_apply<double, NREG>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, sp, maps);
+    else
+        hipLaunchKernelGGL((k_match_apply<float, NREG>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, sp, maps);
+}
+
+hipError_t launch_match_apply(int prec, int nreg, const WorkItem *items, const int2 *blocks, int nblocks,
+                              const Splits &sp, const RegionMap *maps, hipStream_t s) {
+    switch (nreg) {
+    case 1: match_nr<1>(prec, items, blocks, nblocks, sp, maps, s); break;
+    case 2: match_nr<2>(prec, items, blocks, nblocks, sp, maps, s); break;
+    case 3: match_nr<3>(prec, items, blocks, nblocks, sp, maps, s); break;
+    case 4: match_nr<4>(prec, items, blocks, nblocks, sp, maps, s); break;
+    case 5: match_nr<5>(prec, items, blocks, nblocks, sp, maps, s); break;
+    case 6: match_nr<6>(prec, items, blocks, nblocks, sp, maps, s); break;
+    case 7: match_nr<7>(prec, items, blocks, nblocks, sp, maps, s); break;
+    case 8: match_nr<8>(prec, items, blocks, nblocks, sp, maps, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int prec, const WorkItem *items, const int2 *blocks, int nblocks, hipStream_t s) {
+    if (prec == 0)
+        hipLaunchKernelGGL(k_init<double>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks);
+    else
+        hipLaunchKernelGGL(k_init<float>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks);
+    return hipGetLastError();
+}
+
+} // namespace mcpr

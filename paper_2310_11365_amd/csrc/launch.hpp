@@ -1,0 +1,27 @@
+// launch.hpp -- host-side launchers of the kernels in kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace mcpr {
+
+// prec: 0 = fp64 particles, 1 = fp32 particles (fp64 reductions either way)
+hipError_t launch_sum_init(int prec, const WorkItem *items, const int2 *blocks, int nblocks, double2 *part_out,
+                           double *shift_out, hipStream_t s);
+hipError_t launch_em_step(int prec, const WorkItem *items, const int2 *blocks, int nblocks, int j,
+                          const double2 *part_in, const double *shift_in, double2 *part_out, double *shift_out,
+                          double2 *trace, int m, hipStream_t s);
+hipError_t launch_region_partials(int prec, int nr, int mode, const WorkItem *items, const int2 *blocks, int nblocks,
+                                  const double *rshift, const Splits &sp, const RegionMap *maps, RegionPartial *rpart,
+                                  hipStream_t s);
+hipError_t launch_region_combine(int nr, const WorkItem *items, int n_items, const RegionPartial *rpart,
+                                 const double *rshift, RegionStats *out, double *rshift_next, hipStream_t s);
+hipError_t launch_fill_shift(int prec, int nr, const WorkItem *items, int n_items, const double *shift, double *rshift,
+                             hipStream_t s);
+hipError_t launch_match_apply(int prec, int nreg, const WorkItem *items, const int2 *blocks, int nblocks,
+                              const Splits &sp, const RegionMap *maps, hipStream_t s);
+hipError_t launch_init(int prec, const WorkItem *items, const int2 *blocks, int nblocks, hipStream_t s);
+
+} // namespace mcpr
