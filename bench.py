@@ -57,30 +57,27 @@ def load_traffic(kernel: str):
 
 
 def cpu_baseline(seconds_target: float = 15.0):
-    """The oracle as it stands, one thread, one slice of the workload at fp64."""
+    """The oracle as it stands (one thread) on whole slices of the workload at
+    P = 1e6 in fp64, slice after slice until about seconds_target."""
     from oracle import oracle as O
     from paper_2310_11365_amd import workloads as W
     if not os.path.exists(O.LIB):
         O.build(force=False)
-    P = 200_000
-    wl = W.dz_bimodal(P=P, precision=W.FP64)
-    pr = wl.problem
-    x0 = O.sample_p0(pr, P)
-    # calibrate on a few steps, then run as many whole steps as fit the target
-    pr_small = W.dz_bimodal(P=P, precision=W.FP64).problem
-    pr_small.steps_per_slice = 5
+    wl = W.dz_bimodal(precision=W.FP64)
+    pr, P = wl.problem, wl.P
+    x = O.sample_p0(pr, P)
     t0 = time.perf_counter()
-    O.fine(pr_small, x0, 0)
-    per_step = (time.perf_counter() - t0) / 5
-    steps = max(5, min(pr.steps_per_slice, int(seconds_target / max(per_step, 1e-9))))
-    pr_run = W.dz_bimodal(P=P, precision=W.FP64).problem
-    pr_run.steps_per_slice = steps
-    t0 = time.perf_counter()
-    O.fine(pr_run, x0, 0)
+    slices = 0
+    while slices < pr.n_slices:
+        x, _ = O.fine(pr, x, slices)
+        slices += 1
+        if time.perf_counter() - t0 >= seconds_target:
+            break
     dt = time.perf_counter() - t0
-    return {"value": P * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"bimodal workload, P={P} fp64, first {steps} Euler-Maruyama steps of slice 0 "
-                      f"({P * steps:.3g} particle-steps), single thread, {dt:.1f} s"}
+    ps = P * pr.steps_per_slice * slices
+    return {"value": ps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"bimodal workload at fp64, P={P}, serial fine solution of slices 0..{slices - 1} "
+                      f"({ps:.3g} particle-steps), single thread, {dt:.1f} s"}
 
 
 def main():
@@ -91,6 +88,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parareal", action="store_true")
     ap.add_argument("--parareal-iters", type=int, default=4)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
+                    help="first run one plain device-to-device copy of this many MiB (a known-size "
+                         "reference for the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (slice sharding across GPUs is "
@@ -109,6 +109,16 @@ def main():
     pr = wl.problem
     N, m, P = pr.n_slices, pr.steps_per_slice, wl.P
     ps_per_step = N * m * P
+
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy probe: {n * 4} bytes read, {n * 4} bytes written", flush=True)
+        del src, dst
 
     ctx = mcpr.Context(0)
     para = mcpr.Parareal([pr], [P], ctx)
