@@ -298,10 +298,13 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
             ctx->prof1.push_back(e1);
         }
     }
+    int deg = 1;
+    for (const WorkItem &w : t.items)
+        if (w.c[2] != 0.0 || w.c[3] != 0.0) deg = 3;
     for (int j = 0; j < m; ++j) {
         const int a = j & 1, b = a ^ 1;
         if (ctx->profile) HIP_TRY(hipEventRecord(ctx->prof0[j], s));
-        HIP_TRY(mcpr::launch_em_step(prec, items, blocks, nb, j, part[a], shift[a], part[b], shift[b], trace, m, s));
+        HIP_TRY(mcpr::launch_em_step(prec, deg, items, blocks, nb, j, part[a], shift[a], part[b], shift[b], trace, m, s));
         if (ctx->profile) HIP_TRY(hipEventRecord(ctx->prof1[j], s));
     }
     if (ctx->profile) {

@@ -160,6 +160,45 @@ __device__ __forceinline__ int region_of(double x, const Splits &sp) {
 }
 
 // ----------------------------------------------------------------------------
+// Canonical leaf of the per-step sums: one quad, d_e = x_e - shift in the state
+// type (shift is a value of that type, so it is exact in fp64 as well):
+//   q1 = (d0 + d1) + (d2 + d3),   q2 = fma(d3, d3, fma(d2, d2, fma(d1, d1, d0 * d0)))
+// Absent particles have d = 0.  From the quad level up every sum is fp64.
+// ----------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void quad_leaf(const T d[4], double &q1, double &q2) {
+    q1 = (double)((d[0] + d[1]) + (d[2] + d[3]));
+    q2 = (double)fmaT(d[3], d[3], fmaT(d[2], d[2], fmaT(d[1], d[1], d[0] * d[0])));
+}
+
+// Vector access to one quad through the global address space (full quads).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) f32x4 g_f32x4;
+typedef __attribute__((address_space(1))) f64x2 g_f64x2;
+
+__device__ __forceinline__ void gload_quad(const float *base, uint32_t q, float v[4]) {
+    const f32x4 a = ((const g_f32x4 *)(base))[q];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+__device__ __forceinline__ void gload_quad(const double *base, uint32_t q, double v[4]) {
+    const f64x2 a = ((const g_f64x2 *)(base))[2 * q];
+    const f64x2 b = ((const g_f64x2 *)(base))[2 * q + 1];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ void gstore_quad(float *base, uint32_t q, const float v[4]) {
+    f32x4 a;
+    a.x = v[0]; a.y = v[1]; a.z = v[2]; a.w = v[3];
+    ((g_f32x4 *)(base))[q] = a;
+}
+__device__ __forceinline__ void gstore_quad(double *base, uint32_t q, const double v[4]) {
+    f64x2 a, b;
+    a.x = v[0]; a.y = v[1]; b.x = v[2]; b.y = v[3];
+    ((g_f64x2 *)(base))[2 * q] = a;
+    ((g_f64x2 *)(base))[2 * q + 1] = b;
+}
+
+// ----------------------------------------------------------------------------
 // Step-0 sums: shift = x[0] (a value of the ensemble itself, so the result
 // depends on the ensemble only)
 // ----------------------------------------------------------------------------
@@ -174,34 +213,57 @@ __global__ __launch_bounds__(kThreads) void k_sum_init(const WorkItem *__restric
     const T *__restrict__ x = reinterpret_cast<const T *>(W.x);
     const int64_t P = W.P;
     const int R = W.R;
-    const double shift = (double)x[0];
+    const T shift = x[0];
     double a1 = 0.0, a2 = 0.0;
-    const int64_t qbase = (int64_t)bt.y * kThreads * R + threadIdx.x;
-    for (int r = 0; r < R; ++r) {
-        const int64_t p = 4 * (qbase + (int64_t)r * kThreads);
-        if (p < P) {
-            T v[4];
-            load_quad(x, p, P, v);
-            double d[4];
+    const int64_t base = (int64_t)bt.y * 4 * kThreads * R;
+    const T *xs = x + base;
+    if (base + (int64_t)4 * kThreads * R <= P) {
+        for (int r = 0; r < R; ++r) {
+            T v[4], d[4];
+            gload_quad(xs, (uint32_t)(r * kThreads + threadIdx.x), v);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) d[e] = (p + e < P) ? (double)v[e] - shift : 0.0;
-            a1 += (d[0] + d[1]) + (d[2] + d[3]);
-            a2 += (d[0] * d[0] + d[1] * d[1]) + (d[2] * d[2] + d[3] * d[3]);
+            for (int e = 0; e < 4; ++e) d[e] = v[e] - shift;
+            double q1, q2;
+            quad_leaf(d, q1, q2);
+            a1 += q1;
+            a2 += q2;
+        }
+    } else {
+        for (int r = 0; r < R; ++r) {
+            const int64_t p = base + 4 * (int64_t)(r * kThreads + threadIdx.x);
+            if (p < P) {
+                T v[4], d[4];
+                load_quad(x, p, P, v);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) d[e] = (p + e < P) ? v[e] - shift : (T)0;
+                double q1, q2;
+                quad_leaf(d, q1, q2);
+                a1 += q1;
+                a2 += q2;
+            }
         }
     }
-    double s[2] = {a1, a2};
-    block_sum<2>(s, lds);
+    double sm[2] = {a1, a2};
+    block_sum<2>(sm, lds);
     if (threadIdx.x == 0) {
-        part_out[W.part_off + bt.y] = make_double2(s[0], s[1]);
-        if (bt.y == 0) shift_out[bt.x] = shift;
+        part_out[W.part_off + bt.y] = make_double2(sm[0], sm[1]);
+        if (bt.y == 0) shift_out[bt.x] = (double)shift;
     }
 }
 
 // ----------------------------------------------------------------------------
 // One Euler-Maruyama step of every ensemble of the launch (eq. Euler_Maruyama
-// with the X_n term):  x <- x + a(x, m_j, v_j) dt + b(x, m_j, v_j) sqrt(dt) z
+// with the X_n term):  x <- x + a(x, m_j, v_j) dt + b(x, m_j, v_j) sqrt(dt) z,
+// evaluated as  x <- fma(b sqrt(dt), z, p(x))  with  p(x) = x + a(x) dt  a
+// cubic in x (DEG 3) or, when a2 = a3 = 0, a line (DEG 1; bitwise the same).
 // ----------------------------------------------------------------------------
-template <typename T>
+template <typename T, int DEG>
+__device__ __forceinline__ T em_update(T xv, T z, T c0, T c1, T c2, T c3, T e0, T e1) {
+    const T pol = (DEG == 1) ? fmaT(c1, xv, c0) : fmaT(fmaT(fmaT(c3, xv, c2), xv, c1), xv, c0);
+    return fmaT(fmaT(e1, xv, e0), z, pol);
+}
+
+template <typename T, int DEG>
 __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict__ items,
                                                       const int2 *__restrict__ blocks, int32_t j,
                                                       const double2 *__restrict__ part_in,
@@ -222,15 +284,16 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
     ensemble_sums(part_in + W.part_off, W.nsc, S1, S2, lds);
     double mean, var;
     finish_moments(S1, S2, shift_in[item], (double)P, mean, var);
+    const T shift = (T)mean; // shift of this step's output sums, a value of the state type
     if (sc == 0 && threadIdx.x == 0) {
-        shift_out[item] = mean;
+        shift_out[item] = (double)shift;
         if (trace) trace[(int64_t)item * m + j] = make_double2(mean, var);
     }
 
-    // step coefficients: drift * dt as a cubic in x, diffusion * sqrt(dt) affine in x
+    // step coefficients: p(x) = x + a(x) dt as a polynomial, diffusion * sqrt(dt) affine in x
     const double dt = W.dt, sdt = W.sdt;
     const T c0 = (T)((W.c[0] + W.c[4] * mean + W.c[5] * var) * dt);
-    const T c1 = (T)(W.c[1] * dt), c2 = (T)(W.c[2] * dt), c3 = (T)(W.c[3] * dt);
+    const T c1 = (T)(1.0 + W.c[1] * dt), c2 = (T)(W.c[2] * dt), c3 = (T)(W.c[3] * dt);
     const T e0 = (T)((W.c[6] + W.c[8] * mean + W.c[9] * var) * sdt);
     const T e1 = (T)(W.c[7] * sdt);
     const uint32_t step = (uint32_t)(W.step0 + j);
@@ -238,43 +301,60 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
     const uint32_t k0 = W.key0, k1 = W.key1;
 
     double a1 = 0.0, a2 = 0.0;
-    const int64_t qbase = (int64_t)sc * kThreads * R + threadIdx.x;
-    for (int r0 = 0; r0 < R; r0 += 4) {
-        T v[4][4];
-        int64_t pq[4];
+    const int64_t base = (int64_t)sc * 4 * kThreads * R; // first particle of the superchunk
+    if (base + (int64_t)4 * kThreads * R <= P) {
+        // full superchunk: 32-bit quad offsets, no per-quad checks
+        T *xs = x + base;
+        const uint32_t qb = (uint32_t)(base >> 2) + threadIdx.x;
+        for (int r0 = 0; r0 < R; r0 += 4) {
+            T v[4][4];
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            pq[g] = 4 * (qbase + (int64_t)(r0 + g) * kThreads);
-            if (r0 + g < R && pq[g] < P) load_quad(x, pq[g], P, v[g]);
-        }
+            for (int g = 0; g < 4; ++g)
+                if (r0 + g < R) gload_quad(xs, (uint32_t)((r0 + g) * kThreads + threadIdx.x), v[g]);
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            if (r0 + g < R) {
-                const int64_t p = pq[g];
-                if (p < P) {
-                    const Words4 w = philox4x32_10((uint32_t)(p >> 2), step, inst, 0u, k0, k1);
-                    T z[4];
+            for (int g = 0; g < 4; ++g) {
+                if (r0 + g < R) {
+                    const Words4 w = philox4x32_10(qb + (uint32_t)((r0 + g) * kThreads), step, inst, 0u, k0, k1);
+                    T z[4], d[4];
                     box_muller4(w, z);
-                    double d[4];
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        const T xv = v[g][e];
-                        const T drift = fmaT(fmaT(fmaT(c3, xv, c2), xv, c1), xv, c0);
-                        const T diff = fmaT(e1, xv, e0);
-                        const T xn = xv + fmaT(diff, z[e], drift);
-                        v[g][e] = xn;
-                        d[e] = (p + e < P) ? (double)xn - mean : 0.0;
+                        v[g][e] = em_update<T, DEG>(v[g][e], z[e], c0, c1, c2, c3, e0, e1);
+                        d[e] = v[g][e] - shift;
                     }
-                    store_quad(x, p, P, v[g]);
-                    a1 += (d[0] + d[1]) + (d[2] + d[3]);
-                    a2 += (d[0] * d[0] + d[1] * d[1]) + (d[2] * d[2] + d[3] * d[3]);
+                    gstore_quad(xs, (uint32_t)((r0 + g) * kThreads + threadIdx.x), v[g]);
+                    double q1, q2;
+                    quad_leaf(d, q1, q2);
+                    a1 += q1;
+                    a2 += q2;
                 }
             }
         }
+    } else {
+        // the ensemble's last superchunk: per-quad and per-particle bounds
+        for (int r = 0; r < R; ++r) {
+            const int64_t p = base + 4 * (int64_t)(r * kThreads + threadIdx.x);
+            if (p < P) {
+                T v[4], z[4], d[4];
+                load_quad(x, p, P, v);
+                const Words4 w = philox4x32_10((uint32_t)(p >> 2), step, inst, 0u, k0, k1);
+                box_muller4(w, z);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    v[e] = em_update<T, DEG>(v[e], z[e], c0, c1, c2, c3, e0, e1);
+                    d[e] = (p + e < P) ? v[e] - shift : (T)0;
+                }
+                store_quad(x, p, P, v);
+                double q1, q2;
+                quad_leaf(d, q1, q2);
+                a1 += q1;
+                a2 += q2;
+            }
+        }
     }
-    double s[2] = {a1, a2};
-    block_sum<2>(s, lds);
-    if (threadIdx.x == 0) part_out[W.part_off + sc] = make_double2(s[0], s[1]);
+    double sm[2] = {a1, a2};
+    block_sum<2>(sm, lds);
+    if (threadIdx.x == 0) part_out[W.part_off + sc] = make_double2(sm[0], sm[1]);
 }
 
 // ----------------------------------------------------------------------------
@@ -559,15 +639,24 @@ hipError_t launch_sum_init(int prec, const WorkItem *items, const int2 *blocks, 
     return hipGetLastError();
 }
 
-hipError_t launch_em_step(int prec, const WorkItem *items, const int2 *blocks, int nblocks, int j,
+hipError_t launch_em_step(int prec, int deg, const WorkItem *items, const int2 *blocks, int nblocks, int j,
                           const double2 *part_in, const double *shift_in, double2 *part_out, double *shift_out,
                           double2 *trace, int m, hipStream_t s) {
-    if (prec == 0)
-        hipLaunchKernelGGL(k_em_step<double>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j, part_in, shift_in,
-                           part_out, shift_out, trace, m);
-    else
-        hipLaunchKernelGGL(k_em_step<float>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j, part_in, shift_in,
-                           part_out, shift_out, trace, m);
+    if (prec == 0) {
+        if (deg == 1)
+            hipLaunchKernelGGL((k_em_step<double, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j, part_in,
+                               shift_in, part_out, shift_out, trace, m);
+        else
+            hipLaunchKernelGGL((k_em_step<double, 3>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j, part_in,
+                               shift_in, part_out, shift_out, trace, m);
+    } else {
+        if (deg == 1)
+            hipLaunchKernelGGL((k_em_step<float, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j, part_in,
+                               shift_in, part_out, shift_out, trace, m);
+        else
+            hipLaunchKernelGGL((k_em_step<float, 3>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j, part_in,
+                               shift_in, part_out, shift_out, trace, m);
+    }
     return hipGetLastError();
 }
 

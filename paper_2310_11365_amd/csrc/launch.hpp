@@ -10,7 +10,8 @@ namespace mcpr {
 // prec: 0 = fp64 particles, 1 = fp32 particles (fp64 reductions either way)
 hipError_t launch_sum_init(int prec, const WorkItem *items, const int2 *blocks, int nblocks, double2 *part_out,
                            double *shift_out, hipStream_t s);
-hipError_t launch_em_step(int prec, const WorkItem *items, const int2 *blocks, int nblocks, int j,
+// deg: 1 if every ensemble of the launch has a2 = a3 = 0 (drift affine in x), else 3
+hipError_t launch_em_step(int prec, int deg, const WorkItem *items, const int2 *blocks, int nblocks, int j,
                           const double2 *part_in, const double *shift_in, double2 *part_out, double *shift_out,
                           double2 *trace, int m, hipStream_t s);
 hipError_t launch_region_partials(int prec, int nr, int mode, const WorkItem *items, const int2 *blocks, int nblocks,
