@@ -149,8 +149,9 @@ mcpr_status mcpr_moments(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_
  * and n_regions; their coefficients and sizes may differ.
  * stats (device, may be NULL): [n_ens][n_regions + 1] restriction of the
  *   final state.
- * trace (device, may be NULL): [n_ens][steps_per_slice][2] the (mean,
- *   variance) each step used.                                              */
+ * trace (device, may be NULL): [n_ens][steps_per_slice + 1][2]: entry j <
+ *   m is the (mean, variance) step j used, entry m the mean and variance of
+ *   the final state.                                                       */
 mcpr_status mcpr_fine_propagate(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems,
                                 const mcpr_ensemble *ens, int32_t n_ens, mcpr_region_stats *stats,
                                 double *trace, mcpr_stream stream);
@@ -163,6 +164,21 @@ mcpr_status mcpr_fine_propagate(mcpr_ctx *ctx, const mcpr_problem *problems, int
 mcpr_status mcpr_match(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems,
                        const mcpr_ensemble *ens, int32_t n_ens, const mcpr_region_map *maps,
                        int32_t dry_run, mcpr_region_stats *probe, mcpr_stream stream);
+
+/* Pathwise gradient of the slice-end moments through the fine propagator
+ * (discrete adjoint of the Euler-Maruyama scheme with the noise fixed; not in
+ * the paper, used to fit coarse-model and fraction-model parameters).
+ * Runs the serial fine solution of slices ens->slice .. n_slices-1 from the
+ * state ens->x (not modified), with a checkpoint at every slice start, and
+ * reports the (mean, variance) at each slice end (host moments_out
+ * [n][2], may be NULL).  If dL_dmoments (host [n][2], upstream derivatives
+ * of a scalar L with respect to those moments) is given, the backward sweep
+ * recomputes each slice once from its checkpoint and writes
+ * grad_out (host [10]) = dL/d(a0, a1, a2, a3, am, av, b0, b1, bm, bv).
+ * fp64 adjoint state and reductions; synchronises the stream.  Scratch of
+ * (n + 1) + (m + 1) states and two fp64 arrays of P is held by the context. */
+mcpr_status mcpr_adjoint(mcpr_ctx *ctx, const mcpr_problem *problem, const mcpr_ensemble *ens,
+                         const double *dL_dmoments, double *moments_out, double *grad_out, mcpr_stream stream);
 
 /* ---- Parareal driver ----------------------------------------------------- */
 /* One Parareal instance: an independent problem with its own particle count

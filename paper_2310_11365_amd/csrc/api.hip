@@ -46,6 +46,7 @@ struct mcpr_ctx {
     int device = 0;
     std::string err;
     DevBuf items, blocks, part[2], shift[2], rpart, rshift[2], maps, recs;
+    DevBuf adj_ckpt, adj_traj, adj_lam[2], adj_part[2], adj_acc, adj_trace, adj_grad; // adjoint scratch
     HostBuf staging;
     hipEvent_t staged = nullptr; // the last upload from staging has completed
     // profiling of the Euler-Maruyama step launches (off unless enabled)
@@ -307,6 +308,7 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
         HIP_TRY(mcpr::launch_em_step(prec, deg, items, blocks, nb, j, part[a], shift[a], part[b], shift[b], trace, m, s));
         if (ctx->profile) HIP_TRY(hipEventRecord(ctx->prof1[j], s));
     }
+    if (trace) HIP_TRY(mcpr::launch_finish(items, n, part[m & 1], shift[m & 1], trace, m, s));
     if (ctx->profile) {
         HIP_TRY(hipEventSynchronize(ctx->prof1[m - 1]));
         for (int j = 0; j < m; ++j) {
@@ -356,8 +358,10 @@ void mcpr_destroy(mcpr_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    DevBuf *bufs[] = {&ctx->items, &ctx->blocks, &ctx->part[0], &ctx->part[1], &ctx->shift[0], &ctx->shift[1],
-                      &ctx->rpart, &ctx->rshift[0], &ctx->rshift[1], &ctx->maps, &ctx->recs};
+    DevBuf *bufs[] = {&ctx->items,       &ctx->blocks,      &ctx->part[0],     &ctx->part[1],     &ctx->shift[0],
+                      &ctx->shift[1],      &ctx->rpart,       &ctx->rshift[0],   &ctx->rshift[1],   &ctx->maps,
+                      &ctx->recs,          &ctx->adj_ckpt,    &ctx->adj_traj,    &ctx->adj_lam[0],  &ctx->adj_lam[1],
+                      &ctx->adj_part[0],   &ctx->adj_part[1], &ctx->adj_acc,     &ctx->adj_trace,   &ctx->adj_grad};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->staging.p) (void)hipHostFree(ctx->staging.p);
@@ -455,6 +459,116 @@ mcpr_status mcpr_match(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_pr
     HIP_TRY(mcpr::launch_match_apply(p.precision, p.n_regions, (const WorkItem *)ctx->items.p,
                                      (const int2 *)ctx->blocks.p, (int)t.blocks.size(), splits_of(p),
                                      (const RegionMap *)maps, s));
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_adjoint(mcpr_ctx *ctx, const mcpr_problem *problem, const mcpr_ensemble *ens,
+                         const double *dL_dmoments, double *moments_out, double *grad_out, mcpr_stream stream) {
+    mcpr_status st = check_call(ctx, problem, 1, ens, 1);
+    if (st != MCPR_OK) return st;
+    if (ens->problem != 0) return fail(ctx, MCPR_E_INVALID_ARG, "ensemble must use problem 0");
+    if (ens->slice >= problem->n_slices) return fail(ctx, MCPR_E_INVALID_ARG, "first slice beyond n_slices");
+    if (dL_dmoments && !grad_out) return fail(ctx, MCPR_E_INVALID_ARG, "grad_out is null");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const mcpr_problem &p = *problem;
+    const int m = p.steps_per_slice, n0 = ens->slice, NS = p.n_slices - n0;
+    const int64_t P = ens->n_particles, Ps = (P + 3) / 4 * 4;
+    const int prec = p.precision;
+    const size_t esz = prec == MCPR_FP64 ? 8 : 4;
+    const mcpr::Splits sp = splits_of(p);
+    if ((st = ensure(ctx, ctx->adj_ckpt, (size_t)(NS + 1) * Ps * esz)) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->adj_trace, (size_t)NS * (m + 1) * 2 * sizeof(double))) != MCPR_OK) return st;
+    char *ckpt = (char *)ctx->adj_ckpt.p;
+    double *trace_d = (double *)ctx->adj_trace.p;
+
+    // forward: checkpoint every slice start, trace every step's moments
+    HIP_TRY(hipMemcpyAsync(ckpt, ens->x, (size_t)P * esz, hipMemcpyDeviceToDevice, s));
+    for (int n = 0; n < NS; ++n) {
+        char *dst = ckpt + (size_t)(n + 1) * Ps * esz;
+        HIP_TRY(hipMemcpyAsync(dst, ckpt + (size_t)n * Ps * esz, (size_t)P * esz, hipMemcpyDeviceToDevice, s));
+        mcpr_ensemble e = *ens;
+        e.x = dst;
+        e.slice = n0 + n;
+        Tables t;
+        build_tables(problem, &e, 1, t);
+        if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
+        if ((st = fine_sequence(ctx, t, prec, m, p.n_regions, sp, nullptr,
+                                (double2 *)(trace_d + (size_t)n * (m + 1) * 2), s)) != MCPR_OK)
+            return st;
+    }
+    std::vector<double> tr((size_t)NS * (m + 1) * 2);
+    HIP_TRY(hipMemcpyAsync(tr.data(), trace_d, tr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    auto tm = [&](int n, int j) { return tr[((size_t)n * (m + 1) + j) * 2]; };
+    auto tv = [&](int n, int j) { return tr[((size_t)n * (m + 1) + j) * 2 + 1]; };
+    if (moments_out)
+        for (int n = 0; n < NS; ++n) {
+            moments_out[2 * n] = tm(n, m);
+            moments_out[2 * n + 1] = tv(n, m);
+        }
+    if (!dL_dmoments) return MCPR_OK;
+
+    // backward sweep over slices in reverse, each recomputed from its checkpoint
+    Tables tt;
+    mcpr_ensemble et = *ens;
+    if ((st = ensure(ctx, ctx->adj_traj, (size_t)(m + 1) * Ps * esz)) != MCPR_OK) return st;
+    et.x = ctx->adj_traj.p;
+    build_tables(problem, &et, 1, tt);
+    tt.items[0].traj = Ps;
+    const int nsc = tt.total_sc;
+    for (int b = 0; b < 2; ++b) {
+        if ((st = ensure(ctx, ctx->adj_lam[b], (size_t)Ps * sizeof(double))) != MCPR_OK) return st;
+        if ((st = ensure(ctx, ctx->adj_part[b], (size_t)nsc * sizeof(double2))) != MCPR_OK) return st;
+    }
+    if ((st = ensure(ctx, ctx->adj_acc, (size_t)nsc * 10 * sizeof(double))) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->adj_grad, 10 * sizeof(double))) != MCPR_OK) return st;
+    if ((st = upload(ctx, tt, nullptr, 0, s)) != MCPR_OK) return st;
+    HIP_TRY(hipMemsetAsync(ctx->adj_acc.p, 0, (size_t)nsc * 10 * sizeof(double), s));
+    const WorkItem *items = (const WorkItem *)ctx->items.p;
+    const int2 *blocks = (const int2 *)ctx->blocks.p;
+    const int nb = (int)tt.blocks.size();
+    double *lam[2] = {(double *)ctx->adj_lam[0].p, (double *)ctx->adj_lam[1].p};
+    double2 *apart[2] = {(double2 *)ctx->adj_part[0].p, (double2 *)ctx->adj_part[1].p};
+    const bool zprev = p.coef.bm != 0.0 || p.coef.bv != 0.0;
+    const double invP = 1.0 / (double)P;
+    int cur = 0, pc = 0;
+    {
+        // lambda at the final state: the slice-end term of the last slice
+        mcpr::AdjStep a{};
+        a.dm = dL_dmoments[2 * (NS - 1)] * invP;
+        a.dv = 2.0 * dL_dmoments[2 * (NS - 1) + 1] * invP;
+        a.mdir = tm(NS - 1, m);
+        a.step = (n0 + NS) * m;
+        HIP_TRY(mcpr::launch_adj_init(prec, items, blocks, nb, ckpt + (size_t)NS * Ps * esz, lam[cur], a, apart[pc], s));
+    }
+    char *traj = (char *)ctx->adj_traj.p;
+    for (int n = NS - 1; n >= 0; --n) {
+        HIP_TRY(hipMemcpyAsync(traj, ckpt + (size_t)n * Ps * esz, (size_t)P * esz, hipMemcpyDeviceToDevice, s));
+        tt.items[0].step0 = (n0 + n) * m;
+        if ((st = upload(ctx, tt, nullptr, 0, s)) != MCPR_OK) return st;
+        if ((st = fine_sequence(ctx, tt, prec, m, p.n_regions, sp, nullptr, nullptr, s)) != MCPR_OK) return st;
+        for (int j = m - 1; j >= 0; --j) {
+            mcpr::AdjStep a{};
+            a.m = tm(n, j);
+            a.v = tv(n, j);
+            a.step = (n0 + n) * m + j;
+            a.grad = 1;
+            a.zprev = (zprev && (n > 0 || j > 0)) ? 1 : 0;
+            if (j == 0 && n > 0) { // slice end n-1 (the state that starts slice n)
+                a.dm = dL_dmoments[2 * (n - 1)] * invP;
+                a.dv = 2.0 * dL_dmoments[2 * (n - 1) + 1] * invP;
+                a.mdir = tm(n - 1, m);
+            }
+            HIP_TRY(mcpr::launch_adj_step(prec, items, blocks, nb, traj + (size_t)j * Ps * esz, lam[cur], lam[cur ^ 1],
+                                          a, apart[pc], apart[pc ^ 1], (double *)ctx->adj_acc.p, s));
+            cur ^= 1;
+            pc ^= 1;
+        }
+    }
+    HIP_TRY(mcpr::launch_adj_reduce(items, 1, (const double *)ctx->adj_acc.p, (double *)ctx->adj_grad.p, s));
+    HIP_TRY(hipMemcpyAsync(grad_out, ctx->adj_grad.p, 10 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     return MCPR_OK;
 }
 

@@ -52,6 +52,7 @@ struct WorkItem {
     double c[10];      // a0 a1 a2 a3 am av b0 b1 bm bv
     double dt, sdt;    // step and its square root
     double p0[5];      // w, mu1, sd1, mu2, sd2
+    int64_t traj;      // 0: steps work in place; else step j reads x + j*traj and writes x + (j+1)*traj
 };
 
 // Per-superchunk region partial: count, sum d, sum d^2, min, max (d = x - shift).
@@ -71,6 +72,17 @@ struct RegionMap {
     double from, scale, to;
     int32_t mode;
     int32_t boundary;
+};
+
+// Scalars of one backward (adjoint) step s.
+struct AdjStep {
+    double m, v;      // moments step s used
+    double dm, dv;    // direct term at X_s: dm + dv (X_s - mdir)  (zero if none)
+    double mdir;
+    int32_t step;     // global step index s
+    int32_t zprev;    // 1: form sum lambda_s z_{s-1} for the next launch
+    int32_t grad;     // 1: accumulate the parameter gradient of step s
+    int32_t pad;
 };
 
 struct Splits {

@@ -275,7 +275,8 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
     const int2 bt = blocks[blockIdx.x];
     const int item = bt.x, sc = bt.y;
     const WorkItem &W = items[item];
-    T *__restrict__ x = reinterpret_cast<T *>(W.x);
+    T *__restrict__ x = reinterpret_cast<T *>(W.x) + (int64_t)j * W.traj;
+    T *__restrict__ y = x + W.traj; // the output state (the input itself when in place)
     const int64_t P = W.P;
     const int R = W.R;
 
@@ -287,7 +288,7 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
     const T shift = (T)mean; // shift of this step's output sums, a value of the state type
     if (sc == 0 && threadIdx.x == 0) {
         shift_out[item] = (double)shift;
-        if (trace) trace[(int64_t)item * m + j] = make_double2(mean, var);
+        if (trace) trace[(int64_t)item * (m + 1) + j] = make_double2(mean, var);
     }
 
     // step coefficients: p(x) = x + a(x) dt as a polynomial, diffusion * sqrt(dt) affine in x
@@ -304,7 +305,8 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
     const int64_t base = (int64_t)sc * 4 * kThreads * R; // first particle of the superchunk
     if (base + (int64_t)4 * kThreads * R <= P) {
         // full superchunk: 32-bit quad offsets, no per-quad checks
-        T *xs = x + base;
+        const T *xs = x + base;
+        T *ys = y + base;
         const uint32_t qb = (uint32_t)(base >> 2) + threadIdx.x;
         for (int r0 = 0; r0 < R; r0 += 4) {
             T v[4][4];
@@ -322,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
                         v[g][e] = em_update<T, DEG>(v[g][e], z[e], c0, c1, c2, c3, e0, e1);
                         d[e] = v[g][e] - shift;
                     }
-                    gstore_quad(xs, (uint32_t)((r0 + g) * kThreads + threadIdx.x), v[g]);
+                    gstore_quad(ys, (uint32_t)((r0 + g) * kThreads + threadIdx.x), v[g]);
                     double q1, q2;
                     quad_leaf(d, q1, q2);
                     a1 += q1;
@@ -344,7 +346,7 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
                     v[e] = em_update<T, DEG>(v[e], z[e], c0, c1, c2, c3, e0, e1);
                     d[e] = (p + e < P) ? v[e] - shift : (T)0;
                 }
-                store_quad(x, p, P, v);
+                store_quad(y, p, P, v);
                 double q1, q2;
                 quad_leaf(d, q1, q2);
                 a1 += q1;
@@ -355,6 +357,180 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
     double sm[2] = {a1, a2};
     block_sum<2>(sm, lds);
     if (threadIdx.x == 0) part_out[W.part_off + sc] = make_double2(sm[0], sm[1]);
+}
+
+// Moments of the final state of each ensemble (trace entry m): one block per item.
+__global__ __launch_bounds__(kThreads) void k_finish(const WorkItem *__restrict__ items,
+                                                     const double2 *__restrict__ part_in,
+                                                     const double *__restrict__ shift_in,
+                                                     double2 *__restrict__ trace, int32_t m) {
+    __shared__ double lds[8];
+    const WorkItem &W = items[blockIdx.x];
+    double S1, S2;
+    ensemble_sums(part_in + W.part_off, W.nsc, S1, S2, lds);
+    double mean, var;
+    finish_moments(S1, S2, shift_in[blockIdx.x], (double)W.P, mean, var);
+    if (threadIdx.x == 0) trace[(int64_t)blockIdx.x * (m + 1) + m] = make_double2(mean, var);
+}
+
+// ----------------------------------------------------------------------------
+// Discrete adjoint of the fine propagator (pathwise gradients; not in the paper)
+//
+// Forward step s:  X_{s+1} = X_s + a(X_s, m_s, v_s) dt + b(X_s, m_s, v_s) sqrt(dt) z_s
+// with m_s, v_s the population mean and variance of X_s.  With lambda_s =
+// dL/dX_s (total derivative):
+//   lambda_s = lambda_{s+1} (1 + a_x(X_s) dt + b_x sqrt(dt) z_s)
+//            + g_m / P + 2 g_v (X_s - m_s) / P + [slice end] direct_s
+//   g_m = sum_q lambda_{s+1}^q (a_m dt + b_m sqrt(dt) z_s^q)
+//   g_v = sum_q lambda_{s+1}^q (a_v dt + b_v sqrt(dt) z_s^q)
+//   dL/dtheta = sum_s sum_p lambda_{s+1}^p dX_{s+1}^p / dtheta   (theta = a0..bv)
+// g_m and g_v need two ensemble sums of step s (sum lambda_{s+1}, sum
+// lambda_{s+1} z_s); the launch of step s+1 forms them as partials while it
+// writes lambda_{s+1}, exactly as the forward step forms the next mean field.
+// lambda is fp64; X is the recomputed forward state (fp32 or fp64); z_s are the
+// forward's own normals, regenerated.  Every sum uses the canonical order.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ double adj_leaf(const double d[4]) { return (d[0] + d[1]) + (d[2] + d[3]); }
+
+// lambda_S = direct term at the final state; partials for step S-1.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_adj_init(const WorkItem *__restrict__ items,
+                                                       const int2 *__restrict__ blocks, const T *__restrict__ xS,
+                                                       double *__restrict__ lam, AdjStep a,
+                                                       double2 *__restrict__ part_out) {
+    __shared__ double lds[8];
+    const int2 bt = blocks[blockIdx.x];
+    const WorkItem &W = items[bt.x];
+    const int64_t P = W.P;
+    const int R = W.R;
+    const double sdt = W.sdt;
+    double s0 = 0.0, s1 = 0.0;
+    const int64_t base = (int64_t)bt.y * 4 * kThreads * R;
+    for (int r = 0; r < R; ++r) {
+        const int64_t p = base + 4 * (int64_t)(r * kThreads + threadIdx.x);
+        if (p < P) {
+            T xv[4], z[4];
+            load_quad(xS, p, P, xv);
+            const Words4 w = philox4x32_10((uint32_t)(p >> 2), (uint32_t)(a.step - 1), (uint32_t)W.inst, 0u,
+                                           W.key0, W.key1);
+            box_muller4(w, z);
+            double l[4], lz[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool ok = p + e < P;
+                l[e] = ok ? a.dm + a.dv * ((double)xv[e] - a.mdir) : 0.0;
+                lz[e] = l[e] * (double)z[e];
+                if (ok) lam[p + e] = l[e];
+            }
+            s0 += adj_leaf(l);
+            s1 += adj_leaf(lz);
+        }
+    }
+    (void)sdt;
+    double sm[2] = {s0, s1};
+    block_sum<2>(sm, lds);
+    if (threadIdx.x == 0) part_out[W.part_off + bt.y] = make_double2(sm[0], sm[1]);
+}
+
+// One backward step s: lambda_in = lambda_{s+1} -> lambda_out = lambda_s.
+// acc: per-superchunk running gradient sums [nsc][10] (fp64, one writer each).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_adj_step(const WorkItem *__restrict__ items,
+                                                       const int2 *__restrict__ blocks, const T *__restrict__ xs_,
+                                                       const double *__restrict__ lam_in,
+                                                       double *__restrict__ lam_out, AdjStep a,
+                                                       const double2 *__restrict__ part_in,
+                                                       double2 *__restrict__ part_out, double *__restrict__ acc) {
+    __shared__ double lds[4 * 8];
+    const int2 bt = blocks[blockIdx.x];
+    const WorkItem &W = items[bt.x];
+    const int64_t P = W.P;
+    const int R = W.R;
+    const double dt = W.dt, sdt = W.sdt;
+    const double *c = W.c;
+    // mean-field adjoint scalars of step s from the previous launch's partials
+    double Sl, Slz;
+    ensemble_sums(part_in + W.part_off, W.nsc, Sl, Slz, lds);
+    const double gm = c[4] * dt * Sl + c[8] * sdt * Slz;
+    const double gv = c[5] * dt * Sl + c[9] * sdt * Slz;
+    const double c1 = gm / (double)P, c2 = 2.0 * gv / (double)P;
+
+    double g[6] = {0, 0, 0, 0, 0, 0}; // sum l, lx, lx^2, lx^3, lz, lxz   (l = lambda_{s+1})
+    double nx0 = 0.0, nx1 = 0.0;      // sum lambda_s, sum lambda_s z_{s-1}
+    const int64_t base = (int64_t)bt.y * 4 * kThreads * R;
+    for (int r = 0; r < R; ++r) {
+        const int64_t p = base + 4 * (int64_t)(r * kThreads + threadIdx.x);
+        if (p < P) {
+            T xv[4], z[4], zp[4];
+            load_quad(xs_, p, P, xv);
+            const uint32_t q = (uint32_t)(p >> 2);
+            const Words4 w = philox4x32_10(q, (uint32_t)a.step, (uint32_t)W.inst, 0u, W.key0, W.key1);
+            box_muller4(w, z);
+            if (a.zprev) {
+                const Words4 w2 = philox4x32_10(q, (uint32_t)(a.step - 1), (uint32_t)W.inst, 0u, W.key0, W.key1);
+                box_muller4(w2, zp);
+            }
+            double t0[4], t1[4], t2[4], t3[4], t4[4], t5[4], ln[4], lnz[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool ok = p + e < P;
+                const double x = (double)xv[e], zz = (double)z[e];
+                const double l = ok ? lam_in[p + e] : 0.0;
+                const double ax = c[1] + x * (2.0 * c[2] + 3.0 * c[3] * x);
+                double lo = l * (1.0 + ax * dt + c[7] * sdt * zz) + c1 + c2 * (x - a.m);
+                lo += a.dm + a.dv * (x - a.mdir);
+                lo = ok ? lo : 0.0;
+                if (ok) lam_out[p + e] = lo;
+                t0[e] = l;
+                t1[e] = l * x;
+                t2[e] = l * x * x;
+                t3[e] = l * x * x * x;
+                t4[e] = l * zz;
+                t5[e] = l * x * zz;
+                ln[e] = lo;
+                lnz[e] = a.zprev ? lo * (double)zp[e] : 0.0;
+            }
+            g[0] += adj_leaf(t0);
+            g[1] += adj_leaf(t1);
+            g[2] += adj_leaf(t2);
+            g[3] += adj_leaf(t3);
+            g[4] += adj_leaf(t4);
+            g[5] += adj_leaf(t5);
+            nx0 += adj_leaf(ln);
+            nx1 += adj_leaf(lnz);
+        }
+    }
+    double sm[8] = {g[0], g[1], g[2], g[3], g[4], g[5], nx0, nx1};
+    block_sum<8>(sm, lds);
+    if (threadIdx.x == 0) {
+        part_out[W.part_off + bt.y] = make_double2(sm[6], sm[7]);
+        if (a.grad) {
+            double *ac = acc + (int64_t)(W.part_off + bt.y) * 10;
+            ac[0] += dt * sm[0];
+            ac[1] += dt * sm[1];
+            ac[2] += dt * sm[2];
+            ac[3] += dt * sm[3];
+            ac[4] += dt * a.m * sm[0];
+            ac[5] += dt * a.v * sm[0];
+            ac[6] += sdt * sm[4];
+            ac[7] += sdt * sm[5];
+            ac[8] += sdt * a.m * sm[4];
+            ac[9] += sdt * a.v * sm[4];
+        }
+    }
+}
+
+// Sum of the per-superchunk gradient accumulators of one item (one block).
+__global__ __launch_bounds__(kThreads) void k_adj_reduce(const WorkItem *__restrict__ items,
+                                                         const double *__restrict__ acc, double *__restrict__ out) {
+    __shared__ double lds[4 * 10];
+    const WorkItem &W = items[blockIdx.x];
+    double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int s = threadIdx.x; s < W.nsc; s += kThreads)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) v[k] += acc[(int64_t)(W.part_off + s) * 10 + k];
+    block_sum<10>(v, lds);
+    if (threadIdx.x < 10) out[(int64_t)blockIdx.x * 10 + threadIdx.x] = v[threadIdx.x];
 }
 
 // ----------------------------------------------------------------------------
@@ -657,6 +833,40 @@ hipError_t launch_em_step(int prec, int deg, const WorkItem *items, const int2 *
             hipLaunchKernelGGL((k_em_step<float, 3>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j, part_in,
                                shift_in, part_out, shift_out, trace, m);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const WorkItem *items, int n_items, const double2 *part_in, const double *shift_in,
+                         double2 *trace, int m, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(n_items), dim3(kThreads), 0, s, items, part_in, shift_in, trace, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_init(int prec, const WorkItem *items, const int2 *blocks, int nblocks, const void *xS,
+                           double *lam, const AdjStep &a, double2 *part_out, hipStream_t s) {
+    if (prec == 0)
+        hipLaunchKernelGGL(k_adj_init<double>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, (const double *)xS,
+                           lam, a, part_out);
+    else
+        hipLaunchKernelGGL(k_adj_init<float>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, (const float *)xS,
+                           lam, a, part_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_step(int prec, const WorkItem *items, const int2 *blocks, int nblocks, const void *xs,
+                           const double *lam_in, double *lam_out, const AdjStep &a, const double2 *part_in,
+                           double2 *part_out, double *acc, hipStream_t s) {
+    if (prec == 0)
+        hipLaunchKernelGGL(k_adj_step<double>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, (const double *)xs,
+                           lam_in, lam_out, a, part_in, part_out, acc);
+    else
+        hipLaunchKernelGGL(k_adj_step<float>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, (const float *)xs,
+                           lam_in, lam_out, a, part_in, part_out, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_reduce(const WorkItem *items, int n_items, const double *acc, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_reduce, dim3(n_items), dim3(kThreads), 0, s, items, acc, out);
     return hipGetLastError();
 }
 

@@ -14,6 +14,15 @@ hipError_t launch_sum_init(int prec, const WorkItem *items, const int2 *blocks, 
 hipError_t launch_em_step(int prec, int deg, const WorkItem *items, const int2 *blocks, int nblocks, int j,
                           const double2 *part_in, const double *shift_in, double2 *part_out, double *shift_out,
                           double2 *trace, int m, hipStream_t s);
+// trace entry m of each item: moments of its final state from the last step's partials
+hipError_t launch_finish(const WorkItem *items, int n_items, const double2 *part_in, const double *shift_in,
+                         double2 *trace, int m, hipStream_t s);
+hipError_t launch_adj_init(int prec, const WorkItem *items, const int2 *blocks, int nblocks, const void *xS,
+                           double *lam, const AdjStep &a, double2 *part_out, hipStream_t s);
+hipError_t launch_adj_step(int prec, const WorkItem *items, const int2 *blocks, int nblocks, const void *xs,
+                           const double *lam_in, double *lam_out, const AdjStep &a, const double2 *part_in,
+                           double2 *part_out, double *acc, hipStream_t s);
+hipError_t launch_adj_reduce(const WorkItem *items, int n_items, const double *acc, double *out, hipStream_t s);
 hipError_t launch_region_partials(int prec, int nr, int mode, const WorkItem *items, const int2 *blocks, int nblocks,
                                   const double *rshift, const Splits &sp, const RegionMap *maps, RegionPartial *rpart,
                                   hipStream_t s);

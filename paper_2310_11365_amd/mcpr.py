@@ -91,6 +91,8 @@ def lib() -> ctypes.CDLL:
         L.mcpr_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_int64), i32]
         L.mcpr_profile_read.restype = st
+        L.mcpr_adjoint.argtypes = [vp, pP, pE, vp, vp, vp, vp]
+        L.mcpr_adjoint.restype = st
         L.mcpr_parareal_create.argtypes = [vp, pP, i32, ctypes.POINTER(InstanceC), i32, i32, ctypes.c_double,
                                            ctypes.POINTER(vp)]
         L.mcpr_parareal_create.restype = st
@@ -275,12 +277,12 @@ class Propagator:
         import torch
         inst = instances or [0] * len(xs)
         buf = stats_buffer(len(xs), self.I)
-        tr = torch.empty(len(xs) * self.problem.steps_per_slice * 2, dtype=torch.float64,
+        tr = torch.empty(len(xs) * (self.problem.steps_per_slice + 1) * 2, dtype=torch.float64,
                          device="cuda") if trace else None
         self.ctx.fine_propagate([self.pc], [ensemble(x, i, n) for x, i, n in zip(xs, inst, slices)], buf, tr)
         st = stats_to_numpy(buf, len(xs), self.I)
         if trace:
-            return st, tr.cpu().numpy().reshape(len(xs), self.problem.steps_per_slice, 2)
+            return st, tr.cpu().numpy().reshape(len(xs), self.problem.steps_per_slice + 1, 2)
         return st
 
     def match(self, xs: List, maps: np.ndarray, instances=None, dry_run=False):
@@ -291,6 +293,58 @@ class Propagator:
         if dry_run:
             return stats_to_numpy(probe, len(xs), self.I)
         return None
+
+
+COEF_NAMES = ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv")
+
+
+def adjoint(ctx: Context, problem_struct: ProblemC, x0, dL_dmoments=None, instance=0, first_slice=0,
+            stream=None):
+    """Slice-end moments of the serial fine solution from x0 and, given
+    dL/d(moments) [n, 2], the gradient dL/d(a0..bv) through mcpr_adjoint."""
+    n = problem_struct.n_slices - first_slice
+    mom = np.zeros((n, 2))
+    e = ensemble(x0, instance, first_slice)
+    P = (ProblemC * 1)(problem_struct)
+    E = (EnsembleC * 1)(e)
+    if dL_dmoments is None:
+        ctx._check(lib().mcpr_adjoint(ctx.handle, P, E, None, mom.ctypes.data, None, _stream(stream)))
+        return mom, None
+    dl = np.ascontiguousarray(dL_dmoments, dtype=np.float64).reshape(n, 2)
+    g = np.zeros(10)
+    ctx._check(lib().mcpr_adjoint(ctx.handle, P, E, dl.ctypes.data, mom.ctypes.data, g.ctypes.data,
+                                  _stream(stream)))
+    return mom, g
+
+
+def slice_moments_function():
+    """torch.autograd.Function: coefficients (10, float64) -> slice-end
+    (mean, variance) [N, 2] of the fine propagator; backward by the adjoint."""
+    import torch
+
+    class SliceMoments(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, coef, x0, problem, mctx, instance):
+            pc = problem_c(problem, _coef_from(coef))
+            mom, _ = adjoint(mctx, pc, x0, None, instance)
+            fctx.save_for_backward(coef)
+            fctx.x0, fctx.problem, fctx.mctx, fctx.instance = x0, problem, mctx, instance
+            return torch.from_numpy(mom)
+
+        @staticmethod
+        def backward(fctx, grad_out):
+            (coef,) = fctx.saved_tensors
+            pc = problem_c(fctx.problem, _coef_from(coef))
+            _, g = adjoint(fctx.mctx, pc, fctx.x0, grad_out.detach().cpu().numpy(), fctx.instance)
+            return torch.from_numpy(g).to(coef.dtype), None, None, None, None
+
+    return SliceMoments
+
+
+def _coef_from(coef_tensor):
+    from types import SimpleNamespace
+    vals = [float(v) for v in coef_tensor.detach().cpu().tolist()]
+    return SimpleNamespace(**dict(zip(COEF_NAMES, vals)))
 
 
 class Parareal:
