@@ -1,29 +1,39 @@
 #!/usr/bin/env python3
 """Benchmark of the MC-moments Parareal hot path on one MI355X.
 
-Workload: the bimodal Desai-Zwanzig ensemble (P = 1e6 particles per slice,
-N = 50 slices, T = 5, dt = 1e-3, two regions split at 0, fp32 particles with
-fp64 reductions and matching).  One step is one pass of the whole hot path
-over that input: sample p0, restriction, coarse sweep and lifting of all 50
-slices (iteration 0), then one Parareal iteration: the fine propagator on all
-50 slices batched into each Euler-Maruyama launch (5e9 particle-steps),
-slice-end restrictions, the sequential coarse sweep with the iterator, and
-the matching.  value = particle-steps per second of the whole step.
+Default workload (the headline configuration): the bimodal Desai-Zwanzig
+ensemble, P = 1e6 particles per slice, N = 50 slices, T = 5, dt = 1e-3, two
+regions split at 0, fp32 particles with fp64 reductions and matching.
+
+One step is one pass of the whole hot path over the workload's input: sample
+p0, restriction, coarse sweep and lifting of all slices (iteration 0), then one
+Parareal iteration: the fine propagator on every slice of every instance,
+batched into each Euler-Maruyama launch, the slice-end restrictions, the
+sequential coarse sweep with the iterator, and the matching.
+value = particle-steps per second of the whole step.
+
+Other workloads (--workload): ou_batched (64 independent OU instances, P
+log-uniform in [1e4, 2e6], N = 32: 3.7 GB of state, HBM-resident), dz_large
+(P = 1.6e7, N = 256, 79 steps per slice, 16.4 GB ring, learning; also run to
+tolerance 1e-4), ou_linear (P = 1e4, N = 10, fp64: the latency-bound case).
 
 The JSON line also carries:
   roofline      the Euler-Maruyama step kernel: algorithmic bytes per launch
-                (8 B per particle-step: one fp32 read and one fp32 write) over
-                its average launch duration, measured with HIP events around
-                every step launch of the timed region, against 8 TB/s;
+                (8 B per particle-step in fp32, 16 B in fp64: one read and one
+                write of the state) over its mean launch duration, measured
+                with HIP events around each sweep's run of step launches inside
+                the timed region, against 8 TB/s; traffic = HBM bytes per launch
+                from rocprofv3 counters (profiles/traffic.json) while the kernel
+                source is unchanged, else null;
   cpu_baseline  the FP64 oracle on this host (one thread) on a bounded sample
-                of the same workload;
+                of the same workload (default workload only);
   parareal      wall-time of the serial fine solution vs Parareal iterations
-                on the same GPU, with the error of each iterate against the
-                serial solution.
+                on the same GPU, with the error of each iterate against it.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -36,7 +46,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def load_traffic(kernel: str):
+def load_traffic(kernel: str, workload: str):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if any."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -45,13 +55,11 @@ def load_traffic(kernel: str):
         data = json.load(open(path))
     except Exception:
         return None
-    ent = data.get(kernel)
+    ent = data.get(f"{kernel}@{workload}")
     if not ent:
         return None
-    lib = os.path.join(ROOT, "paper_2310_11365_amd", "csrc", "kernels.hip")
-    import hashlib
-    h = hashlib.sha256(open(lib, "rb").read()).hexdigest()[:16]
-    if ent.get("kernels_sha") != h:
+    src = os.path.join(ROOT, "paper_2310_11365_amd", "csrc", "kernels.hip")
+    if ent.get("kernels_sha") != hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]:
         return None  # the kernel changed since the counters were taken
     return ent.get("bytes_per_launch")
 
@@ -80,14 +88,41 @@ def cpu_baseline(seconds_target: float = 15.0):
                       f"({ps:.3g} particle-steps), single thread, {dt:.1f} s"}
 
 
+def make_workload(name: str):
+    """(workload, per-instance particle counts, coefficient overrides, description)."""
+    from paper_2310_11365_amd import workloads as W
+    if name == "dz_bimodal":
+        wl = W.dz_bimodal()
+        return wl, [wl.P], None, ("dz_bimodal: Desai-Zwanzig dX=(X-X^3-0.5(X-E[X]))dt+0.5dW, "
+                                  "X0~0.5N(-1,0.1^2)+0.5N(1,0.1^2), two regions split at 0")
+    if name == "ou_batched":
+        wl = W.ou_batched()
+        return wl, [i["P"] for i in wl.instances], [i["coef"] for i in wl.instances], \
+            ("ou_batched: 64 independent instances of dX=(-theta X+0.5E[X])dt+sigma dW, X0~N(1,0.2^2), "
+             "theta~U[0.1,1], sigma~U[0.2,0.8], P log-uniform in [1e4,2e6]")
+    if name == "dz_large":
+        wl = W.dz_large()
+        return wl, [wl.P], None, ("dz_large: Desai-Zwanzig as dz_bimodal, P=1.6e7, N=256, T=10, "
+                                  "dt=5e-4 (79 steps per slice), fraction-model learning, tol 1e-4")
+    if name == "ou_linear":
+        wl = W.ou_linear()
+        return wl, [wl.P], None, ("ou_linear: dX=(-X+0.5E[X])dt+0.3dW, X0~N(1,0.2^2), P=1e4, N=10, "
+                                  "RK4 coarse h=0.05, fp64")
+    raise SystemExit(f"unknown workload {name}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="dz_bimodal",
+                    choices=["dz_bimodal", "ou_batched", "dz_large", "ou_linear"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parareal", action="store_true")
     ap.add_argument("--parareal-iters", type=int, default=4)
+    ap.add_argument("--parareal-max-s", type=float, default=60.0,
+                    help="stop the run-to-tolerance Parareal measurement after this many seconds")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "reference for the HBM byte counters of a profiler run)")
@@ -105,10 +140,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    wl = W.dz_bimodal()
+    wl, sizes, coefs, desc = make_workload(args.workload)
     pr = wl.problem
-    N, m, P = pr.n_slices, pr.steps_per_slice, wl.P
-    ps_per_step = N * m * P
+    N, m = pr.n_slices, pr.steps_per_slice
+    ps_per_step = N * m * sum(sizes)
+    esize = 8 if pr.precision == W.FP64 else 4
+    kernel = "k_em_step<double>" if pr.precision == W.FP64 else "k_em_step<float>"
 
     if args.copy_probe > 0:
         n = args.copy_probe * (1 << 20) // 4
@@ -121,13 +158,14 @@ def main():
         del src, dst
 
     ctx = mcpr.Context(0)
-    para = mcpr.Parareal([pr], [P], ctx)
+    para = mcpr.Parareal([pr], sizes, ctx, coefs=coefs, learning=wl.learning, tol=wl.tol)
 
     def step():
         para.init()
         para.iterate()
 
-    print(f"# workload {wl.name}: P={P} N={N} m={m} fp32/fp64-reduce; warmup {args.warmup}", flush=True)
+    print(f"# workload {wl.name}: {len(sizes)} instance(s), {sum(sizes)} particles per slice in total, "
+          f"N={N} m={m}; warmup {args.warmup}", flush=True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -145,57 +183,73 @@ def main():
 
     value = ps_per_step * args.steps / elapsed
     avg_launch_s = em_ms / 1e3 / max(em_launches, 1)
-    bytes_per_launch = 8.0 * (em_ps / max(em_launches, 1))  # fp32 read + write per particle-step
+    bytes_per_launch = 2.0 * esize * (em_ps / max(em_launches, 1))  # one read and one write of the state
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = load_traffic("k_em_step<float>")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_em_step<float>", "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(kernel, wl.name),
+                "kernel": kernel, "avg_launch_us": round(avg_launch_s * 1e6, 2),
                 "bytes_per_launch": bytes_per_launch}
 
     out = {"metric": "fine-propagator particle-steps/sec", "value": value, "unit": "particle-steps/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32 state / f64 reductions", "data": "synthetic",
-           "config": {"workload": "dz_bimodal: Desai-Zwanzig dX=(X-X^3-0.5(X-E[X]))dt+0.5dW, "
-                                  "X0~0.5N(-1,0.1^2)+0.5N(1,0.1^2), two regions split at 0",
-                      "particles": P, "slices": N, "steps_per_slice": m, "T": 5.0, "dt": pr.dt,
+           "vs_baseline": None,
+           "dtype": "f64" if pr.precision == W.FP64 else "f32 state / f64 reductions", "data": "synthetic",
+           "config": {"workload": desc, "instances": len(sizes), "particles_per_slice": sum(sizes),
+                      "slices": N, "steps_per_slice": m, "dt": pr.dt,
+                      "state_bytes": (N + 1) * sum(sizes) * esize,
                       "particle_steps_per_step": ps_per_step,
                       "step": "iteration 0 (sample, restrict, coarse, lift) + one Parareal iteration "
                               "over all slices"},
            "roofline": roofline}
 
     if not args.no_parareal:
-        # serial fine solution vs Parareal iterations, same GPU, same kernels
-        prop = mcpr.Propagator(pr, ctx)
-        x = prop.new_particles(P)
+        # serial fine solution (every instance batched, slice after slice) vs Parareal iterations
+        n_inst = len(sizes)
+        pcs = [mcpr.problem_c(pr, coefs[i] if coefs else None) for i in range(n_inst)]
+        xs = [torch.empty(P, dtype=mcpr.torch_dtype(pr.precision), device="cuda") for P in sizes]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        prop.sample(x)
-        ser = [prop.moments([x])[0]]
+        ctx.init_particles(pcs, [mcpr.ensemble(x, i, 0, i) for i, x in enumerate(xs)])
+        buf = mcpr.stats_buffer(n_inst, pr.n_regions)
+        ctx.moments(pcs, [mcpr.ensemble(x, i, 0, i) for i, x in enumerate(xs)], buf)
+        ser = [mcpr.stats_to_numpy(buf, n_inst, pr.n_regions)]
         for n in range(N):
-            ser.append(prop.fine([x], [n])[0])
+            ctx.fine_propagate(pcs, [mcpr.ensemble(x, i, n, i) for i, x in enumerate(xs)], buf)
+            ser.append(mcpr.stats_to_numpy(buf, n_inst, pr.n_regions))
         torch.cuda.synchronize()
         t_serial = time.perf_counter() - t0
-        sm = np.array([r[-1]["mean"] for r in ser])
-        sv = np.array([r[-1]["var"] for r in ser])
+        del xs
+        sm = np.array([[r[i][-1]["mean"] for r in ser] for i in range(n_inst)])
+        sv = np.array([[r[i][-1]["var"] for r in ser] for i in range(n_inst)])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         para.init()
         it = []
-        for k in range(args.parareal_iters):
-            para.iterate()
-            _, glob = para.macro(0)
-            it.append({"k": k + 1, "wall_s": round(time.perf_counter() - t0, 4),
-                       "E_mean": float(np.max(np.abs(glob[:, 0] - sm))),
-                       "E_var": float(np.max(np.abs(glob[:, 1] - sv)))})
-        se_mean = math.sqrt(float(np.max(sv)) / P)
-        out["parareal"] = {"serial_s": round(t_serial, 4), "iterations": it,
+        kmax = N if wl.tol > 0 else args.parareal_iters
+        for k in range(kmax):
+            delta = para.iterate()
+            em = ev = 0.0
+            for i in range(n_inst):
+                _, glob = para.macro(i)
+                em = max(em, float(np.max(np.abs(glob[:, 0] - sm[i]))))
+                ev = max(ev, float(np.max(np.abs(glob[:, 1] - sv[i]))))
+            it.append({"k": k + 1, "wall_s": round(time.perf_counter() - t0, 4), "delta": float(np.max(delta)),
+                       "E_mean": em, "E_var": ev})
+            print(f"# parareal k={k + 1} delta={np.max(delta):.3e} E_mean={em:.3e} E_var={ev:.3e}", flush=True)
+            if wl.tol > 0 and np.max(delta) <= wl.tol:
+                break
+            if time.perf_counter() - t0 > args.parareal_max_s:
+                print("# parareal: time cap reached before the tolerance", flush=True)
+                break
+        se_mean = math.sqrt(float(np.max(sv)) / min(sizes))
+        out["parareal"] = {"serial_s": round(t_serial, 4), "iterations": it, "tol": wl.tol,
                            "mc_standard_error_mean": se_mean,
-                           "note": "one GPU: the fine sweep of an iteration moves as many bytes as the "
-                                   "serial run, so iterations cost about as much as the serial solve"}
+                           "note": "one GPU: an iteration's fine sweep moves as many bytes as the serial "
+                                   "solve, so the gain of Parareal on one GPU is confined to latency-bound "
+                                   "sizes; across GPUs the sweep shards by slices"}
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "dz_bimodal":
         out["cpu_baseline"] = cpu_baseline()
 
     para.close()

@@ -51,6 +51,12 @@ enum { MCPR_FP64 = 0, MCPR_FP32 = 1 }; /* FP32: fp32 particles, fp64 reductions 
 enum { MCPR_P0_NORMAL = 0, MCPR_P0_MIXTURE = 1, MCPR_P0_DELTA = 2 };
 enum { MCPR_MAP_KEEP = 0, MCPR_MAP_AFFINE = 1, MCPR_MAP_RESAMPLE = 2 };
 enum { MCPR_MAX_REGIONS = 8 };
+/* Coarse moment models: the Taylor model (eq. moment_model_class_1) or the
+ * Gaussian assumed-density model (eq. Gaussian_model_McK_V_SDE) with its
+ * expectations by Gauss-Hermite sigma points, 2 (exact to degree 3) or 3
+ * (exact to degree 5, i.e. exact Gaussian closure for the supported cubic
+ * drift and affine diffusion).                                              */
+enum { MCPR_COARSE_TAYLOR = 0, MCPR_COARSE_GAUSS2 = 1, MCPR_COARSE_GAUSS3 = 2 };
 
 /* Drift and diffusion of the scalar McKean-Vlasov SDE (Sec. 1.1, eq.
  * general_McKean_Vlasov) in the class the build supports: polynomial in the
@@ -77,6 +83,8 @@ typedef struct {
     int32_t coarse_substeps; /* RK4 steps per slice of the coarse propagator, >= 1 */
     double split[MCPR_MAX_REGIONS - 1]; /* I-1 increasing boundaries */
     uint64_t seed;
+    int32_t coarse_model;    /* MCPR_COARSE_*: moment model of the coarse propagator */
+    int32_t reserved0;
 } mcpr_problem;
 
 /* One particle ensemble (a micro state u in R^P, Sec. 3.4). */
@@ -120,13 +128,23 @@ void mcpr_destroy(mcpr_ctx *ctx);
 const char *mcpr_last_error(const mcpr_ctx *ctx);
 const char *mcpr_version(void);
 
-/* Measurement: when enabled, mcpr_fine_propagate brackets each of its
+/* Measurement: when enabled, each fine sweep brackets its run of
  * Euler-Maruyama step launches with a pair of HIP events on the call's
- * stream, waits for the last one and accumulates the launches' elapsed time,
- * their number and the particle-steps done (the call then blocks the host). */
+ * stream (launched directly, not from a graph).  mcpr_profile_read waits for
+ * the recorded events and returns the summed elapsed time of those runs,
+ * the number of step launches and the particle-steps done.                  */
 mcpr_status mcpr_profile_enable(mcpr_ctx *ctx, int32_t on);
 mcpr_status mcpr_profile_read(mcpr_ctx *ctx, double *em_ms, int64_t *em_launches, int64_t *particle_steps,
                               int32_t reset);
+
+/* hipGraph replay of the fine sweep (on by default): the launch sequence of
+ * a fine sweep (step-0 sums, the steps, the final moments and records) is
+ * captured once per shape into a graph on a library-owned stream and
+ * replayed; the caller's stream waits on it through events.  Results are
+ * bitwise the same as direct launches.  mcpr_graph_stats: graphs built and
+ * replays so far.                                                           */
+mcpr_status mcpr_set_graphs(mcpr_ctx *ctx, int32_t on);
+mcpr_status mcpr_graph_stats(const mcpr_ctx *ctx, int64_t *builds, int64_t *launches);
 
 /* ---- hot-path calls ------------------------------------------------------ */
 /* Initial law p0 (Sec. 1.1) sampled into each ensemble (tags 1 and 2). */

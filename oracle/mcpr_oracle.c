@@ -26,8 +26,10 @@
  *   or_fine            fine propagator F_n: Euler-Maruyama (eq. Euler_Maruyama)
  *                      on the P-particle system (eq. general_equation).
  *   or_coarse          coarse propagator C_n: Taylor moment model
- *                      (eq. moment_model_class_1, derivation App. D), one pair
- *                      per region (eq. moment_model_Taylor_multimodal), RK4.
+ *                      (eq. moment_model_class_1, derivation App. D) or the
+ *                      Gaussian model with sigma points (eq.
+ *                      Gaussian_model_McK_V_SDE), one pair per region
+ *                      (eq. moment_model_Taylor_multimodal), RK4.
  *   or_transform       matching T (eq. multimodal_M).
  *   or_parareal        generalised micro-macro Parareal
  *                      (eq. mM_parareal_other_k_NEW) with the unimodal and
@@ -64,6 +66,8 @@ typedef struct {
     int32_t coarse_substeps;   /* RK4 steps per slice                          */
     double split[7];           /* region boundaries, increasing                */
     uint64_t seed;
+    int32_t coarse_model;      /* 0 Taylor, 1 Gaussian 2-point, 2 Gaussian 3-point */
+    int32_t pad1;
 } or_problem;
 
 typedef struct {
@@ -307,11 +311,49 @@ static void or_mixture(int I, const double *f, const double *y, double *mbar, do
     *vbar = v;
 }
 
+/* Gaussian assumed-density model (eq. Gaussian_model_McK_V_SDE, with the
+   variance integrand read as 2 (x - M) a + b^2): the expectations over
+   N(M_i, V_i) by Gauss-Hermite quadrature (sigma points).  Two points:
+   M +- sqrt(V), weights 1/2 (exact to degree 3).  Three points: M,
+   M +- sqrt(3V), weights 2/3, 1/6, 1/6 (exact to degree 5).  A negative V
+   places the points as for V = 0.                                           */
+static void or_gaussian_rhs(const or_problem *pr, double M, double V, double mbar, double vbar,
+                            double *dM, double *dV)
+{
+    double xs[3], ws[3];
+    int K;
+    double Vp = V > 0.0 ? V : 0.0;
+    if (pr->coarse_model == 1) {
+        K = 2;
+        xs[0] = M - sqrt(Vp); xs[1] = M + sqrt(Vp);
+        ws[0] = 0.5; ws[1] = 0.5;
+    } else {
+        K = 3;
+        xs[0] = M - sqrt(3.0 * Vp); xs[1] = M; xs[2] = M + sqrt(3.0 * Vp);
+        ws[0] = 1.0 / 6.0; ws[1] = 2.0 / 3.0; ws[2] = 1.0 / 6.0;
+    }
+    double ea = 0.0, exa = 0.0, eb2 = 0.0;
+    for (int k = 0; k < K; k++) {
+        double a = or_drift(pr, xs[k], mbar, vbar);
+        double b = or_diffusion(pr, xs[k], mbar, vbar);
+        ea += ws[k] * a;
+        exa += ws[k] * (xs[k] - M) * a;
+        eb2 += ws[k] * b * b;
+    }
+    *dM = ea;
+    *dV = 2.0 * exa + eb2;
+}
+
 static void or_coarse_rhs(const or_problem *pr, const double *f, const double *y, double *dy)
 {
     int I = pr->n_regions;
     double mbar, vbar;
     or_mixture(I, f, y, &mbar, &vbar);
+    if (pr->coarse_model == 1 || pr->coarse_model == 2) {
+        for (int i = 0; i < I; i++)
+            or_gaussian_rhs(pr, y[2 * i], y[2 * i + 1], mbar, vbar, &dy[2 * i], &dy[2 * i + 1]);
+        return;
+    }
     for (int i = 0; i < I; i++) {
         double M = y[2 * i], V = y[2 * i + 1];
         double A = or_drift(pr, M, mbar, vbar);
@@ -556,7 +598,7 @@ int or_parareal(const or_problem *pr, const double *u0, int64_t P, uint32_t inst
             if (st0[i].n == 0)
                 continue;
             double mu = rho[n * RS + 3 * i + 1], sig = rho[n * RS + 3 * i + 2];
-            if (sig < 0.0)
+            if (!(sig >= 0.0) || !isfinite(sig) || !isfinite(mu))
                 continue;
             or_transform(pr, u0, xn, P, inst, n, i, &st0[i], mu, sig, 1);
         }
@@ -632,7 +674,7 @@ int or_parareal(const or_problem *pr, const double *u0, int64_t P, uint32_t inst
                 }
                 double alM = (a[3 * i + 1] - c[3 * i + 1]) + b[i].mean;
                 double alV = (a[3 * i + 2] - c[3 * i + 2]) + b[i].var;
-                if (!(alV >= 0.0)) {
+                if (!(alV >= 0.0) || !isfinite(alV) || !isfinite(alM)) {
                     out[3 * i] = fi; out[3 * i + 1] = b[i].mean; out[3 * i + 2] = b[i].var;
                     fl[i] = 2;
                     continue;

@@ -40,6 +40,7 @@ class OrProblem(ctypes.Structure):
         ("n_regions", ctypes.c_int32), ("coarse_substeps", ctypes.c_int32),
         ("split", ctypes.c_double * 7),
         ("seed", ctypes.c_uint64),
+        ("coarse_model", ctypes.c_int32), ("pad1", ctypes.c_int32),
     ]
 
 
@@ -113,6 +114,7 @@ def to_c(problem, coef=None) -> OrProblem:
     for i, v in enumerate(problem.splits):
         s.split[i] = float(v)
     s.seed = int(problem.seed)
+    s.coarse_model = int(getattr(problem, "coarse_model", 0))
     return s
 
 

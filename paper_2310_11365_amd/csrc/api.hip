@@ -49,12 +49,22 @@ struct mcpr_ctx {
     DevBuf adj_ckpt, adj_traj, adj_lam[2], adj_part[2], adj_acc, adj_trace, adj_grad; // adjoint scratch
     HostBuf staging;
     hipEvent_t staged = nullptr; // the last upload from staging has completed
-    // profiling of the Euler-Maruyama step launches (off unless enabled)
+    DevBuf trace; // trace of the last fine sweep (copied to the caller's array)
+    // profiling of the Euler-Maruyama step launches (off unless enabled): one
+    // event pair around each call's run of step launches, read lazily
     bool profile = false;
-    std::vector<hipEvent_t> prof0, prof1; // one pair per step launch
-    double prof_ms = 0.0;
+    std::vector<hipEvent_t> prof0, prof1;
+    std::vector<int64_t> prof_ps;
+    size_t prof_used = 0;
     int64_t prof_launches = 0;
-    int64_t prof_particle_steps = 0;
+    // hipGraph of the fine sweep (sum init, m steps, finish, records), replayed
+    // on a library stream ordered against the caller's stream by events
+    bool graphs = true;
+    hipStream_t gstream = nullptr;
+    hipEvent_t gin = nullptr, gout = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<char> gkey;
+    int64_t graph_builds = 0, graph_launches = 0;
 };
 
 namespace {
@@ -131,6 +141,8 @@ mcpr_status check_problem(mcpr_ctx *ctx, const mcpr_problem &p, int idx) {
             return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: splits must increase", idx);
     }
     if (p.coarse_substeps < 1) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: coarse_substeps < 1", idx);
+    if (p.coarse_model < MCPR_COARSE_TAYLOR || p.coarse_model > MCPR_COARSE_GAUSS3)
+        return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: coarse_model %d", idx, p.coarse_model);
     if (p.p0_kind < 0 || p.p0_kind > 2) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: p0_kind", idx);
     const double *c = &p.coef.a0;
     for (int i = 0; i < 10; ++i)
@@ -250,14 +262,20 @@ mcpr::Splits splits_of(const mcpr_problem &p) {
 // Restriction records of the ensembles in the tables.  shift: per-item shift of
 // the first pass (NULL: x[0]).  Two passes when the ensemble is split into
 // regions, so that each region's sums are taken about that region's mean.
-mcpr_status records(mcpr_ctx *ctx, const Tables &t, int prec, int nreg, const mcpr::Splits &sp, const double *shift,
-                    bool two_pass, int mode, const RegionMap *maps, RegionStats *out, hipStream_t s) {
+mcpr_status ensure_records(mcpr_ctx *ctx, const Tables &t, int nreg) {
     const int nr = nreg + 1, n = (int)t.items.size();
     mcpr_status st;
     if ((st = ensure(ctx, ctx->rpart, (size_t)t.total_sc * nr * sizeof(RegionPartial))) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->rshift[0], (size_t)n * nr * sizeof(double))) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->rshift[1], (size_t)n * nr * sizeof(double))) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->recs, (size_t)n * nr * sizeof(RegionStats))) != MCPR_OK) return st;
+    return MCPR_OK;
+}
+
+mcpr_status enqueue_records(mcpr_ctx *ctx, const Tables &t, int prec, int nreg, const mcpr::Splits &sp,
+                            const double *shift, bool two_pass, int mode, const RegionMap *maps, RegionStats *out,
+                            hipStream_t s) {
+    const int nr = nreg + 1, n = (int)t.items.size();
     const WorkItem *items = (const WorkItem *)ctx->items.p;
     const int2 *blocks = (const int2 *)ctx->blocks.p;
     const int nb = (int)t.blocks.size();
@@ -275,7 +293,56 @@ mcpr_status records(mcpr_ctx *ctx, const Tables &t, int prec, int nreg, const mc
     return MCPR_OK;
 }
 
-// The step sequence of the fine propagator on already uploaded tables.
+mcpr_status records(mcpr_ctx *ctx, const Tables &t, int prec, int nreg, const mcpr::Splits &sp, const double *shift,
+                    bool two_pass, int mode, const RegionMap *maps, RegionStats *out, hipStream_t s) {
+    mcpr_status st = ensure_records(ctx, t, nreg);
+    if (st != MCPR_OK) return st;
+    return enqueue_records(ctx, t, prec, nreg, sp, shift, two_pass, mode, maps, out, s);
+}
+
+// The step sequence of the fine propagator on already uploaded tables:
+// step-0 sums, m Euler-Maruyama launches, the final moments (if traced) and
+// the restriction records (if wanted), into ctx-owned buffers.
+mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int m, int nreg, const mcpr::Splits &sp,
+                         bool want_stats, bool want_trace, hipStream_t s, bool profile) {
+    const int n = (int)t.items.size();
+    const WorkItem *items = (const WorkItem *)ctx->items.p;
+    const int2 *blocks = (const int2 *)ctx->blocks.p;
+    const int nb = (int)t.blocks.size();
+    double2 *part[2] = {(double2 *)ctx->part[0].p, (double2 *)ctx->part[1].p};
+    double *shift[2] = {(double *)ctx->shift[0].p, (double *)ctx->shift[1].p};
+    double2 *trace = want_trace ? (double2 *)ctx->trace.p : nullptr;
+    HIP_TRY(mcpr::launch_sum_init(prec, items, blocks, nb, part[0], shift[0], s));
+    if (profile) HIP_TRY(hipEventRecord(ctx->prof0[ctx->prof_used], s));
+    for (int j = 0; j < m; ++j) {
+        const int a = j & 1, b = a ^ 1;
+        HIP_TRY(mcpr::launch_em_step(prec, deg, items, blocks, nb, j, part[a], shift[a], part[b], shift[b], trace, m, s));
+    }
+    if (profile) HIP_TRY(hipEventRecord(ctx->prof1[ctx->prof_used], s));
+    if (trace) HIP_TRY(mcpr::launch_finish(items, n, part[m & 1], shift[m & 1], trace, m, s));
+    if (want_stats) {
+        // shift of the record sums: the mean the last step used
+        return enqueue_records(ctx, t, prec, nreg, sp, shift[m & 1], nreg > 1, 0, nullptr,
+                               (RegionStats *)ctx->recs.p, s);
+    }
+    return MCPR_OK;
+}
+
+// Everything a captured fine sweep depends on besides the device tables.
+std::vector<char> graph_key(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int m, int nreg,
+                            const mcpr::Splits &sp, bool want_stats, bool want_trace) {
+    const void *ptrs[] = {ctx->items.p, ctx->blocks.p, ctx->part[0].p, ctx->part[1].p, ctx->shift[0].p,
+                          ctx->shift[1].p, ctx->rpart.p, ctx->rshift[0].p, ctx->rshift[1].p, ctx->recs.p,
+                          ctx->trace.p};
+    const int64_t ints[] = {(int64_t)t.items.size(), (int64_t)t.blocks.size(), t.total_sc, prec, deg, m, nreg,
+                            want_stats, want_trace};
+    std::vector<char> k(sizeof ptrs + sizeof ints + sizeof sp);
+    std::memcpy(k.data(), ptrs, sizeof ptrs);
+    std::memcpy(k.data() + sizeof ptrs, ints, sizeof ints);
+    std::memcpy(k.data() + sizeof ptrs + sizeof ints, &sp, sizeof sp);
+    return k;
+}
+
 mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int nreg, const mcpr::Splits &sp,
                           RegionStats *stats, double2 *trace, hipStream_t s) {
     const int n = (int)t.items.size();
@@ -284,47 +351,69 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
         if ((st = ensure(ctx, ctx->part[b], (size_t)t.total_sc * sizeof(double2))) != MCPR_OK) return st;
         if ((st = ensure(ctx, ctx->shift[b], (size_t)n * sizeof(double))) != MCPR_OK) return st;
     }
-    const WorkItem *items = (const WorkItem *)ctx->items.p;
-    const int2 *blocks = (const int2 *)ctx->blocks.p;
-    const int nb = (int)t.blocks.size();
-    double2 *part[2] = {(double2 *)ctx->part[0].p, (double2 *)ctx->part[1].p};
-    double *shift[2] = {(double *)ctx->shift[0].p, (double *)ctx->shift[1].p};
-    HIP_TRY(mcpr::launch_sum_init(prec, items, blocks, nb, part[0], shift[0], s));
+    if (stats && (st = ensure_records(ctx, t, nreg)) != MCPR_OK) return st;
+    if (trace && (st = ensure(ctx, ctx->trace, (size_t)n * (m + 1) * sizeof(double2))) != MCPR_OK) return st;
+    int deg = 1;
+    int64_t ps = 0;
+    for (const WorkItem &w : t.items) {
+        if (w.c[2] != 0.0 || w.c[3] != 0.0) deg = 3;
+        ps += w.P;
+    }
     if (ctx->profile) {
-        while ((int)ctx->prof0.size() < m) {
+        if (ctx->prof_used == ctx->prof0.size()) {
             hipEvent_t e0, e1;
             HIP_TRY(hipEventCreate(&e0));
             HIP_TRY(hipEventCreate(&e1));
             ctx->prof0.push_back(e0);
             ctx->prof1.push_back(e1);
+            ctx->prof_ps.push_back(0);
         }
-    }
-    int deg = 1;
-    for (const WorkItem &w : t.items)
-        if (w.c[2] != 0.0 || w.c[3] != 0.0) deg = 3;
-    for (int j = 0; j < m; ++j) {
-        const int a = j & 1, b = a ^ 1;
-        if (ctx->profile) HIP_TRY(hipEventRecord(ctx->prof0[j], s));
-        HIP_TRY(mcpr::launch_em_step(prec, deg, items, blocks, nb, j, part[a], shift[a], part[b], shift[b], trace, m, s));
-        if (ctx->profile) HIP_TRY(hipEventRecord(ctx->prof1[j], s));
-    }
-    if (trace) HIP_TRY(mcpr::launch_finish(items, n, part[m & 1], shift[m & 1], trace, m, s));
-    if (ctx->profile) {
-        HIP_TRY(hipEventSynchronize(ctx->prof1[m - 1]));
-        for (int j = 0; j < m; ++j) {
-            float ms = 0.0f;
-            HIP_TRY(hipEventElapsedTime(&ms, ctx->prof0[j], ctx->prof1[j]));
-            ctx->prof_ms += ms;
-        }
+        ctx->prof_ps[ctx->prof_used] = ps * m;
         ctx->prof_launches += m;
-        int64_t ps = 0;
-        for (const WorkItem &w : t.items) ps += w.P;
-        ctx->prof_particle_steps += ps * m;
+        if ((st = enqueue_fine(ctx, t, prec, deg, m, nreg, sp, stats != nullptr, trace != nullptr, s, true)) != MCPR_OK)
+            return st;
+        ctx->prof_used++;
+    } else if (ctx->graphs) {
+        std::vector<char> key = graph_key(ctx, t, prec, deg, m, nreg, sp, stats != nullptr, trace != nullptr);
+        if (!ctx->gexec || key != ctx->gkey) {
+            if (ctx->gexec) {
+                HIP_TRY(hipStreamSynchronize(ctx->gstream));
+                HIP_TRY(hipGraphExecDestroy(ctx->gexec));
+                ctx->gexec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
+            st = enqueue_fine(ctx, t, prec, deg, m, nreg, sp, stats != nullptr, trace != nullptr, ctx->gstream, false);
+            hipError_t ec = hipStreamEndCapture(ctx->gstream, &g);
+            if (st != MCPR_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (ec != hipSuccess) return fail(ctx, MCPR_E_DEVICE, "graph capture: %s", hipGetErrorString(ec));
+            hipError_t ei = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ei != hipSuccess) {
+                ctx->gexec = nullptr;
+                return fail(ctx, MCPR_E_DEVICE, "graph instantiate: %s", hipGetErrorString(ei));
+            }
+            ctx->gkey = key;
+            ctx->graph_builds++;
+        }
+        HIP_TRY(hipEventRecord(ctx->gin, s));
+        HIP_TRY(hipStreamWaitEvent(ctx->gstream, ctx->gin, 0));
+        HIP_TRY(hipGraphLaunch(ctx->gexec, ctx->gstream));
+        HIP_TRY(hipEventRecord(ctx->gout, ctx->gstream));
+        HIP_TRY(hipStreamWaitEvent(s, ctx->gout, 0));
+        ctx->graph_launches++;
+    } else {
+        if ((st = enqueue_fine(ctx, t, prec, deg, m, nreg, sp, stats != nullptr, trace != nullptr, s, false)) != MCPR_OK)
+            return st;
     }
-    if (stats) {
-        // shift of the record sums: the mean the last step used
-        return records(ctx, t, prec, nreg, sp, shift[m & 1], nreg > 1, 0, nullptr, stats, s);
-    }
+    if (stats)
+        HIP_TRY(hipMemcpyAsync(stats, ctx->recs.p, (size_t)n * (nreg + 1) * sizeof(RegionStats),
+                               hipMemcpyDeviceToDevice, s));
+    if (trace)
+        HIP_TRY(hipMemcpyAsync(trace, ctx->trace.p, (size_t)n * (m + 1) * sizeof(double2), hipMemcpyDeviceToDevice, s));
     return MCPR_OK;
 }
 
@@ -346,8 +435,11 @@ mcpr_status mcpr_create(mcpr_ctx **out, int32_t device) {
     if (hipSetDevice(device) != hipSuccess) return MCPR_E_DEVICE;
     mcpr_ctx *ctx = new mcpr_ctx();
     ctx->device = device;
-    if (hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming) != hipSuccess) {
-        delete ctx;
+    if (hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->gin, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->gout, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking) != hipSuccess) {
+        mcpr_destroy(ctx);
         return MCPR_E_DEVICE;
     }
     *out = ctx;
@@ -361,13 +453,18 @@ void mcpr_destroy(mcpr_ctx *ctx) {
     DevBuf *bufs[] = {&ctx->items,       &ctx->blocks,      &ctx->part[0],     &ctx->part[1],     &ctx->shift[0],
                       &ctx->shift[1],      &ctx->rpart,       &ctx->rshift[0],   &ctx->rshift[1],   &ctx->maps,
                       &ctx->recs,          &ctx->adj_ckpt,    &ctx->adj_traj,    &ctx->adj_lam[0],  &ctx->adj_lam[1],
-                      &ctx->adj_part[0],   &ctx->adj_part[1], &ctx->adj_acc,     &ctx->adj_trace,   &ctx->adj_grad};
+                      &ctx->adj_part[0],   &ctx->adj_part[1], &ctx->adj_acc,     &ctx->adj_trace,   &ctx->adj_grad,
+                      &ctx->trace};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->staging.p) (void)hipHostFree(ctx->staging.p);
     if (ctx->staged) (void)hipEventDestroy(ctx->staged);
     for (hipEvent_t e : ctx->prof0) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->prof1) (void)hipEventDestroy(e);
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->gin) (void)hipEventDestroy(ctx->gin);
+    if (ctx->gout) (void)hipEventDestroy(ctx->gout);
+    if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
     delete ctx;
 }
 
@@ -383,14 +480,36 @@ mcpr_status mcpr_profile_enable(mcpr_ctx *ctx, int32_t on) {
 mcpr_status mcpr_profile_read(mcpr_ctx *ctx, double *em_ms, int64_t *em_launches, int64_t *particle_steps,
                               int32_t reset) {
     if (!ctx) return MCPR_E_INVALID_ARG;
-    if (em_ms) *em_ms = ctx->prof_ms;
-    if (em_launches) *em_launches = ctx->prof_launches;
-    if (particle_steps) *particle_steps = ctx->prof_particle_steps;
-    if (reset) {
-        ctx->prof_ms = 0.0;
-        ctx->prof_launches = 0;
-        ctx->prof_particle_steps = 0;
+    HIP_TRY(hipSetDevice(ctx->device));
+    double ms_total = 0.0;
+    int64_t ps = 0;
+    for (size_t i = 0; i < ctx->prof_used; ++i) {
+        HIP_TRY(hipEventSynchronize(ctx->prof1[i]));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, ctx->prof0[i], ctx->prof1[i]));
+        ms_total += ms;
+        ps += ctx->prof_ps[i];
     }
+    if (em_ms) *em_ms = ms_total;
+    if (em_launches) *em_launches = ctx->prof_launches;
+    if (particle_steps) *particle_steps = ps;
+    if (reset) {
+        ctx->prof_used = 0;
+        ctx->prof_launches = 0;
+    }
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_set_graphs(mcpr_ctx *ctx, int32_t on) {
+    if (!ctx) return MCPR_E_INVALID_ARG;
+    ctx->graphs = on != 0;
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_graph_stats(const mcpr_ctx *ctx, int64_t *builds, int64_t *launches) {
+    if (!ctx) return MCPR_E_INVALID_ARG;
+    if (builds) *builds = ctx->graph_builds;
+    if (launches) *launches = ctx->graph_launches;
     return MCPR_OK;
 }
 
@@ -603,9 +722,58 @@ void mixture(int I, const Macro &r, double &mbar, double &vbar) {
     vbar = v;
 }
 
-void moment_rhs(const mcpr_coef &c, int I, const Macro &r, Macro &d) {
+double drift_at(const mcpr_coef &c, double x, double mbar, double vbar) {
+    return c.a0 + x * (c.a1 + x * (c.a2 + x * c.a3)) + c.am * mbar + c.av * vbar;
+}
+
+double diffusion_at(const mcpr_coef &c, double x, double mbar, double vbar) {
+    return c.b0 + c.b1 * x + c.bm * mbar + c.bv * vbar;
+}
+
+// Gaussian assumed-density model: dM = E[a], dV = 2 E[(x - M) a] + E[b^2] over
+// N(M, V) by Gauss-Hermite sigma points (2: M +- sqrt V, weights 1/2;
+// 3: M, M +- sqrt(3V), weights 2/3, 1/6, 1/6); V < 0 places them as for V = 0.
+void gaussian_rhs(const mcpr_coef &c, int npts, double M, double V, double mbar, double vbar, double &dM,
+                  double &dV) {
+    const double Vp = V > 0.0 ? V : 0.0;
+    double xs[3], ws[3];
+    int K;
+    if (npts == 2) {
+        K = 2;
+        xs[0] = M - std::sqrt(Vp);
+        xs[1] = M + std::sqrt(Vp);
+        ws[0] = ws[1] = 0.5;
+    } else {
+        K = 3;
+        const double h = std::sqrt(3.0 * Vp);
+        xs[0] = M - h;
+        xs[1] = M;
+        xs[2] = M + h;
+        ws[0] = 1.0 / 6.0;
+        ws[1] = 2.0 / 3.0;
+        ws[2] = 1.0 / 6.0;
+    }
+    double ea = 0.0, exa = 0.0, eb2 = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double a = drift_at(c, xs[k], mbar, vbar), b = diffusion_at(c, xs[k], mbar, vbar);
+        ea += ws[k] * a;
+        exa += ws[k] * (xs[k] - M) * a;
+        eb2 += ws[k] * b * b;
+    }
+    dM = ea;
+    dV = 2.0 * exa + eb2;
+}
+
+void moment_rhs(const mcpr_coef &c, int model, int I, const Macro &r, Macro &d) {
     double mbar, vbar;
     mixture(I, r, mbar, vbar);
+    if (model != MCPR_COARSE_TAYLOR) {
+        for (int i = 0; i < I; ++i) {
+            gaussian_rhs(c, model == MCPR_COARSE_GAUSS2 ? 2 : 3, r.M[i], r.V[i], mbar, vbar, d.M[i], d.V[i]);
+            d.f[i] = 0.0;
+        }
+        return;
+    }
     for (int i = 0; i < I; ++i) {
         const double x = r.M[i];
         const double a = c.a0 + x * (c.a1 + x * (c.a2 + x * c.a3)) + c.am * mbar + c.av * vbar;
@@ -624,14 +792,14 @@ Macro coarse_step(const mcpr_problem &p, const Macro &in) {
     const double h = (p.dt * p.steps_per_slice) / p.coarse_substeps;
     Macro y = in, k1, k2, k3, k4, tmp;
     for (int s = 0; s < p.coarse_substeps; ++s) {
-        moment_rhs(p.coef, I, y, k1);
+        moment_rhs(p.coef, p.coarse_model, I, y, k1);
         tmp = y;
         for (int i = 0; i < I; ++i) { tmp.M[i] = y.M[i] + 0.5 * h * k1.M[i]; tmp.V[i] = y.V[i] + 0.5 * h * k1.V[i]; }
-        moment_rhs(p.coef, I, tmp, k2);
+        moment_rhs(p.coef, p.coarse_model, I, tmp, k2);
         for (int i = 0; i < I; ++i) { tmp.M[i] = y.M[i] + 0.5 * h * k2.M[i]; tmp.V[i] = y.V[i] + 0.5 * h * k2.V[i]; }
-        moment_rhs(p.coef, I, tmp, k3);
+        moment_rhs(p.coef, p.coarse_model, I, tmp, k3);
         for (int i = 0; i < I; ++i) { tmp.M[i] = y.M[i] + h * k3.M[i]; tmp.V[i] = y.V[i] + h * k3.V[i]; }
-        moment_rhs(p.coef, I, tmp, k4);
+        moment_rhs(p.coef, p.coarse_model, I, tmp, k4);
         for (int i = 0; i < I; ++i) {
             y.M[i] += (h / 6.0) * (k1.M[i] + 2.0 * k2.M[i] + 2.0 * k3.M[i] + k4.M[i]);
             y.V[i] += (h / 6.0) * (k1.V[i] + 2.0 * k2.V[i] + 2.0 * k3.V[i] + k4.V[i]);
@@ -872,7 +1040,7 @@ mcpr_status mcpr_parareal_init(mcpr_parareal *pr, int32_t sample_u0, mcpr_stream
                 RegionMap mp{0.0, 0.0, 0.0, MCPR_MAP_KEEP, n};
                 const RegionStats &src = in.st0[r];
                 const double mu = in.rho[n].M[r], sig = in.rho[n].V[r];
-                if (src.n > 0 && sig >= 0.0) {
+                if (src.n > 0 && sig >= 0.0 && std::isfinite(sig) && std::isfinite(mu)) {
                     if (src.min == src.max) {
                         mp.mode = MCPR_MAP_RESAMPLE;
                         mp.scale = std::sqrt(sig);
@@ -1001,7 +1169,7 @@ mcpr_status mcpr_parareal_iterate(mcpr_parareal *pr, double *delta_out, mcpr_str
                 }
                 const double alM = (a.M[r] - c.M[r]) + b[r].mean;
                 const double alV = (a.V[r] - c.V[r]) + b[r].var;
-                if (!(alV >= 0.0)) {
+                if (!(alV >= 0.0) || !std::isfinite(alV) || !std::isfinite(alM)) {
                     o.f[r] = fr; o.M[r] = b[r].mean; o.V[r] = b[r].var;
                     fl[r] = 2;
                     continue;

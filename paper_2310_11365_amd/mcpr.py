@@ -39,7 +39,8 @@ class ProblemC(ctypes.Structure):
                 ("p0_mu2", ctypes.c_double), ("p0_sd2", ctypes.c_double), ("dt", ctypes.c_double),
                 ("steps_per_slice", ctypes.c_int32), ("n_slices", ctypes.c_int32),
                 ("n_regions", ctypes.c_int32), ("coarse_substeps", ctypes.c_int32),
-                ("split", ctypes.c_double * (MAX_REGIONS - 1)), ("seed", ctypes.c_uint64)]
+                ("split", ctypes.c_double * (MAX_REGIONS - 1)), ("seed", ctypes.c_uint64),
+                ("coarse_model", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 
 
 class EnsembleC(ctypes.Structure):
@@ -91,6 +92,10 @@ def lib() -> ctypes.CDLL:
         L.mcpr_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_int64), i32]
         L.mcpr_profile_read.restype = st
+        L.mcpr_set_graphs.argtypes = [vp, i32]
+        L.mcpr_set_graphs.restype = st
+        L.mcpr_graph_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.mcpr_graph_stats.restype = st
         L.mcpr_adjoint.argtypes = [vp, pP, pE, vp, vp, vp, vp]
         L.mcpr_adjoint.restype = st
         L.mcpr_parareal_create.argtypes = [vp, pP, i32, ctypes.POINTER(InstanceC), i32, i32, ctypes.c_double,
@@ -132,6 +137,7 @@ def problem_c(problem, coef=None) -> ProblemC:
     for i, v in enumerate(problem.splits):
         s.split[i] = float(v)
     s.seed = int(problem.seed)
+    s.coarse_model = int(getattr(problem, "coarse_model", 0))
     return s
 
 
@@ -197,6 +203,14 @@ class Context:
         self._check(lib().mcpr_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(ps),
                                             1 if reset else 0))
         return ms.value, n.value, ps.value
+
+    def set_graphs(self, on: bool):
+        self._check(lib().mcpr_set_graphs(self._h, 1 if on else 0))
+
+    def graph_stats(self):
+        b, n = ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().mcpr_graph_stats(self._h, ctypes.byref(b), ctypes.byref(n)))
+        return b.value, n.value
 
     def init_particles(self, problems: Sequence[ProblemC], ensembles: Sequence[EnsembleC], stream=None):
         P, E = self._arrays(problems, ensembles)

@@ -26,6 +26,10 @@ import numpy as np
 FP64 = 0
 FP32 = 1  # particle state in fp32, every reduction and the matching in fp64
 
+COARSE_TAYLOR = 0
+COARSE_GAUSS2 = 1
+COARSE_GAUSS3 = 2
+
 P0_NORMAL = 0
 P0_MIXTURE = 1
 P0_DELTA = 2
@@ -72,6 +76,7 @@ class Problem:
     seed: int = 0
     coarse_substeps: int = 1
     precision: int = FP64
+    coarse_model: int = 0  # 0 Taylor (eq. moment_model_class_1), 1/2 Gaussian with 2/3 sigma points
 
     @property
     def n_regions(self) -> int:
@@ -171,7 +176,11 @@ def adjoint_case(kind: str = "ou", P: int = 100_000, precision: int = FP32) -> W
 def dz_large(P: int = 16_000_000, N: int = 256, T: float = 10.0, dt: float = 5e-4,
              tol: float = 1e-4, seed: int = 0) -> Workload:
     """Large bimodal DZ with the fraction-learning extension: P = 1.6e7, N = 256,
-    T = 10, dt = 5e-4 (79 steps per slice), fp32 state, tolerance 1e-4."""
+    T = 10, dt = 5e-4 (79 steps per slice), fp32 state, tolerance 1e-4.  The
+    coarse propagator is the Gaussian model with three sigma points: the
+    second-order Taylor model has no equilibrium for this drift and its
+    trajectory diverges before T = 10."""
     pr = make_problem(dz_coef(), P0(P0_MIXTURE, 0.5, -1.0, 0.1, 1.0, 0.1), T, N, dt, (0.0,), seed,
                       0.05, FP32)
+    pr.coarse_model = COARSE_GAUSS3
     return Workload("dz_large", pr, P, max_iter=N, tol=tol, learning=True)

@@ -300,9 +300,13 @@ def test_parareal_ou_fp64_matches_oracle(mc, ctx, oracle):
     _compare_parareal(mc, ctx, oracle, W.ou_linear(P=10_000, precision=W.FP64), 10, TOL64)
 
 
-def test_parareal_bimodal_fp64_matches_oracle(mc, ctx, oracle):
-    """Two regions, per-region coarse model, matching and in-region checks."""
-    _compare_parareal(mc, ctx, oracle, W.dz_bimodal(P=20_000, N=8, T=2.0, precision=W.FP64), 8, TOL64)
+@pytest.mark.parametrize("model", [W.COARSE_TAYLOR, W.COARSE_GAUSS2, W.COARSE_GAUSS3])
+def test_parareal_bimodal_fp64_matches_oracle(mc, ctx, oracle, model):
+    """Two regions, per-region coarse model (Taylor or Gaussian sigma points),
+    matching and in-region checks."""
+    wl = W.dz_bimodal(P=20_000, N=8, T=2.0, precision=W.FP64)
+    wl.problem.coarse_model = model
+    _compare_parareal(mc, ctx, oracle, wl, 8, TOL64)
 
 
 def test_parareal_exactness_fp32_bitwise(mc, ctx):
@@ -504,3 +508,88 @@ def test_adjoint_autograd_function(mc, ctx):
     dl = 2 * (mom.detach().numpy() - target.numpy())
     _, g = mc.adjoint(ctx, mc.problem_c(pr), x, dl)
     np.testing.assert_allclose(coef.grad.numpy(), g, rtol=0, atol=0)
+
+
+# ---------------------------------------------------------------------------- learning, batching
+def test_parareal_learning_fp64_matches_oracle(mc, ctx, oracle):
+    """Fraction-model learning (Sec. 3.6): asymmetric double well whose
+    particle fractions relax, fp64, every iteration against the oracle."""
+    coef = W.dz_coef(sigma=0.8)
+    pr = W.make_problem(coef, W.P0(W.P0_MIXTURE, 0.8, -1.0, 0.2, 1.0, 0.2), 4.0, 8, 2e-3, (0.0,),
+                        precision=W.FP64, seed=5)
+    P = 20_000
+    para = mc.Parareal([pr], [P], ctx, learning=True)
+    para.init()
+    ores = oracle.parareal(pr, oracle.sample_p0(pr, P), 8, learning=True)
+    assert ores["iterations"] == 8
+    for k in range(8):
+        para.iterate()
+        rho, glob = para.macro(0)
+        og = ores["glob"][k + 1]
+        err_m = np.max(np.abs(glob[:, 0] - og[:, 0]) / (np.abs(og[:, 0]) + np.sqrt(og[:, 1])))
+        err_v = np.max(np.abs(glob[:, 1] - og[:, 1]) / og[:, 1])
+        err_f = np.max(np.abs(rho[:, :, 0] - ores["rho"][k + 1][:, :, 0]))
+        print(f"learning k={k + 1}: mean {err_m:.2e} var {err_v:.2e} fractions {err_f:.2e}")
+        assert err_m <= TOL64 and err_v <= TOL64 and err_f <= TOL64
+        np.testing.assert_array_equal(para.flags(0), ores["flags"][k])
+    # the model really extrapolates: fractions of not-yet-exact slices differ from the
+    # fine fractions' frozen value after the first fit
+    assert np.any(np.abs(ores["rho"][2][3:, 0, 0] - ores["rho"][1][3:, 0, 0]) > 1e-6)
+
+
+def test_parareal_batched_instances_fp64(mc, ctx, oracle):
+    """Several independent instances (different P, drift and noise) in one
+    driver: every step launch covers all their active slices; each instance
+    matches its own oracle run."""
+    base = W.ou_batched(n_inst=4, N=6, precision=W.FP64)
+    pr = base.problem
+    sizes = [3001, 10_007, 20_000, 517]
+    coefs = [W.ou_coef(0.3 + 0.2 * i, 0.25 + 0.1 * i) for i in range(4)]
+    para = mc.Parareal([pr], sizes, ctx, coefs=coefs, instances=[10, 11, 12, 13])
+    para.init()
+    refs = [oracle.parareal(pr, oracle.sample_p0(pr, P, inst=10 + i, coef=coefs[i]), 6, inst=10 + i, coef=coefs[i])
+            for i, P in enumerate(sizes)]
+    for k in range(6):
+        para.iterate()
+        for i in range(4):
+            rho, glob = para.macro(i)
+            og = refs[i]["glob"][k + 1]
+            err = np.max(np.abs(glob - og) / np.maximum(np.abs(og), 1e-300))
+            assert err <= TOL64, (k, i, err)
+            np.testing.assert_array_equal(para.flags(i), refs[i]["flags"][k])
+
+
+# ---------------------------------------------------------------------------- graphs
+def test_graph_replays_match_direct_launches(mc, ctx):
+    """The captured fine sweep, replayed several times with eager work and
+    synchronisations in between, gives bit for bit what direct launches give."""
+    import torch
+    wl = W.dz_bimodal(P=200_003, N=4)
+    pr = wl.problem
+    pc = mc.problem_c(pr)
+    g = mc.Context(0)
+    g.set_graphs(True)
+    d = mc.Context(0)
+    d.set_graphs(False)
+    xs_g = [torch.empty(wl.P, dtype=torch.float32, device="cuda") for _ in range(3)]
+    xs_d = [torch.empty(wl.P, dtype=torch.float32, device="cuda") for _ in range(3)]
+    for i in range(3):
+        g.init_particles([pc], [mc.ensemble(xs_g[i], i)])
+        d.init_particles([pc], [mc.ensemble(xs_d[i], i)])
+    b0 = g.graph_stats()
+    for rep in range(4):
+        sg = mc.stats_buffer(3, 2)
+        sd = mc.stats_buffer(3, 2)
+        tg = torch.empty(3 * (pr.steps_per_slice + 1) * 2, dtype=torch.float64, device="cuda")
+        td = torch.empty_like(tg)
+        g.fine_propagate([pc], [mc.ensemble(x, i, rep) for i, x in enumerate(xs_g)], sg, tg)
+        d.fine_propagate([pc], [mc.ensemble(x, i, rep) for i, x in enumerate(xs_d)], sd, td)
+        torch.cuda.synchronize()
+        _ = (xs_g[0] * 2.0).sum().item()  # eager work between replays
+        for i in range(3):
+            assert torch.equal(xs_g[i], xs_d[i]), (rep, i)
+        assert torch.equal(sg, sd) and torch.equal(tg, td)
+    b1 = g.graph_stats()
+    assert b1[1] - b0[1] == 4 and b1[0] - b0[0] == 1  # one capture, four replays
+    g.close()
+    d.close()

@@ -299,6 +299,66 @@ def test_coarse_multimodal_equivalent_for_linear(oracle):
     assert abs(M2 - y1[0]) < 1e-11 and abs(V2 - y1[1]) < 1e-11
 
 
+@pytest.mark.parametrize("model", [W.COARSE_GAUSS2, W.COARSE_GAUSS3])
+def test_gaussian_model_equals_taylor_for_linear(oracle, model):
+    """For linear coefficients every Gaussian closure is exact and equals the
+    Taylor model (Lemma on exactness for linear SDEs)."""
+    coef = W.Coef(a0=0.3, a1=-0.8, am=0.4, av=0.1, b0=0.2, b1=0.3, bm=0.1, bv=0.05)
+    pt = W.make_problem(coef, W.P0(), 0.5, 1, 1e-3, (0.0,), coarse_h=0.01)
+    pg = W.make_problem(coef, W.P0(), 0.5, 1, 1e-3, (0.0,), coarse_h=0.01)
+    pg.coarse_model = model
+    f = np.array([0.35, 0.65])
+    y = np.array([-0.7, 0.05, 1.1, 0.02])
+    np.testing.assert_allclose(oracle.coarse(pg, f, y), oracle.coarse(pt, f, y), rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("model,c4", [(W.COARSE_GAUSS2, 1.0), (W.COARSE_GAUSS3, 3.0)])
+def test_gaussian_model_closed_form_cubic(oracle, model, c4):
+    """Cubic drift, affine diffusion, x ~ N(M, V):
+    E[a] = a0 + a1 M + a2 (M^2 + V) + a3 (M^3 + 3 M V) + am mbar + av vbar,
+    E[(x - M) a] = a1 V + 2 a2 M V + a3 (3 M^2 V + c4 V^2),
+    E[b^2] = (b0 + b1 M + bm mbar + bv vbar)^2 + b1^2 V,
+    with c4 = 3 (exact Gaussian fourth moment, three sigma points) or
+    c4 = 1 (two sigma points M +- sqrt(V))."""
+    c = W.Coef(a0=0.1, a1=0.5, a2=-0.2, a3=-1.0, am=0.5, av=0.3, b0=0.4, b1=0.1, bm=-0.05, bv=0.2)
+    pr = W.make_problem(c, W.P0(), 0.1, 1, 1e-3, (0.0,), coarse_h=1e-4)
+    pr.coarse_model = model
+    f = np.array([0.3, 0.7])
+    y0 = np.array([-1.0, 0.02, 0.9, 0.05])
+
+    def rhs(t, u):
+        M, V = u[0::2], u[1::2]
+        mbar = f @ M
+        vbar = f @ (V + (M - mbar) ** 2)
+        out = []
+        for i in range(2):
+            m, v = M[i], V[i]
+            ea = c.a0 + c.a1 * m + c.a2 * (m * m + v) + c.a3 * (m ** 3 + 3 * m * v) + c.am * mbar + c.av * vbar
+            exa = c.a1 * v + 2 * c.a2 * m * v + c.a3 * (3 * m * m * v + c4 * v * v)
+            eb2 = (c.b0 + c.b1 * m + c.bm * mbar + c.bv * vbar) ** 2 + c.b1 ** 2 * v
+            out += [ea, 2 * exa + eb2]
+        return out
+    sol = solve_ivp(rhs, (0, pr.slice_length), y0, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(oracle.coarse(pr, f, y0), sol.y[:, -1], rtol=1e-10)
+
+
+def test_gaussian_model_stable_for_large_bimodal(oracle):
+    """The large bimodal workload's coarse trajectory stays finite with the
+    three-point Gaussian model over T = 10; the Taylor model's diverges."""
+    wl = W.dz_large()
+    y = np.array([-1.0, 0.01, 1.0, 0.01])
+    f = np.array([0.5, 0.5])
+    yt = y.copy()
+    pt = W.dz_large().problem
+    pt.coarse_model = W.COARSE_TAYLOR
+    for _ in range(wl.problem.n_slices):
+        y = oracle.coarse(wl.problem, f, y)
+        with np.errstate(all="ignore"):
+            yt = oracle.coarse(pt, f, yt)
+    assert np.all(np.isfinite(y)) and np.all(y[1::2] > 0) and np.all(y[1::2] < 1)
+    assert not np.all(np.isfinite(yt)) or np.max(np.abs(yt)) > 1e3
+
+
 def test_coarse_matches_particles_for_linear(oracle):
     """The exact moment model and the particle system agree to within the MC
     error plus the O(dt) bias of EM."""
