@@ -188,7 +188,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(kernel, wl.name),
                 "kernel": kernel, "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                "bytes_per_launch": bytes_per_launch}
+                "bytes_per_launch": bytes_per_launch,
+                "step_variants_tuned": ctx.tuned_variants()}
 
     out = {"metric": "fine-propagator particle-steps/sec", "value": value, "unit": "particle-steps/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

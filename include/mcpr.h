@@ -144,6 +144,17 @@ mcpr_status mcpr_profile_read(mcpr_ctx *ctx, double *em_ms, int64_t *em_launches
  * bitwise the same as direct launches.  mcpr_graph_stats: graphs built and
  * replays so far.                                                           */
 mcpr_status mcpr_set_graphs(mcpr_ctx *ctx, int32_t on);
+
+/* Step-kernel launch variants, all giving the same bits: bit 0 non-temporal
+ * loads and stores of the state (pays off when the state does not fit the
+ * Infinity Cache), bit 1 the step's mean field formed once per ensemble by a
+ * small launch instead of by every block (pays off with many blocks per
+ * ensemble).  mode -1 (default): the first fine sweep of each launch shape
+ * (with at least 8 steps) times the four variants on its first 8 steps and
+ * keeps the fastest for that shape; 0..3 forces a variant.
+ * mcpr_tuned_variant: the variant chosen for the index-th tuned shape, or -1. */
+mcpr_status mcpr_set_tuning(mcpr_ctx *ctx, int32_t mode);
+int32_t mcpr_tuned_variant(const mcpr_ctx *ctx, int32_t index);
 mcpr_status mcpr_graph_stats(const mcpr_ctx *ctx, int64_t *builds, int64_t *launches);
 
 /* ---- hot-path calls ------------------------------------------------------ */

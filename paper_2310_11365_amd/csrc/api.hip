@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -65,6 +66,11 @@ struct mcpr_ctx {
     hipGraphExec_t gexec = nullptr;
     std::vector<char> gkey;
     int64_t graph_builds = 0, graph_launches = 0;
+    // step-kernel variant per launch shape: -1 autotune, 0..3 forced
+    int tuning = -1;
+    std::map<std::vector<char>, int> tuned;
+    hipEvent_t tune_ev[2][8] = {};
+    DevBuf mv; // per-item (mean, variance) of the separate-combine variant
 };
 
 namespace {
@@ -303,8 +309,10 @@ mcpr_status records(mcpr_ctx *ctx, const Tables &t, int prec, int nreg, const mc
 // The step sequence of the fine propagator on already uploaded tables:
 // step-0 sums, m Euler-Maruyama launches, the final moments (if traced) and
 // the restriction records (if wanted), into ctx-owned buffers.
-mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int m, int nreg, const mcpr::Splits &sp,
-                         bool want_stats, bool want_trace, hipStream_t s, bool profile) {
+// variant < 0: the first 8 steps cycle through the four variants, each launch
+// bracketed by events (the autotuner's trial; every variant gives the same bits).
+mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int variant, int m, int nreg,
+                         const mcpr::Splits &sp, bool want_stats, bool want_trace, hipStream_t s, bool profile) {
     const int n = (int)t.items.size();
     const WorkItem *items = (const WorkItem *)ctx->items.p;
     const int2 *blocks = (const int2 *)ctx->blocks.p;
@@ -314,9 +322,15 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
     double2 *trace = want_trace ? (double2 *)ctx->trace.p : nullptr;
     HIP_TRY(mcpr::launch_sum_init(prec, items, blocks, nb, part[0], shift[0], s));
     if (profile) HIP_TRY(hipEventRecord(ctx->prof0[ctx->prof_used], s));
+    double2 *mv = (double2 *)ctx->mv.p;
     for (int j = 0; j < m; ++j) {
         const int a = j & 1, b = a ^ 1;
-        HIP_TRY(mcpr::launch_em_step(prec, deg, items, blocks, nb, j, part[a], shift[a], part[b], shift[b], trace, m, s));
+        const bool trial = variant < 0 && j < 8;
+        const int v = trial ? (j & 3) : (variant < 0 ? 0 : variant);
+        if (trial) HIP_TRY(hipEventRecord(ctx->tune_ev[0][j], s));
+        HIP_TRY(mcpr::launch_em_step(prec, deg, v, items, n, blocks, nb, j, part[a], shift[a], mv, part[b], shift[b],
+                                     trace, m, s));
+        if (trial) HIP_TRY(hipEventRecord(ctx->tune_ev[1][j], s));
     }
     if (profile) HIP_TRY(hipEventRecord(ctx->prof1[ctx->prof_used], s));
     if (trace) HIP_TRY(mcpr::launch_finish(items, n, part[m & 1], shift[m & 1], trace, m, s));
@@ -329,13 +343,13 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
 }
 
 // Everything a captured fine sweep depends on besides the device tables.
-std::vector<char> graph_key(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int m, int nreg,
+std::vector<char> graph_key(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int variant, int m, int nreg,
                             const mcpr::Splits &sp, bool want_stats, bool want_trace) {
     const void *ptrs[] = {ctx->items.p, ctx->blocks.p, ctx->part[0].p, ctx->part[1].p, ctx->shift[0].p,
                           ctx->shift[1].p, ctx->rpart.p, ctx->rshift[0].p, ctx->rshift[1].p, ctx->recs.p,
-                          ctx->trace.p};
+                          ctx->trace.p,  ctx->mv.p};
     const int64_t ints[] = {(int64_t)t.items.size(), (int64_t)t.blocks.size(), t.total_sc, prec, deg, m, nreg,
-                            want_stats, want_trace};
+                            want_stats, want_trace, variant};
     std::vector<char> k(sizeof ptrs + sizeof ints + sizeof sp);
     std::memcpy(k.data(), ptrs, sizeof ptrs);
     std::memcpy(k.data() + sizeof ptrs, ints, sizeof ints);
@@ -353,13 +367,53 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
     }
     if (stats && (st = ensure_records(ctx, t, nreg)) != MCPR_OK) return st;
     if (trace && (st = ensure(ctx, ctx->trace, (size_t)n * (m + 1) * sizeof(double2))) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->mv, (size_t)n * sizeof(double2))) != MCPR_OK) return st;
     int deg = 1;
     int64_t ps = 0;
     for (const WorkItem &w : t.items) {
         if (w.c[2] != 0.0 || w.c[3] != 0.0) deg = 3;
         ps += w.P;
     }
-    if (ctx->profile) {
+    // step-kernel variant: forced, tuned for this launch shape, or tuned now
+    std::vector<char> tkey(6 * sizeof(int64_t));
+    {
+        const int64_t tk[6] = {prec, deg, n, (int64_t)t.blocks.size(), t.total_sc, ps};
+        std::memcpy(tkey.data(), tk, sizeof tk);
+    }
+    int variant = 0;
+    bool tune_now = false;
+    if (ctx->tuning >= 0) {
+        variant = ctx->tuning & 3;
+    } else {
+        auto it = ctx->tuned.find(tkey);
+        if (it != ctx->tuned.end()) {
+            variant = it->second;
+        } else if (m >= 8 && !ctx->profile) {
+            tune_now = true;
+        }
+    }
+    if (tune_now) {
+        if (!ctx->tune_ev[0][0])
+            for (int k = 0; k < 2; ++k)
+                for (int j = 0; j < 8; ++j) HIP_TRY(hipEventCreate(&ctx->tune_ev[k][j]));
+        if ((st = enqueue_fine(ctx, t, prec, deg, -1, m, nreg, sp, stats != nullptr, trace != nullptr, s, false)) !=
+            MCPR_OK)
+            return st;
+        HIP_TRY(hipEventSynchronize(ctx->tune_ev[1][7]));
+        float best = 0.0f;
+        int pick = 0;
+        for (int v = 0; v < 4; ++v) {
+            float t0 = 0.0f, t1 = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&t0, ctx->tune_ev[0][v], ctx->tune_ev[1][v]));
+            HIP_TRY(hipEventElapsedTime(&t1, ctx->tune_ev[0][v + 4], ctx->tune_ev[1][v + 4]));
+            const float tv = std::min(t0, t1);
+            if (v == 0 || tv < best) {
+                best = tv;
+                pick = v;
+            }
+        }
+        ctx->tuned[tkey] = pick;
+    } else if (ctx->profile) {
         if (ctx->prof_used == ctx->prof0.size()) {
             hipEvent_t e0, e1;
             HIP_TRY(hipEventCreate(&e0));
@@ -370,11 +424,12 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
         }
         ctx->prof_ps[ctx->prof_used] = ps * m;
         ctx->prof_launches += m;
-        if ((st = enqueue_fine(ctx, t, prec, deg, m, nreg, sp, stats != nullptr, trace != nullptr, s, true)) != MCPR_OK)
+        if ((st = enqueue_fine(ctx, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr, s, true)) !=
+            MCPR_OK)
             return st;
         ctx->prof_used++;
     } else if (ctx->graphs) {
-        std::vector<char> key = graph_key(ctx, t, prec, deg, m, nreg, sp, stats != nullptr, trace != nullptr);
+        std::vector<char> key = graph_key(ctx, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr);
         if (!ctx->gexec || key != ctx->gkey) {
             if (ctx->gexec) {
                 HIP_TRY(hipStreamSynchronize(ctx->gstream));
@@ -383,7 +438,8 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
             }
             hipGraph_t g = nullptr;
             HIP_TRY(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
-            st = enqueue_fine(ctx, t, prec, deg, m, nreg, sp, stats != nullptr, trace != nullptr, ctx->gstream, false);
+            st = enqueue_fine(ctx, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr, ctx->gstream,
+                              false);
             hipError_t ec = hipStreamEndCapture(ctx->gstream, &g);
             if (st != MCPR_OK) {
                 if (g) (void)hipGraphDestroy(g);
@@ -406,7 +462,8 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
         HIP_TRY(hipStreamWaitEvent(s, ctx->gout, 0));
         ctx->graph_launches++;
     } else {
-        if ((st = enqueue_fine(ctx, t, prec, deg, m, nreg, sp, stats != nullptr, trace != nullptr, s, false)) != MCPR_OK)
+        if ((st = enqueue_fine(ctx, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr, s, false)) !=
+            MCPR_OK)
             return st;
     }
     if (stats)
@@ -454,13 +511,16 @@ void mcpr_destroy(mcpr_ctx *ctx) {
                       &ctx->shift[1],      &ctx->rpart,       &ctx->rshift[0],   &ctx->rshift[1],   &ctx->maps,
                       &ctx->recs,          &ctx->adj_ckpt,    &ctx->adj_traj,    &ctx->adj_lam[0],  &ctx->adj_lam[1],
                       &ctx->adj_part[0],   &ctx->adj_part[1], &ctx->adj_acc,     &ctx->adj_trace,   &ctx->adj_grad,
-                      &ctx->trace};
+                      &ctx->trace,         &ctx->mv};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->staging.p) (void)hipHostFree(ctx->staging.p);
     if (ctx->staged) (void)hipEventDestroy(ctx->staged);
     for (hipEvent_t e : ctx->prof0) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->prof1) (void)hipEventDestroy(e);
+    for (int k = 0; k < 2; ++k)
+        for (int j = 0; j < 8; ++j)
+            if (ctx->tune_ev[k][j]) (void)hipEventDestroy(ctx->tune_ev[k][j]);
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->gin) (void)hipEventDestroy(ctx->gin);
     if (ctx->gout) (void)hipEventDestroy(ctx->gout);
@@ -504,6 +564,19 @@ mcpr_status mcpr_set_graphs(mcpr_ctx *ctx, int32_t on) {
     if (!ctx) return MCPR_E_INVALID_ARG;
     ctx->graphs = on != 0;
     return MCPR_OK;
+}
+
+mcpr_status mcpr_set_tuning(mcpr_ctx *ctx, int32_t mode) {
+    if (!ctx || mode < -1 || mode > 3) return MCPR_E_INVALID_ARG;
+    ctx->tuning = mode;
+    return MCPR_OK;
+}
+
+int32_t mcpr_tuned_variant(const mcpr_ctx *ctx, int32_t index) {
+    if (!ctx || index < 0) return -1;
+    for (const auto &kv : ctx->tuned)
+        if (index-- == 0) return kv.second;
+    return -1;
 }
 
 mcpr_status mcpr_graph_stats(const mcpr_ctx *ctx, int64_t *builds, int64_t *launches) {

@@ -23,12 +23,16 @@ constexpr int kQuadsPerChunk = kThreads; // quads per thread-row of a superchunk
 constexpr int kMaxRegions = 8;
 constexpr int kMaxSuperchunksTarget = 256;
 
-// Quads per thread R of a superchunk (power of two, 1..64): the smallest R
-// with at most kMaxSuperchunksTarget superchunks.
+// Quads per thread R of a superchunk (power of two, 1..16): the smallest R
+// with at most kMaxSuperchunksTarget superchunks (P <= 4.2e6); larger
+// ensembles keep R = 16 and have more superchunks (shorter blocks stream
+// HBM better than fewer long ones).
+constexpr int kMaxQuadsPerThread = 16;
 inline int canonical_quads_per_thread(int64_t P) {
     int64_t quads = (P + 3) / 4;
     int R = 1;
-    while (R < 64 && (quads + (int64_t)kThreads * R - 1) / ((int64_t)kThreads * R) > kMaxSuperchunksTarget)
+    while (R < kMaxQuadsPerThread &&
+           (quads + (int64_t)kThreads * R - 1) / ((int64_t)kThreads * R) > kMaxSuperchunksTarget)
         R *= 2;
     return R;
 }

@@ -177,25 +177,38 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) f32x4 g_f32x4;
 typedef __attribute__((address_space(1))) f64x2 g_f64x2;
 
+template <bool NT>
 __device__ __forceinline__ void gload_quad(const float *base, uint32_t q, float v[4]) {
-    const f32x4 a = ((const g_f32x4 *)(base))[q];
+    const g_f32x4 *p = ((const g_f32x4 *)(base)) + q;
+    const f32x4 a = NT ? __builtin_nontemporal_load(p) : *p;
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
+template <bool NT>
 __device__ __forceinline__ void gload_quad(const double *base, uint32_t q, double v[4]) {
-    const f64x2 a = ((const g_f64x2 *)(base))[2 * q];
-    const f64x2 b = ((const g_f64x2 *)(base))[2 * q + 1];
+    const g_f64x2 *p = ((const g_f64x2 *)(base)) + 2 * q;
+    const f64x2 a = NT ? __builtin_nontemporal_load(p) : p[0];
+    const f64x2 b = NT ? __builtin_nontemporal_load(p + 1) : p[1];
     v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
+template <bool NT>
 __device__ __forceinline__ void gstore_quad(float *base, uint32_t q, const float v[4]) {
     f32x4 a;
     a.x = v[0]; a.y = v[1]; a.z = v[2]; a.w = v[3];
-    ((g_f32x4 *)(base))[q] = a;
+    g_f32x4 *p = ((g_f32x4 *)(base)) + q;
+    if (NT) __builtin_nontemporal_store(a, p); else *p = a;
 }
+template <bool NT>
 __device__ __forceinline__ void gstore_quad(double *base, uint32_t q, const double v[4]) {
     f64x2 a, b;
     a.x = v[0]; a.y = v[1]; b.x = v[2]; b.y = v[3];
-    ((g_f64x2 *)(base))[2 * q] = a;
-    ((g_f64x2 *)(base))[2 * q + 1] = b;
+    g_f64x2 *p = ((g_f64x2 *)(base)) + 2 * q;
+    if (NT) {
+        __builtin_nontemporal_store(a, p);
+        __builtin_nontemporal_store(b, p + 1);
+    } else {
+        p[0] = a;
+        p[1] = b;
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -220,7 +233,7 @@ __global__ __launch_bounds__(kThreads) void k_sum_init(const WorkItem *__restric
     if (base + (int64_t)4 * kThreads * R <= P) {
         for (int r = 0; r < R; ++r) {
             T v[4], d[4];
-            gload_quad(xs, (uint32_t)(r * kThreads + threadIdx.x), v);
+            gload_quad<false>(xs, (uint32_t)(r * kThreads + threadIdx.x), v);
 #pragma unroll
             for (int e = 0; e < 4; ++e) d[e] = v[e] - shift;
             double q1, q2;
@@ -263,11 +276,30 @@ __device__ __forceinline__ T em_update(T xv, T z, T c0, T c1, T c2, T c3, T e0, 
     return fmaT(fmaT(e1, xv, e0), z, pol);
 }
 
-template <typename T, int DEG>
+// Mean field of step j from the previous launch's partials: one block per item
+// (the variant of the step kernel that does not combine in every block).
+__global__ __launch_bounds__(kThreads) void k_combine(const WorkItem *__restrict__ items,
+                                                      const double2 *__restrict__ part_in,
+                                                      const double *__restrict__ shift_in,
+                                                      double2 *__restrict__ mv_out) {
+    __shared__ double lds[8];
+    const WorkItem &W = items[blockIdx.x];
+    double S1, S2;
+    ensemble_sums(part_in + W.part_off, W.nsc, S1, S2, lds);
+    double mean, var;
+    finish_moments(S1, S2, shift_in[blockIdx.x], (double)W.P, mean, var);
+    if (threadIdx.x == 0) mv_out[blockIdx.x] = make_double2(mean, var);
+}
+
+// NT: non-temporal loads and stores of the state.  MV: the mean field comes
+// from k_combine (mv_in) instead of each block combining the partials itself;
+// both give the same bits (same order, same operations).
+template <typename T, int DEG, bool NT, bool MV>
 __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict__ items,
                                                       const int2 *__restrict__ blocks, int32_t j,
                                                       const double2 *__restrict__ part_in,
                                                       const double *__restrict__ shift_in,
+                                                      const double2 *__restrict__ mv_in,
                                                       double2 *__restrict__ part_out,
                                                       double *__restrict__ shift_out,
                                                       double2 *__restrict__ trace, int32_t m) {
@@ -281,10 +313,16 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
     const int R = W.R;
 
     // mean field at the start of the step
-    double S1, S2;
-    ensemble_sums(part_in + W.part_off, W.nsc, S1, S2, lds);
     double mean, var;
-    finish_moments(S1, S2, shift_in[item], (double)P, mean, var);
+    if (MV) {
+        const double2 mvv = mv_in[item];
+        mean = mvv.x;
+        var = mvv.y;
+    } else {
+        double S1, S2;
+        ensemble_sums(part_in + W.part_off, W.nsc, S1, S2, lds);
+        finish_moments(S1, S2, shift_in[item], (double)P, mean, var);
+    }
     const T shift = (T)mean; // shift of this step's output sums, a value of the state type
     if (sc == 0 && threadIdx.x == 0) {
         shift_out[item] = (double)shift;
@@ -312,7 +350,7 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
             T v[4][4];
 #pragma unroll
             for (int g = 0; g < 4; ++g)
-                if (r0 + g < R) gload_quad(xs, (uint32_t)((r0 + g) * kThreads + threadIdx.x), v[g]);
+                if (r0 + g < R) gload_quad<NT>(xs, (uint32_t)((r0 + g) * kThreads + threadIdx.x), v[g]);
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 if (r0 + g < R) {
@@ -324,7 +362,7 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
                         v[g][e] = em_update<T, DEG>(v[g][e], z[e], c0, c1, c2, c3, e0, e1);
                         d[e] = v[g][e] - shift;
                     }
-                    gstore_quad(ys, (uint32_t)((r0 + g) * kThreads + threadIdx.x), v[g]);
+                    gstore_quad<NT>(ys, (uint32_t)((r0 + g) * kThreads + threadIdx.x), v[g]);
                     double q1, q2;
                     quad_leaf(d, q1, q2);
                     a1 += q1;
@@ -815,23 +853,49 @@ hipError_t launch_sum_init(int prec, const WorkItem *items, const int2 *blocks, 
     return hipGetLastError();
 }
 
-hipError_t launch_em_step(int prec, int deg, const WorkItem *items, const int2 *blocks, int nblocks, int j,
-                          const double2 *part_in, const double *shift_in, double2 *part_out, double *shift_out,
-                          double2 *trace, int m, hipStream_t s) {
+template <typename T, int DEG>
+static void em_step_variant(int variant, const WorkItem *items, const int2 *blocks, int nblocks, int j,
+                            const double2 *part_in, const double *shift_in, const double2 *mv, double2 *part_out,
+                            double *shift_out, double2 *trace, int m, hipStream_t s) {
+    switch (variant & 3) {
+    case 0:
+        hipLaunchKernelGGL((k_em_step<T, DEG, false, false>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                           part_in, shift_in, mv, part_out, shift_out, trace, m);
+        break;
+    case 1:
+        hipLaunchKernelGGL((k_em_step<T, DEG, true, false>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                           part_in, shift_in, mv, part_out, shift_out, trace, m);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_em_step<T, DEG, false, true>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                           part_in, shift_in, mv, part_out, shift_out, trace, m);
+        break;
+    default:
+        hipLaunchKernelGGL((k_em_step<T, DEG, true, true>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                           part_in, shift_in, mv, part_out, shift_out, trace, m);
+        break;
+    }
+}
+
+hipError_t launch_em_step(int prec, int deg, int variant, const WorkItem *items, int n_items, const int2 *blocks,
+                          int nblocks, int j, const double2 *part_in, const double *shift_in, double2 *mv,
+                          double2 *part_out, double *shift_out, double2 *trace, int m, hipStream_t s) {
+    if (variant & 2)
+        hipLaunchKernelGGL(k_combine, dim3(n_items), dim3(kThreads), 0, s, items, part_in, shift_in, mv);
     if (prec == 0) {
         if (deg == 1)
-            hipLaunchKernelGGL((k_em_step<double, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j, part_in,
-                               shift_in, part_out, shift_out, trace, m);
+            em_step_variant<double, 1>(variant, items, blocks, nblocks, j, part_in, shift_in, mv, part_out, shift_out,
+                                       trace, m, s);
         else
-            hipLaunchKernelGGL((k_em_step<double, 3>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j, part_in,
-                               shift_in, part_out, shift_out, trace, m);
+            em_step_variant<double, 3>(variant, items, blocks, nblocks, j, part_in, shift_in, mv, part_out, shift_out,
+                                       trace, m, s);
     } else {
         if (deg == 1)
-            hipLaunchKernelGGL((k_em_step<float, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j, part_in,
-                               shift_in, part_out, shift_out, trace, m);
+            em_step_variant<float, 1>(variant, items, blocks, nblocks, j, part_in, shift_in, mv, part_out, shift_out,
+                                      trace, m, s);
         else
-            hipLaunchKernelGGL((k_em_step<float, 3>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j, part_in,
-                               shift_in, part_out, shift_out, trace, m);
+            em_step_variant<float, 3>(variant, items, blocks, nblocks, j, part_in, shift_in, mv, part_out, shift_out,
+                                      trace, m, s);
     }
     return hipGetLastError();
 }

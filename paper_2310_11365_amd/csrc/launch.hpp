@@ -10,10 +10,13 @@ namespace mcpr {
 // prec: 0 = fp64 particles, 1 = fp32 particles (fp64 reductions either way)
 hipError_t launch_sum_init(int prec, const WorkItem *items, const int2 *blocks, int nblocks, double2 *part_out,
                            double *shift_out, hipStream_t s);
-// deg: 1 if every ensemble of the launch has a2 = a3 = 0 (drift affine in x), else 3
-hipError_t launch_em_step(int prec, int deg, const WorkItem *items, const int2 *blocks, int nblocks, int j,
-                          const double2 *part_in, const double *shift_in, double2 *part_out, double *shift_out,
-                          double2 *trace, int m, hipStream_t s);
+// deg: 1 if every ensemble of the launch has a2 = a3 = 0 (drift affine in x), else 3.
+// variant (bitwise-equivalent launch shapes): bit 0 non-temporal state access,
+// bit 1 mean field combined by one block per item (into mv, n_items entries)
+// instead of by every block.
+hipError_t launch_em_step(int prec, int deg, int variant, const WorkItem *items, int n_items, const int2 *blocks,
+                          int nblocks, int j, const double2 *part_in, const double *shift_in, double2 *mv,
+                          double2 *part_out, double *shift_out, double2 *trace, int m, hipStream_t s);
 // trace entry m of each item: moments of its final state from the last step's partials
 hipError_t launch_finish(const WorkItem *items, int n_items, const double2 *part_in, const double *shift_in,
                          double2 *trace, int m, hipStream_t s);

@@ -94,6 +94,10 @@ def lib() -> ctypes.CDLL:
         L.mcpr_profile_read.restype = st
         L.mcpr_set_graphs.argtypes = [vp, i32]
         L.mcpr_set_graphs.restype = st
+        L.mcpr_set_tuning.argtypes = [vp, i32]
+        L.mcpr_set_tuning.restype = st
+        L.mcpr_tuned_variant.argtypes = [vp, i32]
+        L.mcpr_tuned_variant.restype = i32
         L.mcpr_graph_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.mcpr_graph_stats.restype = st
         L.mcpr_adjoint.argtypes = [vp, pP, pE, vp, vp, vp, vp]
@@ -206,6 +210,19 @@ class Context:
 
     def set_graphs(self, on: bool):
         self._check(lib().mcpr_set_graphs(self._h, 1 if on else 0))
+
+    def set_tuning(self, mode: int):
+        """-1: autotune the step-kernel variant per launch shape; 0..3: force one."""
+        self._check(lib().mcpr_set_tuning(self._h, int(mode)))
+
+    def tuned_variants(self):
+        out, i = [], 0
+        while True:
+            v = lib().mcpr_tuned_variant(self._h, i)
+            if v < 0:
+                return out
+            out.append(v)
+            i += 1
 
     def graph_stats(self):
         b, n = ctypes.c_int64(), ctypes.c_int64()

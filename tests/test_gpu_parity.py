@@ -569,8 +569,10 @@ def test_graph_replays_match_direct_launches(mc, ctx):
     pc = mc.problem_c(pr)
     g = mc.Context(0)
     g.set_graphs(True)
+    g.set_tuning(0)  # no autotuner trial sweep: the first call captures
     d = mc.Context(0)
     d.set_graphs(False)
+    d.set_tuning(0)
     xs_g = [torch.empty(wl.P, dtype=torch.float32, device="cuda") for _ in range(3)]
     xs_d = [torch.empty(wl.P, dtype=torch.float32, device="cuda") for _ in range(3)]
     for i in range(3):
@@ -593,3 +595,31 @@ def test_graph_replays_match_direct_launches(mc, ctx):
     assert b1[1] - b0[1] == 4 and b1[0] - b0[0] == 1  # one capture, four replays
     g.close()
     d.close()
+
+
+# ---------------------------------------------------------------------------- launch variants
+@pytest.mark.parametrize("P", [1_000_003, 6_000_000])
+def test_step_variants_bitwise(mc, ctx, P):
+    """The four step-kernel launch variants (non-temporal access, separate
+    mean-field combine) and the autotuned choice give identical bits."""
+    import torch
+    pr = W.dz_bimodal(P=P, N=3).problem
+    pc = mc.problem_c(pr)
+    ref = None
+    for mode in (0, 1, 2, 3, -1):
+        c = mc.Context(0)
+        c.set_tuning(mode)
+        x = torch.empty(P, dtype=torch.float32, device="cuda")
+        c.init_particles([pc], [mc.ensemble(x, 0)])
+        st = mc.stats_buffer(1, 2)
+        tr = torch.empty((pr.steps_per_slice + 1) * 2, dtype=torch.float64, device="cuda")
+        for n in range(2):
+            c.fine_propagate([pc], [mc.ensemble(x, 0, n)], st, tr)
+        got = (x.clone(), st.clone(), tr.clone())
+        if mode == -1:
+            assert len(c.tuned_variants()) == 1
+        c.close()
+        if ref is None:
+            ref = got
+        else:
+            assert all(torch.equal(a, b) for a, b in zip(ref, got)), mode
