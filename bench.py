@@ -145,7 +145,7 @@ def main():
     N, m = pr.n_slices, pr.steps_per_slice
     ps_per_step = N * m * sum(sizes)
     esize = 8 if pr.precision == W.FP64 else 4
-    kernel = "k_em_step<double>" if pr.precision == W.FP64 else "k_em_step<float>"
+    tname = "double" if pr.precision == W.FP64 else "float"
 
     if args.copy_probe > 0:
         n = args.copy_probe * (1 << 20) // 4
@@ -185,6 +185,12 @@ def main():
     avg_launch_s = em_ms / 1e3 / max(em_launches, 1)
     bytes_per_launch = 2.0 * esize * (em_ps / max(em_launches, 1))  # one read and one write of the state
     achieved = bytes_per_launch / avg_launch_s / 1e9
+    # the kernel instantiation that ran: drift degree and the autotuned launch variant
+    all_coefs = coefs if coefs else [pr.coef]
+    deg = 1 if all(c.a2 == 0.0 and c.a3 == 0.0 for c in all_coefs) else 3
+    tv = ctx.tuned_variants()
+    variant = tv[0] if tv else 0
+    kernel = f"k_em_step<{tname}, {deg}, {'true' if variant & 1 else 'false'}, {'true' if variant & 2 else 'false'}>"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(kernel, wl.name),
                 "kernel": kernel, "avg_launch_us": round(avg_launch_s * 1e6, 2),

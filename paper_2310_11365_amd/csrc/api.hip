@@ -69,7 +69,8 @@ struct mcpr_ctx {
     // step-kernel variant per launch shape: -1 autotune, 0..3 forced
     int tuning = -1;
     std::map<std::vector<char>, int> tuned;
-    hipEvent_t tune_ev[2][8] = {};
+    hipEvent_t tune_ev[2][16] = {};
+    int tune_steps = 0;
     DevBuf mv; // per-item (mean, variance) of the separate-combine variant
 };
 
@@ -325,7 +326,7 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
     double2 *mv = (double2 *)ctx->mv.p;
     for (int j = 0; j < m; ++j) {
         const int a = j & 1, b = a ^ 1;
-        const bool trial = variant < 0 && j < 8;
+        const bool trial = variant < 0 && j < ctx->tune_steps;
         const int v = trial ? (j & 3) : (variant < 0 ? 0 : variant);
         if (trial) HIP_TRY(hipEventRecord(ctx->tune_ev[0][j], s));
         HIP_TRY(mcpr::launch_em_step(prec, deg, v, items, n, blocks, nb, j, part[a], shift[a], mv, part[b], shift[b],
@@ -393,25 +394,26 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
         }
     }
     if (tune_now) {
+        // trial: steps 0..K-1 cycle through the variants (K = 16 when the sweep
+        // has 16 steps, else 8); best time of each; a variant other than the
+        // plain one must beat it by 2 %
         if (!ctx->tune_ev[0][0])
             for (int k = 0; k < 2; ++k)
-                for (int j = 0; j < 8; ++j) HIP_TRY(hipEventCreate(&ctx->tune_ev[k][j]));
+                for (int j = 0; j < 16; ++j) HIP_TRY(hipEventCreate(&ctx->tune_ev[k][j]));
+        ctx->tune_steps = m >= 16 ? 16 : 8;
         if ((st = enqueue_fine(ctx, t, prec, deg, -1, m, nreg, sp, stats != nullptr, trace != nullptr, s, false)) !=
             MCPR_OK)
             return st;
-        HIP_TRY(hipEventSynchronize(ctx->tune_ev[1][7]));
-        float best = 0.0f;
-        int pick = 0;
-        for (int v = 0; v < 4; ++v) {
-            float t0 = 0.0f, t1 = 0.0f;
-            HIP_TRY(hipEventElapsedTime(&t0, ctx->tune_ev[0][v], ctx->tune_ev[1][v]));
-            HIP_TRY(hipEventElapsedTime(&t1, ctx->tune_ev[0][v + 4], ctx->tune_ev[1][v + 4]));
-            const float tv = std::min(t0, t1);
-            if (v == 0 || tv < best) {
-                best = tv;
-                pick = v;
-            }
+        HIP_TRY(hipEventSynchronize(ctx->tune_ev[1][ctx->tune_steps - 1]));
+        float tv[4] = {0, 0, 0, 0};
+        for (int j = 0; j < ctx->tune_steps; ++j) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, ctx->tune_ev[0][j], ctx->tune_ev[1][j]));
+            if (j < 4 || ms < tv[j & 3]) tv[j & 3] = ms;
         }
+        int pick = 0;
+        for (int v = 1; v < 4; ++v)
+            if (tv[v] < 0.98f * tv[0] && tv[v] < tv[pick]) pick = v;
         ctx->tuned[tkey] = pick;
     } else if (ctx->profile) {
         if (ctx->prof_used == ctx->prof0.size()) {
@@ -519,7 +521,7 @@ void mcpr_destroy(mcpr_ctx *ctx) {
     for (hipEvent_t e : ctx->prof0) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->prof1) (void)hipEventDestroy(e);
     for (int k = 0; k < 2; ++k)
-        for (int j = 0; j < 8; ++j)
+        for (int j = 0; j < 16; ++j)
             if (ctx->tune_ev[k][j]) (void)hipEventDestroy(ctx->tune_ev[k][j]);
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->gin) (void)hipEventDestroy(ctx->gin);
@@ -1091,6 +1093,7 @@ mcpr_status mcpr_parareal_init(mcpr_parareal *pr, int32_t sample_u0, mcpr_stream
     std::vector<mcpr_ensemble> lens;
     std::vector<mcpr_problem> lprobs;
     std::vector<RegionMap> maps;
+    std::vector<const void *> lsrc;
     for (int i = 0; i < n_inst; ++i) {
         Instance &in = pr->inst[i];
         in.done = false;
@@ -1106,7 +1109,7 @@ mcpr_status mcpr_parareal_init(mcpr_parareal *pr, int32_t sample_u0, mcpr_stream
         std::fill(in.flags.begin(), in.flags.end(), 0);
         for (int n = 1; n <= N; ++n) {
             char *dst = in.ring + (size_t)n * in.stride * pr->esize;
-            HIP_TRY(hipMemcpyAsync(dst, in.ring, (size_t)in.P * pr->esize, hipMemcpyDeviceToDevice, s));
+            lsrc.push_back(in.ring);
             lprobs.push_back(in.pb);
             lens.push_back(mcpr_ensemble{dst, in.P, in.inst, n, (int)lprobs.size() - 1, 0});
             for (int r = 0; r < I; ++r) {
@@ -1130,11 +1133,14 @@ mcpr_status mcpr_parareal_init(mcpr_parareal *pr, int32_t sample_u0, mcpr_stream
         }
     }
     if (!lens.empty()) {
-        if ((st = ensure(ctx, pr->dmaps, maps.size() * sizeof(RegionMap))) != MCPR_OK) return st;
-        HIP_TRY(hipMemcpyAsync(pr->dmaps.p, maps.data(), maps.size() * sizeof(RegionMap), hipMemcpyHostToDevice, s));
-        if ((st = mcpr_match(ctx, lprobs.data(), (int)lprobs.size(), lens.data(), (int)lens.size(),
-                             (const mcpr_region_map *)pr->dmaps.p, 0, nullptr, stream)) != MCPR_OK)
-            return st;
+        // one launch writes every lifted slot from u0 (slot 0 of its instance)
+        Tables t;
+        build_tables(lprobs.data(), lens.data(), (int)lens.size(), t);
+        for (size_t e = 0; e < lens.size(); ++e) t.items[e].src = lsrc[e];
+        if ((st = upload(ctx, t, maps.data(), maps.size() * sizeof(RegionMap), s)) != MCPR_OK) return st;
+        HIP_TRY(mcpr::launch_match_apply(pr->prec, I, (const WorkItem *)ctx->items.p, (const int2 *)ctx->blocks.p,
+                                         (int)t.blocks.size(), splits_of(pr->inst[0].pb),
+                                         (const RegionMap *)ctx->maps.p, s));
     }
     HIP_TRY(hipStreamSynchronize(s));
     pr->k = 0;

@@ -57,6 +57,7 @@ struct WorkItem {
     double dt, sdt;    // step and its square root
     double p0[5];      // w, mu1, sd1, mu2, sd2
     int64_t traj;      // 0: steps work in place; else step j reads x + j*traj and writes x + (j+1)*traj
+    const void *src;   // matching only: read from src instead of x (NULL: in place)
 };
 
 // Per-superchunk region partial: count, sum d, sum d^2, min, max (d = x - shift).

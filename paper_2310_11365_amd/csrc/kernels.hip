@@ -772,6 +772,7 @@ __global__ __launch_bounds__(kThreads) void k_match_apply(const WorkItem *__rest
     const int2 bt = blocks[blockIdx.x];
     const WorkItem &W = items[bt.x];
     T *__restrict__ x = reinterpret_cast<T *>(W.x);
+    const T *__restrict__ xin = W.src ? reinterpret_cast<const T *>(W.src) : x;
     const int64_t P = W.P;
     const int R = W.R;
     RegionMap mp[NREG];
@@ -783,7 +784,7 @@ __global__ __launch_bounds__(kThreads) void k_match_apply(const WorkItem *__rest
         const int64_t p = 4 * Q;
         if (p < P) {
             T v[4];
-            load_quad(x, p, P, v);
+            load_quad(xin, p, P, v);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int g = region_of<NREG>((double)v[e], sp);
