@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--parareal-iters", type=int, default=4)
     ap.add_argument("--parareal-max-s", type=float, default=60.0,
                     help="stop the run-to-tolerance Parareal measurement after this many seconds")
+    ap.add_argument("--variant", type=int, default=-1, choices=[-1, 0, 1, 2, 3],
+                    help="step-kernel launch variant: -1 autotune (default), 0..3 force")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "reference for the HBM byte counters of a profiler run)")
@@ -158,6 +160,7 @@ def main():
         del src, dst
 
     ctx = mcpr.Context(0)
+    ctx.set_tuning(args.variant)
     para = mcpr.Parareal([pr], sizes, ctx, coefs=coefs, learning=wl.learning, tol=wl.tol)
 
     def step():
@@ -189,7 +192,7 @@ def main():
     all_coefs = coefs if coefs else [pr.coef]
     deg = 1 if all(c.a2 == 0.0 and c.a3 == 0.0 for c in all_coefs) else 3
     tv = ctx.tuned_variants()
-    variant = tv[0] if tv else 0
+    variant = args.variant if args.variant >= 0 else (tv[0] if tv else 0)
     kernel = f"k_em_step<{tname}, {deg}, {'true' if variant & 1 else 'false'}, {'true' if variant & 2 else 'false'}>"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(kernel, wl.name),

@@ -150,10 +150,11 @@ mcpr_status mcpr_set_graphs(mcpr_ctx *ctx, int32_t on);
  * Infinity Cache), bit 1 the step's mean field formed once per ensemble by a
  * small launch instead of by every block (pays off with many blocks per
  * ensemble).  mode -1 (default): the first fine sweep of each launch shape
- * (with at least 8 steps) times the four variants on its first 16 steps (8
- * if it has fewer than 16), keeps each variant's best time, and adopts a
- * variant other than 0 for that shape only if it beats variant 0 by 2 %;
- * 0..3 forces a variant.
+ * (with at least 8 steps) runs each variant on 4 consecutive steps of its
+ * first 16 (2 of its first 8 if it has fewer than 16), times each variant by
+ * its launches after the first (which inherits the previous variant's cache
+ * state), and adopts a variant other than 0 for that shape only if it beats
+ * variant 0 by 1 %; 0..3 forces a variant.
  * mcpr_tuned_variant: the variant chosen for the index-th tuned shape, or -1. */
 mcpr_status mcpr_set_tuning(mcpr_ctx *ctx, int32_t mode);
 int32_t mcpr_tuned_variant(const mcpr_ctx *ctx, int32_t index);

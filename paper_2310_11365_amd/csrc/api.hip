@@ -327,7 +327,7 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
     for (int j = 0; j < m; ++j) {
         const int a = j & 1, b = a ^ 1;
         const bool trial = variant < 0 && j < ctx->tune_steps;
-        const int v = trial ? (j & 3) : (variant < 0 ? 0 : variant);
+        const int v = trial ? (j / (ctx->tune_steps / 4)) : (variant < 0 ? 0 : variant);
         if (trial) HIP_TRY(hipEventRecord(ctx->tune_ev[0][j], s));
         HIP_TRY(mcpr::launch_em_step(prec, deg, v, items, n, blocks, nb, j, part[a], shift[a], mv, part[b], shift[b],
                                      trace, m, s));
@@ -394,9 +394,11 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
         }
     }
     if (tune_now) {
-        // trial: steps 0..K-1 cycle through the variants (K = 16 when the sweep
-        // has 16 steps, else 8); best time of each; a variant other than the
-        // plain one must beat it by 2 %
+        // trial: the first K steps (K = 16 when the sweep has 16 steps, else 8)
+        // run each variant on K/4 consecutive launches; a variant's time is the
+        // mean of its launches after the first (the first one inherits the cache
+        // state the previous variant left); a variant other than the plain one
+        // must beat it by 1 %
         if (!ctx->tune_ev[0][0])
             for (int k = 0; k < 2; ++k)
                 for (int j = 0; j < 16; ++j) HIP_TRY(hipEventCreate(&ctx->tune_ev[k][j]));
@@ -406,14 +408,16 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
             return st;
         HIP_TRY(hipEventSynchronize(ctx->tune_ev[1][ctx->tune_steps - 1]));
         float tv[4] = {0, 0, 0, 0};
+        const int per = ctx->tune_steps / 4;
         for (int j = 0; j < ctx->tune_steps; ++j) {
+            if (j % per == 0) continue;
             float ms = 0.0f;
             HIP_TRY(hipEventElapsedTime(&ms, ctx->tune_ev[0][j], ctx->tune_ev[1][j]));
-            if (j < 4 || ms < tv[j & 3]) tv[j & 3] = ms;
+            tv[j / per] += ms / (float)(per - 1);
         }
         int pick = 0;
         for (int v = 1; v < 4; ++v)
-            if (tv[v] < 0.98f * tv[0] && tv[v] < tv[pick]) pick = v;
+            if (tv[v] < 0.99f * tv[0] && tv[v] < tv[pick]) pick = v;
         ctx->tuned[tkey] = pick;
     } else if (ctx->profile) {
         if (ctx->prof_used == ctx->prof0.size()) {

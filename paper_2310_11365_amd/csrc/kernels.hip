@@ -312,6 +312,17 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
     const int64_t P = W.P;
     const int R = W.R;
 
+    // the first group of a full superchunk's quads does not depend on the mean
+    // field: issue its loads before the combine so the two latencies overlap
+    const int64_t base = (int64_t)sc * 4 * kThreads * R; // first particle of the superchunk
+    const bool full = base + (int64_t)4 * kThreads * R <= P;
+    T v[4][4];
+    if (full) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+            if (g < R) gload_quad<NT>(x + base, (uint32_t)(g * kThreads + threadIdx.x), v[g]);
+    }
+
     // mean field at the start of the step
     double mean, var;
     if (MV) {
@@ -340,17 +351,17 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
     const uint32_t k0 = W.key0, k1 = W.key1;
 
     double a1 = 0.0, a2 = 0.0;
-    const int64_t base = (int64_t)sc * 4 * kThreads * R; // first particle of the superchunk
-    if (base + (int64_t)4 * kThreads * R <= P) {
+    if (full) {
         // full superchunk: 32-bit quad offsets, no per-quad checks
         const T *xs = x + base;
         T *ys = y + base;
         const uint32_t qb = (uint32_t)(base >> 2) + threadIdx.x;
         for (int r0 = 0; r0 < R; r0 += 4) {
-            T v[4][4];
+            if (r0 > 0) {
 #pragma unroll
-            for (int g = 0; g < 4; ++g)
-                if (r0 + g < R) gload_quad<NT>(xs, (uint32_t)((r0 + g) * kThreads + threadIdx.x), v[g]);
+                for (int g = 0; g < 4; ++g)
+                    if (r0 + g < R) gload_quad<NT>(xs, (uint32_t)((r0 + g) * kThreads + threadIdx.x), v[g]);
+            }
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 if (r0 + g < R) {
