@@ -289,13 +289,15 @@ mcpr_status enqueue_records(mcpr_ctx *ctx, const Tables &t, int prec, int nreg, 
     double *rs0 = (double *)ctx->rshift[0].p, *rs1 = (double *)ctx->rshift[1].p;
     RegionPartial *rp = (RegionPartial *)ctx->rpart.p;
     HIP_TRY(mcpr::launch_fill_shift(prec, nr, items, n, shift, rs0, s));
-    HIP_TRY(mcpr::launch_region_partials(prec, nr, mode, items, blocks, nb, rs0, sp, maps, rp, s));
     if (two_pass) {
-        HIP_TRY(mcpr::launch_region_combine(nr, items, n, rp, rs0, (RegionStats *)ctx->recs.p, rs1, s));
-        HIP_TRY(mcpr::launch_region_partials(prec, nr, mode, items, blocks, nb, rs1, sp, maps, rp, s));
-        HIP_TRY(mcpr::launch_region_combine(nr, items, n, rp, rs1, out, nullptr, s));
+        // first pass: region means only; second pass about each region's mean
+        HIP_TRY(mcpr::launch_region_partials(prec, nr, mode, false, items, blocks, nb, rs0, sp, maps, rp, s));
+        HIP_TRY(mcpr::launch_region_combine(nr, false, items, n, rp, rs0, nullptr, rs1, s));
+        HIP_TRY(mcpr::launch_region_partials(prec, nr, mode, true, items, blocks, nb, rs1, sp, maps, rp, s));
+        HIP_TRY(mcpr::launch_region_combine(nr, true, items, n, rp, rs1, out, nullptr, s));
     } else {
-        HIP_TRY(mcpr::launch_region_combine(nr, items, n, rp, rs0, out, nullptr, s));
+        HIP_TRY(mcpr::launch_region_partials(prec, nr, mode, true, items, blocks, nb, rs0, sp, maps, rp, s));
+        HIP_TRY(mcpr::launch_region_combine(nr, true, items, n, rp, rs0, out, nullptr, s));
     }
     return MCPR_OK;
 }

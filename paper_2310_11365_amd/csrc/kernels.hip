@@ -617,83 +617,104 @@ __device__ __forceinline__ double apply_map<double>(const RegionMap &mp, double 
     return xv;
 }
 
-template <typename T, int NR, int MODE>
+// Region partials of one superchunk, per region i < NREG (the whole-ensemble
+// record is formed from the regions' in the combine).  FULL = false: count and
+// sum of (y - shift_i) only (the first pass, which needs region means); FULL =
+// true: also the sum of squares, min and max.
+template <typename T, int NREG, int MODE, bool FULL>
+__device__ __forceinline__ void region_accumulate(const T v[4], int64_t p, int64_t P, uint32_t Q, const WorkItem &W,
+                                                  const Splits &sp, const RegionMap *mp, const double *sh,
+                                                  double *acc, double *mn, double *mx, bool checked) {
+    int g[4];
+    double y[4];
+    bool ok[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        ok[e] = !checked || (p + e < P);
+        g[e] = region_of<NREG>((double)v[e], sp);
+        if (MODE == 1) {
+            RegionMap m0 = mp[0];
+#pragma unroll
+            for (int i = 1; i < NREG; ++i)
+                if (g[e] == i) m0 = mp[i];
+            y[e] = apply_map<T>(m0, v[e], Q, e, (uint32_t)W.inst, W.key0, W.key1);
+        } else {
+            y[e] = (double)v[e];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NREG; ++i) {
+        double d[4], c[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const bool in = ok[e] && (NREG == 1 || g[e] == i);
+            d[e] = in ? y[e] - sh[i] : 0.0;
+            c[e] = in ? 1.0 : 0.0;
+            if (FULL && in) {
+                mn[i] = fmin(mn[i], y[e]);
+                mx[i] = fmax(mx[i], y[e]);
+            }
+        }
+        acc[3 * i] += (c[0] + c[1]) + (c[2] + c[3]);
+        acc[3 * i + 1] += (d[0] + d[1]) + (d[2] + d[3]);
+        if (FULL) acc[3 * i + 2] += (d[0] * d[0] + d[1] * d[1]) + (d[2] * d[2] + d[3] * d[3]);
+    }
+}
+
+template <typename T, int NREG, int MODE, bool FULL>
 __global__ __launch_bounds__(kThreads) void k_region_partials(const WorkItem *__restrict__ items,
                                                               const int2 *__restrict__ blocks,
                                                               const double *__restrict__ rshift, Splits sp,
                                                               const RegionMap *__restrict__ maps,
                                                               RegionPartial *__restrict__ rpart) {
-    constexpr int NREG = NR - 1;
-    __shared__ double lds[4 * 3 * NR + 8 * NR];
+    constexpr int NR = NREG + 1; // record stride (the whole-ensemble entry comes last)
+    __shared__ double lds[4 * 3 * NREG + 8 * NREG];
     const int2 bt = blocks[blockIdx.x];
     const WorkItem &W = items[bt.x];
     const T *__restrict__ x = reinterpret_cast<const T *>(W.x);
     const int64_t P = W.P;
     const int R = W.R;
-    double sh[NR];
+    double sh[NREG];
 #pragma unroll
-    for (int i = 0; i < NR; ++i) sh[i] = rshift[(int64_t)bt.x * NR + i];
-    RegionMap mp[NREG > 0 ? NREG : 1];
+    for (int i = 0; i < NREG; ++i) sh[i] = rshift[(int64_t)bt.x * NR + i];
+    RegionMap mp[NREG];
     if (MODE == 1) {
 #pragma unroll
         for (int i = 0; i < NREG; ++i) mp[i] = maps[(int64_t)bt.x * NREG + i];
     }
-    double acc[3 * NR], mn[NR], mx[NR];
+    double acc[3 * NREG], mn[NREG], mx[NREG];
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
+    for (int i = 0; i < NREG; ++i) {
         acc[3 * i] = acc[3 * i + 1] = acc[3 * i + 2] = 0.0;
         mn[i] = __builtin_inf();
         mx[i] = -__builtin_inf();
     }
-    const int64_t qbase = (int64_t)bt.y * kThreads * R + threadIdx.x;
-    for (int r = 0; r < R; ++r) {
-        const int64_t Q = qbase + (int64_t)r * kThreads;
-        const int64_t p = 4 * Q;
-        if (p < P) {
+    const int64_t base = (int64_t)bt.y * 4 * kThreads * R;
+    if (base + (int64_t)4 * kThreads * R <= P) {
+        const uint32_t qb = (uint32_t)(base >> 2) + threadIdx.x;
+        for (int r = 0; r < R; ++r) {
             T v[4];
-            load_quad(x, p, P, v);
-            int g[4];
-            double y[4];
-            bool ok[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                ok[e] = (p + e < P);
-                g[e] = region_of<NREG>((double)v[e], sp);
-                if (MODE == 1) {
-                    RegionMap m0 = mp[0];
-#pragma unroll
-                    for (int i = 1; i < NREG; ++i)
-                        if (g[e] == i) m0 = mp[i];
-                    y[e] = apply_map<T>(m0, v[e], (uint32_t)Q, e, (uint32_t)W.inst, W.key0, W.key1);
-                } else {
-                    y[e] = (double)v[e];
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                double d[4], c[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const bool in = ok[e] && (i == NREG || g[e] == i);
-                    d[e] = in ? y[e] - sh[i] : 0.0;
-                    c[e] = in ? 1.0 : 0.0;
-                    if (in) {
-                        mn[i] = fmin(mn[i], y[e]);
-                        mx[i] = fmax(mx[i], y[e]);
-                    }
-                }
-                acc[3 * i] += (c[0] + c[1]) + (c[2] + c[3]);
-                acc[3 * i + 1] += (d[0] + d[1]) + (d[2] + d[3]);
-                acc[3 * i + 2] += (d[0] * d[0] + d[1] * d[1]) + (d[2] * d[2] + d[3] * d[3]);
+            gload_quad<false>(x + base, (uint32_t)(r * kThreads + threadIdx.x), v);
+            region_accumulate<T, NREG, MODE, FULL>(v, 0, P, qb + (uint32_t)(r * kThreads), W, sp, mp, sh, acc, mn, mx,
+                                                   false);
+        }
+    } else {
+        for (int r = 0; r < R; ++r) {
+            const int64_t Q = (base >> 2) + (int64_t)r * kThreads + threadIdx.x;
+            const int64_t p = 4 * Q;
+            if (p < P) {
+                T v[4];
+                load_quad(x, p, P, v);
+                region_accumulate<T, NREG, MODE, FULL>(v, p, P, (uint32_t)Q, W, sp, mp, sh, acc, mn, mx, true);
             }
         }
     }
-    block_sum<3 * NR>(acc, lds);
-    block_minmax<NR>(mn, mx, lds);
+    block_sum<3 * NREG>(acc, lds);
+    if (FULL) block_minmax<NREG>(mn, mx, lds);
     if (threadIdx.x == 0) {
-        RegionPartial *out = rpart + (int64_t)(W.part_off + bt.y) * NR;
+        RegionPartial *out = rpart + (int64_t)(W.part_off + bt.y) * NREG;
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
+        for (int i = 0; i < NREG; ++i) {
             RegionPartial rp;
             rp.cnt = acc[3 * i];
             rp.s1 = acc[3 * i + 1];
@@ -705,60 +726,110 @@ __global__ __launch_bounds__(kThreads) void k_region_partials(const WorkItem *__
     }
 }
 
-// One block per item: region partials -> records.  If rshift_next is set it
-// receives the region means (the shifts of a second, better conditioned pass).
-template <int NR>
+// One block per item: region partials -> records (regions, then the whole
+// ensemble from the regions: total count, count-weighted mean, law of total
+// variance, extreme min and max).  If rshift_next is set it receives the
+// region means (the shifts of the second, full pass); the records then are
+// not written.
+template <int NREG, bool FULL>
 __global__ __launch_bounds__(kThreads) void k_region_combine(const WorkItem *__restrict__ items,
                                                              const RegionPartial *__restrict__ rpart,
                                                              const double *__restrict__ rshift,
                                                              RegionStats *__restrict__ out,
                                                              double *__restrict__ rshift_next) {
-    __shared__ double lds[4 * 3 * NR + 8 * NR];
+    constexpr int NR = NREG + 1;
+    __shared__ double lds[4 * 3 * NREG + 8 * NREG];
     const WorkItem &W = items[blockIdx.x];
-    double acc[3 * NR], mn[NR], mx[NR];
+    double acc[3 * NREG], mn[NREG], mx[NREG];
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
+    for (int i = 0; i < NREG; ++i) {
         acc[3 * i] = acc[3 * i + 1] = acc[3 * i + 2] = 0.0;
         mn[i] = __builtin_inf();
         mx[i] = -__builtin_inf();
     }
     for (int s = threadIdx.x; s < W.nsc; s += kThreads) {
-        const RegionPartial *rp = rpart + (int64_t)(W.part_off + s) * NR;
+        const RegionPartial *rp = rpart + (int64_t)(W.part_off + s) * NREG;
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
+        for (int i = 0; i < NREG; ++i) {
             acc[3 * i] += rp[i].cnt;
             acc[3 * i + 1] += rp[i].s1;
-            acc[3 * i + 2] += rp[i].s2;
-            mn[i] = fmin(mn[i], rp[i].mn);
-            mx[i] = fmax(mx[i], rp[i].mx);
-        }
-    }
-    block_sum<3 * NR>(acc, lds);
-    block_minmax<NR>(mn, mx, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            const double sh = rshift[(int64_t)blockIdx.x * NR + i];
-            RegionStats st;
-            st.n = (int64_t)acc[3 * i];
-            st.min = mn[i];
-            st.max = mx[i];
-            st.nonfinite = !(isfinite(acc[3 * i + 1]) && isfinite(acc[3 * i + 2]));
-            st.reserved = 0;
-            if (st.n == 0) {
-                st.mean = 0.0;
-                st.var = 0.0;
-            } else if (mn[i] == mx[i]) {
-                st.mean = mn[i];
-                st.var = 0.0;
-            } else {
-                finish_moments(acc[3 * i + 1], acc[3 * i + 2], sh, acc[3 * i], st.mean, st.var);
+            if (FULL) {
+                acc[3 * i + 2] += rp[i].s2;
+                mn[i] = fmin(mn[i], rp[i].mn);
+                mx[i] = fmax(mx[i], rp[i].mx);
             }
-            out[(int64_t)blockIdx.x * NR + i] = st;
-            if (rshift_next)
-                rshift_next[(int64_t)blockIdx.x * NR + i] = (st.n > 0 && isfinite(st.mean)) ? st.mean : sh;
         }
     }
+    block_sum<3 * NREG>(acc, lds);
+    if (FULL) block_minmax<NREG>(mn, mx, lds);
+    if (threadIdx.x != 0) return;
+    if (!FULL) {
+#pragma unroll
+        for (int i = 0; i < NREG; ++i) {
+            const double sh = rshift[(int64_t)blockIdx.x * NR + i];
+            const double mean = sh + acc[3 * i + 1] / acc[3 * i];
+            rshift_next[(int64_t)blockIdx.x * NR + i] = (acc[3 * i] > 0.0 && isfinite(mean)) ? mean : sh;
+        }
+        return;
+    }
+    RegionStats st[NREG];
+    int64_t ntot = 0;
+    bool nonfinite = false;
+    double gmin = __builtin_inf(), gmax = -__builtin_inf();
+#pragma unroll
+    for (int i = 0; i < NREG; ++i) {
+        const double sh = rshift[(int64_t)blockIdx.x * NR + i];
+        st[i].n = (int64_t)acc[3 * i];
+        st[i].min = mn[i];
+        st[i].max = mx[i];
+        st[i].nonfinite = !(isfinite(acc[3 * i + 1]) && isfinite(acc[3 * i + 2]));
+        st[i].reserved = 0;
+        if (st[i].n == 0) {
+            st[i].mean = 0.0;
+            st[i].var = 0.0;
+        } else if (mn[i] == mx[i]) {
+            st[i].mean = mn[i];
+            st[i].var = 0.0;
+        } else {
+            finish_moments(acc[3 * i + 1], acc[3 * i + 2], sh, acc[3 * i], st[i].mean, st[i].var);
+        }
+        ntot += st[i].n;
+        nonfinite = nonfinite || st[i].nonfinite;
+        gmin = fmin(gmin, mn[i]);
+        gmax = fmax(gmax, mx[i]);
+        out[(int64_t)blockIdx.x * NR + i] = st[i];
+    }
+    RegionStats g;
+    g.n = ntot;
+    g.min = gmin;
+    g.max = gmax;
+    g.nonfinite = nonfinite;
+    g.reserved = 0;
+    if (NREG == 1) {
+        g.mean = st[0].mean;
+        g.var = st[0].var;
+    } else if (ntot == 0) {
+        g.mean = 0.0;
+        g.var = 0.0;
+    } else if (gmin == gmax) {
+        g.mean = gmin;
+        g.var = 0.0;
+    } else {
+        double m = 0.0;
+#pragma unroll
+        for (int i = 0; i < NREG; ++i)
+            if (st[i].n > 0) m += ((double)st[i].n / (double)ntot) * st[i].mean;
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < NREG; ++i)
+            if (st[i].n > 0) {
+                const double dm = st[i].mean - m;
+                v += ((double)st[i].n / (double)ntot) * (st[i].var + dm * dm);
+            }
+        g.mean = m;
+        g.var = v;
+    }
+    out[(int64_t)blockIdx.x * NR + NREG] = g;
 }
 
 // Shifts for the first restriction pass: the value the step sums were shifted
@@ -946,62 +1017,62 @@ hipError_t launch_adj_reduce(const WorkItem *items, int n_items, const double *a
     return hipGetLastError();
 }
 
-template <int NR>
-static void region_partials_nr(int prec, int mode, const WorkItem *items, const int2 *blocks, int nblocks,
+template <int NREG>
+static void region_partials_nr(int prec, int mode, bool full, const WorkItem *items, const int2 *blocks, int nblocks,
                                const double *rshift, const Splits &sp, const RegionMap *maps, RegionPartial *rpart,
                                hipStream_t s) {
+#define MCPR_RP(T, MODE, FULL)                                                                                     \
+    hipLaunchKernelGGL((k_region_partials<T, NREG, MODE, FULL>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, \
+                       rshift, sp, maps, rpart)
     if (prec == 0) {
-        if (mode == 0)
-            hipLaunchKernelGGL((k_region_partials<double, NR, 0>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks,
-                               rshift, sp, maps, rpart);
-        else
-            hipLaunchKernelGGL((k_region_partials<double, NR, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks,
-                               rshift, sp, maps, rpart);
+        if (mode == 0) { if (full) MCPR_RP(double, 0, true); else MCPR_RP(double, 0, false); }
+        else { if (full) MCPR_RP(double, 1, true); else MCPR_RP(double, 1, false); }
     } else {
-        if (mode == 0)
-            hipLaunchKernelGGL((k_region_partials<float, NR, 0>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks,
-                               rshift, sp, maps, rpart);
-        else
-            hipLaunchKernelGGL((k_region_partials<float, NR, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks,
-                               rshift, sp, maps, rpart);
+        if (mode == 0) { if (full) MCPR_RP(float, 0, true); else MCPR_RP(float, 0, false); }
+        else { if (full) MCPR_RP(float, 1, true); else MCPR_RP(float, 1, false); }
     }
+#undef MCPR_RP
 }
 
-hipError_t launch_region_partials(int prec, int nr, int mode, const WorkItem *items, const int2 *blocks, int nblocks,
-                                  const double *rshift, const Splits &sp, const RegionMap *maps, RegionPartial *rpart,
-                                  hipStream_t s) {
-    switch (nr) {
-    case 2: region_partials_nr<2>(prec, mode, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
-    case 3: region_partials_nr<3>(prec, mode, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
-    case 4: region_partials_nr<4>(prec, mode, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
-    case 5: region_partials_nr<5>(prec, mode, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
-    case 6: region_partials_nr<6>(prec, mode, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
-    case 7: region_partials_nr<7>(prec, mode, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
-    case 8: region_partials_nr<8>(prec, mode, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
-    case 9: region_partials_nr<9>(prec, mode, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
+hipError_t launch_region_partials(int prec, int nr, int mode, bool full, const WorkItem *items, const int2 *blocks,
+                                  int nblocks, const double *rshift, const Splits &sp, const RegionMap *maps,
+                                  RegionPartial *rpart, hipStream_t s) {
+    switch (nr - 1) {
+    case 1: region_partials_nr<1>(prec, mode, full, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
+    case 2: region_partials_nr<2>(prec, mode, full, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
+    case 3: region_partials_nr<3>(prec, mode, full, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
+    case 4: region_partials_nr<4>(prec, mode, full, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
+    case 5: region_partials_nr<5>(prec, mode, full, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
+    case 6: region_partials_nr<6>(prec, mode, full, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
+    case 7: region_partials_nr<7>(prec, mode, full, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
+    case 8: region_partials_nr<8>(prec, mode, full, items, blocks, nblocks, rshift, sp, maps, rpart, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <int NR>
-static void region_combine_nr(const WorkItem *items, int n_items, const RegionPartial *rpart, const double *rshift,
-                              RegionStats *out, double *rshift_next, hipStream_t s) {
-    hipLaunchKernelGGL((k_region_combine<NR>), dim3(n_items), dim3(kThreads), 0, s, items, rpart, rshift, out,
-                       rshift_next);
+template <int NREG>
+static void region_combine_nr(bool full, const WorkItem *items, int n_items, const RegionPartial *rpart,
+                              const double *rshift, RegionStats *out, double *rshift_next, hipStream_t s) {
+    if (full)
+        hipLaunchKernelGGL((k_region_combine<NREG, true>), dim3(n_items), dim3(kThreads), 0, s, items, rpart, rshift,
+                           out, rshift_next);
+    else
+        hipLaunchKernelGGL((k_region_combine<NREG, false>), dim3(n_items), dim3(kThreads), 0, s, items, rpart, rshift,
+                           out, rshift_next);
 }
 
-hipError_t launch_region_combine(int nr, const WorkItem *items, int n_items, const RegionPartial *rpart,
+hipError_t launch_region_combine(int nr, bool full, const WorkItem *items, int n_items, const RegionPartial *rpart,
                                  const double *rshift, RegionStats *out, double *rshift_next, hipStream_t s) {
-    switch (nr) {
-    case 2: region_combine_nr<2>(items, n_items, rpart, rshift, out, rshift_next, s); break;
-    case 3: region_combine_nr<3>(items, n_items, rpart, rshift, out, rshift_next, s); break;
-    case 4: region_combine_nr<4>(items, n_items, rpart, rshift, out, rshift_next, s); break;
-    case 5: region_combine_nr<5>(items, n_items, rpart, rshift, out, rshift_next, s); break;
-    case 6: region_combine_nr<6>(items, n_items, rpart, rshift, out, rshift_next, s); break;
-    case 7: region_combine_nr<7>(items, n_items, rpart, rshift, out, rshift_next, s); break;
-    case 8: region_combine_nr<8>(items, n_items, rpart, rshift, out, rshift_next, s); break;
-    case 9: region_combine_nr<9>(items, n_items, rpart, rshift, out, rshift_next, s); break;
+    switch (nr - 1) {
+    case 1: region_combine_nr<1>(full, items, n_items, rpart, rshift, out, rshift_next, s); break;
+    case 2: region_combine_nr<2>(full, items, n_items, rpart, rshift, out, rshift_next, s); break;
+    case 3: region_combine_nr<3>(full, items, n_items, rpart, rshift, out, rshift_next, s); break;
+    case 4: region_combine_nr<4>(full, items, n_items, rpart, rshift, out, rshift_next, s); break;
+    case 5: region_combine_nr<5>(full, items, n_items, rpart, rshift, out, rshift_next, s); break;
+    case 6: region_combine_nr<6>(full, items, n_items, rpart, rshift, out, rshift_next, s); break;
+    case 7: region_combine_nr<7>(full, items, n_items, rpart, rshift, out, rshift_next, s); break;
+    case 8: region_combine_nr<8>(full, items, n_items, rpart, rshift, out, rshift_next, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

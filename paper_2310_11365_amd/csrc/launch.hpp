@@ -26,10 +26,13 @@ hipError_t launch_adj_step(int prec, const WorkItem *items, const int2 *blocks, 
                            const double *lam_in, double *lam_out, const AdjStep &a, const double2 *part_in,
                            double2 *part_out, double *acc, hipStream_t s);
 hipError_t launch_adj_reduce(const WorkItem *items, int n_items, const double *acc, double *out, hipStream_t s);
-hipError_t launch_region_partials(int prec, int nr, int mode, const WorkItem *items, const int2 *blocks, int nblocks,
-                                  const double *rshift, const Splits &sp, const RegionMap *maps, RegionPartial *rpart,
-                                  hipStream_t s);
-hipError_t launch_region_combine(int nr, const WorkItem *items, int n_items, const RegionPartial *rpart,
+// Restriction: nr = regions + 1 (record stride).  full = false: region counts
+// and means only (a first pass, whose combine writes the region means to
+// rshift_next); full = true: complete records.
+hipError_t launch_region_partials(int prec, int nr, int mode, bool full, const WorkItem *items, const int2 *blocks,
+                                  int nblocks, const double *rshift, const Splits &sp, const RegionMap *maps,
+                                  RegionPartial *rpart, hipStream_t s);
+hipError_t launch_region_combine(int nr, bool full, const WorkItem *items, int n_items, const RegionPartial *rpart,
                                  const double *rshift, RegionStats *out, double *rshift_next, hipStream_t s);
 hipError_t launch_fill_shift(int prec, int nr, const WorkItem *items, int n_items, const double *shift, double *rshift,
                              hipStream_t s);

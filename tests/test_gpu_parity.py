@@ -623,3 +623,23 @@ def test_step_variants_bitwise(mc, ctx, P):
             ref = got
         else:
             assert all(torch.equal(a, b) for a, b in zip(ref, got)), mode
+
+
+def test_parareal_single_particle_region_fp64(mc, ctx, oracle):
+    """A region holding one particle (its variance is exactly 0, the degenerate
+    case of the matching operator) through every iteration, against the oracle."""
+    pr = W.make_problem(W.dz_coef(sigma=0.3), W.P0(W.P0_MIXTURE, 0.0008, -1.0, 0.05, 1.0, 0.1), 0.8, 4, 1e-2,
+                        (0.0,), precision=W.FP64, seed=7)
+    P = 2000
+    para = mc.Parareal([pr], [P], ctx)
+    para.init()
+    u0 = oracle.sample_p0(pr, P)
+    assert int(np.sum(u0 < 0)) == 1
+    ores = oracle.parareal(pr, u0, 4)
+    for k in range(4):
+        para.iterate()
+        rho, glob = para.macro(0)
+        np.testing.assert_array_equal(para.flags(0), ores["flags"][k])
+        np.testing.assert_array_equal(rho[:, :, 0], ores["rho"][k + 1][:, :, 0])
+        err = np.max(np.abs(glob - ores["glob"][k + 1]) / np.maximum(np.abs(ores["glob"][k + 1]), 1e-300))
+        assert err <= TOL64
