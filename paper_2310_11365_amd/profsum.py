@@ -1,0 +1,96 @@
+"""Summaries of rocprofv3 output databases (kernel traces and byte counters).
+
+Reads the SQLite databases rocprofv3 writes (-d DIR -o run) and prints the
+per-kernel statistics and the HBM byte counts per dispatch, scaled by the
+reading of a plain device copy of known size (bench.py --copy-probe).  Used to
+write the summaries kept under profiles/.
+
+    python -m paper_2310_11365_amd.profsum trace DB [--bench-log LOG]
+    python -m paper_2310_11365_amd.profsum traffic FETCH_DB WRITE_DB --kernel NAME --copy-mib 1024
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sqlite3
+import statistics
+
+
+def kernel_table(db_path: str, limit: int = 12):
+    cur = sqlite3.connect(db_path).cursor()
+    rows = list(cur.execute("select name, total_calls, total_duration, average, percentage from top_kernels "
+                            "order by total_duration desc limit ?", (limit,)))
+    return [(r[0].split("(")[0].replace("void ", ""), int(r[1]), float(r[2]), float(r[3]), float(r[4])) for r in rows]
+
+
+def durations(db_path: str, kernel: str):
+    cur = sqlite3.connect(db_path).cursor()
+    out = []
+    for name, d in cur.execute("select name, duration from kernels"):
+        if name.split("(")[0].replace("void ", "").replace("mcpr::", "") == kernel:
+            out.append(d / 1e3)
+    return out
+
+
+def counter_per_dispatch(db_path: str, kernel: str):
+    cur = sqlite3.connect(db_path).cursor()
+    q = list(cur.execute("select kernel_name, value from counters_collection"))
+    vals = [v for k, v in q if k.split("(")[0].replace("void ", "").replace("mcpr::", "") == kernel]
+    copies = [v for k, v in q if "copyBuffer" in k]
+    return vals, (max(copies) if copies else None)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("--kernel", default=None)
+    t.add_argument("--bench-log", default=None)
+    c = sub.add_parser("traffic")
+    c.add_argument("fetch_db")
+    c.add_argument("write_db")
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--copy-mib", type=int, default=1024)
+    c.add_argument("--algorithmic-bytes", type=float, required=True)
+    a = ap.parse_args()
+    if a.cmd == "trace":
+        print("| kernel | calls | total us | mean us | % |")
+        print("|---|---|---|---|---|")
+        for name, calls, tot, avg, pct in kernel_table(a.db):
+            print(f"| `{name}` | {calls} | {tot:.1f} | {avg:.2f} | {pct:.2f} |")
+        if a.kernel:
+            d = durations(a.db, a.kernel)
+            if d:
+                print(f"\n`{a.kernel}`: {len(d)} dispatches, mean {statistics.mean(d):.2f} us, median "
+                      f"{statistics.median(d):.2f} us, min {min(d):.2f} us, max {max(d):.2f} us")
+        if a.bench_log:
+            for line in open(a.bench_log):
+                if line.startswith("{"):
+                    r = json.loads(line)["roofline"]
+                    print(f"\nbench.py, same run: {r['kernel']} mean {r['avg_launch_us']} us per launch by HIP events, "
+                          f"{r['achieved']} GB/s algorithmic")
+    else:
+        kib = a.copy_mib * 1024.0
+        out = {}
+        for name, db in (("FETCH_SIZE", a.fetch_db), ("WRITE_SIZE", a.write_db)):
+            vals, copy = counter_per_dispatch(db, a.kernel)
+            scale = kib / copy
+            out[name] = dict(n=len(vals), raw_kib=statistics.mean(vals), copy_kib=copy, scale=scale,
+                             bytes=statistics.mean(vals) * scale * 1024.0)
+        tot = out["FETCH_SIZE"]["bytes"] + out["WRITE_SIZE"]["bytes"]
+        print("| counter | copy of %d MiB reads (KiB) | scale | kernel raw KiB per dispatch | scaled bytes per dispatch |"
+              % a.copy_mib)
+        print("|---|---|---|---|---|")
+        for name in ("FETCH_SIZE", "WRITE_SIZE"):
+            o = out[name]
+            print(f"| {name} | {o['copy_kib']:.0f} | {o['scale']:.4f} | {o['raw_kib']:.1f} ({o['n']} dispatches) | "
+                  f"{o['bytes']:.4e} |")
+        print(f"\ntraffic per dispatch {tot:.4e} B; algorithmic {a.algorithmic_bytes:.4e} B; "
+              f"ratio {tot / a.algorithmic_bytes:.4f}")
+        print(json.dumps({"bytes_per_launch": tot, "fetch_bytes": out["FETCH_SIZE"]["bytes"],
+                          "write_bytes": out["WRITE_SIZE"]["bytes"]}))
+
+
+if __name__ == "__main__":
+    main()
