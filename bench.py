@@ -15,7 +15,13 @@ value = particle-steps per second of the whole step.
 Other workloads (--workload): ou_batched (64 independent OU instances, P
 log-uniform in [1e4, 2e6], N = 32: 3.7 GB of state, HBM-resident), dz_large
 (P = 1.6e7, N = 256, 79 steps per slice, 16.4 GB ring, learning; also run to
-tolerance 1e-4), ou_linear (P = 1e4, N = 10, fp64: the latency-bound case).
+tolerance 1e-4), ou_linear (P = 1e4, N = 10, fp64: the latency-bound case),
+adjoint_ou / adjoint_dz (the gradient of the slice-end moments' squared error
+through the fine propagator, P = 1e5, T = 2, dt = 1e-3, N = 20, fp32 state:
+one step is one mcpr_adjoint call, i.e. the forward solution with slice-start
+checkpoints, each slice recomputed, and the backward sweep; value = forward
+particle-steps differentiated per second, roofline = the backward step kernel,
+20 B per particle-step: the state read, the fp64 adjoint read and written).
 
 The JSON line also carries:
   roofline      the Euler-Maruyama step kernel: algorithmic bytes per launch
@@ -111,20 +117,86 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def bench_adjoint(args):
+    import numpy as np
+    import torch
+
+    from paper_2310_11365_amd import mcpr
+    from paper_2310_11365_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    kind = args.workload.split("_", 1)[1]
+    wl = W.adjoint_case(kind, precision=W.FP32)
+    pr, P = wl.problem, wl.P
+    N, m = pr.n_slices, pr.steps_per_slice
+    ctx = mcpr.Context(0)
+    ctx.set_tuning(args.variant)
+    prop = mcpr.Propagator(pr, ctx)
+    x = prop.new_particles(P)
+    prop.sample(x)
+    pc = mcpr.problem_c(pr)
+    # targets: the slice-end moments at every coefficient scaled by 1.1, same noise
+    coef_t = W.Coef(*[1.1 * c for c in pr.coef.as_list()])
+    tgt, _ = mcpr.adjoint(ctx, mcpr.problem_c(pr, coef_t), x)
+    mom, _ = mcpr.adjoint(ctx, pc, x)
+    dl = 2.0 * (mom - tgt)
+    J = float(np.sum((mom - tgt) ** 2))
+
+    print(f"# workload {wl.name}: P={P} N={N} m={m}; warmup {args.warmup}", flush=True)
+    for _ in range(args.warmup):
+        mcpr.adjoint(ctx, pc, x, dl)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read_adjoint(reset=True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, g = mcpr.adjoint(ctx, pc, x, dl)
+        print(f"# step {i + 1}/{args.steps} done", flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    adj_ms, adj_steps, adj_ps = ctx.profile_read_adjoint(reset=True)
+    ctx.profile(False)
+
+    ps_per_step = N * m * P
+    avg_s = adj_ms / 1e3 / max(adj_steps, 1)
+    bytes_per_launch = 20.0 * adj_ps / max(adj_steps, 1)
+    achieved = bytes_per_launch / avg_s / 1e9
+    nsc = -(-((P + 3) // 4) // (256 * (1 if P < 65536 else 4)))
+    kernel = f"k_adj_step<float, {'true' if nsc > 256 else 'false'}>"
+    out = {"metric": "fine-propagator particle-steps/sec", "value": ps_per_step * args.steps / elapsed,
+           "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 state / f64 adjoint and reductions", "data": "synthetic",
+           "config": {"workload": f"{wl.name}: gradient of sum_n (m_n - M_n)^2 + (v_n - V_n)^2 with respect to "
+                                  f"the ten drift and diffusion coefficients, targets at 1.1x the coefficients",
+                      "instances": 1, "particles_per_slice": P, "slices": N, "steps_per_slice": m, "dt": pr.dt,
+                      "particle_steps_per_step": ps_per_step,
+                      "step": "one adjoint call: forward with slice checkpoints, per-slice recomputation, "
+                              "backward sweep", "J": J, "grad_norm": float(np.linalg.norm(g))},
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
+                        "avg_launch_us": round(avg_s * 1e6, 2), "bytes_per_launch": bytes_per_launch,
+                        "note": "1e5 particles: launch-latency bound, far from the HBM roof"}}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="dz_bimodal",
-                    choices=["dz_bimodal", "ou_batched", "dz_large", "ou_linear"])
+                    choices=["dz_bimodal", "ou_batched", "dz_large", "ou_linear", "adjoint_ou", "adjoint_dz"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parareal", action="store_true")
     ap.add_argument("--parareal-iters", type=int, default=4)
     ap.add_argument("--parareal-max-s", type=float, default=60.0,
                     help="stop the run-to-tolerance Parareal measurement after this many seconds")
-    ap.add_argument("--variant", type=int, default=-1, choices=[-1, 0, 1, 2, 3],
-                    help="step-kernel launch variant: -1 autotune (default), 0..3 force")
+    ap.add_argument("--variant", type=int, default=-1, choices=list(range(-1, 4)),
+                    help="step-kernel launch variant: -1 autotune (default), 0..3 force (bit 0 non-temporal, "
+                         "bit 1 separate mean-field combine)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "reference for the HBM byte counters of a profiler run)")
@@ -133,6 +205,9 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path (slice sharding across GPUs is "
               "described in DESIGN.md but not implemented); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload.startswith("adjoint_"):
+        return bench_adjoint(args)
 
     import numpy as np
     import torch

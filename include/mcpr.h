@@ -136,6 +136,11 @@ const char *mcpr_version(void);
 mcpr_status mcpr_profile_enable(mcpr_ctx *ctx, int32_t on);
 mcpr_status mcpr_profile_read(mcpr_ctx *ctx, double *em_ms, int64_t *em_launches, int64_t *particle_steps,
                               int32_t reset);
+/* The same for mcpr_adjoint's backward sweep: one event pair around each
+ * slice's run of backward step launches; returns their summed time, the
+ * number of backward steps and the particle-steps they covered.             */
+mcpr_status mcpr_profile_read_adjoint(mcpr_ctx *ctx, double *ms, int64_t *launches, int64_t *particle_steps,
+                                      int32_t reset);
 
 /* hipGraph replay of the fine sweep (on by default): the launch sequence of
  * a fine sweep (step-0 sums, the steps, the final moments and records) is
@@ -150,11 +155,13 @@ mcpr_status mcpr_set_graphs(mcpr_ctx *ctx, int32_t on);
  * Infinity Cache), bit 1 the step's mean field formed once per ensemble by a
  * small launch instead of by every block (pays off with many blocks per
  * ensemble).  mode -1 (default): the first fine sweep of each launch shape
- * (with at least 8 steps) runs each variant on 4 consecutive steps of its
- * first 16 (2 of its first 8 if it has fewer than 16), times each variant by
- * its launches after the first (which inherits the previous variant's cache
- * state), and adopts a variant other than 0 for that shape only if it beats
- * variant 0 by 1 %; 0..3 forces a variant.
+ * (with at least 8 steps) runs each candidate variant on consecutive steps of
+ * its first 16 (8 if it has fewer than 16), times each by its launches after
+ * the first (which inherits the previous candidate's cache state), and adopts
+ * a candidate other than the first for that shape only if it beats the first
+ * by 1 %.  Candidates: 0..3, or only 2 and 3 when an ensemble of the launch
+ * has more than 256 superchunks (more than 1048576 particles), where 2 is
+ * also the untuned default.  0..3 forces a variant.
  * mcpr_tuned_variant: the variant chosen for the index-th tuned shape, or -1. */
 mcpr_status mcpr_set_tuning(mcpr_ctx *ctx, int32_t mode);
 int32_t mcpr_tuned_variant(const mcpr_ctx *ctx, int32_t index);
@@ -253,6 +260,17 @@ mcpr_status mcpr_parareal_iterate(mcpr_parareal *pr, double *delta_out, mcpr_str
 
 /* Number of iterations done (k). */
 int32_t mcpr_parareal_iteration(const mcpr_parareal *pr);
+
+/* Given particle fractions for instance inst (the reference variant of
+ * Sec. 5.4 that uses the exact particle fractions, e.g. those of a serial
+ * fine solution, in place of the Parareal approximations): fractions is a
+ * host array [(N+1)][I], copied.  From the next mcpr_parareal_init or
+ * mcpr_parareal_iterate on, every macro state rho^k_n carries fractions[n]
+ * (after the learning override, if any); the cached coarse outputs keep the
+ * fractions they were computed with, so exact slices still take the I(a,b,a)
+ * branch.  NULL returns to the method's own fractions.  Errors:
+ * MCPR_E_INVALID_ARG for a bad instance or a negative or non-finite value. */
+mcpr_status mcpr_parareal_set_fractions(mcpr_parareal *pr, int32_t inst, const double *fractions);
 
 /* Macro state of instance i (host arrays): rho [(N+1)][I][3] = (fraction,
  * mean, variance) per region; glob [(N+1)][2] = mixture mean and variance

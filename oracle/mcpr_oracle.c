@@ -33,8 +33,10 @@
  *   or_transform       matching T (eq. multimodal_M).
  *   or_parareal        generalised micro-macro Parareal
  *                      (eq. mM_parareal_other_k_NEW) with the unimodal and
- *                      multimodal MC-moments iterators (Definitions of Sec. 3.4)
- *                      and the learning extension (Sec. 3.6).
+ *                      multimodal MC-moments iterators (Definitions of Sec. 3.4),
+ *                      the learning extension (Sec. 3.6) and the reference
+ *                      variant with given (exact) particle fractions (the
+ *                      variants listed in Sec. 5.4).
  *   or_fraction_fit    least-squares fit of the two-region rate model
  *                      (eq. exponential_for_particle_fractions, App. H).
  *   or_adjoint         pathwise gradient of a moment-misfit through the
@@ -563,12 +565,17 @@ void or_serial(const or_problem *pr, double *x, int64_t P, uint32_t inst, or_sta
 /*   states   optional (K+1) x (N+1) x P: u^k_n (n = 0..N; entries of        */
 /*            slices already exact are copied from their exact values)       */
 /* learning != 0 enables the particle-fraction model (two regions only).     */
+/* frac (optional, (N+1) x I): given particle fractions; every macro state   */
+/* rho^k_n then carries frac[n] as its fractions (set after rho^k_n is       */
+/* formed, after the learning override), while the cached coarse outputs    */
+/* keep the fractions they were computed with.  With the fractions of the   */
+/* serial fine solution this is the paper's exact-fraction reference.       */
 /* Returns the number of iterations performed (stops at K, or when delta <=  */
 /* tol, or when every slice is exact).                                       */
 /* ------------------------------------------------------------------------- */
 int or_parareal(const or_problem *pr, const double *u0, int64_t P, uint32_t inst, int32_t K,
-                double tol, int32_t learning, double *rho_out, double *glob_out, int32_t *flags,
-                double *delta, double *states)
+                double tol, int32_t learning, const double *frac, double *rho_out, double *glob_out,
+                int32_t *flags, double *delta, double *states)
 {
     int N = pr->n_slices, I = pr->n_regions;
     size_t RS = (size_t)I * 3;
@@ -586,9 +593,13 @@ int or_parareal(const or_problem *pr, const double *u0, int64_t P, uint32_t inst
     or_stats st0[9];
     or_restrict(pr, u0, P, st0);
     or_rho_from_stats(I, P, st0, rho);
+    if (frac)
+        for (int i = 0; i < I; i++) rho[3 * i] = frac[i];
     for (int n = 0; n < N; n++) {
         or_coarse_rho(pr, rho + n * RS, rho + (n + 1) * RS);
         memcpy(cache + n * RS, rho + (n + 1) * RS, sizeof(double) * RS);
+        if (frac)
+            for (int i = 0; i < I; i++) rho[(n + 1) * RS + 3 * i] = frac[(size_t)(n + 1) * I + i];
     }
     memcpy(cur, u0, sizeof(double) * P);
     for (int n = 1; n <= N; n++) {
@@ -661,6 +672,8 @@ int or_parareal(const or_problem *pr, const double *u0, int64_t P, uint32_t inst
                 /* I(a, b, a) = (R(b), b) */
                 or_rho_from_stats(I, P, b, out);
                 for (int i = 0; i < I; i++) fl[i] = 0;
+                if (frac)
+                    for (int i = 0; i < I; i++) out[3 * i] = frac[(size_t)(n + 1) * I + i];
                 continue;
             }
             for (int i = 0; i < I; i++) {
@@ -701,6 +714,8 @@ int or_parareal(const or_problem *pr, const double *u0, int64_t P, uint32_t inst
                 out[0] = phat[n + 1];
                 out[3] = 1.0 - phat[n + 1];
             }
+            if (frac)
+                for (int i = 0; i < I; i++) out[3 * i] = frac[(size_t)(n + 1) * I + i];
         }
 
         /* successive-iterate difference of the global moments */

@@ -84,7 +84,7 @@ def lib():
         L.or_fraction_fit.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
         L.or_serial.argtypes = [pp, dp, ctypes.c_int64, ctypes.c_uint32, sp]
         L.or_parareal.argtypes = [pp, dp, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_double,
-                                  ctypes.c_int32, dp, dp, ctypes.POINTER(ctypes.c_int32), dp, dp]
+                                  ctypes.c_int32, dp, dp, dp, ctypes.POINTER(ctypes.c_int32), dp, dp]
         L.or_parareal.restype = ctypes.c_int
         L.or_adjoint.argtypes = [pp, dp, ctypes.c_int64, ctypes.c_uint32, dp, dp, dp]
         L.or_adjoint.restype = ctypes.c_double
@@ -223,9 +223,10 @@ def serial(problem, x0: np.ndarray, inst=0, coef=None):
 
 
 def parareal(problem, u0: np.ndarray, K: int, tol: float = 0.0, inst=0, learning=False,
-             keep_states=False, coef=None):
+             keep_states=False, coef=None, fractions=None):
     """MC-moments Parareal; returns a dict with rho[k,n,i,3], glob[k,n,2],
-    flags[k,n,i], delta[k], iterations, and optionally states[k,n,P]."""
+    flags[k,n,i], delta[k], iterations, and optionally states[k,n,P].
+    fractions: optional [N+1, I] given particle fractions of every macro state."""
     N, I = problem.n_slices, problem.n_regions
     u0 = np.ascontiguousarray(u0, dtype=np.float64)
     P = u0.size
@@ -235,9 +236,14 @@ def parareal(problem, u0: np.ndarray, K: int, tol: float = 0.0, inst=0, learning
     delta = np.zeros(max(K, 1))
     states = np.zeros((K + 1, N + 1, P)) if keep_states else None
     pr = to_c(problem, coef)
+    fr = None
+    if fractions is not None:
+        fr = np.ascontiguousarray(fractions, dtype=np.float64).reshape(N + 1, I)
+    null = ctypes.POINTER(ctypes.c_double)()
     its = lib().or_parareal(ctypes.byref(pr), _dp(u0), P, inst, K, tol, 1 if learning else 0,
-                            _dp(rho), _dp(glob), flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                            _dp(delta), _dp(states) if keep_states else ctypes.POINTER(ctypes.c_double)())
+                            _dp(fr) if fr is not None else null, _dp(rho), _dp(glob),
+                            flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(delta),
+                            _dp(states) if keep_states else null)
     out = dict(rho=rho[:its + 1], glob=glob[:its + 1], flags=flags[:its], delta=delta[:its], iterations=its)
     if keep_states:
         out["states"] = states[:its + 1]

@@ -43,11 +43,17 @@ struct HostBuf {
 
 } // namespace
 
+// Launches in the step-variant autotuner's trial (at most 4 candidates x 4).
+constexpr int kTuneSteps = 16;
+// The adjoint's backward steps use one-quad superchunks below this many particles.
+constexpr int64_t kAdjointSmall = 262144;
+
 struct mcpr_ctx {
     int device = 0;
     std::string err;
     DevBuf items, blocks, part[2], shift[2], rpart, rshift[2], maps, recs;
-    DevBuf adj_ckpt, adj_traj, adj_lam[2], adj_part[2], adj_acc, adj_trace, adj_grad; // adjoint scratch
+    DevBuf adj_ckpt, adj_traj, adj_lam[2], adj_part[2], adj_acc, adj_trace, adj_grad, adj_sums; // adjoint scratch
+    DevBuf adj_items, adj_blocks; // the backward sweep's work and block tables
     HostBuf staging;
     hipEvent_t staged = nullptr; // the last upload from staging has completed
     DevBuf trace; // trace of the last fine sweep (copied to the caller's array)
@@ -58,6 +64,10 @@ struct mcpr_ctx {
     std::vector<int64_t> prof_ps;
     size_t prof_used = 0;
     int64_t prof_launches = 0;
+    // the same for the adjoint's backward step launches (one pair per slice)
+    std::vector<hipEvent_t> aprof0, aprof1;
+    size_t aprof_used = 0;
+    int64_t aprof_launches = 0, aprof_ps = 0;
     // hipGraph of the fine sweep (sum init, m steps, finish, records), replayed
     // on a library stream ordered against the caller's stream by events
     bool graphs = true;
@@ -69,8 +79,10 @@ struct mcpr_ctx {
     // step-kernel variant per launch shape: -1 autotune, 0..3 forced
     int tuning = -1;
     std::map<std::vector<char>, int> tuned;
-    hipEvent_t tune_ev[2][16] = {};
+    hipEvent_t tune_ev[2][kTuneSteps] = {};
     int tune_steps = 0;
+    int tune_cand[4] = {0, 1, 2, 3}; // variants of the trial, the first is the reference
+    int tune_nc = 4;
     DevBuf mv; // per-item (mean, variance) of the separate-combine variant
 };
 
@@ -201,7 +213,7 @@ mcpr_status check_call(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_pr
 // ----------------------------------------------------------------------------
 struct Tables {
     std::vector<WorkItem> items;
-    std::vector<int2> blocks;
+    std::vector<int2> blocks; // one entry per superchunk: (item, superchunk)
     int total_sc = 0;
 };
 
@@ -239,25 +251,31 @@ void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_
     t.total_sc = off;
 }
 
-// Upload items and blocks (and optionally maps) through the pinned staging buffer.
-mcpr_status upload(mcpr_ctx *ctx, const Tables &t, const void *maps, size_t map_bytes, hipStream_t s) {
+// Upload items and blocks (and optionally maps) through the pinned staging
+// buffer, into the given device buffers.
+mcpr_status upload_into(mcpr_ctx *ctx, const Tables &t, DevBuf &ditems, DevBuf &dblocks, const void *maps,
+                        size_t map_bytes, hipStream_t s) {
     const size_t ib = t.items.size() * sizeof(WorkItem), bb = t.blocks.size() * sizeof(int2);
     mcpr_status st;
-    if ((st = ensure(ctx, ctx->items, ib)) != MCPR_OK) return st;
-    if ((st = ensure(ctx, ctx->blocks, bb)) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ditems, ib)) != MCPR_OK) return st;
+    if ((st = ensure(ctx, dblocks, bb)) != MCPR_OK) return st;
     if (map_bytes && (st = ensure(ctx, ctx->maps, map_bytes)) != MCPR_OK) return st;
     char *h;
     if ((st = stage(ctx, align256(ib) + align256(bb) + align256(map_bytes), &h)) != MCPR_OK) return st;
     std::memcpy(h, t.items.data(), ib);
     std::memcpy(h + align256(ib), t.blocks.data(), bb);
-    HIP_TRY(hipMemcpyAsync(ctx->items.p, h, ib, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(ctx->blocks.p, h + align256(ib), bb, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ditems.p, h, ib, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dblocks.p, h + align256(ib), bb, hipMemcpyHostToDevice, s));
     if (map_bytes) {
         std::memcpy(h + align256(ib) + align256(bb), maps, map_bytes);
         HIP_TRY(hipMemcpyAsync(ctx->maps.p, h + align256(ib) + align256(bb), map_bytes, hipMemcpyHostToDevice, s));
     }
     HIP_TRY(hipEventRecord(ctx->staged, s));
     return MCPR_OK;
+}
+
+mcpr_status upload(mcpr_ctx *ctx, const Tables &t, const void *maps, size_t map_bytes, hipStream_t s) {
+    return upload_into(ctx, t, ctx->items, ctx->blocks, maps, map_bytes, s);
 }
 
 mcpr::Splits splits_of(const mcpr_problem &p) {
@@ -312,8 +330,9 @@ mcpr_status records(mcpr_ctx *ctx, const Tables &t, int prec, int nreg, const mc
 // The step sequence of the fine propagator on already uploaded tables:
 // step-0 sums, m Euler-Maruyama launches, the final moments (if traced) and
 // the restriction records (if wanted), into ctx-owned buffers.
-// variant < 0: the first 8 steps cycle through the four variants, each launch
-// bracketed by events (the autotuner's trial; every variant gives the same bits).
+// variant < 0: the first tune_steps steps run the candidate variants in turn,
+// each launch bracketed by events (the autotuner's trial; every variant gives
+// the same bits).
 mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int variant, int m, int nreg,
                          const mcpr::Splits &sp, bool want_stats, bool want_trace, hipStream_t s, bool profile) {
     const int n = (int)t.items.size();
@@ -329,7 +348,8 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
     for (int j = 0; j < m; ++j) {
         const int a = j & 1, b = a ^ 1;
         const bool trial = variant < 0 && j < ctx->tune_steps;
-        const int v = trial ? (j / (ctx->tune_steps / 4)) : (variant < 0 ? 0 : variant);
+        const int v = trial ? ctx->tune_cand[j / (ctx->tune_steps / ctx->tune_nc)]
+                            : (variant < 0 ? ctx->tune_cand[0] : variant);
         if (trial) HIP_TRY(hipEventRecord(ctx->tune_ev[0][j], s));
         HIP_TRY(mcpr::launch_em_step(prec, deg, v, items, n, blocks, nb, j, part[a], shift[a], mv, part[b], shift[b],
                                      trace, m, s));
@@ -371,19 +391,25 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
     if (stats && (st = ensure_records(ctx, t, nreg)) != MCPR_OK) return st;
     if (trace && (st = ensure(ctx, ctx->trace, (size_t)n * (m + 1) * sizeof(double2))) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->mv, (size_t)n * sizeof(double2))) != MCPR_OK) return st;
-    int deg = 1;
+    int deg = 1, max_nsc = 0;
     int64_t ps = 0;
     for (const WorkItem &w : t.items) {
         if (w.c[2] != 0.0 || w.c[3] != 0.0) deg = 3;
         ps += w.P;
+        max_nsc = std::max(max_nsc, w.nsc);
     }
+    // An ensemble of more than 256 superchunks makes every block of the
+    // in-block-combine variants read more than one partial per thread: only
+    // the separate-combine variants are candidates then, and the default is
+    // the plain one of those.
+    const bool many = max_nsc > mcpr::kThreads;
     // step-kernel variant: forced, tuned for this launch shape, or tuned now
     std::vector<char> tkey(6 * sizeof(int64_t));
     {
         const int64_t tk[6] = {prec, deg, n, (int64_t)t.blocks.size(), t.total_sc, ps};
         std::memcpy(tkey.data(), tk, sizeof tk);
     }
-    int variant = 0;
+    int variant = many ? 2 : 0;
     bool tune_now = false;
     if (ctx->tuning >= 0) {
         variant = ctx->tuning & 3;
@@ -391,26 +417,37 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
         auto it = ctx->tuned.find(tkey);
         if (it != ctx->tuned.end()) {
             variant = it->second;
-        } else if (m >= 8 && !ctx->profile) {
+        } else if (!ctx->profile) {
             tune_now = true;
         }
     }
     if (tune_now) {
-        // trial: the first K steps (K = 16 when the sweep has 16 steps, else 8)
-        // run each variant on K/4 consecutive launches; a variant's time is the
-        // mean of its launches after the first (the first one inherits the cache
-        // state the previous variant left); a variant other than the plain one
-        // must beat it by 1 %
+        int nc = 0;
+        for (int v = many ? 2 : 0; v < 4; ++v) ctx->tune_cand[nc++] = v;
+        // K/nc consecutive launches per candidate: four when the sweep is long
+        // enough, else two, else no trial (the default is kept)
+        const int per = m >= 4 * nc ? 4 : (m >= 2 * nc ? 2 : 0);
+        ctx->tune_nc = nc;
+        ctx->tune_steps = per * nc;
+        if (per == 0) {
+            ctx->tuned[tkey] = variant;
+            tune_now = false;
+        }
+    }
+    if (tune_now) {
+        // trial: the first K steps run each candidate on K/nc consecutive
+        // launches; a candidate's time is the mean of its launches after the
+        // first (the first one inherits the cache state the previous candidate
+        // left); a candidate other than the first must beat it by 1 %
         if (!ctx->tune_ev[0][0])
             for (int k = 0; k < 2; ++k)
-                for (int j = 0; j < 16; ++j) HIP_TRY(hipEventCreate(&ctx->tune_ev[k][j]));
-        ctx->tune_steps = m >= 16 ? 16 : 8;
+                for (int j = 0; j < kTuneSteps; ++j) HIP_TRY(hipEventCreate(&ctx->tune_ev[k][j]));
         if ((st = enqueue_fine(ctx, t, prec, deg, -1, m, nreg, sp, stats != nullptr, trace != nullptr, s, false)) !=
             MCPR_OK)
             return st;
         HIP_TRY(hipEventSynchronize(ctx->tune_ev[1][ctx->tune_steps - 1]));
         float tv[4] = {0, 0, 0, 0};
-        const int per = ctx->tune_steps / 4;
+        const int per = ctx->tune_steps / ctx->tune_nc;
         for (int j = 0; j < ctx->tune_steps; ++j) {
             if (j % per == 0) continue;
             float ms = 0.0f;
@@ -418,9 +455,9 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
             tv[j / per] += ms / (float)(per - 1);
         }
         int pick = 0;
-        for (int v = 1; v < 4; ++v)
-            if (tv[v] < 0.99f * tv[0] && tv[v] < tv[pick]) pick = v;
-        ctx->tuned[tkey] = pick;
+        for (int c = 1; c < ctx->tune_nc; ++c)
+            if (tv[c] < 0.99f * tv[0] && tv[c] < tv[pick]) pick = c;
+        ctx->tuned[tkey] = ctx->tune_cand[pick];
     } else if (ctx->profile) {
         if (ctx->prof_used == ctx->prof0.size()) {
             hipEvent_t e0, e1;
@@ -519,15 +556,17 @@ void mcpr_destroy(mcpr_ctx *ctx) {
                       &ctx->shift[1],      &ctx->rpart,       &ctx->rshift[0],   &ctx->rshift[1],   &ctx->maps,
                       &ctx->recs,          &ctx->adj_ckpt,    &ctx->adj_traj,    &ctx->adj_lam[0],  &ctx->adj_lam[1],
                       &ctx->adj_part[0],   &ctx->adj_part[1], &ctx->adj_acc,     &ctx->adj_trace,   &ctx->adj_grad,
-                      &ctx->trace,         &ctx->mv};
+                      &ctx->adj_sums,      &ctx->adj_items,   &ctx->adj_blocks,  &ctx->trace,       &ctx->mv};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->staging.p) (void)hipHostFree(ctx->staging.p);
     if (ctx->staged) (void)hipEventDestroy(ctx->staged);
     for (hipEvent_t e : ctx->prof0) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->prof1) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->aprof0) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->aprof1) (void)hipEventDestroy(e);
     for (int k = 0; k < 2; ++k)
-        for (int j = 0; j < 16; ++j)
+        for (int j = 0; j < kTuneSteps; ++j)
             if (ctx->tune_ev[k][j]) (void)hipEventDestroy(ctx->tune_ev[k][j]);
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->gin) (void)hipEventDestroy(ctx->gin);
@@ -564,6 +603,28 @@ mcpr_status mcpr_profile_read(mcpr_ctx *ctx, double *em_ms, int64_t *em_launches
     if (reset) {
         ctx->prof_used = 0;
         ctx->prof_launches = 0;
+    }
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_profile_read_adjoint(mcpr_ctx *ctx, double *ms, int64_t *launches, int64_t *particle_steps,
+                                      int32_t reset) {
+    if (!ctx) return MCPR_E_INVALID_ARG;
+    HIP_TRY(hipSetDevice(ctx->device));
+    double ms_total = 0.0;
+    for (size_t i = 0; i < ctx->aprof_used; ++i) {
+        HIP_TRY(hipEventSynchronize(ctx->aprof1[i]));
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, ctx->aprof0[i], ctx->aprof1[i]));
+        ms_total += t;
+    }
+    if (ms) *ms = ms_total;
+    if (launches) *launches = ctx->aprof_launches;
+    if (particle_steps) *particle_steps = ctx->aprof_ps;
+    if (reset) {
+        ctx->aprof_used = 0;
+        ctx->aprof_launches = 0;
+        ctx->aprof_ps = 0;
     }
     return MCPR_OK;
 }
@@ -716,18 +777,34 @@ mcpr_status mcpr_adjoint(mcpr_ctx *ctx, const mcpr_problem *problem, const mcpr_
     et.x = ctx->adj_traj.p;
     build_tables(problem, &et, 1, tt);
     tt.items[0].traj = Ps;
-    const int nsc = tt.total_sc;
+    // The backward steps have sums of their own (the adjoint's ensemble sums
+    // and the gradient sums), so they need not share the forward superchunks:
+    // one quad per thread below 262144 particles, where a single ensemble's
+    // launch is latency bound and short blocks finish sooner.
+    Tables tb = tt;
+    {
+        WorkItem &w = tb.items[0];
+        w.R = P < kAdjointSmall ? 1 : mcpr::kMaxQuadsPerThread;
+        w.nsc = (int32_t)mcpr::superchunks(P, w.R);
+        tb.blocks.clear();
+        for (int sc = 0; sc < w.nsc; ++sc) tb.blocks.push_back(make_int2(0, sc));
+        tb.total_sc = w.nsc;
+    }
+    const int nsc = tb.total_sc;
     for (int b = 0; b < 2; ++b) {
         if ((st = ensure(ctx, ctx->adj_lam[b], (size_t)Ps * sizeof(double))) != MCPR_OK) return st;
         if ((st = ensure(ctx, ctx->adj_part[b], (size_t)nsc * sizeof(double2))) != MCPR_OK) return st;
     }
     if ((st = ensure(ctx, ctx->adj_acc, (size_t)nsc * 10 * sizeof(double))) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->adj_grad, 10 * sizeof(double))) != MCPR_OK) return st;
-    if ((st = upload(ctx, tt, nullptr, 0, s)) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->adj_sums, sizeof(double2))) != MCPR_OK) return st;
+    // more than 256 superchunks: one launch forms the adjoint's ensemble sums
+    double2 *sums = nsc > mcpr::kThreads ? (double2 *)ctx->adj_sums.p : nullptr;
+    if ((st = upload_into(ctx, tb, ctx->adj_items, ctx->adj_blocks, nullptr, 0, s)) != MCPR_OK) return st;
     HIP_TRY(hipMemsetAsync(ctx->adj_acc.p, 0, (size_t)nsc * 10 * sizeof(double), s));
-    const WorkItem *items = (const WorkItem *)ctx->items.p;
-    const int2 *blocks = (const int2 *)ctx->blocks.p;
-    const int nb = (int)tt.blocks.size();
+    const WorkItem *items = (const WorkItem *)ctx->adj_items.p;
+    const int2 *blocks = (const int2 *)ctx->adj_blocks.p;
+    const int nb = (int)tb.blocks.size();
     double *lam[2] = {(double *)ctx->adj_lam[0].p, (double *)ctx->adj_lam[1].p};
     double2 *apart[2] = {(double2 *)ctx->adj_part[0].p, (double2 *)ctx->adj_part[1].p};
     const bool zprev = p.coef.bm != 0.0 || p.coef.bv != 0.0;
@@ -748,6 +825,17 @@ mcpr_status mcpr_adjoint(mcpr_ctx *ctx, const mcpr_problem *problem, const mcpr_
         tt.items[0].step0 = (n0 + n) * m;
         if ((st = upload(ctx, tt, nullptr, 0, s)) != MCPR_OK) return st;
         if ((st = fine_sequence(ctx, tt, prec, m, p.n_regions, sp, nullptr, nullptr, s)) != MCPR_OK) return st;
+        const bool prof = ctx->profile;
+        if (prof) {
+            if (ctx->aprof_used == ctx->aprof0.size()) {
+                hipEvent_t e0, e1;
+                HIP_TRY(hipEventCreate(&e0));
+                HIP_TRY(hipEventCreate(&e1));
+                ctx->aprof0.push_back(e0);
+                ctx->aprof1.push_back(e1);
+            }
+            HIP_TRY(hipEventRecord(ctx->aprof0[ctx->aprof_used], s));
+        }
         for (int j = m - 1; j >= 0; --j) {
             mcpr::AdjStep a{};
             a.m = tm(n, j);
@@ -760,10 +848,17 @@ mcpr_status mcpr_adjoint(mcpr_ctx *ctx, const mcpr_problem *problem, const mcpr_
                 a.dv = 2.0 * dL_dmoments[2 * (n - 1) + 1] * invP;
                 a.mdir = tm(n - 1, m);
             }
-            HIP_TRY(mcpr::launch_adj_step(prec, items, blocks, nb, traj + (size_t)j * Ps * esz, lam[cur], lam[cur ^ 1],
-                                          a, apart[pc], apart[pc ^ 1], (double *)ctx->adj_acc.p, s));
+            HIP_TRY(mcpr::launch_adj_step(prec, items, 1, blocks, nb, traj + (size_t)j * Ps * esz, lam[cur],
+                                          lam[cur ^ 1], a, apart[pc], sums, apart[pc ^ 1], (double *)ctx->adj_acc.p,
+                                          s));
             cur ^= 1;
             pc ^= 1;
+        }
+        if (prof) {
+            HIP_TRY(hipEventRecord(ctx->aprof1[ctx->aprof_used], s));
+            ctx->aprof_used++;
+            ctx->aprof_launches += m;
+            ctx->aprof_ps += P * m;
         }
     }
     HIP_TRY(mcpr::launch_adj_reduce(items, 1, (const double *)ctx->adj_acc.p, (double *)ctx->adj_grad.p, s));
@@ -973,7 +1068,16 @@ struct Instance {
     bool done = false;
     bool have_fit = false;
     double kappa = 0.0, pstar = 0.0;
+    std::vector<double> fgiven;      // [(N+1)][I] given fractions (empty: the method's own)
 };
+
+// The given fractions replace those of macro state n (the exact-fraction
+// reference variant); the cached coarse outputs keep the fractions they were
+// computed with.
+void apply_given(const Instance &in, int I, int n, Macro &o) {
+    if (in.fgiven.empty()) return;
+    for (int r = 0; r < I; ++r) o.f[r] = in.fgiven[(size_t)n * I + r];
+}
 
 } // namespace
 
@@ -1108,9 +1212,11 @@ mcpr_status mcpr_parareal_init(mcpr_parareal *pr, int32_t sample_u0, mcpr_stream
         for (const RegionStats &r : in.st0)
             if (r.nonfinite) return fail(ctx, MCPR_E_NONFINITE, "instance %d: non-finite initial particles", i);
         in.rho[0] = macro_of(in.st0.data(), I, in.P);
+        apply_given(in, I, 0, in.rho[0]);
         for (int n = 0; n < N; ++n) {
             in.rho[n + 1] = coarse_step(in.pb, in.rho[n]);
             in.cache[n] = in.rho[n + 1];
+            apply_given(in, I, n + 1, in.rho[n + 1]);
         }
         std::fill(in.flags.begin(), in.flags.end(), 0);
         for (int n = 1; n <= N; ++n) {
@@ -1239,6 +1345,7 @@ mcpr_status mcpr_parareal_iterate(mcpr_parareal *pr, double *delta_out, mcpr_str
             if (bit_equal(a, c, I) || n < k) {
                 o = macro_of(b, I, in.P);
                 for (int r = 0; r < I; ++r) fl[r] = 0;
+                apply_given(in, I, n + 1, o);
                 continue;
             }
             const size_t e = ebase + (size_t)(n - k); // this slice's ensemble (n >= k here)
@@ -1301,6 +1408,7 @@ mcpr_status mcpr_parareal_iterate(mcpr_parareal *pr, double *delta_out, mcpr_str
                 o.f[0] = phat[n + 1];
                 o.f[1] = 1.0 - phat[n + 1];
             }
+            apply_given(in, I, n + 1, o);
         }
 
         // successive-iterate difference of the global moments
@@ -1335,6 +1443,22 @@ mcpr_status mcpr_parareal_iterate(mcpr_parareal *pr, double *delta_out, mcpr_str
     }
     HIP_TRY(hipStreamSynchronize(s));
     pr->k = k + 1;
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_parareal_set_fractions(mcpr_parareal *pr, int32_t inst, const double *fractions) {
+    if (!pr) return MCPR_E_INVALID_ARG;
+    if (inst < 0 || inst >= (int)pr->inst.size()) return fail(pr->ctx, MCPR_E_INVALID_ARG, "instance %d", inst);
+    Instance &in = pr->inst[inst];
+    if (!fractions) {
+        in.fgiven.clear();
+        return MCPR_OK;
+    }
+    const size_t n = (size_t)(pr->N + 1) * pr->I;
+    for (size_t j = 0; j < n; ++j)
+        if (!(fractions[j] >= 0.0) || !std::isfinite(fractions[j]))
+            return fail(pr->ctx, MCPR_E_INVALID_ARG, "fraction %zu is negative or not finite", j);
+    in.fgiven.assign(fractions, fractions + n);
     return MCPR_OK;
 }
 

@@ -21,21 +21,18 @@ namespace mcpr {
 constexpr int kThreads = 256;        // threads per block; fixed by the canonical tree
 constexpr int kQuadsPerChunk = kThreads; // quads per thread-row of a superchunk
 constexpr int kMaxRegions = 8;
-constexpr int kMaxSuperchunksTarget = 256;
 
-// Quads per thread R of a superchunk (power of two, 1..16): the smallest R
-// with at most kMaxSuperchunksTarget superchunks (P <= 4.2e6); larger
-// ensembles keep R = 16 and have more superchunks (shorter blocks stream
-// HBM better than fewer long ones).
-constexpr int kMaxQuadsPerThread = 16;
-inline int canonical_quads_per_thread(int64_t P) {
-    int64_t quads = (P + 3) / 4;
-    int R = 1;
-    while (R < kMaxQuadsPerThread &&
-           (quads + (int64_t)kThreads * R - 1) / ((int64_t)kThreads * R) > kMaxSuperchunksTarget)
-        R *= 2;
-    return R;
-}
+// Quads per thread R of a superchunk: 1 below 65536 particles (at most 64
+// superchunks; short blocks suit small ensembles, whose launches are latency
+// bound), else 4 (1024 quads, 16 KB of fp32 state per superchunk; every
+// kernel issues a thread's four 16-byte loads before using them).  Measured
+// on MI355X over ensembles of 1e4 to 1.6e7 particles, four quads per thread
+// stream HBM better than shorter or longer superchunks; large ensembles simply
+// have many superchunks, whose partials the step kernel's separate-combine
+// variant reduces once per step.
+constexpr int kMaxQuadsPerThread = 4;
+constexpr int64_t kSmallEnsemble = 65536;
+inline int canonical_quads_per_thread(int64_t P) { return P < kSmallEnsemble ? 1 : kMaxQuadsPerThread; }
 
 inline int64_t superchunks(int64_t P, int R) {
     int64_t quads = (P + 3) / 4;

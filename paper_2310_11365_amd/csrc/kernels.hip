@@ -312,14 +312,14 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
     const int64_t P = W.P;
     const int R = W.R;
 
-    // the first group of a full superchunk's quads does not depend on the mean
-    // field: issue its loads before the combine so the two latencies overlap
+    // a full superchunk's quads (R <= 4 per thread) do not depend on the mean
+    // field: issue their loads before the combine so the two latencies overlap
     const int64_t base = (int64_t)sc * 4 * kThreads * R; // first particle of the superchunk
     const bool full = base + (int64_t)4 * kThreads * R <= P;
-    T v[4][4];
+    T v[kMaxQuadsPerThread][4];
     if (full) {
 #pragma unroll
-        for (int g = 0; g < 4; ++g)
+        for (int g = 0; g < kMaxQuadsPerThread; ++g)
             if (g < R) gload_quad<NT>(x + base, (uint32_t)(g * kThreads + threadIdx.x), v[g]);
     }
 
@@ -356,29 +356,22 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
         const T *xs = x + base;
         T *ys = y + base;
         const uint32_t qb = (uint32_t)(base >> 2) + threadIdx.x;
-        for (int r0 = 0; r0 < R; r0 += 4) {
-            if (r0 > 0) {
 #pragma unroll
-                for (int g = 0; g < 4; ++g)
-                    if (r0 + g < R) gload_quad<NT>(xs, (uint32_t)((r0 + g) * kThreads + threadIdx.x), v[g]);
-            }
+        for (int g = 0; g < kMaxQuadsPerThread; ++g) {
+            if (g < R) {
+                const Words4 w = philox4x32_10(qb + (uint32_t)(g * kThreads), step, inst, 0u, k0, k1);
+                T z[4], d[4];
+                box_muller4(w, z);
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                if (r0 + g < R) {
-                    const Words4 w = philox4x32_10(qb + (uint32_t)((r0 + g) * kThreads), step, inst, 0u, k0, k1);
-                    T z[4], d[4];
-                    box_muller4(w, z);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        v[g][e] = em_update<T, DEG>(v[g][e], z[e], c0, c1, c2, c3, e0, e1);
-                        d[e] = v[g][e] - shift;
-                    }
-                    gstore_quad<NT>(ys, (uint32_t)((r0 + g) * kThreads + threadIdx.x), v[g]);
-                    double q1, q2;
-                    quad_leaf(d, q1, q2);
-                    a1 += q1;
-                    a2 += q2;
+                for (int e = 0; e < 4; ++e) {
+                    v[g][e] = em_update<T, DEG>(v[g][e], z[e], c0, c1, c2, c3, e0, e1);
+                    d[e] = v[g][e] - shift;
                 }
+                gstore_quad<NT>(ys, (uint32_t)(g * kThreads + threadIdx.x), v[g]);
+                double q1, q2;
+                quad_leaf(d, q1, q2);
+                a1 += q1;
+                a2 += q2;
             }
         }
     } else {
@@ -481,14 +474,29 @@ __global__ __launch_bounds__(kThreads) void k_adj_init(const WorkItem *__restric
     if (threadIdx.x == 0) part_out[W.part_off + bt.y] = make_double2(sm[0], sm[1]);
 }
 
+// Ensemble sums of each item's superchunk partials, one block per item (the
+// adjoint step's combine for ensembles of many superchunks).
+__global__ __launch_bounds__(kThreads) void k_item_sums(const WorkItem *__restrict__ items,
+                                                        const double2 *__restrict__ part_in,
+                                                        double2 *__restrict__ sums) {
+    __shared__ double lds[8];
+    const WorkItem &W = items[blockIdx.x];
+    double S1, S2;
+    ensemble_sums(part_in + W.part_off, W.nsc, S1, S2, lds);
+    if (threadIdx.x == 0) sums[blockIdx.x] = make_double2(S1, S2);
+}
+
 // One backward step s: lambda_in = lambda_{s+1} -> lambda_out = lambda_s.
 // acc: per-superchunk running gradient sums [nsc][10] (fp64, one writer each).
-template <typename T>
+// PRE: the two ensemble sums come from k_item_sums instead of every block
+// combining the partials itself (same order, same bits).
+template <typename T, bool PRE>
 __global__ __launch_bounds__(kThreads) void k_adj_step(const WorkItem *__restrict__ items,
                                                        const int2 *__restrict__ blocks, const T *__restrict__ xs_,
                                                        const double *__restrict__ lam_in,
                                                        double *__restrict__ lam_out, AdjStep a,
                                                        const double2 *__restrict__ part_in,
+                                                       const double2 *__restrict__ sums,
                                                        double2 *__restrict__ part_out, double *__restrict__ acc) {
     __shared__ double lds[4 * 8];
     const int2 bt = blocks[blockIdx.x];
@@ -497,21 +505,49 @@ __global__ __launch_bounds__(kThreads) void k_adj_step(const WorkItem *__restric
     const int R = W.R;
     const double dt = W.dt, sdt = W.sdt;
     const double *c = W.c;
+    // this thread's quads of the state and of lambda_{s+1}: loads issued
+    // before the combine so that their latencies overlap
+    constexpr int Q = kMaxQuadsPerThread;
+    const int64_t base = (int64_t)bt.y * 4 * kThreads * R;
+    T xq[Q][4];
+    double lq[Q][4];
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+        const int64_t p = base + 4 * (int64_t)(r * kThreads + threadIdx.x);
+        if (r < R && p < P) {
+            load_quad(xs_, p, P, xq[r]);
+            if (p + 3 < P) {
+                const double2 l01 = *reinterpret_cast<const double2 *>(lam_in + p);
+                const double2 l23 = *reinterpret_cast<const double2 *>(lam_in + p + 2);
+                lq[r][0] = l01.x; lq[r][1] = l01.y; lq[r][2] = l23.x; lq[r][3] = l23.y;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) lq[r][e] = p + e < P ? lam_in[p + e] : 0.0;
+            }
+        }
+    }
+
     // mean-field adjoint scalars of step s from the previous launch's partials
     double Sl, Slz;
-    ensemble_sums(part_in + W.part_off, W.nsc, Sl, Slz, lds);
+    if (PRE) {
+        const double2 sv = sums[bt.x];
+        Sl = sv.x;
+        Slz = sv.y;
+    } else {
+        ensemble_sums(part_in + W.part_off, W.nsc, Sl, Slz, lds);
+    }
     const double gm = c[4] * dt * Sl + c[8] * sdt * Slz;
     const double gv = c[5] * dt * Sl + c[9] * sdt * Slz;
     const double c1 = gm / (double)P, c2 = 2.0 * gv / (double)P;
 
     double g[6] = {0, 0, 0, 0, 0, 0}; // sum l, lx, lx^2, lx^3, lz, lxz   (l = lambda_{s+1})
     double nx0 = 0.0, nx1 = 0.0;      // sum lambda_s, sum lambda_s z_{s-1}
-    const int64_t base = (int64_t)bt.y * 4 * kThreads * R;
-    for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
         const int64_t p = base + 4 * (int64_t)(r * kThreads + threadIdx.x);
-        if (p < P) {
-            T xv[4], z[4], zp[4];
-            load_quad(xs_, p, P, xv);
+        if (r < R && p < P) {
+            T z[4], zp[4];
+            const T *xv = xq[r];
             const uint32_t q = (uint32_t)(p >> 2);
             const Words4 w = philox4x32_10(q, (uint32_t)a.step, (uint32_t)W.inst, 0u, W.key0, W.key1);
             box_muller4(w, z);
@@ -524,7 +560,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_step(const WorkItem *__restric
             for (int e = 0; e < 4; ++e) {
                 const bool ok = p + e < P;
                 const double x = (double)xv[e], zz = (double)z[e];
-                const double l = ok ? lam_in[p + e] : 0.0;
+                const double l = lq[r][e];
                 const double ax = c[1] + x * (2.0 * c[2] + 3.0 * c[3] * x);
                 double lo = l * (1.0 + ax * dt + c[7] * sdt * zz) + c1 + c2 * (x - a.m);
                 lo += a.dm + a.dv * (x - a.mdir);
@@ -1000,15 +1036,28 @@ hipError_t launch_adj_init(int prec, const WorkItem *items, const int2 *blocks, 
     return hipGetLastError();
 }
 
-hipError_t launch_adj_step(int prec, const WorkItem *items, const int2 *blocks, int nblocks, const void *xs,
-                           const double *lam_in, double *lam_out, const AdjStep &a, const double2 *part_in,
-                           double2 *part_out, double *acc, hipStream_t s) {
-    if (prec == 0)
-        hipLaunchKernelGGL(k_adj_step<double>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, (const double *)xs,
-                           lam_in, lam_out, a, part_in, part_out, acc);
+template <typename T>
+static void adj_step_variant(bool pre, const WorkItem *items, const int2 *blocks, int nblocks, const void *xs,
+                             const double *lam_in, double *lam_out, const AdjStep &a, const double2 *part_in,
+                             const double2 *sums, double2 *part_out, double *acc, hipStream_t s) {
+    if (pre)
+        hipLaunchKernelGGL((k_adj_step<T, true>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks,
+                           (const T *)xs, lam_in, lam_out, a, part_in, sums, part_out, acc);
     else
-        hipLaunchKernelGGL(k_adj_step<float>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, (const float *)xs,
-                           lam_in, lam_out, a, part_in, part_out, acc);
+        hipLaunchKernelGGL((k_adj_step<T, false>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks,
+                           (const T *)xs, lam_in, lam_out, a, part_in, sums, part_out, acc);
+}
+
+hipError_t launch_adj_step(int prec, const WorkItem *items, int n_items, const int2 *blocks, int nblocks,
+                           const void *xs, const double *lam_in, double *lam_out, const AdjStep &a,
+                           const double2 *part_in, double2 *sums, double2 *part_out, double *acc, hipStream_t s) {
+    if (sums) hipLaunchKernelGGL(k_item_sums, dim3(n_items), dim3(kThreads), 0, s, items, part_in, sums);
+    if (prec == 0)
+        adj_step_variant<double>(sums != nullptr, items, blocks, nblocks, xs, lam_in, lam_out, a, part_in, sums,
+                                 part_out, acc, s);
+    else
+        adj_step_variant<float>(sums != nullptr, items, blocks, nblocks, xs, lam_in, lam_out, a, part_in, sums,
+                                part_out, acc, s);
     return hipGetLastError();
 }
 

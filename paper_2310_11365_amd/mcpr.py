@@ -92,6 +92,8 @@ def lib() -> ctypes.CDLL:
         L.mcpr_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_int64), i32]
         L.mcpr_profile_read.restype = st
+        L.mcpr_profile_read_adjoint.argtypes = L.mcpr_profile_read.argtypes
+        L.mcpr_profile_read_adjoint.restype = st
         L.mcpr_set_graphs.argtypes = [vp, i32]
         L.mcpr_set_graphs.restype = st
         L.mcpr_set_tuning.argtypes = [vp, i32]
@@ -115,6 +117,8 @@ def lib() -> ctypes.CDLL:
         L.mcpr_parareal_iteration.restype = i32
         L.mcpr_parareal_macro.argtypes = [vp, i32, vp, vp]
         L.mcpr_parareal_macro.restype = st
+        L.mcpr_parareal_set_fractions.argtypes = [vp, i32, vp]
+        L.mcpr_parareal_set_fractions.restype = st
         L.mcpr_parareal_flags.argtypes = [vp, i32, vp]
         L.mcpr_parareal_flags.restype = st
         L.mcpr_parareal_slot.argtypes = [vp, i32, i32, ctypes.POINTER(vp)]
@@ -208,11 +212,19 @@ class Context:
                                             1 if reset else 0))
         return ms.value, n.value, ps.value
 
+    def profile_read_adjoint(self, reset: bool = True):
+        """(elapsed ms of the adjoint's backward step launches, backward steps, particle-steps)."""
+        ms, n, ps = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().mcpr_profile_read_adjoint(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(ps),
+                                                    1 if reset else 0))
+        return ms.value, n.value, ps.value
+
     def set_graphs(self, on: bool):
         self._check(lib().mcpr_set_graphs(self._h, 1 if on else 0))
 
     def set_tuning(self, mode: int):
-        """-1: autotune the step-kernel variant per launch shape; 0..3: force one."""
+        """-1: autotune the step-kernel variant per launch shape; 0..3: force one
+        (bit 0 non-temporal, bit 1 separate mean-field combine)."""
         self._check(lib().mcpr_set_tuning(self._h, int(mode)))
 
     def tuned_variants(self):
@@ -433,6 +445,15 @@ class Parareal:
     @property
     def iteration(self) -> int:
         return int(lib().mcpr_parareal_iteration(self._h))
+
+    def set_fractions(self, fractions, i=0):
+        """Given particle fractions [N+1, I] of every macro state of instance i
+        (None: the method's own), from the next init or iterate on."""
+        if fractions is None:
+            self.ctx._check(lib().mcpr_parareal_set_fractions(self._h, i, None))
+            return
+        self._given = np.ascontiguousarray(fractions, dtype=np.float64).reshape(self.N + 1, self.I)
+        self.ctx._check(lib().mcpr_parareal_set_fractions(self._h, i, self._given.ctypes.data))
 
     def macro(self, i=0):
         rho = np.zeros((self.N + 1, self.I, 3))

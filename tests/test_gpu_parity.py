@@ -134,7 +134,7 @@ def test_fine_fp64_ou_matches_oracle(mc, ctx, oracle, slice_index):
     assert np.max(np.abs(x.cpu().numpy() - ox)) < 1e-12
 
 
-@pytest.mark.parametrize("P", [1, 3, 4, 5, 1029, 262_147])
+@pytest.mark.parametrize("P", [1, 3, 4, 5, 1029, 65_535, 65_537, 262_147])
 def test_fine_fp64_ragged_sizes(mc, ctx, oracle, P):
     """Ragged ensembles: tail quads, one and several superchunks."""
     pr = W.make_problem(W.dz_coef(), W.P0(W.P0_MIXTURE, 0.5, -1.0, 0.1, 1.0, 0.1), 0.2, 10, 1e-3, (0.0,),
@@ -273,11 +273,13 @@ def test_match_resample_point_mass(mc, ctx, oracle):
 
 
 # ---------------------------------------------------------------------------- Parareal
-def _compare_parareal(mc, ctx, oracle, wl, K, tol):
+def _compare_parareal(mc, ctx, oracle, wl, K, tol, fractions=None):
     pr = wl.problem
     para = mc.Parareal([pr], [wl.P], ctx, tol=0.0)
+    if fractions is not None:
+        para.set_fractions(fractions)
     para.init()
-    ores = oracle.parareal(pr, oracle.sample_p0(pr, wl.P), K)
+    ores = oracle.parareal(pr, oracle.sample_p0(pr, wl.P), K, fractions=fractions)
     rho, glob = para.macro(0)
     assert rel_close(glob, ores["glob"][0], tol)
     for k in range(min(K, ores["iterations"])):
@@ -307,6 +309,33 @@ def test_parareal_bimodal_fp64_matches_oracle(mc, ctx, oracle, model):
     wl = W.dz_bimodal(P=20_000, N=8, T=2.0, precision=W.FP64)
     wl.problem.coarse_model = model
     _compare_parareal(mc, ctx, oracle, wl, 8, TOL64)
+
+
+def test_parareal_unimodal_coarse_on_bimodal_fp64(mc, ctx, oracle):
+    """The unimodal variant on the bimodal problem (one region, Gaussian
+    coarse model with three sigma points; the first variant of Sec. 5.4)."""
+    wl = W.dz_bimodal(P=20_000, N=8, T=2.0, precision=W.FP64)
+    wl.problem.splits = ()
+    wl.problem.coarse_model = W.COARSE_GAUSS3
+    _compare_parareal(mc, ctx, oracle, wl, 8, TOL64)
+
+
+def test_parareal_exact_fractions_fp64_matches_oracle(mc, ctx, oracle):
+    """Reference variant with the exact particle fractions (those of the
+    oracle's serial solution) in every macro state, against the oracle run
+    with the same fractions."""
+    wl = W.dz_bimodal(P=20_000, N=8, T=2.0, precision=W.FP64)
+    pr = wl.problem
+    _, st = oracle.serial(pr, oracle.sample_p0(pr, wl.P))
+    fr = st[:, :pr.n_regions]["n"] / wl.P
+    _compare_parareal(mc, ctx, oracle, wl, 8, TOL64, fractions=fr)
+    para = mc.Parareal([pr], [wl.P], ctx)
+    for v in (-0.1, np.nan, np.inf):
+        bad = fr.copy()
+        bad[2, 0] = v
+        with pytest.raises(mc.MCPRError):
+            para.set_fractions(bad)
+    para.close()
 
 
 def test_parareal_exactness_fp32_bitwise(mc, ctx):
@@ -405,12 +434,13 @@ def _adj_problem(kind, prec, T=0.2, N=4, dt=1e-2):
     return W.make_problem(c, W.P0(W.P0_MIXTURE, 0.5, -1.0, 0.1, 1.0, 0.1), T, N, dt, (0.0,), precision=prec)
 
 
-@pytest.mark.parametrize("kind", ["ou", "dz"])
-def test_adjoint_fp64_matches_oracle(mc, ctx, oracle, kind):
+@pytest.mark.parametrize("kind,P,T,N", [("ou", 3001, 0.8, 4), ("dz", 3001, 0.8, 4), ("dz", 1_100_003, 0.1, 2)])
+def test_adjoint_fp64_matches_oracle(mc, ctx, oracle, kind, P, T, N):
     """J and dJ/d(a0..bv) of J = sum_n (m_n - M_n)^2 + (v_n - V_n)^2 against the
-    oracle's adjoint, every coefficient active (P = 3001, 4 slices of 20 steps)."""
-    pr = _adj_problem(kind, W.FP64, T=0.8, N=4, dt=1e-2)
-    P = 3001
+    oracle's adjoint, every coefficient active (P = 3001: 4 slices of 20 steps;
+    P = 1.1e6: more than 256 superchunks, so the adjoint's ensemble sums come
+    from their own launch)."""
+    pr = _adj_problem(kind, W.FP64, T=T, N=N, dt=1e-2)
     prop = mc.Propagator(pr, ctx)
     x = prop.new_particles(P)
     prop.sample(x)
@@ -598,24 +628,27 @@ def test_graph_replays_match_direct_launches(mc, ctx):
 
 
 # ---------------------------------------------------------------------------- launch variants
-@pytest.mark.parametrize("P", [1_000_003, 6_000_000])
-def test_step_variants_bitwise(mc, ctx, P):
+@pytest.mark.parametrize("sizes", [[1_000_003], [6_000_000], [70_001, 65_535, 300_001, 5_003, 1]],
+                         ids=["R4", "R4-many-superchunks", "mixed-R-batch"])
+def test_step_variants_bitwise(mc, ctx, sizes):
     """The four step-kernel launch variants (non-temporal access, separate
-    mean-field combine) and the autotuned choice give identical bits."""
+    mean-field combine) and the autotuned choice give identical bits, for one
+    ensemble of four-quad superchunks, one with more than 256 superchunks, and
+    a batch mixing one- and four-quad superchunks with ragged ends."""
     import torch
-    pr = W.dz_bimodal(P=P, N=3).problem
+    pr = W.dz_bimodal(N=3).problem
     pc = mc.problem_c(pr)
     ref = None
     for mode in (0, 1, 2, 3, -1):
         c = mc.Context(0)
         c.set_tuning(mode)
-        x = torch.empty(P, dtype=torch.float32, device="cuda")
-        c.init_particles([pc], [mc.ensemble(x, 0)])
-        st = mc.stats_buffer(1, 2)
-        tr = torch.empty((pr.steps_per_slice + 1) * 2, dtype=torch.float64, device="cuda")
+        xs = [torch.empty(P, dtype=torch.float32, device="cuda") for P in sizes]
+        c.init_particles([pc], [mc.ensemble(x, i) for i, x in enumerate(xs)])
+        st = mc.stats_buffer(len(sizes), 2)
+        tr = torch.empty(len(sizes) * (pr.steps_per_slice + 1) * 2, dtype=torch.float64, device="cuda")
         for n in range(2):
-            c.fine_propagate([pc], [mc.ensemble(x, 0, n)], st, tr)
-        got = (x.clone(), st.clone(), tr.clone())
+            c.fine_propagate([pc], [mc.ensemble(x, i, n) for i, x in enumerate(xs)], st, tr)
+        got = [x.clone() for x in xs] + [st.clone(), tr.clone()]
         if mode == -1:
             assert len(c.tuned_variants()) == 1
         c.close()

@@ -414,11 +414,14 @@ def test_transform_acceptance_is_per_particle(oracle):
 
 
 # --------------------------------------------------------------------------- driver
-def _invariant_check(oracle, wl, K):
+def _invariant_check(oracle, wl, K, exact_fractions=False):
     pr = wl.problem
     u0 = oracle.sample_p0(pr, wl.P)
     xs, st_serial = oracle.serial(pr, u0)
-    res = oracle.parareal(pr, u0, K, keep_states=True)
+    fr = None
+    if exact_fractions:
+        fr = st_serial[:, :pr.n_regions]["n"] / wl.P
+    res = oracle.parareal(pr, u0, K, keep_states=True, fractions=fr)
     # serial states, slice by slice
     ser = [u0.copy()]
     x = u0.copy()
@@ -453,6 +456,33 @@ def test_parareal_exactness_bimodal(oracle):
     fl = res["flags"]
     for k in range(fl.shape[0]):
         assert np.all(fl[k, :k + 1] == 0)  # exact slices take the I(a,b,a) branch
+
+
+def test_parareal_exact_fractions_variant(oracle):
+    """Reference variant with the serial solution's particle fractions (the
+    exact-fraction variant of Sec. 5.4): exactness still holds bit for bit,
+    every macro state carries the given fractions at every iteration, and the
+    first iterate differs from the plain variant's (the fractions enter the
+    coarse model's mean-field arguments)."""
+    wl = W.dz_bimodal(P=800, N=6)
+    res, st = _invariant_check(oracle, wl, 6, exact_fractions=True)
+    fr = st[:, :2]["n"] / wl.P
+    for k in range(res["iterations"] + 1):
+        np.testing.assert_array_equal(res["rho"][k, :, :, 0], fr)
+    u0 = oracle.sample_p0(wl.problem, wl.P)
+    plain = oracle.parareal(wl.problem, u0, 2)
+    assert not np.array_equal(plain["glob"][1], res["glob"][1])
+
+
+def test_parareal_given_fractions_unimodal_is_plain(oracle):
+    """With one region every fraction is 1: giving them changes nothing, bit for bit."""
+    wl = W.ou_linear(P=500, N=5)
+    pr = wl.problem
+    u0 = oracle.sample_p0(pr, wl.P)
+    a = oracle.parareal(pr, u0, 3, keep_states=True)
+    b = oracle.parareal(pr, u0, 3, keep_states=True, fractions=np.ones((pr.n_slices + 1, 1)))
+    for key in ("rho", "glob", "flags", "delta", "states"):
+        np.testing.assert_array_equal(a[key], b[key])
 
 
 def test_parareal_linear_converges_fast(oracle):
