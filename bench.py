@@ -64,10 +64,17 @@ def load_traffic(kernel: str, workload: str):
     ent = data.get(f"{kernel}@{workload}")
     if not ent:
         return None
-    src = os.path.join(ROOT, "paper_2310_11365_amd", "csrc", "kernels.hip")
-    if ent.get("kernels_sha") != hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]:
+    if ent.get("kernels_sha") != kernels_sha():
         return None  # the kernel changed since the counters were taken
     return ent.get("bytes_per_launch")
+
+
+def kernels_sha() -> str:
+    """Hash of the device sources (kernels, RNG, shared types)."""
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "rng.hpp", "common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2310_11365_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(seconds_target: float = 15.0):

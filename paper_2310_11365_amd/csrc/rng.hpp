@@ -17,14 +17,22 @@ struct Words4 {
     uint32_t w0, w1, w2, w3;
 };
 
+// Three-input XOR in one instruction: gfx950's v_bitop3_b32 with truth table
+// 0x96 (the parity of the three inputs, whatever their order).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                 uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        // round 0: the callers' counter words 1..3 and the key are uniform
+        // across the wave, so plain XORs leave most of it to the scalar unit
+        const uint32_t n0 = r == 0 ? ((uint32_t)(p1 >> 32) ^ c1 ^ k0) : xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = r == 0 ? ((uint32_t)(p0 >> 32) ^ c3 ^ k1) : xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;

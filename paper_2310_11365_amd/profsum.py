@@ -7,6 +7,7 @@ write the summaries kept under profiles/.
 
     python -m paper_2310_11365_amd.profsum trace DB [--bench-log LOG]
     python -m paper_2310_11365_amd.profsum traffic FETCH_DB WRITE_DB --kernel NAME --copy-mib 1024
+    python -m paper_2310_11365_amd.profsum valu DB --kernel NAME --trace-us MEAN_US
 """
 from __future__ import annotations
 
@@ -40,6 +41,21 @@ def counter_per_dispatch(db_path: str, kernel: str):
     return vals, (max(copies) if copies else None)
 
 
+def counters_of(db_path: str, kernel: str):
+    """Mean value per dispatch of every counter collected for kernel."""
+    cur = sqlite3.connect(db_path).cursor()
+    vals = {}
+    for k, name, v in cur.execute("select kernel_name, counter_name, value from counters_collection"):
+        if k.split("(")[0].replace("void ", "").replace("mcpr::", "") == kernel:
+            vals.setdefault(name, []).append(v)
+    return {n: (statistics.mean(v), len(v)) for n, v in vals.items()}
+
+
+# MI355X: 256 compute units of 4 SIMDs; a wave64 VALU instruction occupies its
+# SIMD for at least 4 cycles (16 lanes per cycle); 2.4 GHz peak engine clock.
+SIMDS, VALU_CYCLES, CLOCK_HZ = 1024, 4, 2.4e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -53,6 +69,10 @@ def main():
     c.add_argument("--kernel", required=True)
     c.add_argument("--copy-mib", type=int, default=1024)
     c.add_argument("--algorithmic-bytes", type=float, required=True)
+    v = sub.add_parser("valu")
+    v.add_argument("db")
+    v.add_argument("--kernel", required=True)
+    v.add_argument("--trace-us", type=float, required=True, help="mean duration of the kernel (kernel trace)")
     a = ap.parse_args()
     if a.cmd == "trace":
         print("| kernel | calls | total us | mean us | % |")
@@ -70,6 +90,18 @@ def main():
                     r = json.loads(line)["roofline"]
                     print(f"\nbench.py, same run: {r['kernel']} mean {r['avg_launch_us']} us per launch by HIP events, "
                           f"{r['achieved']} GB/s algorithmic")
+    elif a.cmd == "valu":
+        cs = counters_of(a.db, a.kernel)
+        print("| counter | mean per dispatch | dispatches |")
+        print("|---|---|---|")
+        for name in sorted(cs):
+            print(f"| {name} | {cs[name][0]:.6g} | {cs[name][1]} |")
+        insts = cs["SQ_INSTS_VALU"][0]
+        t_issue = insts * VALU_CYCLES / (SIMDS * CLOCK_HZ) * 1e6
+        print(f"\nVALU issue time at full rate: {insts:.4g} wave instructions x {VALU_CYCLES} cycles / "
+              f"({SIMDS} SIMDs x {CLOCK_HZ / 1e9:.1f} GHz) = {t_issue:.2f} us; kernel {a.trace_us:.2f} us; "
+              f"ratio {t_issue / a.trace_us:.3f}")
+        print(json.dumps({"valu_insts_per_launch": insts, "valu_issue_us": t_issue, "valu_frac": t_issue / a.trace_us}))
     else:
         kib = a.copy_mib * 1024.0
         out = {}
