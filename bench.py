@@ -16,6 +16,9 @@ Other workloads (--workload): ou_batched (64 independent OU instances, P
 log-uniform in [1e4, 2e6], N = 32: 3.7 GB of state, HBM-resident), dz_large
 (P = 1.6e7, N = 256, 79 steps per slice, 16.4 GB ring, learning; also run to
 tolerance 1e-4), ou_linear (P = 1e4, N = 10, fp64: the latency-bound case),
+gbm (geometric Brownian motion with interaction and multiplicative noise,
+P = 1e6, N = 10, fp32; the parareal section adds the error of the QoI
+sin(X^2) of every slice against the serial solution),
 adjoint_ou / adjoint_dz (the gradient of the slice-end moments' squared error
 through the fine propagator, P = 1e5, T = 2, dt = 1e-3, N = 20, fp32 state:
 one step is one mcpr_adjoint call, i.e. the forward solution with slice-start
@@ -117,6 +120,10 @@ def make_workload(name: str):
         wl = W.dz_large()
         return wl, [wl.P], None, ("dz_large: Desai-Zwanzig as dz_bimodal, P=1.6e7, N=256, T=10, "
                                   "dt=5e-4 (79 steps per slice), fraction-model learning, tol 1e-4")
+    if name == "gbm":
+        wl = W.gbm(P=1_000_000, precision=W.FP32)
+        return wl, [wl.P], None, ("gbm: dX=(-X/2+0.8E[X]+1/3)dt+(s X+s E[X]+1/6)dW, s=sqrt(1/8), X0~N(1,1/4), "
+                                  "P=1e6, T=1, N=10, QoI sin(X^2)")
     if name == "ou_linear":
         wl = W.ou_linear()
         return wl, [wl.P], None, ("ou_linear: dX=(-X+0.5E[X])dt+0.3dW, X0~N(1,0.2^2), P=1e4, N=10, "
@@ -195,7 +202,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="dz_bimodal",
-                    choices=["dz_bimodal", "ou_batched", "dz_large", "ou_linear", "adjoint_ou", "adjoint_dz"])
+                    choices=["dz_bimodal", "ou_batched", "dz_large", "ou_linear", "gbm", "adjoint_ou", "adjoint_dz"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parareal", action="store_true")
     ap.add_argument("--parareal-iters", type=int, default=4)
@@ -306,15 +313,24 @@ def main():
         buf = mcpr.stats_buffer(n_inst, pr.n_regions)
         ctx.moments(pcs, [mcpr.ensemble(x, i, 0, i) for i, x in enumerate(xs)], buf)
         ser = [mcpr.stats_to_numpy(buf, n_inst, pr.n_regions)]
-        for n in range(N):
-            ctx.fine_propagate(pcs, [mcpr.ensemble(x, i, n, i) for i, x in enumerate(xs)], buf)
-            ser.append(mcpr.stats_to_numpy(buf, n_inst, pr.n_regions))
+        qoi_kind = mcpr.QOI_SIN_X2 if wl.name == "gbm" else None
+        qbuf = torch.empty(n_inst, dtype=torch.float64, device="cuda")
+        ser_q = []
+        for n in range(N + 1):
+            if n > 0:
+                ctx.fine_propagate(pcs, [mcpr.ensemble(x, i, n - 1, i) for i, x in enumerate(xs)], buf)
+                ser.append(mcpr.stats_to_numpy(buf, n_inst, pr.n_regions))
+            if qoi_kind is not None:  # the QoI of each slice, timed with the serial run (a small share)
+                ctx.qoi(pcs, [mcpr.ensemble(x, i, n, i) for i, x in enumerate(xs)], qoi_kind, qbuf)
+                ser_q.append(qbuf.cpu().numpy().copy())
         torch.cuda.synchronize()
         t_serial = time.perf_counter() - t0
         del xs
         sm = np.array([[r[i][-1]["mean"] for r in ser] for i in range(n_inst)])
         sv = np.array([[r[i][-1]["var"] for r in ser] for i in range(n_inst)])
         torch.cuda.synchronize()
+        if qoi_kind is not None:
+            para.track_qoi(True)
         t0 = time.perf_counter()
         para.init()
         it = []
@@ -326,8 +342,12 @@ def main():
                 _, glob = para.macro(i)
                 em = max(em, float(np.max(np.abs(glob[:, 0] - sm[i]))))
                 ev = max(ev, float(np.max(np.abs(glob[:, 1] - sv[i]))))
-            it.append({"k": k + 1, "wall_s": round(time.perf_counter() - t0, 4), "delta": float(np.max(delta)),
-                       "E_mean": em, "E_var": ev})
+            rec = {"k": k + 1, "wall_s": round(time.perf_counter() - t0, 4), "delta": float(np.max(delta)),
+                   "E_mean": em, "E_var": ev}
+            if qoi_kind is not None:
+                sq = np.array(ser_q)  # [N+1, n_inst]
+                rec["E_qoi"] = max(float(np.max(np.abs(para.qoi(qoi_kind, i) - sq[:, i]))) for i in range(n_inst))
+            it.append(rec)
             print(f"# parareal k={k + 1} delta={np.max(delta):.3e} E_mean={em:.3e} E_var={ev:.3e}", flush=True)
             if wl.tol > 0 and np.max(delta) <= wl.tol:
                 break

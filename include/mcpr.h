@@ -128,6 +128,16 @@ void mcpr_destroy(mcpr_ctx *ctx);
 const char *mcpr_last_error(const mcpr_ctx *ctx);
 const char *mcpr_version(void);
 
+/* Quantity of interest (Sec. 1.1: the sample average of Phi over the
+ * ensemble; Sec. 5.2 uses Phi(x) = sin(x^2) for the geometric Brownian motion
+ * example): out[e] = (1/P) sum_p Phi(x_p) of ensemble e, Phi evaluated in
+ * fp64 from the state, summed in the canonical order.  out: device array
+ * [n_ens].  Asynchronous.  Errors: MCPR_E_INVALID_ARG for an unknown kind or
+ * a null out, and as mcpr_fine_propagate for the ensembles.                  */
+enum { MCPR_QOI_X = 0, MCPR_QOI_X2 = 1, MCPR_QOI_SIN_X2 = 2 };
+mcpr_status mcpr_qoi(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems, const mcpr_ensemble *ens,
+                     int32_t n_ens, int32_t kind, double *out, mcpr_stream stream);
+
 /* Measurement: when enabled, each fine sweep brackets its run of
  * Euler-Maruyama step launches with a pair of HIP events on the call's
  * stream (launched directly, not from a graph).  mcpr_profile_read waits for
@@ -248,18 +258,34 @@ void mcpr_parareal_destroy(mcpr_parareal *pr);
 
 /* Iteration 0: if sample_u0, draw u0 from p0 into slot 0 (else slot 0 must
  * hold u0); rho_0 = R(u0); rho^0_{n+1} = C_n(rho^0_n); u^0_n = T(rho^0_n, u0)
- * per region.  Synchronises the stream. */
+ * per region.  Waits for the records of u0 (the host needs them) and returns
+ * with the lifting queued on the stream. */
 mcpr_status mcpr_parareal_init(mcpr_parareal *pr, int32_t sample_u0, mcpr_stream stream);
 
 /* One iteration k -> k+1 for every instance that has not stopped: F on the
  * slices n >= k of all instances in one batched sweep, sequential coarse
  * sweep with the iterator on the host, matching on the device.  delta_out
  * (host, may be NULL): [n_inst] max over n of the change of the global mean
- * and variance.  Synchronises the stream. */
+ * and variance.  Waits for the sweep's records (the host needs them) and
+ * returns with the matching queued on the stream: synchronise the stream
+ * before reading the ring. */
 mcpr_status mcpr_parareal_iterate(mcpr_parareal *pr, double *delta_out, mcpr_stream stream);
 
 /* Number of iterations done (k). */
 int32_t mcpr_parareal_iteration(const mcpr_parareal *pr);
+
+/* Quantity of interest of every slice of the current iterate of instance
+ * inst: out (host) [N+1], out[n] = (1/P) sum Phi over u^k_n (mcpr_qoi).  The
+ * ring holds slices k..N only; the slices below k are exact and their values
+ * come from the QoI recorded when each became exact, which needs tracking
+ * (mcpr_parareal_track_qoi) switched on before mcpr_parareal_init, else
+ * MCPR_E_INVALID_ARG once k > 0.  Synchronises the stream. */
+mcpr_status mcpr_parareal_qoi(mcpr_parareal *pr, int32_t inst, int32_t kind, double *out, mcpr_stream stream);
+
+/* QoI tracking: when on, init and every iterate also queue the QoI (every
+ * kind) of the slice that has just become exact (three small reductions of
+ * one ensemble per instance). */
+mcpr_status mcpr_parareal_track_qoi(mcpr_parareal *pr, int32_t on);
 
 /* Given particle fractions for instance inst (the reference variant of
  * Sec. 5.4 that uses the exact particle fractions, e.g. those of a serial
@@ -282,7 +308,10 @@ mcpr_status mcpr_parareal_macro(const mcpr_parareal *pr, int32_t inst, double *r
  * region, 4 empty region. */
 mcpr_status mcpr_parareal_flags(const mcpr_parareal *pr, int32_t inst, int32_t *flags);
 
-/* Device pointer of u^k_n (slice-start state n of the current iteration k). */
+/* Device pointer of u^k_n (slice-start state n of the current iteration k of
+ * instance inst, which stops counting when it reaches its tolerance).  Only
+ * slices n >= k are held (the ring has N+1 slots); n < k gives
+ * MCPR_E_INVALID_ARG. */
 mcpr_status mcpr_parareal_slot(const mcpr_parareal *pr, int32_t inst, int32_t n, void **x);
 
 #ifdef __cplusplus

@@ -20,6 +20,9 @@
  *                      MC-moments Parareal", Sec. 5 protocol).
  *   or_normals4        Box-Muller on the four words of one Philox call.
  *   or_sample_p0       initial law p0 of the SDE (Sec. 1.1, Sec. 5.4 setups).
+ *   or_qoi             empirical mean of a quantity of interest Phi (Sec. 1.1;
+ *                      Phi(x) = sin(x^2) in the geometric Brownian motion
+ *                      example of Sec. 5.2).
  *   or_restrict        restriction R: per-region fraction, mean, variance
  *                      (eq. multimodal_R) and the mixture moments
  *                      (eq. mixture_of_distributions_mean_variance).
@@ -188,6 +191,21 @@ void or_moments(const double *x, int64_t P, double *mean, double *var)
     }
     *mean = m;
     *var = (double)(s2 / (long double)P);
+}
+
+/* Empirical mean of a quantity of interest over the ensemble, (1/P) sum
+   Phi(x_p) (Sec. 1.1, the sample average of Phi; the nonlinear QoI of the
+   geometric Brownian motion example of Sec. 5.2 is Phi(x) = sin(x^2)).
+   kind 0: x, 1: x^2, 2: sin(x^2).                                            */
+double or_qoi(const double *x, int64_t P, int32_t kind)
+{
+    long double s = 0.0L;
+    for (int64_t p = 0; p < P; p++) {
+        double v = x[p];
+        double phi = kind == 0 ? v : (kind == 1 ? v * v : sin(v * v));
+        s += (long double)phi;
+    }
+    return (double)(s / (long double)P);
 }
 
 /* region of x: D_i = [split_{i-1}, split_i), split_0 = -inf, split_I = +inf;

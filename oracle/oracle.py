@@ -83,6 +83,8 @@ def lib():
         L.or_rho_global.argtypes = [ctypes.c_int, dp, dp, dp]
         L.or_fraction_fit.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
         L.or_serial.argtypes = [pp, dp, ctypes.c_int64, ctypes.c_uint32, sp]
+        L.or_qoi.argtypes = [dp, ctypes.c_int64, ctypes.c_int32]
+        L.or_qoi.restype = ctypes.c_double
         L.or_parareal.argtypes = [pp, dp, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_double,
                                   ctypes.c_int32, dp, dp, dp, ctypes.POINTER(ctypes.c_int32), dp, dp]
         L.or_parareal.restype = ctypes.c_int
@@ -150,6 +152,15 @@ def moments(x: np.ndarray):
     m, v = ctypes.c_double(), ctypes.c_double()
     lib().or_moments(_dp(x), x.size, ctypes.byref(m), ctypes.byref(v))
     return m.value, v.value
+
+
+QOI_X, QOI_X2, QOI_SIN_X2 = 0, 1, 2
+
+
+def qoi(x: np.ndarray, kind: int) -> float:
+    """(1/P) sum Phi(x_p); kind 0: x, 1: x^2, 2: sin(x^2)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return float(lib().or_qoi(_dp(x), x.size, kind))
 
 
 def region_of(problem, x: float) -> int:

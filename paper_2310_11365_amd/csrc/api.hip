@@ -686,6 +686,23 @@ mcpr_status mcpr_moments(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_
     return records(ctx, t, p.precision, p.n_regions, splits_of(p), nullptr, true, 0, nullptr, (RegionStats *)stats, s);
 }
 
+mcpr_status mcpr_qoi(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems, const mcpr_ensemble *ens,
+                     int32_t n_ens, int32_t kind, double *out, mcpr_stream stream) {
+    mcpr_status st = check_call(ctx, problems, n_problems, ens, n_ens);
+    if (st != MCPR_OK) return st;
+    if (!out) return fail(ctx, MCPR_E_INVALID_ARG, "out is null");
+    if (kind < MCPR_QOI_X || kind > MCPR_QOI_SIN_X2) return fail(ctx, MCPR_E_INVALID_ARG, "QoI kind %d", kind);
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Tables t;
+    build_tables(problems, ens, n_ens, t);
+    if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->part[0], (size_t)t.total_sc * sizeof(double2))) != MCPR_OK) return st;
+    HIP_TRY(mcpr::launch_qoi(problems[ens[0].problem].precision, kind, (const WorkItem *)ctx->items.p, n_ens,
+                             (const int2 *)ctx->blocks.p, (int)t.blocks.size(), (double2 *)ctx->part[0].p, out, s));
+    return MCPR_OK;
+}
+
 mcpr_status mcpr_fine_propagate(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems,
                                 const mcpr_ensemble *ens, int32_t n_ens, mcpr_region_stats *stats, double *trace,
                                 mcpr_stream stream) {
@@ -1069,6 +1086,8 @@ struct Instance {
     bool have_fit = false;
     double kappa = 0.0, pstar = 0.0;
     std::vector<double> fgiven;      // [(N+1)][I] given fractions (empty: the method's own)
+    int k = 0;                       // this instance's iteration count (it stops early at tol)
+    std::vector<double> qcache;      // [(N+1)][3] QoI of each slice when it became exact
 };
 
 // The given fractions replace those of macro state n (the exact-fraction
@@ -1090,7 +1109,15 @@ struct mcpr_parareal {
     size_t esize;
     std::vector<Instance> inst;
     DevBuf dstats, dmaps;
-    HostBuf hstats;
+    HostBuf hmaps;                 // pinned source of the matching maps
+    hipEvent_t hmaps_done = nullptr; // the last copy out of hmaps has completed
+    // QoI of the newest exact slice of each instance, queued at the end of
+    // init and iterate when tracking is on, harvested at the next call
+    bool track_qoi = false;
+    DevBuf dq;
+    HostBuf hq;
+    hipEvent_t hq_done = nullptr;
+    std::vector<std::pair<int, int>> hq_who; // (instance, slice) of each queued entry
 };
 
 namespace {
@@ -1109,6 +1136,58 @@ mcpr_status fetch(mcpr_parareal *pr, size_t count, std::vector<RegionStats> &out
     out.resize(count);
     HIP_TRY(hipMemcpyAsync(out.data(), pr->dstats.p, count * sizeof(RegionStats), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return MCPR_OK;
+}
+
+// Move the QoI values queued by the previous call into the instances' caches.
+mcpr_status harvest_qoi(mcpr_parareal *pr) {
+    if (pr->hq_who.empty()) return MCPR_OK;
+    mcpr_ctx *ctx = pr->ctx;
+    HIP_TRY(hipEventSynchronize(pr->hq_done));
+    const size_t cnt = pr->hq_who.size();
+    const double *h = (const double *)pr->hq.p;
+    for (size_t j = 0; j < cnt; ++j) {
+        Instance &in = pr->inst[pr->hq_who[j].first];
+        const int n = pr->hq_who[j].second;
+        for (int kind = 0; kind < 3; ++kind) in.qcache[(size_t)n * 3 + kind] = h[kind * cnt + j];
+    }
+    pr->hq_who.clear();
+    return MCPR_OK;
+}
+
+// Queue the QoI (every kind) of slot 0, the newest exact slice, of the given
+// instances; the values arrive in host memory with the stream.
+mcpr_status queue_exact_qoi(mcpr_parareal *pr, const std::vector<int> &insts, mcpr_stream stream) {
+    if (!pr->track_qoi || insts.empty()) return MCPR_OK;
+    mcpr_ctx *ctx = pr->ctx;
+    hipStream_t s = (hipStream_t)stream;
+    mcpr_status st;
+    if ((st = harvest_qoi(pr)) != MCPR_OK) return st;
+    const size_t cnt = insts.size(), bytes = 3 * cnt * sizeof(double);
+    std::vector<mcpr_problem> probs(cnt);
+    std::vector<mcpr_ensemble> ens(cnt);
+    for (size_t j = 0; j < cnt; ++j) {
+        Instance &in = pr->inst[insts[j]];
+        probs[j] = in.pb;
+        ens[j] = mcpr_ensemble{slot_ptr(pr, in, in.k, in.k), in.P, in.inst, in.k, (int)j, 0};
+        pr->hq_who.emplace_back(insts[j], in.k);
+    }
+    if ((st = ensure(ctx, pr->dq, bytes)) != MCPR_OK) return st;
+    if (bytes > pr->hq.cap) {
+        if (pr->hq.p) HIP_TRY(hipHostFree(pr->hq.p));
+        pr->hq.p = nullptr;
+        pr->hq.cap = 0;
+        if (hipHostMalloc(&pr->hq.p, bytes, hipHostMallocDefault) != hipSuccess)
+            return fail(ctx, MCPR_E_OOM, "pinned allocation of %zu bytes failed", bytes);
+        pr->hq.cap = bytes;
+    }
+    if (!pr->hq_done) HIP_TRY(hipEventCreateWithFlags(&pr->hq_done, hipEventDisableTiming));
+    for (int kind = 0; kind < 3; ++kind)
+        if ((st = mcpr_qoi(ctx, probs.data(), (int)cnt, ens.data(), (int)cnt, kind, (double *)pr->dq.p + kind * cnt,
+                           stream)) != MCPR_OK)
+            return st;
+    HIP_TRY(hipMemcpyAsync(pr->hq.p, pr->dq.p, bytes, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(pr->hq_done, s));
     return MCPR_OK;
 }
 
@@ -1161,6 +1240,7 @@ mcpr_status mcpr_parareal_create(mcpr_ctx *ctx, const mcpr_problem *problems, in
         in.cache.resize(pr->N);
         in.rec.resize((size_t)(pr->N + 1) * (pr->I + 1));
         in.flags.assign((size_t)pr->N * pr->I, 0);
+        in.qcache.assign((size_t)(pr->N + 1) * 3, 0.0);
     }
     *out = pr;
     return MCPR_OK;
@@ -1171,6 +1251,11 @@ void mcpr_parareal_destroy(mcpr_parareal *pr) {
     (void)hipDeviceSynchronize();
     if (pr->dstats.p) (void)hipFree(pr->dstats.p);
     if (pr->dmaps.p) (void)hipFree(pr->dmaps.p);
+    if (pr->hmaps.p) (void)hipHostFree(pr->hmaps.p);
+    if (pr->hmaps_done) (void)hipEventDestroy(pr->hmaps_done);
+    if (pr->dq.p) (void)hipFree(pr->dq.p);
+    if (pr->hq.p) (void)hipHostFree(pr->hq.p);
+    if (pr->hq_done) (void)hipEventDestroy(pr->hq_done);
     delete pr;
 }
 
@@ -1207,6 +1292,7 @@ mcpr_status mcpr_parareal_init(mcpr_parareal *pr, int32_t sample_u0, mcpr_stream
     for (int i = 0; i < n_inst; ++i) {
         Instance &in = pr->inst[i];
         in.done = false;
+        in.k = 0;
         in.have_fit = false;
         in.st0.assign(h.begin() + (size_t)i * (I + 1), h.begin() + (size_t)(i + 1) * (I + 1));
         for (const RegionStats &r : in.st0)
@@ -1254,9 +1340,13 @@ mcpr_status mcpr_parareal_init(mcpr_parareal *pr, int32_t sample_u0, mcpr_stream
                                          (int)t.blocks.size(), splits_of(pr->inst[0].pb),
                                          (const RegionMap *)ctx->maps.p, s));
     }
-    HIP_TRY(hipStreamSynchronize(s));
+    // no final synchronisation: the lifting is ordered on the stream, and the
+    // host has already taken everything it needs
     pr->k = 0;
-    return MCPR_OK;
+    pr->hq_who.clear();
+    std::vector<int> all(n_inst);
+    for (int i = 0; i < n_inst; ++i) all[i] = i;
+    return queue_exact_qoi(pr, all, stream);
 }
 
 mcpr_status mcpr_parareal_iterate(mcpr_parareal *pr, double *delta_out, mcpr_stream stream) {
@@ -1276,7 +1366,7 @@ mcpr_status mcpr_parareal_iterate(mcpr_parareal *pr, double *delta_out, mcpr_str
         if (in.done || k >= N) continue;
         probs.push_back(in.pb);
         for (int n = k; n < N; ++n) {
-            ens.push_back(mcpr_ensemble{slot_ptr(pr, in, n, k), in.P, in.inst, n, (int)probs.size() - 1, 0});
+            ens.push_back(mcpr_ensemble{slot_ptr(pr, in, n, in.k), in.P, in.inst, n, (int)probs.size() - 1, 0});
             who.emplace_back(i, n);
         }
     }
@@ -1435,14 +1525,68 @@ mcpr_status mcpr_parareal_iterate(mcpr_parareal *pr, double *delta_out, mcpr_str
             mmaps.insert(mmaps.end(), maps.begin() + e * I, maps.begin() + (e + 1) * I);
         }
     if (!mens.empty()) {
-        if ((st = ensure(ctx, pr->dmaps, mmaps.size() * sizeof(RegionMap))) != MCPR_OK) return st;
-        HIP_TRY(hipMemcpyAsync(pr->dmaps.p, mmaps.data(), mmaps.size() * sizeof(RegionMap), hipMemcpyHostToDevice, s));
+        const size_t mb = mmaps.size() * sizeof(RegionMap);
+        if ((st = ensure(ctx, pr->dmaps, mb)) != MCPR_OK) return st;
+        // through a pinned buffer, so that the call can return before the copy ends
+        if (!pr->hmaps_done) HIP_TRY(hipEventCreateWithFlags(&pr->hmaps_done, hipEventDisableTiming));
+        HIP_TRY(hipEventSynchronize(pr->hmaps_done));
+        if (mb > pr->hmaps.cap) {
+            if (pr->hmaps.p) HIP_TRY(hipHostFree(pr->hmaps.p));
+            pr->hmaps.p = nullptr;
+            pr->hmaps.cap = 0;
+            if (hipHostMalloc(&pr->hmaps.p, mb, hipHostMallocDefault) != hipSuccess)
+                return fail(ctx, MCPR_E_OOM, "pinned allocation of %zu bytes failed", mb);
+            pr->hmaps.cap = mb;
+        }
+        std::memcpy(pr->hmaps.p, mmaps.data(), mb);
+        HIP_TRY(hipMemcpyAsync(pr->dmaps.p, pr->hmaps.p, mb, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipEventRecord(pr->hmaps_done, s));
         if ((st = mcpr_match(ctx, probs.data(), (int)probs.size(), mens.data(), (int)mens.size(),
                              (const mcpr_region_map *)pr->dmaps.p, 0, nullptr, stream)) != MCPR_OK)
             return st;
     }
-    HIP_TRY(hipStreamSynchronize(s));
+    // no final synchronisation: the matching is ordered on the stream
     pr->k = k + 1;
+    std::vector<int> moved;
+    for (int i = 0; i < n_inst; ++i) {
+        Instance &in = pr->inst[i];
+        if (in.k == k && k < N) { // propagated in this call
+            in.k = k + 1;
+            moved.push_back(i);
+        }
+    }
+    return queue_exact_qoi(pr, moved, stream);
+}
+
+mcpr_status mcpr_parareal_qoi(mcpr_parareal *pr, int32_t inst, int32_t kind, double *out, mcpr_stream stream) {
+    if (!pr) return MCPR_E_INVALID_ARG;
+    mcpr_ctx *ctx = pr->ctx;
+    if (inst < 0 || inst >= (int)pr->inst.size()) return fail(ctx, MCPR_E_INVALID_ARG, "instance %d", inst);
+    if (!out) return fail(ctx, MCPR_E_INVALID_ARG, "out is null");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (kind < MCPR_QOI_X || kind > MCPR_QOI_SIN_X2) return fail(ctx, MCPR_E_INVALID_ARG, "QoI kind %d", kind);
+    const Instance &in = pr->inst[inst];
+    const int N = pr->N, k0 = in.k;
+    if (k0 > 0 && !pr->track_qoi)
+        return fail(ctx, MCPR_E_INVALID_ARG, "slices below k are no longer held: enable QoI tracking before init");
+    mcpr_status st;
+    if ((st = harvest_qoi(pr)) != MCPR_OK) return st;
+    for (int n = 0; n < k0; ++n) out[n] = in.qcache[(size_t)n * 3 + kind];
+    // slices k..N are in the ring
+    std::vector<mcpr_ensemble> ens(N + 1 - k0);
+    for (int n = k0; n <= N; ++n) ens[n - k0] = mcpr_ensemble{slot_ptr(pr, in, n, k0), in.P, in.inst, n, 0, 0};
+    if ((st = ensure(ctx, pr->dstats, (size_t)(N + 1) * sizeof(double))) != MCPR_OK) return st;
+    if ((st = mcpr_qoi(ctx, &in.pb, 1, ens.data(), N + 1 - k0, kind, (double *)pr->dstats.p, stream)) != MCPR_OK)
+        return st;
+    HIP_TRY(hipMemcpyAsync(out + k0, pr->dstats.p, (size_t)(N + 1 - k0) * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_parareal_track_qoi(mcpr_parareal *pr, int32_t on) {
+    if (!pr) return MCPR_E_INVALID_ARG;
+    pr->track_qoi = on != 0;
     return MCPR_OK;
 }
 
@@ -1485,7 +1629,9 @@ mcpr_status mcpr_parareal_flags(const mcpr_parareal *pr, int32_t inst, int32_t *
 
 mcpr_status mcpr_parareal_slot(const mcpr_parareal *pr, int32_t inst, int32_t n, void **x) {
     if (!pr || !x || inst < 0 || inst >= (int)pr->inst.size() || n < 0 || n > pr->N) return MCPR_E_INVALID_ARG;
-    *x = slot_ptr(pr, pr->inst[inst], n, pr->k);
+    const Instance &in = pr->inst[inst];
+    if (n < in.k) return fail(pr->ctx, MCPR_E_INVALID_ARG, "slice %d is below the iteration count %d: not held", n, in.k);
+    *x = slot_ptr(pr, in, n, in.k);
     return MCPR_OK;
 }
 

@@ -401,6 +401,55 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
     if (threadIdx.x == 0) part_out[W.part_off + sc] = make_double2(sm[0], sm[1]);
 }
 
+// ----------------------------------------------------------------------------
+// Quantity of interest: (1/P) sum Phi(x_p), Phi evaluated in fp64 (KIND 0: x,
+// 1: x^2, 2: sin(x^2), the nonlinear QoI of the geometric Brownian motion
+// example).  Per-superchunk partials in the canonical order, then one block
+// per item forms the ensemble sum and divides by P.
+// ----------------------------------------------------------------------------
+template <int KIND>
+__device__ __forceinline__ double qoi_phi(double x) {
+    return KIND == 0 ? x : (KIND == 1 ? x * x : sin(x * x));
+}
+
+template <typename T, int KIND>
+__global__ __launch_bounds__(kThreads) void k_qoi_partials(const WorkItem *__restrict__ items,
+                                                           const int2 *__restrict__ blocks,
+                                                           double2 *__restrict__ part_out) {
+    __shared__ double lds[8];
+    const int2 bt = blocks[blockIdx.x];
+    const WorkItem &W = items[bt.x];
+    const T *__restrict__ x = reinterpret_cast<const T *>(W.x);
+    const int64_t P = W.P;
+    const int R = W.R;
+    double a1 = 0.0;
+    const int64_t base = (int64_t)bt.y * 4 * kThreads * R;
+    for (int r = 0; r < R; ++r) {
+        const int64_t p = base + 4 * (int64_t)(r * kThreads + threadIdx.x);
+        if (p < P) {
+            T v[4];
+            load_quad(x, p, P, v);
+            double f[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) f[e] = (p + e < P) ? qoi_phi<KIND>((double)v[e]) : 0.0;
+            a1 += (f[0] + f[1]) + (f[2] + f[3]);
+        }
+    }
+    double sm[2] = {a1, 0.0};
+    block_sum<2>(sm, lds);
+    if (threadIdx.x == 0) part_out[W.part_off + bt.y] = make_double2(sm[0], 0.0);
+}
+
+__global__ __launch_bounds__(kThreads) void k_qoi_finish(const WorkItem *__restrict__ items,
+                                                         const double2 *__restrict__ part_in,
+                                                         double *__restrict__ out) {
+    __shared__ double lds[8];
+    const WorkItem &W = items[blockIdx.x];
+    double S1, S2;
+    ensemble_sums(part_in + W.part_off, W.nsc, S1, S2, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = S1 / (double)W.P;
+}
+
 // Moments of the final state of each ensemble (trace entry m): one block per item.
 __global__ __launch_bounds__(kThreads) void k_finish(const WorkItem *__restrict__ items,
                                                      const double2 *__restrict__ part_in,
@@ -1016,6 +1065,27 @@ hipError_t launch_em_step(int prec, int deg, int variant, const WorkItem *items,
             em_step_variant<float, 3>(variant, items, blocks, nblocks, j, part_in, shift_in, mv, part_out, shift_out,
                                       trace, m, s);
     }
+    return hipGetLastError();
+}
+
+template <typename T>
+static void qoi_partials(int kind, const WorkItem *items, const int2 *blocks, int nblocks, double2 *part,
+                         hipStream_t s) {
+    if (kind == 0)
+        hipLaunchKernelGGL((k_qoi_partials<T, 0>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, part);
+    else if (kind == 1)
+        hipLaunchKernelGGL((k_qoi_partials<T, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, part);
+    else
+        hipLaunchKernelGGL((k_qoi_partials<T, 2>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, part);
+}
+
+hipError_t launch_qoi(int prec, int kind, const WorkItem *items, int n_items, const int2 *blocks, int nblocks,
+                      double2 *part, double *out, hipStream_t s) {
+    if (prec == 0)
+        qoi_partials<double>(kind, items, blocks, nblocks, part, s);
+    else
+        qoi_partials<float>(kind, items, blocks, nblocks, part, s);
+    hipLaunchKernelGGL(k_qoi_finish, dim3(n_items), dim3(kThreads), 0, s, items, part, out);
     return hipGetLastError();
 }
 

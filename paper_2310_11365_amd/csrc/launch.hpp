@@ -42,5 +42,8 @@ hipError_t launch_fill_shift(int prec, int nr, const WorkItem *items, int n_item
 hipError_t launch_match_apply(int prec, int nreg, const WorkItem *items, const int2 *blocks, int nblocks,
                               const Splits &sp, const RegionMap *maps, hipStream_t s);
 hipError_t launch_init(int prec, const WorkItem *items, const int2 *blocks, int nblocks, hipStream_t s);
+// out[i] = (1/P) sum Phi(x_p) of item i; part: scratch of one partial per superchunk.
+hipError_t launch_qoi(int prec, int kind, const WorkItem *items, int n_items, const int2 *blocks, int nblocks,
+                      double2 *part, double *out, hipStream_t s);
 
 } // namespace mcpr

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmcpr.so")
 
 FP64, FP32 = 0, 1
 MAP_KEEP, MAP_AFFINE, MAP_RESAMPLE = 0, 1, 2
+QOI_X, QOI_X2, QOI_SIN_X2 = 0, 1, 2
 MAX_REGIONS = 8
 
 STATUS = {0: "MCPR_OK", -1: "MCPR_E_INVALID_ARG", -2: "MCPR_E_OOM", -3: "MCPR_E_DEVICE",
@@ -83,6 +84,8 @@ def lib() -> ctypes.CDLL:
         L.mcpr_init_particles.restype = st
         L.mcpr_moments.argtypes = [vp, pP, i32, pE, i32, vp, vp]
         L.mcpr_moments.restype = st
+        L.mcpr_qoi.argtypes = [vp, pP, i32, pE, i32, i32, vp, vp]
+        L.mcpr_qoi.restype = st
         L.mcpr_fine_propagate.argtypes = [vp, pP, i32, pE, i32, vp, vp, vp]
         L.mcpr_fine_propagate.restype = st
         L.mcpr_match.argtypes = [vp, pP, i32, pE, i32, vp, i32, vp, vp]
@@ -115,6 +118,10 @@ def lib() -> ctypes.CDLL:
         L.mcpr_parareal_iterate.restype = st
         L.mcpr_parareal_iteration.argtypes = [vp]
         L.mcpr_parareal_iteration.restype = i32
+        L.mcpr_parareal_qoi.argtypes = [vp, i32, i32, vp, vp]
+        L.mcpr_parareal_qoi.restype = st
+        L.mcpr_parareal_track_qoi.argtypes = [vp, i32]
+        L.mcpr_parareal_track_qoi.restype = st
         L.mcpr_parareal_macro.argtypes = [vp, i32, vp, vp]
         L.mcpr_parareal_macro.restype = st
         L.mcpr_parareal_set_fractions.argtypes = [vp, i32, vp]
@@ -251,6 +258,12 @@ class Context:
         self._check(lib().mcpr_moments(self._h, P, len(problems), E, len(ensembles), _ptr(stats_dev),
                                        _stream(stream)))
 
+    def qoi(self, problems, ensembles, kind: int, out_dev, stream=None):
+        """out_dev: a float64 device tensor of >= n_ens entries; out[e] = (1/P) sum Phi(x)."""
+        P, E = self._arrays(problems, ensembles)
+        self._check(lib().mcpr_qoi(self._h, P, len(problems), E, len(ensembles), int(kind), _ptr(out_dev),
+                                   _stream(stream)))
+
     def fine_propagate(self, problems, ensembles, stats_dev=None, trace_dev=None, stream=None):
         P, E = self._arrays(problems, ensembles)
         self._check(lib().mcpr_fine_propagate(self._h, P, len(problems), E, len(ensembles),
@@ -315,6 +328,13 @@ class Propagator:
         buf = stats_buffer(len(xs), self.I)
         self.ctx.moments([self.pc], [ensemble(x, i) for x, i in zip(xs, inst)], buf)
         return stats_to_numpy(buf, len(xs), self.I)
+
+    def qoi(self, xs: List, kind: int = QOI_SIN_X2, instances=None) -> np.ndarray:
+        import torch
+        inst = instances or [0] * len(xs)
+        out = torch.empty(len(xs), dtype=torch.float64, device=xs[0].device)
+        self.ctx.qoi([self.pc], [ensemble(x, i) for x, i in zip(xs, inst)], kind, out)
+        return out.cpu().numpy()
 
     def fine(self, xs: List, slices: Sequence[int], instances=None, trace=False):
         import torch
@@ -445,6 +465,16 @@ class Parareal:
     @property
     def iteration(self) -> int:
         return int(lib().mcpr_parareal_iteration(self._h))
+
+    def track_qoi(self, on: bool = True):
+        """Record the QoI of each slice as it becomes exact (call before init)."""
+        self.ctx._check(lib().mcpr_parareal_track_qoi(self._h, 1 if on else 0))
+
+    def qoi(self, kind: int = QOI_SIN_X2, i: int = 0, stream=None) -> np.ndarray:
+        """(1/P) sum Phi over u^k_n of instance i, n = 0..N."""
+        out = np.zeros(self.N + 1)
+        self.ctx._check(lib().mcpr_parareal_qoi(self._h, i, int(kind), out.ctypes.data, _stream(stream)))
+        return out
 
     def set_fractions(self, fractions, i=0):
         """Given particle fractions [N+1, I] of every macro state of instance i

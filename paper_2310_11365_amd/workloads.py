@@ -139,6 +139,24 @@ def ou_linear(P: int = 10_000, precision: int = FP64, N: int = 10, T: float = 1.
     return Workload("ou_linear", pr, P, max_iter=N, tol=0.0)
 
 
+def gbm_coef() -> Coef:
+    """Geometric Brownian motion with interaction (the nonlinear-QoI example of
+    Sec. 5.2): dX = (alpha X + beta E[X] + a) dt + (sigma X + omega E[X] + b) dW,
+    alpha = -1/2, beta = 4/5, a = 1/3, sigma = omega = (1/2) sqrt(1/2), b = 1/6."""
+    s = 0.5 * math.sqrt(0.5)
+    return Coef(a0=1.0 / 3.0, a1=-0.5, am=0.8, b0=1.0 / 6.0, b1=s, bm=s)
+
+
+def gbm(P: int = 100_000, precision: int = FP64, N: int = 10, T: float = 1.0, dt: float = 1e-3,
+        seed: int = 0, coarse_model: int = 0) -> Workload:
+    """Geometric Brownian motion with interaction and the QoI sin(x^2):
+    X0 ~ N(1, 1/4) (variance 1/4: standard deviation 1/2), one region; the
+    paper prints no horizon or sizes, so T = 1, N = 10, dt = 1e-3, P = 1e5."""
+    pr = make_problem(gbm_coef(), P0(P0_NORMAL, 1.0, 1.0, 0.5), T, N, dt, (), seed, 0.05, precision)
+    pr.coarse_model = coarse_model
+    return Workload("gbm", pr, P, max_iter=N, tol=0.0)
+
+
 def dz_bimodal(P: int = 1_000_000, precision: int = FP32, N: int = 50, T: float = 5.0,
                dt: float = 1e-3, seed: int = 0) -> Workload:
     """Bimodal Desai-Zwanzig, X0 ~ 0.5 N(-1, 0.1^2) + 0.5 N(1, 0.1^2), P = 1e6,

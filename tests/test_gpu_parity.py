@@ -320,6 +320,63 @@ def test_parareal_unimodal_coarse_on_bimodal_fp64(mc, ctx, oracle):
     _compare_parareal(mc, ctx, oracle, wl, 8, TOL64)
 
 
+@pytest.mark.parametrize("model", [W.COARSE_TAYLOR, W.COARSE_GAUSS2, W.COARSE_GAUSS3])
+def test_parareal_gbm_qoi_fp64_matches_oracle(mc, ctx, oracle, model):
+    """Geometric Brownian motion with interaction (multiplicative noise in x and
+    E[X]) and the QoI sin(x^2) of Sec. 5.2, with the three coarse models: every
+    iterate's macro states and the QoI of every slice against the oracle, and
+    the QoI of the slices already exact equal to the serial solution's."""
+    wl = W.gbm(P=20_000, N=6, T=0.6, coarse_model=model)
+    pr = wl.problem
+    u0 = oracle.sample_p0(pr, wl.P)
+    ores = oracle.parareal(pr, u0, 6, keep_states=True)
+    ser = [u0]
+    for n in range(pr.n_slices):
+        ser.append(oracle.fine(pr, ser[-1], n)[0])
+    para = mc.Parareal([pr], [wl.P], ctx)
+    para.track_qoi(True)
+    para.init()
+    for k in range(ores["iterations"] + 1):
+        if k > 0:
+            para.iterate()
+        q = para.qoi(mc.QOI_SIN_X2)
+        oq = np.array([oracle.qoi(ores["states"][k][n], oracle.QOI_SIN_X2) for n in range(pr.n_slices + 1)])
+        assert np.max(np.abs(q - oq)) <= TOL64 * np.max(np.abs(oq)), (k, q - oq)
+        for n in range(k + 1):
+            assert abs(q[n] - oracle.qoi(ser[n], oracle.QOI_SIN_X2)) <= TOL64, (k, n)
+        _, glob = para.macro(0)
+        assert rel_close(glob, ores["glob"][k], TOL64)
+    para.close()
+    untracked = mc.Parareal([pr], [wl.P], ctx)
+    untracked.init()
+    untracked.iterate()
+    with pytest.raises(mc.MCPRError):
+        untracked.qoi(mc.QOI_SIN_X2)
+    with pytest.raises(mc.MCPRError):
+        untracked.slot(0, 0)
+    untracked.close()
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32])
+@pytest.mark.parametrize("P", [1, 5, 1029, 65_537])
+def test_qoi_matches_oracle(mc, ctx, oracle, prec, P):
+    """(1/P) sum Phi for Phi = x, x^2, sin(x^2) after one slice of the GBM
+    problem: the reduction against the oracle's on the same particles (to
+    rounding of the order), and against the oracle's own fp64 solution."""
+    pr = W.gbm(precision=prec).problem
+    prop = mc.Propagator(pr, ctx)
+    x = prop.new_particles(P)
+    prop.sample(x)
+    prop.fine([x], [0])
+    ox, _ = oracle.fine(pr, oracle.sample_p0(pr, P), 0)
+    xg = x.double().cpu().numpy()
+    for kind in (mc.QOI_X, mc.QOI_X2, mc.QOI_SIN_X2):
+        q = prop.qoi([x], kind)[0]
+        assert abs(q - oracle.qoi(xg, kind)) <= 1e-14 * max(1.0, abs(q)), kind
+        tol = TOL64 if prec == W.FP64 else 2e-5
+        assert abs(q - oracle.qoi(ox, kind)) <= tol * max(1.0, abs(q)), (kind, q, oracle.qoi(ox, kind))
+
+
 def test_parareal_exact_fractions_fp64_matches_oracle(mc, ctx, oracle):
     """Reference variant with the exact particle fractions (those of the
     oracle's serial solution) in every macro state, against the oracle run

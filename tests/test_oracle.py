@@ -117,6 +117,29 @@ def test_mixture_identity_random(oracle):
     assert abs(gV - st[2]["var"]) < 1e-13 * st[2]["var"]
 
 
+# --------------------------------------------------------------------------- QoI
+def test_qoi_exact_values(oracle):
+    """(1/P) sum Phi: sin(0) = 0 and sin(pi/2) = 1 give exactly 1/2; x and x^2
+    against exact rationals."""
+    assert oracle.qoi(np.array([0.0, math.sqrt(math.pi / 2)]), oracle.QOI_SIN_X2) == 0.5
+    x = np.array([0.5, -1.25, 3.0, 0.125])
+    fr = [Fraction(v) for v in x]
+    assert oracle.qoi(x, oracle.QOI_X) == float(sum(fr) / 4)
+    assert oracle.qoi(x, oracle.QOI_X2) == float(sum(v * v for v in fr) / 4)
+
+
+def test_qoi_sin_x2_gaussian_closed_form(oracle):
+    """For X ~ N(mu, s^2), E[exp(i X^2)] = (1 - 2 i s^2)^(-1/2) exp(i mu^2 / (1 - 2 i s^2)),
+    so E[sin X^2] is its imaginary part (mu = 1, s = 1/2: the GBM example's p0)."""
+    import cmath
+    pr = W.gbm().problem
+    x = oracle.sample_p0(pr, 400_000)
+    z = 1 - 2j * 0.25
+    exact = (cmath.exp(1j / z) / cmath.sqrt(z)).imag
+    se = np.sin(x * x).std() / math.sqrt(x.size)
+    assert abs(oracle.qoi(x, oracle.QOI_SIN_X2) - exact) < 4 * se
+
+
 # --------------------------------------------------------------------------- p0
 def test_initial_law_sample_moments(oracle):
     pr = W.ou_linear().problem
