@@ -66,6 +66,9 @@ enum { MCPR_COARSE_TAYLOR = 0, MCPR_COARSE_GAUSS2 = 1, MCPR_COARSE_GAUSS3 = 2 };
 typedef struct {
     double a0, a1, a2, a3, am, av;
     double b0, b1, bm, bv;
+    double axs; /* drift term axs * x * E[X^2], E[X^2] = v + m^2 (the polynomial-drift
+                   example of App. on the exactness of the moment model); the
+                   adjoint needs axs = 0 */
 } mcpr_coef;
 
 /* One problem: coefficients, initial law p0, time grid, regions of

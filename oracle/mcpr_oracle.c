@@ -60,6 +60,9 @@ typedef struct {
     double a0, a1, a2, a3, am, av;
     /* diffusion b(x, m, v) = b0 + b1 x + bm m + bv v                         */
     double b0, b1, bm, bv;
+    /* drift term axs x E[X^2] with E[X^2] = v + m^2 (polynomial drift of the
+       appendix on the exactness of the moment model)                        */
+    double axs;
     /* initial law: kind 0 = N(mu1, sd1^2), 1 = w N(mu1,sd1^2) + (1-w) N(mu2,sd2^2),
        2 = point mass at mu1                                                  */
     int32_t p0_kind, pad0;
@@ -269,7 +272,8 @@ void or_restrict(const or_problem *pr, const double *x, int64_t P, or_stats *out
 /* ------------------------------------------------------------------------- */
 static double or_drift(const or_problem *pr, double x, double m, double v)
 {
-    return ((pr->a3 * x + pr->a2) * x + pr->a1) * x + (pr->a0 + pr->am * m + pr->av * v);
+    return ((pr->a3 * x + pr->a2) * x + pr->a1) * x + (pr->a0 + pr->am * m + pr->av * v) +
+           pr->axs * x * (v + m * m);
 }
 
 static double or_diffusion(const or_problem *pr, double x, double m, double v)
@@ -377,7 +381,7 @@ static void or_coarse_rhs(const or_problem *pr, const double *f, const double *y
     for (int i = 0; i < I; i++) {
         double M = y[2 * i], V = y[2 * i + 1];
         double A = or_drift(pr, M, mbar, vbar);
-        double Ax = pr->a1 + 2.0 * pr->a2 * M + 3.0 * pr->a3 * M * M;
+        double Ax = pr->a1 + 2.0 * pr->a2 * M + 3.0 * pr->a3 * M * M + pr->axs * (vbar + mbar * mbar);
         double Axx = 2.0 * pr->a2 + 6.0 * pr->a3 * M;
         double B = or_diffusion(pr, M, mbar, vbar);
         double Bx = pr->b1;
@@ -781,6 +785,8 @@ int or_parareal(const or_problem *pr, const double *u0, int64_t P, uint32_t inst
 double or_adjoint(const or_problem *pr, const double *x0, int64_t P, uint32_t inst,
                   const double *Mhat, const double *Vhat, double *grad)
 {
+    if (pr->axs != 0.0) /* the x E[X^2] term is not differentiated here */
+        return NAN;
     int N = pr->n_slices, m = pr->steps_per_slice;
     int64_t S = (int64_t)N * m;
     double dt = pr->dt, sdt = sqrt(dt);

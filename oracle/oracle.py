@@ -31,7 +31,7 @@ def build(force: bool = True) -> str:
 
 
 class OrProblem(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_double) for n in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv")] + [
+    _fields_ = [(n, ctypes.c_double) for n in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs")] + [
         ("p0_kind", ctypes.c_int32), ("pad0", ctypes.c_int32),
         ("p0_w", ctypes.c_double), ("p0_mu1", ctypes.c_double), ("p0_sd1", ctypes.c_double),
         ("p0_mu2", ctypes.c_double), ("p0_sd2", ctypes.c_double),
@@ -103,8 +103,8 @@ def to_c(problem, coef=None) -> OrProblem:
     """Convert a workloads.Problem (optionally with an instance's coefficients)."""
     c = coef if coef is not None else problem.coef
     s = OrProblem()
-    for name in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv"):
-        setattr(s, name, float(getattr(c, name)))
+    for name in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs"):
+        setattr(s, name, float(getattr(c, name, 0.0)))
     s.p0_kind = int(problem.p0.kind)
     s.p0_w, s.p0_mu1, s.p0_sd1 = float(problem.p0.w), float(problem.p0.mu1), float(problem.p0.sd1)
     s.p0_mu2, s.p0_sd2 = float(problem.p0.mu2), float(problem.p0.sd2)

@@ -237,7 +237,7 @@ void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_
         w.key0 = (uint32_t)(p.seed & 0xffffffffu);
         w.key1 = (uint32_t)(p.seed >> 32);
         const double *c = &p.coef.a0;
-        for (int i = 0; i < 10; ++i) w.c[i] = c[i];
+        for (int i = 0; i < 11; ++i) w.c[i] = c[i];
         w.dt = p.dt;
         w.sdt = std::sqrt(p.dt);
         w.p0[0] = p.p0_w;
@@ -746,6 +746,8 @@ mcpr_status mcpr_adjoint(mcpr_ctx *ctx, const mcpr_problem *problem, const mcpr_
     if (st != MCPR_OK) return st;
     if (ens->problem != 0) return fail(ctx, MCPR_E_INVALID_ARG, "ensemble must use problem 0");
     if (ens->slice >= problem->n_slices) return fail(ctx, MCPR_E_INVALID_ARG, "first slice beyond n_slices");
+    if (problem->coef.axs != 0.0)
+        return fail(ctx, MCPR_E_UNSUPPORTED, "the adjoint needs axs = 0 (no x E[X^2] drift term)");
     if (dL_dmoments && !grad_out) return fail(ctx, MCPR_E_INVALID_ARG, "grad_out is null");
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
@@ -916,7 +918,7 @@ void mixture(int I, const Macro &r, double &mbar, double &vbar) {
 }
 
 double drift_at(const mcpr_coef &c, double x, double mbar, double vbar) {
-    return c.a0 + x * (c.a1 + x * (c.a2 + x * c.a3)) + c.am * mbar + c.av * vbar;
+    return c.a0 + x * (c.a1 + x * (c.a2 + x * c.a3)) + c.am * mbar + c.av * vbar + c.axs * x * (vbar + mbar * mbar);
 }
 
 double diffusion_at(const mcpr_coef &c, double x, double mbar, double vbar) {
@@ -969,8 +971,8 @@ void moment_rhs(const mcpr_coef &c, int model, int I, const Macro &r, Macro &d) 
     }
     for (int i = 0; i < I; ++i) {
         const double x = r.M[i];
-        const double a = c.a0 + x * (c.a1 + x * (c.a2 + x * c.a3)) + c.am * mbar + c.av * vbar;
-        const double ax = c.a1 + x * (2.0 * c.a2 + 3.0 * c.a3 * x);
+        const double a = drift_at(c, x, mbar, vbar);
+        const double ax = c.a1 + x * (2.0 * c.a2 + 3.0 * c.a3 * x) + c.axs * (vbar + mbar * mbar);
         const double axx = 2.0 * c.a2 + 6.0 * c.a3 * x;
         const double b = c.b0 + c.b1 * x + c.bm * mbar + c.bv * vbar;
         const double bx = c.b1;

@@ -343,7 +343,8 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
     // step coefficients: p(x) = x + a(x) dt as a polynomial, diffusion * sqrt(dt) affine in x
     const double dt = W.dt, sdt = W.sdt;
     const T c0 = (T)((W.c[0] + W.c[4] * mean + W.c[5] * var) * dt);
-    const T c1 = (T)(1.0 + W.c[1] * dt), c2 = (T)(W.c[2] * dt), c3 = (T)(W.c[3] * dt);
+    const T c1 = (T)(1.0 + (W.c[1] + W.c[10] * (var + mean * mean)) * dt), c2 = (T)(W.c[2] * dt),
+            c3 = (T)(W.c[3] * dt);
     const T e0 = (T)((W.c[6] + W.c[8] * mean + W.c[9] * var) * sdt);
     const T e1 = (T)(W.c[7] * sdt);
     const uint32_t step = (uint32_t)(W.step0 + j);

@@ -31,7 +31,7 @@ class MCPRError(RuntimeError):
 
 
 class Coef(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_double) for n in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv")]
+    _fields_ = [(n, ctypes.c_double) for n in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs")]
 
 
 class ProblemC(ctypes.Structure):
@@ -138,8 +138,8 @@ def problem_c(problem, coef=None) -> ProblemC:
     """workloads.Problem (plus optional per-instance coefficients) -> mcpr_problem."""
     c = coef if coef is not None else problem.coef
     s = ProblemC()
-    for n in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv"):
-        setattr(s.coef, n, float(getattr(c, n)))
+    for n in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs"):
+        setattr(s.coef, n, float(getattr(c, n, 0.0)))
     s.p0_kind = int(problem.p0.kind)
     s.precision = int(problem.precision)
     s.p0_w, s.p0_mu1, s.p0_sd1 = float(problem.p0.w), float(problem.p0.mu1), float(problem.p0.sd1)

@@ -37,7 +37,7 @@ P0_DELTA = 2
 
 @dataclasses.dataclass
 class Coef:
-    """a(x,m,v) = a0 + a1 x + a2 x^2 + a3 x^3 + am m + av v;
+    """a(x,m,v) = a0 + a1 x + a2 x^2 + a3 x^3 + am m + av v + axs x (v + m^2);
     b(x,m,v) = b0 + b1 x + bm m + bv v."""
     a0: float = 0.0
     a1: float = 0.0
@@ -49,6 +49,7 @@ class Coef:
     b1: float = 0.0
     bm: float = 0.0
     bv: float = 0.0
+    axs: float = 0.0  # coefficient of x E[X^2]
 
     def as_list(self) -> List[float]:
         return [self.a0, self.a1, self.a2, self.a3, self.am, self.av,
@@ -155,6 +156,18 @@ def gbm(P: int = 100_000, precision: int = FP64, N: int = 10, T: float = 1.0, dt
     pr = make_problem(gbm_coef(), P0(P0_NORMAL, 1.0, 1.0, 0.5), T, N, dt, (), seed, 0.05, precision)
     pr.coarse_model = coarse_model
     return Workload("gbm", pr, P, max_iter=N, tol=0.0)
+
+
+def polydrift(P: int = 100_000, precision: int = FP64, N: int = 10, T: float = 2.0, dt: float = 1e-3,
+              alpha: float = 0.5, seed: int = 0, coarse_model: int = 0) -> Workload:
+    """Polynomial drift dX = (alpha X + E[X] - X E[X^2]) dt + X dW, X(0) = 1
+    (the example of the appendix on the exactness of the moment model; the
+    Taylor model is its exact moment system).  alpha is not printed there:
+    alpha = 1/2, for which (M, E[X^2]) settle at (sqrt(3)/2, 3/2)."""
+    pr = make_problem(Coef(a1=alpha, am=1.0, axs=-1.0, b1=1.0), P0(P0_DELTA, 1.0, 1.0, 0.0), T, N, dt, (),
+                      seed, 0.05, precision)
+    pr.coarse_model = coarse_model
+    return Workload("polydrift", pr, P, max_iter=N, tol=0.0)
 
 
 def dz_bimodal(P: int = 1_000_000, precision: int = FP32, N: int = 50, T: float = 5.0,

@@ -149,8 +149,8 @@ def test_fine_fp64_ragged_sizes(mc, ctx, oracle, P):
 
 def test_fine_fp64_all_coefficients(mc, ctx, oracle):
     """Cubic drift with a2, variance coupling in drift and diffusion,
-    multiplicative and mean-field noise."""
-    coef = W.Coef(a0=0.1, a1=0.5, a2=-0.2, a3=-1.0, am=0.5, av=0.3, b0=0.4, b1=0.1, bm=-0.05, bv=0.2)
+    multiplicative and mean-field noise, the x E[X^2] drift term."""
+    coef = W.Coef(a0=0.1, a1=0.5, a2=-0.2, a3=-1.0, am=0.5, av=0.3, b0=0.4, b1=0.1, bm=-0.05, bv=0.2, axs=-0.3)
     pr = W.make_problem(coef, W.P0(W.P0_MIXTURE, 0.5, -1.0, 0.1, 1.0, 0.1), 0.5, 5, 1e-3, (0.0,),
                         precision=W.FP64, seed=3)
     P = 20_011
@@ -287,7 +287,10 @@ def _compare_parareal(mc, ctx, oracle, wl, K, tol, fractions=None):
         rho, glob = para.macro(0)
         og = ores["glob"][k + 1]
         err_m = np.max(np.abs(glob[:, 0] - og[:, 0]) / (np.abs(og[:, 0]) + np.sqrt(og[:, 1])))
-        err_v = np.max(np.abs(glob[:, 1] - og[:, 1]) / og[:, 1])
+        dv = np.abs(glob[:, 1] - og[:, 1])
+        pos = og[:, 1] > 0
+        err_v = float(np.max(dv[pos] / og[pos, 1])) if pos.any() else 0.0
+        assert np.all(dv[~pos] == 0.0), "point masses: variance exactly 0 on both sides"
         print(f"k={k + 1}: max rel err mean {err_m:.2e} var {err_v:.2e}")
         assert err_m <= tol and err_v <= tol, k
         np.testing.assert_array_equal(para.flags(0), ores["flags"][k])
@@ -375,6 +378,14 @@ def test_qoi_matches_oracle(mc, ctx, oracle, prec, P):
         assert abs(q - oracle.qoi(xg, kind)) <= 1e-14 * max(1.0, abs(q)), kind
         tol = TOL64 if prec == W.FP64 else 2e-5
         assert abs(q - oracle.qoi(ox, kind)) <= tol * max(1.0, abs(q)), (kind, q, oracle.qoi(ox, kind))
+
+
+@pytest.mark.parametrize("model", [W.COARSE_TAYLOR, W.COARSE_GAUSS3])
+def test_parareal_polydrift_fp64_matches_oracle(mc, ctx, oracle, model):
+    """Polynomial drift X E[X^2] with multiplicative noise from X(0) = 1 (a
+    point mass: lifting resamples), against the oracle at every iteration."""
+    wl = W.polydrift(P=20_000, N=8, T=1.6, coarse_model=model)
+    _compare_parareal(mc, ctx, oracle, wl, 8, TOL64)
 
 
 def test_parareal_exact_fractions_fp64_matches_oracle(mc, ctx, oracle):
@@ -517,6 +528,17 @@ def test_adjoint_fp64_matches_oracle(mc, ctx, oracle, kind, P, T, N):
     np.testing.assert_allclose(g, go, rtol=1e-9, atol=1e-11 * scale)
 
 
+def test_adjoint_rejects_x_second_moment_term(mc, ctx):
+    """The adjoint does not differentiate the x E[X^2] drift term: refused."""
+    pr = W.polydrift(P=1000, N=2, T=0.2, precision=W.FP64).problem
+    prop = mc.Propagator(pr, ctx)
+    x = prop.new_particles(1000)
+    prop.sample(x)
+    with pytest.raises(mc.MCPRError) as e:
+        mc.adjoint(ctx, mc.problem_c(pr), x)
+    assert e.value.status == -5
+
+
 def test_adjoint_linear_tangent_recursion(mc, ctx, oracle):
     """Linear OU with additive noise: m_{s+1} = c m_s + a0 dt + b0 sqrt(dt) mean(z_s),
     c = 1 + (a1 + am) dt, so D_s = dm_s/da1 obeys D_{s+1} = c D_s + dt m_s and
@@ -614,7 +636,10 @@ def test_parareal_learning_fp64_matches_oracle(mc, ctx, oracle):
         rho, glob = para.macro(0)
         og = ores["glob"][k + 1]
         err_m = np.max(np.abs(glob[:, 0] - og[:, 0]) / (np.abs(og[:, 0]) + np.sqrt(og[:, 1])))
-        err_v = np.max(np.abs(glob[:, 1] - og[:, 1]) / og[:, 1])
+        dv = np.abs(glob[:, 1] - og[:, 1])
+        pos = og[:, 1] > 0
+        err_v = float(np.max(dv[pos] / og[pos, 1])) if pos.any() else 0.0
+        assert np.all(dv[~pos] == 0.0), "point masses: variance exactly 0 on both sides"
         err_f = np.max(np.abs(rho[:, :, 0] - ores["rho"][k + 1][:, :, 0]))
         print(f"learning k={k + 1}: mean {err_m:.2e} var {err_v:.2e} fractions {err_f:.2e}")
         assert err_m <= TOL64 and err_v <= TOL64 and err_f <= TOL64

@@ -202,9 +202,10 @@ def test_em_per_realisation_identities(oracle, slice_index):
 
 def test_em_nonlinear_bruteforce(oracle):
     """Tiny ensemble, full coefficient set (cubic drift, multiplicative and
-    mean-field diffusion, variance dependence): step by step against a direct
-    evaluation with exact rational arithmetic of each step's moments."""
-    coef = W.Coef(a0=0.1, a1=0.5, a2=-0.2, a3=-1.0, am=0.5, av=0.3, b0=0.4, b1=0.1, bm=-0.05, bv=0.2)
+    mean-field diffusion, variance dependence, the x E[X^2] term): step by
+    step against a direct evaluation with exact rational arithmetic of each
+    step's moments."""
+    coef = W.Coef(a0=0.1, a1=0.5, a2=-0.2, a3=-1.0, am=0.5, av=0.3, b0=0.4, b1=0.1, bm=-0.05, bv=0.2, axs=-0.3)
     pr = W.make_problem(coef, W.P0(W.P0_MIXTURE, 0.5, -1.0, 0.1, 1.0, 0.1), 0.05, 5, 1e-3, (0.0,))
     P = 6
     x0 = oracle.sample_p0(pr, P)
@@ -217,7 +218,8 @@ def test_em_nonlinear_bruteforce(oracle):
         new = []
         for p in range(P):
             x = X[p]
-            a = coef.a0 + coef.a1 * x + coef.a2 * x * x + coef.a3 * x ** 3 + coef.am * M + coef.av * V
+            a = (coef.a0 + coef.a1 * x + coef.a2 * x * x + coef.a3 * x ** 3 + coef.am * M + coef.av * V
+                 + coef.axs * x * (V + M * M))
             b = coef.b0 + coef.b1 * x + coef.bm * M + coef.bv * V
             new.append(x + a * pr.dt + b * math.sqrt(pr.dt) * z[p])
         X = new
@@ -283,6 +285,33 @@ def test_coarse_linear_lemma(oracle):
                 (2 * coef.a1 + coef.b1 ** 2) * V + (coef.b0 + (coef.b1 + coef.bm) * M) ** 2]
     sol = solve_ivp(rhs, (0, pr.slice_length), y0, rtol=1e-13, atol=1e-15)
     np.testing.assert_allclose(y, sol.y[:, -1], rtol=1e-11)
+
+
+def test_coarse_polynomial_drift_is_exact_moment_ode(oracle):
+    """dX = (alpha X + E[X] - X E[X^2]) dt + X dW (the polynomial-drift example
+    of the appendix on the exactness of the moment model): the Taylor model is
+    the known exact moment system dM = (alpha + 1) M - M S,
+    dS = (2 alpha + 1) S + 2 M^2 - 2 S^2 with S = E[X^2].  The oracle's RK4
+    (h = 0.05) against a tight solve of that system, in (M, Sigma = S - M^2)."""
+    alpha = 0.5
+    wl = W.polydrift(alpha=alpha, N=10, T=2.0)
+    pr = wl.problem
+    y0 = np.array([1.0, 0.0])  # X(0) = 1
+    y = y0.copy()
+    ts = [0.0]
+    ys = [y.copy()]
+    for n in range(pr.n_slices):
+        y = oracle.coarse(pr, np.array([1.0]), y)
+        ys.append(y.copy())
+        ts.append((n + 1) * pr.slice_length)
+
+    def rhs(t, u):
+        M, S = u
+        return [(alpha + 1) * M - M * S, (2 * alpha + 1) * S + 2 * M * M - 2 * S * S]
+    sol = solve_ivp(rhs, (0.0, ts[-1]), [1.0, 1.0], t_eval=ts, rtol=1e-12, atol=1e-14)
+    for n in range(1, len(ts)):
+        M, S = sol.y[0, n], sol.y[1, n]
+        assert abs(ys[n][0] - M) < 1e-6 and abs(ys[n][1] - (S - M * M)) < 1e-6, n
 
 
 def test_coarse_nonlinear_model_terms(oracle):
