@@ -69,6 +69,13 @@ typedef struct {
     double axs; /* drift term axs * x * E[X^2], E[X^2] = v + m^2 (the polynomial-drift
                    example of App. on the exactness of the moment model); the
                    adjoint needs axs = 0 */
+    /* Trigonometric drift terms ksin sin x + kc E_q[sin(X_q - x)], where the
+     * mean-field average is (1/P) sum_q sin(X_q - x) = S cos x - C sin x with
+     * S, C the population means of sin X and cos X (the plane rotator of
+     * Sec. 5.2: ksin = -1, kc = K).  With either nonzero the per-step mean
+     * field is (S, C) instead of (m, v), so am, av, axs, bm and bv must be 0
+     * (else MCPR_E_UNSUPPORTED), and the adjoint refuses the problem.        */
+    double ksin, kc;
 } mcpr_coef;
 
 /* One problem: coefficients, initial law p0, time grid, regions of
@@ -87,7 +94,8 @@ typedef struct {
     double split[MCPR_MAX_REGIONS - 1]; /* I-1 increasing boundaries */
     uint64_t seed;
     int32_t coarse_model;    /* MCPR_COARSE_*: moment model of the coarse propagator */
-    int32_t reserved0;
+    int32_t wrap;            /* 1: after every Euler-Maruyama step each particle is shifted modulo
+                                2 pi into [0, 2 pi) (the plane rotator's convention); 0: none */
 } mcpr_problem;
 
 /* One particle ensemble (a micro state u in R^P, Sec. 3.4). */

@@ -63,6 +63,10 @@ typedef struct {
     /* drift term axs x E[X^2] with E[X^2] = v + m^2 (polynomial drift of the
        appendix on the exactness of the moment model)                        */
     double axs;
+    /* trigonometric drift ksin sin x + kc (1/P) sum_q sin(X_q - x), the
+       second written as kc (S cos x - C sin x) with S, C the population means
+       of sin X and cos X (plane rotator of Sec. 5.2)                         */
+    double ksin, kc;
     /* initial law: kind 0 = N(mu1, sd1^2), 1 = w N(mu1,sd1^2) + (1-w) N(mu2,sd2^2),
        2 = point mass at mu1                                                  */
     int32_t p0_kind, pad0;
@@ -75,8 +79,13 @@ typedef struct {
     double split[7];           /* region boundaries, increasing                */
     uint64_t seed;
     int32_t coarse_model;      /* 0 Taylor, 1 Gaussian 2-point, 2 Gaussian 3-point */
-    int32_t pad1;
+    int32_t wrap;              /* 1: shift each particle modulo 2 pi into [0, 2 pi) after every step */
 } or_problem;
+
+#define OR_TWO_PI 6.283185307179586 /* the double nearest 2 pi */
+
+/* the trigonometric mean field (S, C) replaces (m, v) as the per-step mean field */
+static int or_is_trig(const or_problem *pr) { return pr->ksin != 0.0 || pr->kc != 0.0; }
 
 typedef struct {
     int64_t n;
@@ -270,10 +279,10 @@ void or_restrict(const or_problem *pr, const double *x, int64_t P, or_stats *out
 /* ------------------------------------------------------------------------- */
 /* Coefficients                                                               */
 /* ------------------------------------------------------------------------- */
-static double or_drift(const or_problem *pr, double x, double m, double v)
+static double or_drift(const or_problem *pr, double x, double m, double v, double S, double C)
 {
     return ((pr->a3 * x + pr->a2) * x + pr->a1) * x + (pr->a0 + pr->am * m + pr->av * v) +
-           pr->axs * x * (v + m * m);
+           pr->axs * x * (v + m * m) + pr->ksin * sin(x) + pr->kc * (S * cos(x) - C * sin(x));
 }
 
 static double or_diffusion(const or_problem *pr, double x, double m, double v)
@@ -286,26 +295,42 @@ static double or_diffusion(const or_problem *pr, double x, double m, double v)
 /* slice n draws its normals at global step index s = n*m + j, so that every */
 /* Parareal iteration and the serial run use the same numbers.  The mean     */
 /* field is the population mean and variance at the start of each step.     */
-/* If trace is non-NULL it receives (m_j, v_j) for j = 0..m-1.               */
+/* With trigonometric drift terms the mean field is (S_j, C_j), the means   */
+/* of sin X and cos X, instead.  If trace is non-NULL it receives the mean   */
+/* field of each step, j = 0..m-1.  wrap: x <- x - 2 pi floor(x / (2 pi))    */
+/* after every step.                                                          */
 /* ------------------------------------------------------------------------- */
 void or_fine(const or_problem *pr, double *x, int64_t P, uint32_t inst, int32_t slice, double *trace)
 {
     int32_t msteps = pr->steps_per_slice;
     double dt = pr->dt;
     double sdt = sqrt(dt);
+    int trig = or_is_trig(pr);
     for (int32_t j = 0; j < msteps; j++) {
         uint32_t s = (uint32_t)(slice * msteps + j);
-        double mj, vj;
-        or_moments(x, P, &mj, &vj);
+        double mj = 0.0, vj = 0.0, Sj = 0.0, Cj = 0.0;
+        if (trig) {
+            long double ss = 0.0L, cs = 0.0L;
+            for (int64_t p = 0; p < P; p++) {
+                ss += (long double)sin(x[p]);
+                cs += (long double)cos(x[p]);
+            }
+            Sj = (double)(ss / (long double)P);
+            Cj = (double)(cs / (long double)P);
+        } else {
+            or_moments(x, P, &mj, &vj);
+        }
         if (trace) {
-            trace[2 * j] = mj;
-            trace[2 * j + 1] = vj;
+            trace[2 * j] = trig ? Sj : mj;
+            trace[2 * j + 1] = trig ? Cj : vj;
         }
         for (int64_t p = 0; p < P; p++) {
             double z = or_normal_of(pr->seed, p, s, inst, OR_TAG_EM);
-            double a = or_drift(pr, x[p], mj, vj);
+            double a = or_drift(pr, x[p], mj, vj, Sj, Cj);
             double b = or_diffusion(pr, x[p], mj, vj);
             x[p] = x[p] + a * dt + b * sdt * z;
+            if (pr->wrap)
+                x[p] = x[p] - OR_TWO_PI * floor(x[p] / OR_TWO_PI);
         }
     }
 }
@@ -335,30 +360,34 @@ static void or_mixture(int I, const double *f, const double *y, double *mbar, do
     *vbar = v;
 }
 
-/* Gaussian assumed-density model (eq. Gaussian_model_McK_V_SDE, with the
-   variance integrand read as 2 (x - M) a + b^2): the expectations over
-   N(M_i, V_i) by Gauss-Hermite quadrature (sigma points).  Two points:
-   M +- sqrt(V), weights 1/2 (exact to degree 3).  Three points: M,
+/* Sigma points of N(M, V) for the Gaussian models (Gauss-Hermite): two
+   points M +- sqrt(V), weights 1/2 (exact to degree 3); three points M,
    M +- sqrt(3V), weights 2/3, 1/6, 1/6 (exact to degree 5).  A negative V
-   places the points as for V = 0.                                           */
-static void or_gaussian_rhs(const or_problem *pr, double M, double V, double mbar, double vbar,
-                            double *dM, double *dV)
+   places the points as for V = 0.  Returns the number of points.           */
+static int or_sigma_points(int model, double M, double V, double *xs, double *ws)
 {
-    double xs[3], ws[3];
-    int K;
     double Vp = V > 0.0 ? V : 0.0;
-    if (pr->coarse_model == 1) {
-        K = 2;
+    if (model == 1) {
         xs[0] = M - sqrt(Vp); xs[1] = M + sqrt(Vp);
         ws[0] = 0.5; ws[1] = 0.5;
-    } else {
-        K = 3;
-        xs[0] = M - sqrt(3.0 * Vp); xs[1] = M; xs[2] = M + sqrt(3.0 * Vp);
-        ws[0] = 1.0 / 6.0; ws[1] = 2.0 / 3.0; ws[2] = 1.0 / 6.0;
+        return 2;
     }
+    xs[0] = M - sqrt(3.0 * Vp); xs[1] = M; xs[2] = M + sqrt(3.0 * Vp);
+    ws[0] = 1.0 / 6.0; ws[1] = 2.0 / 3.0; ws[2] = 1.0 / 6.0;
+    return 3;
+}
+
+/* Gaussian assumed-density model (eq. Gaussian_model_McK_V_SDE, with the
+   variance integrand read as 2 (x - M) a + b^2): the expectations over
+   N(M_i, V_i) by the sigma points.                                         */
+static void or_gaussian_rhs(const or_problem *pr, double M, double V, double mbar, double vbar,
+                            double S, double C, double *dM, double *dV)
+{
+    double xs[3], ws[3];
+    int K = or_sigma_points(pr->coarse_model, M, V, xs, ws);
     double ea = 0.0, exa = 0.0, eb2 = 0.0;
     for (int k = 0; k < K; k++) {
-        double a = or_drift(pr, xs[k], mbar, vbar);
+        double a = or_drift(pr, xs[k], mbar, vbar, S, C);
         double b = or_diffusion(pr, xs[k], mbar, vbar);
         ea += ws[k] * a;
         exa += ws[k] * (xs[k] - M) * a;
@@ -368,21 +397,51 @@ static void or_gaussian_rhs(const or_problem *pr, double M, double V, double mba
     *dV = 2.0 * exa + eb2;
 }
 
+/* Trigonometric mean field of a macro state: S = sum_i f_i E_i[sin X],
+   C = sum_i f_i E_i[cos X], with E_i taken at the region's mean (the Taylor
+   model, which gives the paper's plane-rotator moment model) or by the
+   region's sigma points (Gaussian models).                                  */
+static void or_trig_field(const or_problem *pr, const double *f, const double *y, double *S, double *C)
+{
+    int I = pr->n_regions;
+    double s = 0.0, c = 0.0;
+    for (int i = 0; i < I; i++) {
+        if (!(f[i] > 0.0))
+            continue;
+        if (pr->coarse_model == 0) {
+            s += f[i] * sin(y[2 * i]);
+            c += f[i] * cos(y[2 * i]);
+        } else {
+            double xs[3], ws[3];
+            int K = or_sigma_points(pr->coarse_model, y[2 * i], y[2 * i + 1], xs, ws);
+            for (int k = 0; k < K; k++) {
+                s += f[i] * ws[k] * sin(xs[k]);
+                c += f[i] * ws[k] * cos(xs[k]);
+            }
+        }
+    }
+    *S = s;
+    *C = c;
+}
+
 static void or_coarse_rhs(const or_problem *pr, const double *f, const double *y, double *dy)
 {
     int I = pr->n_regions;
-    double mbar, vbar;
+    double mbar, vbar, S = 0.0, C = 0.0;
     or_mixture(I, f, y, &mbar, &vbar);
+    if (or_is_trig(pr))
+        or_trig_field(pr, f, y, &S, &C);
     if (pr->coarse_model == 1 || pr->coarse_model == 2) {
         for (int i = 0; i < I; i++)
-            or_gaussian_rhs(pr, y[2 * i], y[2 * i + 1], mbar, vbar, &dy[2 * i], &dy[2 * i + 1]);
+            or_gaussian_rhs(pr, y[2 * i], y[2 * i + 1], mbar, vbar, S, C, &dy[2 * i], &dy[2 * i + 1]);
         return;
     }
     for (int i = 0; i < I; i++) {
         double M = y[2 * i], V = y[2 * i + 1];
-        double A = or_drift(pr, M, mbar, vbar);
-        double Ax = pr->a1 + 2.0 * pr->a2 * M + 3.0 * pr->a3 * M * M + pr->axs * (vbar + mbar * mbar);
-        double Axx = 2.0 * pr->a2 + 6.0 * pr->a3 * M;
+        double A = or_drift(pr, M, mbar, vbar, S, C);
+        double Ax = pr->a1 + 2.0 * pr->a2 * M + 3.0 * pr->a3 * M * M + pr->axs * (vbar + mbar * mbar) +
+                    pr->ksin * cos(M) - pr->kc * (S * sin(M) + C * cos(M));
+        double Axx = 2.0 * pr->a2 + 6.0 * pr->a3 * M - pr->ksin * sin(M) - pr->kc * (S * cos(M) - C * sin(M));
         double B = or_diffusion(pr, M, mbar, vbar);
         double Bx = pr->b1;
         dy[2 * i] = A + 0.5 * Axx * V;
@@ -785,7 +844,7 @@ int or_parareal(const or_problem *pr, const double *u0, int64_t P, uint32_t inst
 double or_adjoint(const or_problem *pr, const double *x0, int64_t P, uint32_t inst,
                   const double *Mhat, const double *Vhat, double *grad)
 {
-    if (pr->axs != 0.0) /* the x E[X^2] term is not differentiated here */
+    if (pr->axs != 0.0 || or_is_trig(pr) || pr->wrap) /* terms not differentiated here */
         return NAN;
     int N = pr->n_slices, m = pr->steps_per_slice;
     int64_t S = (int64_t)N * m;
@@ -802,7 +861,7 @@ double or_adjoint(const or_problem *pr, const double *x0, int64_t P, uint32_t in
         double mj = mom[2 * s], vj = mom[2 * s + 1];
         for (int64_t p = 0; p < P; p++) {
             double z = or_normal_of(pr->seed, p, (uint32_t)s, inst, OR_TAG_EM);
-            xn[p] = xs[p] + or_drift(pr, xs[p], mj, vj) * dt + or_diffusion(pr, xs[p], mj, vj) * sdt * z;
+            xn[p] = xs[p] + or_drift(pr, xs[p], mj, vj, 0.0, 0.0) * dt + or_diffusion(pr, xs[p], mj, vj) * sdt * z;
         }
     }
     or_moments(X + (size_t)S * P, P, &mom[2 * S], &mom[2 * S + 1]);

@@ -31,7 +31,8 @@ def build(force: bool = True) -> str:
 
 
 class OrProblem(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_double) for n in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs")] + [
+    _fields_ = [(n, ctypes.c_double) for n in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs",
+                                               "ksin", "kc")] + [
         ("p0_kind", ctypes.c_int32), ("pad0", ctypes.c_int32),
         ("p0_w", ctypes.c_double), ("p0_mu1", ctypes.c_double), ("p0_sd1", ctypes.c_double),
         ("p0_mu2", ctypes.c_double), ("p0_sd2", ctypes.c_double),
@@ -40,7 +41,7 @@ class OrProblem(ctypes.Structure):
         ("n_regions", ctypes.c_int32), ("coarse_substeps", ctypes.c_int32),
         ("split", ctypes.c_double * 7),
         ("seed", ctypes.c_uint64),
-        ("coarse_model", ctypes.c_int32), ("pad1", ctypes.c_int32),
+        ("coarse_model", ctypes.c_int32), ("wrap", ctypes.c_int32),
     ]
 
 
@@ -103,7 +104,7 @@ def to_c(problem, coef=None) -> OrProblem:
     """Convert a workloads.Problem (optionally with an instance's coefficients)."""
     c = coef if coef is not None else problem.coef
     s = OrProblem()
-    for name in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs"):
+    for name in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs", "ksin", "kc"):
         setattr(s, name, float(getattr(c, name, 0.0)))
     s.p0_kind = int(problem.p0.kind)
     s.p0_w, s.p0_mu1, s.p0_sd1 = float(problem.p0.w), float(problem.p0.mu1), float(problem.p0.sd1)
@@ -117,6 +118,7 @@ def to_c(problem, coef=None) -> OrProblem:
         s.split[i] = float(v)
     s.seed = int(problem.seed)
     s.coarse_model = int(getattr(problem, "coarse_model", 0))
+    s.wrap = int(getattr(problem, "wrap", 0))
     return s
 
 

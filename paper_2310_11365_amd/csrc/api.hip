@@ -144,6 +144,8 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 // ----------------------------------------------------------------------------
 // validation
 // ----------------------------------------------------------------------------
+bool is_trig(const mcpr_problem &p) { return p.coef.ksin != 0.0 || p.coef.kc != 0.0; }
+
 mcpr_status check_problem(mcpr_ctx *ctx, const mcpr_problem &p, int idx) {
     if (p.precision != MCPR_FP64 && p.precision != MCPR_FP32)
         return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: precision %d", idx, p.precision);
@@ -164,13 +166,19 @@ mcpr_status check_problem(mcpr_ctx *ctx, const mcpr_problem &p, int idx) {
         return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: coarse_model %d", idx, p.coarse_model);
     if (p.p0_kind < 0 || p.p0_kind > 2) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: p0_kind", idx);
     const double *c = &p.coef.a0;
-    for (int i = 0; i < 10; ++i)
+    for (int i = 0; i < 13; ++i)
         if (!std::isfinite(c[i])) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: coefficient %d not finite", idx, i);
+    if (p.wrap != 0 && p.wrap != 1) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: wrap must be 0 or 1", idx);
+    if (is_trig(p) && (p.coef.am != 0.0 || p.coef.av != 0.0 || p.coef.axs != 0.0 || p.coef.bm != 0.0 ||
+                       p.coef.bv != 0.0))
+        return fail(ctx, MCPR_E_UNSUPPORTED,
+                    "problem %d: trigonometric drift terms exclude the (m, v) mean-field coefficients", idx);
     return MCPR_OK;
 }
 
 bool same_layout(const mcpr_problem &a, const mcpr_problem &b) {
-    if (a.precision != b.precision || a.steps_per_slice != b.steps_per_slice || a.n_regions != b.n_regions)
+    if (a.precision != b.precision || a.steps_per_slice != b.steps_per_slice || a.n_regions != b.n_regions ||
+        is_trig(a) != is_trig(b))
         return false;
     for (int i = 0; i + 1 < a.n_regions; ++i)
         if (a.split[i] != b.split[i]) return false;
@@ -194,7 +202,9 @@ mcpr_status check_call(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_pr
             return fail(ctx, MCPR_E_INVALID_ARG, "ensemble %d: problem index %d", e, E.problem);
         if (!same_layout(problems[E.problem], *first))
             return fail(ctx, MCPR_E_INVALID_ARG,
-                        "ensemble %d: precision, steps_per_slice and regions must agree within a call", e);
+                        "ensemble %d: precision, steps_per_slice, regions and the kind of mean field must agree "
+                        "within a call",
+                        e);
         if (!E.x) return fail(ctx, MCPR_E_INVALID_ARG, "ensemble %d: null particle pointer", e);
         if (((uintptr_t)E.x & 15) != 0) return fail(ctx, MCPR_E_INVALID_ARG, "ensemble %d: pointer not 16-byte aligned", e);
         if (E.n_particles < 1 || E.n_particles > ((int64_t)1 << 34))
@@ -237,7 +247,9 @@ void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_
         w.key0 = (uint32_t)(p.seed & 0xffffffffu);
         w.key1 = (uint32_t)(p.seed >> 32);
         const double *c = &p.coef.a0;
-        for (int i = 0; i < 11; ++i) w.c[i] = c[i];
+        for (int i = 0; i < 13; ++i) w.c[i] = c[i];
+        w.wrap = p.wrap;
+        w.trig = is_trig(p) ? 1 : 0;
         w.dt = p.dt;
         w.sdt = std::sqrt(p.dt);
         w.p0[0] = p.p0_w;
@@ -342,7 +354,11 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
     double2 *part[2] = {(double2 *)ctx->part[0].p, (double2 *)ctx->part[1].p};
     double *shift[2] = {(double *)ctx->shift[0].p, (double *)ctx->shift[1].p};
     double2 *trace = want_trace ? (double2 *)ctx->trace.p : nullptr;
-    HIP_TRY(mcpr::launch_sum_init(prec, items, blocks, nb, part[0], shift[0], s));
+    const bool trig = t.items[0].trig != 0; // the same for every item of a call
+    if (trig)
+        HIP_TRY(mcpr::launch_sum_init_trig(prec, items, blocks, nb, part[0], shift[0], s));
+    else
+        HIP_TRY(mcpr::launch_sum_init(prec, items, blocks, nb, part[0], shift[0], s));
     if (profile) HIP_TRY(hipEventRecord(ctx->prof0[ctx->prof_used], s));
     double2 *mv = (double2 *)ctx->mv.p;
     for (int j = 0; j < m; ++j) {
@@ -351,15 +367,24 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
         const int v = trial ? ctx->tune_cand[j / (ctx->tune_steps / ctx->tune_nc)]
                             : (variant < 0 ? ctx->tune_cand[0] : variant);
         if (trial) HIP_TRY(hipEventRecord(ctx->tune_ev[0][j], s));
-        HIP_TRY(mcpr::launch_em_step(prec, deg, v, items, n, blocks, nb, j, part[a], shift[a], mv, part[b], shift[b],
-                                     trace, m, s));
+        if (trig)
+            HIP_TRY(mcpr::launch_em_step_trig(prec, deg, items, blocks, nb, j, part[a], part[b], shift[b], trace, m, s));
+        else
+            HIP_TRY(mcpr::launch_em_step(prec, deg, v, items, n, blocks, nb, j, part[a], shift[a], mv, part[b],
+                                         shift[b], trace, m, s));
         if (trial) HIP_TRY(hipEventRecord(ctx->tune_ev[1][j], s));
     }
     if (profile) HIP_TRY(hipEventRecord(ctx->prof1[ctx->prof_used], s));
-    if (trace) HIP_TRY(mcpr::launch_finish(items, n, part[m & 1], shift[m & 1], trace, m, s));
+    if (trace) {
+        if (trig)
+            HIP_TRY(mcpr::launch_finish_trig(items, n, part[m & 1], trace, m, s));
+        else
+            HIP_TRY(mcpr::launch_finish(items, n, part[m & 1], shift[m & 1], trace, m, s));
+    }
     if (want_stats) {
-        // shift of the record sums: the mean the last step used
-        return enqueue_records(ctx, t, prec, nreg, sp, shift[m & 1], nreg > 1, 0, nullptr,
+        // shift of the record sums: the mean the last step used (with the
+        // trigonometric mean field there is none: two passes then)
+        return enqueue_records(ctx, t, prec, nreg, sp, shift[m & 1], nreg > 1 || trig, 0, nullptr,
                                (RegionStats *)ctx->recs.p, s);
     }
     return MCPR_OK;
@@ -372,7 +397,7 @@ std::vector<char> graph_key(mcpr_ctx *ctx, const Tables &t, int prec, int deg, i
                           ctx->shift[1].p, ctx->rpart.p, ctx->rshift[0].p, ctx->rshift[1].p, ctx->recs.p,
                           ctx->trace.p,  ctx->mv.p};
     const int64_t ints[] = {(int64_t)t.items.size(), (int64_t)t.blocks.size(), t.total_sc, prec, deg, m, nreg,
-                            want_stats, want_trace, variant};
+                            want_stats, want_trace, variant, t.items[0].trig};
     std::vector<char> k(sizeof ptrs + sizeof ints + sizeof sp);
     std::memcpy(k.data(), ptrs, sizeof ptrs);
     std::memcpy(k.data() + sizeof ptrs, ints, sizeof ints);
@@ -417,7 +442,7 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
         auto it = ctx->tuned.find(tkey);
         if (it != ctx->tuned.end()) {
             variant = it->second;
-        } else if (!ctx->profile) {
+        } else if (!ctx->profile && !t.items[0].trig) {
             tune_now = true;
         }
     }
@@ -746,8 +771,8 @@ mcpr_status mcpr_adjoint(mcpr_ctx *ctx, const mcpr_problem *problem, const mcpr_
     if (st != MCPR_OK) return st;
     if (ens->problem != 0) return fail(ctx, MCPR_E_INVALID_ARG, "ensemble must use problem 0");
     if (ens->slice >= problem->n_slices) return fail(ctx, MCPR_E_INVALID_ARG, "first slice beyond n_slices");
-    if (problem->coef.axs != 0.0)
-        return fail(ctx, MCPR_E_UNSUPPORTED, "the adjoint needs axs = 0 (no x E[X^2] drift term)");
+    if (problem->coef.axs != 0.0 || is_trig(*problem) || problem->wrap)
+        return fail(ctx, MCPR_E_UNSUPPORTED, "the adjoint needs axs = ksin = kc = 0 and no wrap");
     if (dL_dmoments && !grad_out) return fail(ctx, MCPR_E_INVALID_ARG, "grad_out is null");
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
@@ -917,40 +942,47 @@ void mixture(int I, const Macro &r, double &mbar, double &vbar) {
     vbar = v;
 }
 
-double drift_at(const mcpr_coef &c, double x, double mbar, double vbar) {
-    return c.a0 + x * (c.a1 + x * (c.a2 + x * c.a3)) + c.am * mbar + c.av * vbar + c.axs * x * (vbar + mbar * mbar);
+// Drift and diffusion at x with the mean field (mbar, vbar) and, for the
+// trigonometric terms, (S, C) = the means of sin X and cos X.
+double drift_at(const mcpr_coef &c, double x, double mbar, double vbar, double S, double C) {
+    double a = c.a0 + x * (c.a1 + x * (c.a2 + x * c.a3)) + c.am * mbar + c.av * vbar + c.axs * x * (vbar + mbar * mbar);
+    if (c.ksin != 0.0 || c.kc != 0.0) a += c.ksin * std::sin(x) + c.kc * (S * std::cos(x) - C * std::sin(x));
+    return a;
 }
 
 double diffusion_at(const mcpr_coef &c, double x, double mbar, double vbar) {
     return c.b0 + c.b1 * x + c.bm * mbar + c.bv * vbar;
 }
 
-// Gaussian assumed-density model: dM = E[a], dV = 2 E[(x - M) a] + E[b^2] over
-// N(M, V) by Gauss-Hermite sigma points (2: M +- sqrt V, weights 1/2;
-// 3: M, M +- sqrt(3V), weights 2/3, 1/6, 1/6); V < 0 places them as for V = 0.
-void gaussian_rhs(const mcpr_coef &c, int npts, double M, double V, double mbar, double vbar, double &dM,
-                  double &dV) {
+// Sigma points of N(M, V) (Gauss-Hermite): 2 points M +- sqrt V, weights 1/2;
+// 3 points M, M +- sqrt(3V), weights 2/3, 1/6, 1/6; V < 0 as V = 0.
+int sigma_points(int npts, double M, double V, double *xs, double *ws) {
     const double Vp = V > 0.0 ? V : 0.0;
-    double xs[3], ws[3];
-    int K;
     if (npts == 2) {
-        K = 2;
         xs[0] = M - std::sqrt(Vp);
         xs[1] = M + std::sqrt(Vp);
         ws[0] = ws[1] = 0.5;
-    } else {
-        K = 3;
-        const double h = std::sqrt(3.0 * Vp);
-        xs[0] = M - h;
-        xs[1] = M;
-        xs[2] = M + h;
-        ws[0] = 1.0 / 6.0;
-        ws[1] = 2.0 / 3.0;
-        ws[2] = 1.0 / 6.0;
+        return 2;
     }
+    const double h = std::sqrt(3.0 * Vp);
+    xs[0] = M - h;
+    xs[1] = M;
+    xs[2] = M + h;
+    ws[0] = 1.0 / 6.0;
+    ws[1] = 2.0 / 3.0;
+    ws[2] = 1.0 / 6.0;
+    return 3;
+}
+
+// Gaussian assumed-density model: dM = E[a], dV = 2 E[(x - M) a] + E[b^2] over
+// N(M, V) by the sigma points.
+void gaussian_rhs(const mcpr_coef &c, int npts, double M, double V, double mbar, double vbar, double S, double C,
+                  double &dM, double &dV) {
+    double xs[3], ws[3];
+    const int K = sigma_points(npts, M, V, xs, ws);
     double ea = 0.0, exa = 0.0, eb2 = 0.0;
     for (int k = 0; k < K; ++k) {
-        const double a = drift_at(c, xs[k], mbar, vbar), b = diffusion_at(c, xs[k], mbar, vbar);
+        const double a = drift_at(c, xs[k], mbar, vbar, S, C), b = diffusion_at(c, xs[k], mbar, vbar);
         ea += ws[k] * a;
         exa += ws[k] * (xs[k] - M) * a;
         eb2 += ws[k] * b * b;
@@ -959,21 +991,48 @@ void gaussian_rhs(const mcpr_coef &c, int npts, double M, double V, double mbar,
     dV = 2.0 * exa + eb2;
 }
 
+// Trigonometric mean field of a macro state: S = sum_i f_i E_i[sin X], C
+// likewise, E_i at the region mean (Taylor model) or by its sigma points.
+void trig_field(const mcpr_coef &c, int model, int I, const Macro &r, double &S, double &C) {
+    S = C = 0.0;
+    if (c.ksin == 0.0 && c.kc == 0.0) return;
+    for (int i = 0; i < I; ++i) {
+        if (!(r.f[i] > 0.0)) continue;
+        if (model == MCPR_COARSE_TAYLOR) {
+            S += r.f[i] * std::sin(r.M[i]);
+            C += r.f[i] * std::cos(r.M[i]);
+        } else {
+            double xs[3], ws[3];
+            const int K = sigma_points(model == MCPR_COARSE_GAUSS2 ? 2 : 3, r.M[i], r.V[i], xs, ws);
+            for (int k = 0; k < K; ++k) {
+                S += r.f[i] * ws[k] * std::sin(xs[k]);
+                C += r.f[i] * ws[k] * std::cos(xs[k]);
+            }
+        }
+    }
+}
+
 void moment_rhs(const mcpr_coef &c, int model, int I, const Macro &r, Macro &d) {
-    double mbar, vbar;
+    double mbar, vbar, S, C;
     mixture(I, r, mbar, vbar);
+    trig_field(c, model, I, r, S, C);
     if (model != MCPR_COARSE_TAYLOR) {
         for (int i = 0; i < I; ++i) {
-            gaussian_rhs(c, model == MCPR_COARSE_GAUSS2 ? 2 : 3, r.M[i], r.V[i], mbar, vbar, d.M[i], d.V[i]);
+            gaussian_rhs(c, model == MCPR_COARSE_GAUSS2 ? 2 : 3, r.M[i], r.V[i], mbar, vbar, S, C, d.M[i], d.V[i]);
             d.f[i] = 0.0;
         }
         return;
     }
     for (int i = 0; i < I; ++i) {
         const double x = r.M[i];
-        const double a = drift_at(c, x, mbar, vbar);
-        const double ax = c.a1 + x * (2.0 * c.a2 + 3.0 * c.a3 * x) + c.axs * (vbar + mbar * mbar);
-        const double axx = 2.0 * c.a2 + 6.0 * c.a3 * x;
+        const double a = drift_at(c, x, mbar, vbar, S, C);
+        double ax = c.a1 + x * (2.0 * c.a2 + 3.0 * c.a3 * x) + c.axs * (vbar + mbar * mbar);
+        double axx = 2.0 * c.a2 + 6.0 * c.a3 * x;
+        if (c.ksin != 0.0 || c.kc != 0.0) {
+            const double sx = std::sin(x), cx = std::cos(x);
+            ax += c.ksin * cx - c.kc * (S * sx + C * cx);
+            axx += -c.ksin * sx - c.kc * (S * cx - C * sx);
+        }
         const double b = c.b0 + c.b1 * x + c.bm * mbar + c.bv * vbar;
         const double bx = c.b1;
         d.M[i] = a + 0.5 * axx * r.V[i];

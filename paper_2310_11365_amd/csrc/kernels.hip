@@ -403,6 +403,154 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
 }
 
 // ----------------------------------------------------------------------------
+// Trigonometric mean field (plane rotator, Sec. 5.2): the drift
+//   a(x) = a0 + a1 x + a2 x^2 + a3 x^3 + ksin sin x + kc (1/P) sum_q sin(X_q - x)
+// with (1/P) sum_q sin(X_q - x) = S cos x - C sin x, S and C the population
+// means of sin X and cos X.  The per-step mean field is (S, C): every launch
+// writes per-superchunk partials (sum sin x, sum cos x) of its output in the
+// canonical order (quad leaf in the state type, fp64 from the quad up), and
+// the next launch combines them.  wrap: x <- x - 2 pi floor(x / (2 pi)).
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void sincos_T(float x, float &s, float &c) {
+    const float t = x * 0.15915494309189535f; // turns: v_sin_f32 / v_cos_f32 take sin(2 pi t)
+    s = __builtin_amdgcn_sinf(t);
+    c = __builtin_amdgcn_cosf(t);
+}
+__device__ __forceinline__ void sincos_T(double x, double &s, double &c) { sincos(x, &s, &c); }
+__device__ __forceinline__ float wrap_T(float x) {
+    const float tp = 6.28318530717958648f;
+    return x - tp * floorf(x / tp);
+}
+__device__ __forceinline__ double wrap_T(double x) {
+    const double tp = 6.283185307179586;
+    return x - tp * floor(x / tp);
+}
+
+template <typename T>
+__device__ __forceinline__ void trig_leaf(const T v[4], int64_t p, int64_t P, double &q1, double &q2) {
+    T s[4], c[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        sincos_T(v[e], s[e], c[e]);
+        if (p + e >= P) s[e] = c[e] = (T)0;
+    }
+    q1 = (double)((s[0] + s[1]) + (s[2] + s[3]));
+    q2 = (double)((c[0] + c[1]) + (c[2] + c[3]));
+}
+
+// Step-0 trigonometric sums of each superchunk.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sum_init_trig(const WorkItem *__restrict__ items,
+                                                            const int2 *__restrict__ blocks,
+                                                            double2 *__restrict__ part_out,
+                                                            double *__restrict__ shift_out) {
+    __shared__ double lds[8];
+    const int2 bt = blocks[blockIdx.x];
+    const WorkItem &W = items[bt.x];
+    const T *__restrict__ x = reinterpret_cast<const T *>(W.x);
+    const int64_t P = W.P;
+    const int R = W.R;
+    double a1 = 0.0, a2 = 0.0;
+    const int64_t base = (int64_t)bt.y * 4 * kThreads * R;
+    for (int r = 0; r < R; ++r) {
+        const int64_t p = base + 4 * (int64_t)(r * kThreads + threadIdx.x);
+        if (p < P) {
+            T v[4];
+            load_quad(x, p, P, v);
+            double q1, q2;
+            trig_leaf(v, p, P, q1, q2);
+            a1 += q1;
+            a2 += q2;
+        }
+    }
+    double sm[2] = {a1, a2};
+    block_sum<2>(sm, lds);
+    if (threadIdx.x == 0) {
+        part_out[W.part_off + bt.y] = make_double2(sm[0], sm[1]);
+        if (bt.y == 0) shift_out[bt.x] = 0.0;
+    }
+}
+
+// One Euler-Maruyama step with the trigonometric mean field.
+template <typename T, int DEG>
+__global__ __launch_bounds__(kThreads) void k_em_step_trig(const WorkItem *__restrict__ items,
+                                                           const int2 *__restrict__ blocks, int32_t j,
+                                                           const double2 *__restrict__ part_in,
+                                                           double2 *__restrict__ part_out,
+                                                           double *__restrict__ shift_out,
+                                                           double2 *__restrict__ trace, int32_t m) {
+    __shared__ double lds[8];
+    const int2 bt = blocks[blockIdx.x];
+    const int item = bt.x, sc = bt.y;
+    const WorkItem &W = items[item];
+    T *__restrict__ x = reinterpret_cast<T *>(W.x) + (int64_t)j * W.traj;
+    T *__restrict__ y = x + W.traj;
+    const int64_t P = W.P;
+    const int R = W.R;
+    const int64_t base = (int64_t)sc * 4 * kThreads * R;
+    T v[kMaxQuadsPerThread][4];
+#pragma unroll
+    for (int g = 0; g < kMaxQuadsPerThread; ++g) {
+        const int64_t p = base + 4 * (int64_t)(g * kThreads + threadIdx.x);
+        if (g < R && p < P) load_quad(x, p, P, v[g]);
+    }
+    double S1, S2;
+    ensemble_sums(part_in + W.part_off, W.nsc, S1, S2, lds);
+    const double Sm = S1 / (double)P, Cm = S2 / (double)P;
+    if (sc == 0 && threadIdx.x == 0) {
+        shift_out[item] = 0.0;
+        if (trace) trace[(int64_t)item * (m + 1) + j] = make_double2(Sm, Cm);
+    }
+    const double dt = W.dt, sdt = W.sdt;
+    const T c0 = (T)(W.c[0] * dt);
+    const T c1 = (T)(1.0 + W.c[1] * dt), c2 = (T)(W.c[2] * dt), c3 = (T)(W.c[3] * dt);
+    const T ks = (T)((W.c[11] - W.c[12] * Cm) * dt), kcs = (T)(W.c[12] * Sm * dt);
+    const T e0 = (T)(W.c[6] * sdt), e1 = (T)(W.c[7] * sdt);
+    const uint32_t step = (uint32_t)(W.step0 + j);
+    const uint32_t inst = (uint32_t)W.inst;
+    double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+    for (int g = 0; g < kMaxQuadsPerThread; ++g) {
+        const int64_t p = base + 4 * (int64_t)(g * kThreads + threadIdx.x);
+        if (g < R && p < P) {
+            const Words4 w = philox4x32_10((uint32_t)(p >> 2), step, inst, 0u, W.key0, W.key1);
+            T z[4], u[4];
+            box_muller4(w, z);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                T sx, cx;
+                sincos_T(v[g][e], sx, cx);
+                const T xv = v[g][e];
+                const T pol0 = (DEG == 1) ? fmaT(c1, xv, c0) : fmaT(fmaT(fmaT(c3, xv, c2), xv, c1), xv, c0);
+                const T pol = fmaT(kcs, cx, fmaT(ks, sx, pol0));
+                u[e] = fmaT(fmaT(e1, v[g][e], e0), z[e], pol);
+                if (W.wrap) u[e] = wrap_T(u[e]);
+            }
+            store_quad(y, p, P, u);
+            double q1, q2;
+            trig_leaf(u, p, P, q1, q2);
+            a1 += q1;
+            a2 += q2;
+        }
+    }
+    double sm[2] = {a1, a2};
+    block_sum<2>(sm, lds);
+    if (threadIdx.x == 0) part_out[W.part_off + sc] = make_double2(sm[0], sm[1]);
+}
+
+// Trace entry m with the trigonometric mean field: the means of sin and cos.
+__global__ __launch_bounds__(kThreads) void k_finish_trig(const WorkItem *__restrict__ items,
+                                                          const double2 *__restrict__ part_in,
+                                                          double2 *__restrict__ trace, int32_t m) {
+    __shared__ double lds[8];
+    const WorkItem &W = items[blockIdx.x];
+    double S1, S2;
+    ensemble_sums(part_in + W.part_off, W.nsc, S1, S2, lds);
+    if (threadIdx.x == 0)
+        trace[(int64_t)blockIdx.x * (m + 1) + m] = make_double2(S1 / (double)W.P, S2 / (double)W.P);
+}
+
+// ----------------------------------------------------------------------------
 // Quantity of interest: (1/P) sum Phi(x_p), Phi evaluated in fp64 (KIND 0: x,
 // 1: x^2, 2: sin(x^2), the nonlinear QoI of the geometric Brownian motion
 // example).  Per-superchunk partials in the canonical order, then one block
@@ -1066,6 +1214,44 @@ hipError_t launch_em_step(int prec, int deg, int variant, const WorkItem *items,
             em_step_variant<float, 3>(variant, items, blocks, nblocks, j, part_in, shift_in, mv, part_out, shift_out,
                                       trace, m, s);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_init_trig(int prec, const WorkItem *items, const int2 *blocks, int nblocks,
+                                double2 *part_out, double *shift_out, hipStream_t s) {
+    if (prec == 0)
+        hipLaunchKernelGGL(k_sum_init_trig<double>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, part_out,
+                           shift_out);
+    else
+        hipLaunchKernelGGL(k_sum_init_trig<float>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, part_out,
+                           shift_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_em_step_trig(int prec, int deg, const WorkItem *items, const int2 *blocks, int nblocks, int j,
+                               const double2 *part_in, double2 *part_out, double *shift_out, double2 *trace, int m,
+                               hipStream_t s) {
+    if (prec == 0) {
+        if (deg == 1)
+            hipLaunchKernelGGL((k_em_step_trig<double, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                               part_in, part_out, shift_out, trace, m);
+        else
+            hipLaunchKernelGGL((k_em_step_trig<double, 3>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                               part_in, part_out, shift_out, trace, m);
+    } else {
+        if (deg == 1)
+            hipLaunchKernelGGL((k_em_step_trig<float, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                               part_in, part_out, shift_out, trace, m);
+        else
+            hipLaunchKernelGGL((k_em_step_trig<float, 3>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                               part_in, part_out, shift_out, trace, m);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_trig(const WorkItem *items, int n_items, const double2 *part_in, double2 *trace, int m,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_finish_trig, dim3(n_items), dim3(kThreads), 0, s, items, part_in, trace, m);
     return hipGetLastError();
 }
 

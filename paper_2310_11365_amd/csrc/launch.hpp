@@ -42,6 +42,15 @@ hipError_t launch_fill_shift(int prec, int nr, const WorkItem *items, int n_item
 hipError_t launch_match_apply(int prec, int nreg, const WorkItem *items, const int2 *blocks, int nblocks,
                               const Splits &sp, const RegionMap *maps, hipStream_t s);
 hipError_t launch_init(int prec, const WorkItem *items, const int2 *blocks, int nblocks, hipStream_t s);
+// Trigonometric mean field (every item of the launch has ksin or kc nonzero):
+// step-0 sums, the step, and the final trace entry (mean sin, mean cos).
+hipError_t launch_sum_init_trig(int prec, const WorkItem *items, const int2 *blocks, int nblocks,
+                                double2 *part_out, double *shift_out, hipStream_t s);
+hipError_t launch_em_step_trig(int prec, int deg, const WorkItem *items, const int2 *blocks, int nblocks, int j,
+                               const double2 *part_in, double2 *part_out, double *shift_out, double2 *trace, int m,
+                               hipStream_t s);
+hipError_t launch_finish_trig(const WorkItem *items, int n_items, const double2 *part_in, double2 *trace, int m,
+                              hipStream_t s);
 // out[i] = (1/P) sum Phi(x_p) of item i; part: scratch of one partial per superchunk.
 hipError_t launch_qoi(int prec, int kind, const WorkItem *items, int n_items, const int2 *blocks, int nblocks,
                       double2 *part, double *out, hipStream_t s);

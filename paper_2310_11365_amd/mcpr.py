@@ -31,7 +31,8 @@ class MCPRError(RuntimeError):
 
 
 class Coef(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_double) for n in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs")]
+    _fields_ = [(n, ctypes.c_double) for n in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs",
+                                               "ksin", "kc")]
 
 
 class ProblemC(ctypes.Structure):
@@ -41,7 +42,7 @@ class ProblemC(ctypes.Structure):
                 ("steps_per_slice", ctypes.c_int32), ("n_slices", ctypes.c_int32),
                 ("n_regions", ctypes.c_int32), ("coarse_substeps", ctypes.c_int32),
                 ("split", ctypes.c_double * (MAX_REGIONS - 1)), ("seed", ctypes.c_uint64),
-                ("coarse_model", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("coarse_model", ctypes.c_int32), ("wrap", ctypes.c_int32)]
 
 
 class EnsembleC(ctypes.Structure):
@@ -138,7 +139,7 @@ def problem_c(problem, coef=None) -> ProblemC:
     """workloads.Problem (plus optional per-instance coefficients) -> mcpr_problem."""
     c = coef if coef is not None else problem.coef
     s = ProblemC()
-    for n in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs"):
+    for n in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs", "ksin", "kc"):
         setattr(s.coef, n, float(getattr(c, n, 0.0)))
     s.p0_kind = int(problem.p0.kind)
     s.precision = int(problem.precision)
@@ -153,6 +154,7 @@ def problem_c(problem, coef=None) -> ProblemC:
         s.split[i] = float(v)
     s.seed = int(problem.seed)
     s.coarse_model = int(getattr(problem, "coarse_model", 0))
+    s.wrap = int(getattr(problem, "wrap", 0))
     return s
 
 

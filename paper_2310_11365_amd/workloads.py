@@ -50,6 +50,8 @@ class Coef:
     bm: float = 0.0
     bv: float = 0.0
     axs: float = 0.0  # coefficient of x E[X^2]
+    ksin: float = 0.0  # coefficient of sin x
+    kc: float = 0.0  # coupling K of the mean field (1/P) sum_q sin(X_q - x)
 
     def as_list(self) -> List[float]:
         return [self.a0, self.a1, self.a2, self.a3, self.am, self.av,
@@ -78,6 +80,7 @@ class Problem:
     coarse_substeps: int = 1
     precision: int = FP64
     coarse_model: int = 0  # 0 Taylor (eq. moment_model_class_1), 1/2 Gaussian with 2/3 sigma points
+    wrap: int = 0  # 1: particles shifted modulo 2 pi into [0, 2 pi) after every step
 
     @property
     def n_regions(self) -> int:
@@ -168,6 +171,20 @@ def polydrift(P: int = 100_000, precision: int = FP64, N: int = 10, T: float = 2
                       seed, 0.05, precision)
     pr.coarse_model = coarse_model
     return Workload("polydrift", pr, P, max_iter=N, tol=0.0)
+
+
+def rotator(P: int = 100_000, precision: int = FP64, N: int = 20, T: float = 10.0, dt: float = 1e-3,
+            K: float = 1.0, kT: float = 0.5, wrap: int = 1, seed: int = 0, coarse_model: int = 0) -> Workload:
+    """Plane rotator (Sec. 5.2): dX = [K E_q[sin(X_q - X)] - sin X] dt + sqrt(2 kB T) dW,
+    X0 ~ N(pi/4, 3 pi/4) (variance 3 pi/4), shifted modulo 2 pi into [0, 2 pi)
+    after every step; T = 10, dt = 1e-3, 1e5 particles as in the paper.  K and
+    kB T are not printed: K = 1, kB T = 1/2 (unit noise)."""
+    pr = make_problem(Coef(ksin=-1.0, kc=K, b0=math.sqrt(2.0 * kT)),
+                      P0(P0_NORMAL, 1.0, math.pi / 4, math.sqrt(3 * math.pi / 4)), T, N, dt, (), seed, 0.05,
+                      precision)
+    pr.coarse_model = coarse_model
+    pr.wrap = wrap
+    return Workload("rotator", pr, P, max_iter=N, tol=0.0)
 
 
 def dz_bimodal(P: int = 1_000_000, precision: int = FP32, N: int = 50, T: float = 5.0,

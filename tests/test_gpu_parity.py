@@ -163,6 +163,39 @@ def test_fine_fp64_all_coefficients(mc, ctx, oracle):
     assert rel_close(tr[0, :-1], otr, TOL64)
 
 
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32])
+def test_fine_rotator_matches_oracle(mc, ctx, oracle, prec):
+    """Plane rotator: trigonometric mean field (means of sin X and cos X, per
+    step) and the shift modulo 2 pi, one slice against the oracle: records,
+    the per-step trace of (mean sin, mean cos), every particle in [0, 2 pi)."""
+    wl = W.rotator(P=30_011, N=10, T=1.0, precision=prec)
+    pr = wl.problem
+    prop = mc.Propagator(pr, ctx)
+    x = prop.new_particles(wl.P)
+    prop.sample(x)
+    g, tr = prop.fine([x], [3], trace=True)
+    ox, otr = oracle.fine(pr, oracle.sample_p0(pr, wl.P), 3, trace=True)
+    xg = x.double().cpu().numpy()
+    assert np.all((xg >= 0) & (xg <= 2 * math.pi))
+    if prec == W.FP64:
+        assert_records_close(g[0], oracle.restrict(pr, ox), TOL64)
+        assert np.max(np.abs(tr[0, :-1] - otr)) <= TOL64
+        assert np.max(np.abs(xg - ox)) < 1e-11
+    else:
+        og = oracle.restrict(pr, ox)[-1]
+        assert abs(g[0][-1]["mean"] - og["mean"]) <= FP32_M * (abs(og["mean"]) + math.sqrt(og["var"]))
+        assert abs(g[0][-1]["var"] - og["var"]) <= FP32_V * og["var"]
+        assert np.max(np.abs(tr[0, :-1] - otr)) <= 1e-5
+
+
+@pytest.mark.parametrize("model", [W.COARSE_TAYLOR, W.COARSE_GAUSS3])
+def test_parareal_rotator_fp64_matches_oracle(mc, ctx, oracle, model):
+    """Plane rotator through the whole Parareal iteration (Taylor model: the
+    paper's printed rotator model; three sigma points), against the oracle."""
+    wl = W.rotator(P=20_000, N=8, T=2.0, coarse_model=model)
+    _compare_parareal(mc, ctx, oracle, wl, 8, TOL64)
+
+
 def test_fine_fp32_bimodal_bound(mc, ctx, oracle):
     """fp32 particles / fp64 reductions against the fp64 oracle (bimodal
     workload, P = 1e5, one slice).  Bound: |dM| <= 2e-5 (|M| + sqrt V),

@@ -314,6 +314,57 @@ def test_coarse_polynomial_drift_is_exact_moment_ode(oracle):
         assert abs(ys[n][0] - M) < 1e-6 and abs(ys[n][1] - (S - M * M)) < 1e-6, n
 
 
+def test_rotator_em_bruteforce_pair_sum(oracle):
+    """Plane rotator, tiny ensemble: every step against the direct pair sum
+    (K/P) sum_q sin(X_q - X_p) - sin X_p, unit noise, and the shift modulo
+    2 pi into [0, 2 pi); the trace holds the means of sin X and cos X."""
+    wl = W.rotator(P=5, N=4, T=0.2, dt=1e-2)
+    pr = wl.problem
+    c = pr.coef
+    x0 = oracle.sample_p0(pr, 5)
+    x1, tr = oracle.fine(pr, x0, 1, trace=True)
+    X = x0.copy()
+    two_pi = 6.283185307179586
+    for j in range(pr.steps_per_slice):
+        z = _em_normals(oracle, pr, 5, pr.steps_per_slice + j)
+        assert abs(tr[j, 0] - np.mean(np.sin(X))) < 1e-15 and abs(tr[j, 1] - np.mean(np.cos(X))) < 1e-15
+        pair = np.array([np.mean(np.sin(X - xp)) for xp in X])
+        X = X + (c.kc * pair + c.ksin * np.sin(X)) * pr.dt + c.b0 * math.sqrt(pr.dt) * z
+        X = X - two_pi * np.floor(X / two_pi)
+    np.testing.assert_allclose(x1, X, rtol=0, atol=1e-13)
+    assert np.all((x1 >= 0) & (x1 < two_pi))
+
+
+def test_rotator_taylor_model_is_the_printed_one(oracle):
+    """One region: the Taylor model of the plane rotator is dM = -sin M +
+    (Sigma/2) sin M, dSigma = 2 (-K - cos M) Sigma + 2 kB T (the paper's model,
+    read with a_x = -K - cos M); the oracle's RK4 against a tight solve."""
+    K, kT = 1.3, 0.4
+    wl = W.rotator(K=K, kT=kT, N=10, T=2.0)
+    pr = wl.problem
+    y = np.array([math.pi / 4, 0.3])
+    ys, ts = [y.copy()], [0.0]
+    for n in range(pr.n_slices):
+        y = oracle.coarse(pr, np.array([1.0]), y)
+        ys.append(y.copy())
+        ts.append((n + 1) * pr.slice_length)
+
+    def rhs(t, u):
+        M, S = u
+        return [-math.sin(M) + 0.5 * S * math.sin(M), 2 * (-K - math.cos(M)) * S + 2 * kT]
+    sol = solve_ivp(rhs, (0.0, ts[-1]), ys[0], t_eval=ts, rtol=1e-12, atol=1e-14)
+    for n in range(1, len(ts)):
+        assert np.max(np.abs(ys[n] - sol.y[:, n])) < 1e-6, n
+    # without noise a point mass stays one, the sigma points collapse, and the
+    # Gaussian models coincide with the Taylor model (M' = -sin M)
+    pr0 = W.rotator(K=K, kT=0.0, N=10, T=2.0).problem
+    t = oracle.coarse(pr0, np.array([1.0]), np.array([0.7, 0.0]))
+    for model in (W.COARSE_GAUSS2, W.COARSE_GAUSS3):
+        pr0.coarse_model = model
+        g = oracle.coarse(pr0, np.array([1.0]), np.array([0.7, 0.0]))
+        assert abs(g[0] - t[0]) < 1e-14 and g[1] == 0.0 and t[1] == 0.0
+
+
 def test_coarse_nonlinear_model_terms(oracle):
     """Double well: dM_i = a(M_i, mbar) + a_xx(M_i) V_i / 2 and
     dV_i = 2 a_x(M_i) V_i + b^2, regions coupled through the mixture mean."""
