@@ -19,6 +19,11 @@ tolerance 1e-4), ou_linear (P = 1e4, N = 10, fp64: the latency-bound case),
 gbm (geometric Brownian motion with interaction and multiplicative noise,
 P = 1e6, N = 10, fp32; the parareal section adds the error of the QoI
 sin(X^2) of every slice against the serial solution),
+burgers (the particle system of the viscous Burgers equation, drift
+1 - F_P(X) with the empirical CDF F_P, X(0) = 0, P = 1e6, N = 10, T = 1,
+fp32: each Euler-Maruyama step ranks the ensemble by a segmented radix sort;
+the roofline line then covers the whole step sequence, sort included, against
+the same 8 B per particle-step of state traffic),
 adjoint_ou / adjoint_dz (the gradient of the slice-end moments' squared error
 through the fine propagator, P = 1e5, T = 2, dt = 1e-3, N = 20, fp32 state:
 one step is one mcpr_adjoint call, i.e. the forward solution with slice-start
@@ -75,7 +80,7 @@ def load_traffic(kernel: str, workload: str):
 def kernels_sha() -> str:
     """Hash of the device sources (kernels, RNG, shared types)."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "rng.hpp", "common.hpp"):
+    for f in ("kernels.hip", "cdf.hip", "rng.hpp", "common.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2310_11365_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -124,6 +129,10 @@ def make_workload(name: str):
         wl = W.gbm(P=1_000_000, precision=W.FP32)
         return wl, [wl.P], None, ("gbm: dX=(-X/2+0.8E[X]+1/3)dt+(s X+s E[X]+1/6)dW, s=sqrt(1/8), X0~N(1,1/4), "
                                   "P=1e6, T=1, N=10, QoI sin(X^2)")
+    if name == "burgers":
+        wl = W.burgers(P=1_000_000, precision=W.FP32)
+        return wl, [wl.P], None, ("burgers: dX=(1-F_P(X))dt+dW, F_P the empirical CDF with H(0)=1/2, X0=0, "
+                                  "P=1e6, T=1, N=10; a segmented radix sort of the ensemble per step")
     if name == "ou_linear":
         wl = W.ou_linear()
         return wl, [wl.P], None, ("ou_linear: dX=(-X+0.5E[X])dt+0.3dW, X0~N(1,0.2^2), P=1e4, N=10, "
@@ -202,7 +211,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="dz_bimodal",
-                    choices=["dz_bimodal", "ou_batched", "dz_large", "ou_linear", "gbm", "adjoint_ou", "adjoint_dz"])
+                    choices=["dz_bimodal", "ou_batched", "dz_large", "ou_linear", "gbm", "burgers", "adjoint_ou",
+                             "adjoint_dz"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parareal", action="store_true")
     ap.add_argument("--parareal-iters", type=int, default=4)
@@ -283,6 +293,10 @@ def main():
     tv = ctx.tuned_variants()
     variant = args.variant if args.variant >= 0 else (tv[0] if tv else 0)
     kernel = f"k_em_step<{tname}, {deg}, {'true' if variant & 1 else 'false'}, {'true' if variant & 2 else 'false'}>"
+    if pr.coef.acdf != 0.0:
+        # the events bracket every launch of a step: gather, sort, flags, scans, rank, update
+        kernel = (f"empirical-CDF step sequence (k_cdf_gather, segmented radix sort, k_cdf_flags, 2 max-scans, "
+                  f"k_cdf_rank, k_em_step_cdf<{tname}, {deg}>)")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(kernel, wl.name),
                 "kernel": kernel, "avg_launch_us": round(avg_launch_s * 1e6, 2),

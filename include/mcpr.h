@@ -76,6 +76,13 @@ typedef struct {
      * field is (S, C) instead of (m, v), so am, av, axs, bm and bv must be 0
      * (else MCPR_E_UNSUPPORTED), and the adjoint refuses the problem.        */
     double ksin, kc;
+    /* Empirical-CDF drift term acdf (1 - F_P(x)), F_P(x) = (1/P) sum_q H(x - X_q)
+     * with the step function H(0) = 1/2 (the Burgers example of Sec. 5.2:
+     * acdf = 1, b0 = sigma, X(0) = 0).  With acdf nonzero every step ranks the
+     * ensemble (a segmented sort), the problem has one region and the Taylor
+     * (Gaussian-density) coarse model, and the other mean-field coefficients
+     * (am, av, axs, bm, bv, ksin, kc) must be 0, else MCPR_E_UNSUPPORTED.     */
+    double acdf;
 } mcpr_coef;
 
 /* One problem: coefficients, initial law p0, time grid, regions of

@@ -67,6 +67,9 @@ typedef struct {
        second written as kc (S cos x - C sin x) with S, C the population means
        of sin X and cos X (plane rotator of Sec. 5.2)                         */
     double ksin, kc;
+    /* empirical-CDF drift acdf (1 - F_P(x)), F_P(x) = (1/P) sum_q H(x - X_q),
+       H(0) = 1/2 (Burgers example of Sec. 5.2)                              */
+    double acdf;
     /* initial law: kind 0 = N(mu1, sd1^2), 1 = w N(mu1,sd1^2) + (1-w) N(mu2,sd2^2),
        2 = point mass at mu1                                                  */
     int32_t p0_kind, pad0;
@@ -285,6 +288,44 @@ static double or_drift(const or_problem *pr, double x, double m, double v, doubl
            pr->axs * x * (v + m * m) + pr->ksin * sin(x) + pr->kc * (S * cos(x) - C * sin(x));
 }
 
+/* Empirical CDF with the step function H(0) = 1/2 at every particle:
+   F[p] = (1/P) sum_q H(x_p - x_q) = (#{q : x_q < x_p} + #{q : x_q = x_p} / 2) / P,
+   counted by sorting: the particles of a run of equal values [s, t) in sorted
+   order have s smaller ones and t - s equal ones (themselves included).      */
+typedef struct {
+    double x;
+    int64_t i;
+} or_keyed;
+
+static int or_cmp_keyed(const void *a, const void *b)
+{
+    const or_keyed *u = (const or_keyed *)a, *w = (const or_keyed *)b;
+    if (u->x < w->x) return -1;
+    if (u->x > w->x) return 1;
+    return (u->i > w->i) - (u->i < w->i);
+}
+
+void or_empirical_cdf(const double *x, int64_t P, double *F)
+{
+    or_keyed *k = (or_keyed *)malloc(sizeof(or_keyed) * (size_t)P);
+    for (int64_t p = 0; p < P; p++) {
+        k[p].x = x[p];
+        k[p].i = p;
+    }
+    qsort(k, (size_t)P, sizeof(or_keyed), or_cmp_keyed);
+    int64_t s = 0;
+    while (s < P) {
+        int64_t t = s + 1;
+        while (t < P && k[t].x == k[s].x)
+            t++;
+        double cnt = (double)s + 0.5 * (double)(t - s);
+        for (int64_t r = s; r < t; r++)
+            F[k[r].i] = cnt / (double)P;
+        s = t;
+    }
+    free(k);
+}
+
 static double or_diffusion(const or_problem *pr, double x, double m, double v)
 {
     return pr->b1 * x + (pr->b0 + pr->bm * m + pr->bv * v);
@@ -306,6 +347,7 @@ void or_fine(const or_problem *pr, double *x, int64_t P, uint32_t inst, int32_t 
     double dt = pr->dt;
     double sdt = sqrt(dt);
     int trig = or_is_trig(pr);
+    double *F = pr->acdf != 0.0 ? (double *)malloc(sizeof(double) * (size_t)P) : NULL;
     for (int32_t j = 0; j < msteps; j++) {
         uint32_t s = (uint32_t)(slice * msteps + j);
         double mj = 0.0, vj = 0.0, Sj = 0.0, Cj = 0.0;
@@ -324,15 +366,20 @@ void or_fine(const or_problem *pr, double *x, int64_t P, uint32_t inst, int32_t 
             trace[2 * j] = trig ? Sj : mj;
             trace[2 * j + 1] = trig ? Cj : vj;
         }
+        if (F)
+            or_empirical_cdf(x, P, F);
         for (int64_t p = 0; p < P; p++) {
             double z = or_normal_of(pr->seed, p, s, inst, OR_TAG_EM);
             double a = or_drift(pr, x[p], mj, vj, Sj, Cj);
+            if (F)
+                a += pr->acdf * (1.0 - F[p]);
             double b = or_diffusion(pr, x[p], mj, vj);
             x[p] = x[p] + a * dt + b * sdt * z;
             if (pr->wrap)
                 x[p] = x[p] - OR_TWO_PI * floor(x[p] / OR_TWO_PI);
         }
     }
+    free(F);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -446,6 +493,13 @@ static void or_coarse_rhs(const or_problem *pr, const double *f, const double *y
         double Bx = pr->b1;
         dy[2 * i] = A + 0.5 * Axx * V;
         dy[2 * i + 1] = (2.0 * Ax + Bx * Bx) * V + B * B;
+        if (pr->acdf != 0.0) {
+            /* density assumed N(M, V): 1 - CDF(M) = 1/2, d(1 - CDF)/dx at M =
+               -1/sqrt(2 pi V), second derivative 0 (the Burgers moment model) */
+            double Vp = V > 0.0 ? V : 0.0;
+            dy[2 * i] += 0.5 * pr->acdf;
+            dy[2 * i + 1] += -2.0 * pr->acdf * sqrt(Vp) / sqrt(2.0 * 3.141592653589793);
+        }
     }
 }
 

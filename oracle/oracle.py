@@ -32,7 +32,7 @@ def build(force: bool = True) -> str:
 
 class OrProblem(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs",
-                                               "ksin", "kc")] + [
+                                               "ksin", "kc", "acdf")] + [
         ("p0_kind", ctypes.c_int32), ("pad0", ctypes.c_int32),
         ("p0_w", ctypes.c_double), ("p0_mu1", ctypes.c_double), ("p0_sd1", ctypes.c_double),
         ("p0_mu2", ctypes.c_double), ("p0_sd2", ctypes.c_double),
@@ -84,6 +84,8 @@ def lib():
         L.or_rho_global.argtypes = [ctypes.c_int, dp, dp, dp]
         L.or_fraction_fit.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
         L.or_serial.argtypes = [pp, dp, ctypes.c_int64, ctypes.c_uint32, sp]
+        L.or_empirical_cdf.argtypes = [dp, ctypes.c_int64, dp]
+        L.or_empirical_cdf.restype = None
         L.or_qoi.argtypes = [dp, ctypes.c_int64, ctypes.c_int32]
         L.or_qoi.restype = ctypes.c_double
         L.or_parareal.argtypes = [pp, dp, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_double,
@@ -104,7 +106,7 @@ def to_c(problem, coef=None) -> OrProblem:
     """Convert a workloads.Problem (optionally with an instance's coefficients)."""
     c = coef if coef is not None else problem.coef
     s = OrProblem()
-    for name in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs", "ksin", "kc"):
+    for name in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs", "ksin", "kc", "acdf"):
         setattr(s, name, float(getattr(c, name, 0.0)))
     s.p0_kind = int(problem.p0.kind)
     s.p0_w, s.p0_mu1, s.p0_sd1 = float(problem.p0.w), float(problem.p0.mu1), float(problem.p0.sd1)
@@ -163,6 +165,14 @@ def qoi(x: np.ndarray, kind: int) -> float:
     """(1/P) sum Phi(x_p); kind 0: x, 1: x^2, 2: sin(x^2)."""
     x = np.ascontiguousarray(x, dtype=np.float64)
     return float(lib().or_qoi(_dp(x), x.size, kind))
+
+
+def empirical_cdf(x: np.ndarray) -> np.ndarray:
+    """F[p] = (1/P) sum_q H(x_p - x_q), H(0) = 1/2."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    F = np.zeros_like(x)
+    lib().or_empirical_cdf(_dp(x), x.size, _dp(F))
+    return F
 
 
 def region_of(problem, x: float) -> int:

@@ -54,6 +54,10 @@ struct mcpr_ctx {
     DevBuf items, blocks, part[2], shift[2], rpart, rshift[2], maps, recs;
     DevBuf adj_ckpt, adj_traj, adj_lam[2], adj_part[2], adj_acc, adj_trace, adj_grad, adj_sums; // adjoint scratch
     DevBuf adj_items, adj_blocks; // the backward sweep's work and block tables
+    // empirical-CDF drift: sort keys and indices, run flags and scans, counts,
+    // segment bounds, library scratch
+    DevBuf cdf_keys[2], cdf_vals[2], cdf_fwd[2], cdf_bwd[2], cdf_F, cdf_seg, cdf_tmp;
+    mcpr::CdfBuffers cdfb{};
     HostBuf staging;
     hipEvent_t staged = nullptr; // the last upload from staging has completed
     DevBuf trace; // trace of the last fine sweep (copied to the caller's array)
@@ -145,6 +149,7 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 // validation
 // ----------------------------------------------------------------------------
 bool is_trig(const mcpr_problem &p) { return p.coef.ksin != 0.0 || p.coef.kc != 0.0; }
+bool is_cdf(const mcpr_problem &p) { return p.coef.acdf != 0.0; }
 
 mcpr_status check_problem(mcpr_ctx *ctx, const mcpr_problem &p, int idx) {
     if (p.precision != MCPR_FP64 && p.precision != MCPR_FP32)
@@ -166,8 +171,15 @@ mcpr_status check_problem(mcpr_ctx *ctx, const mcpr_problem &p, int idx) {
         return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: coarse_model %d", idx, p.coarse_model);
     if (p.p0_kind < 0 || p.p0_kind > 2) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: p0_kind", idx);
     const double *c = &p.coef.a0;
-    for (int i = 0; i < 13; ++i)
+    for (int i = 0; i < 14; ++i)
         if (!std::isfinite(c[i])) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: coefficient %d not finite", idx, i);
+    if (is_cdf(p) && (p.coef.am != 0.0 || p.coef.av != 0.0 || p.coef.axs != 0.0 || p.coef.bm != 0.0 ||
+                      p.coef.bv != 0.0 || is_trig(p) || p.wrap != 0 || p.n_regions != 1 ||
+                      p.coarse_model != MCPR_COARSE_TAYLOR))
+        return fail(ctx, MCPR_E_UNSUPPORTED,
+                    "problem %d: the empirical-CDF drift needs one region, the Taylor model and no other "
+                    "mean-field coefficient",
+                    idx);
     if (p.wrap != 0 && p.wrap != 1) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: wrap must be 0 or 1", idx);
     if (is_trig(p) && (p.coef.am != 0.0 || p.coef.av != 0.0 || p.coef.axs != 0.0 || p.coef.bm != 0.0 ||
                        p.coef.bv != 0.0))
@@ -178,7 +190,7 @@ mcpr_status check_problem(mcpr_ctx *ctx, const mcpr_problem &p, int idx) {
 
 bool same_layout(const mcpr_problem &a, const mcpr_problem &b) {
     if (a.precision != b.precision || a.steps_per_slice != b.steps_per_slice || a.n_regions != b.n_regions ||
-        is_trig(a) != is_trig(b))
+        is_trig(a) != is_trig(b) || is_cdf(a) != is_cdf(b))
         return false;
     for (int i = 0; i + 1 < a.n_regions; ++i)
         if (a.split[i] != b.split[i]) return false;
@@ -225,11 +237,13 @@ struct Tables {
     std::vector<WorkItem> items;
     std::vector<int2> blocks; // one entry per superchunk: (item, superchunk)
     int total_sc = 0;
+    int64_t total_keys = 0;   // concatenated sort positions (empirical-CDF drift)
 };
 
 void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_t n_ens, Tables &t) {
     t.items.resize(n_ens);
     t.blocks.clear();
+    t.total_keys = 0;
     int off = 0;
     for (int e = 0; e < n_ens; ++e) {
         const mcpr_ensemble &E = ens[e];
@@ -247,9 +261,12 @@ void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_
         w.key0 = (uint32_t)(p.seed & 0xffffffffu);
         w.key1 = (uint32_t)(p.seed >> 32);
         const double *c = &p.coef.a0;
-        for (int i = 0; i < 13; ++i) w.c[i] = c[i];
+        for (int i = 0; i < 14; ++i) w.c[i] = c[i];
         w.wrap = p.wrap;
         w.trig = is_trig(p) ? 1 : 0;
+        w.cdf = is_cdf(p) ? 1 : 0;
+        w.koff = t.total_keys;
+        t.total_keys += (E.n_particles + 3) / 4 * 4;
         w.dt = p.dt;
         w.sdt = std::sqrt(p.dt);
         w.p0[0] = p.p0_w;
@@ -355,6 +372,9 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
     double *shift[2] = {(double *)ctx->shift[0].p, (double *)ctx->shift[1].p};
     double2 *trace = want_trace ? (double2 *)ctx->trace.p : nullptr;
     const bool trig = t.items[0].trig != 0; // the same for every item of a call
+    const bool cdf = t.items[0].cdf != 0;
+    const uint32_t nkeys = (uint32_t)t.total_keys;
+    if (cdf) HIP_TRY(mcpr::launch_cdf_setup(items, n, nkeys, ctx->cdfb, s));
     if (trig)
         HIP_TRY(mcpr::launch_sum_init_trig(prec, items, blocks, nb, part[0], shift[0], s));
     else
@@ -367,7 +387,11 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
         const int v = trial ? ctx->tune_cand[j / (ctx->tune_steps / ctx->tune_nc)]
                             : (variant < 0 ? ctx->tune_cand[0] : variant);
         if (trial) HIP_TRY(hipEventRecord(ctx->tune_ev[0][j], s));
-        if (trig)
+        if (cdf) {
+            HIP_TRY(mcpr::launch_cdf_counts(prec, items, n, blocks, nb, nkeys, j, ctx->cdfb, s));
+            HIP_TRY(mcpr::launch_em_step_cdf(prec, deg, items, blocks, nb, j, part[a], shift[a], ctx->cdfb.F, part[b],
+                                             shift[b], trace, m, s));
+        } else if (trig)
             HIP_TRY(mcpr::launch_em_step_trig(prec, deg, items, blocks, nb, j, part[a], part[b], shift[b], trace, m, s));
         else
             HIP_TRY(mcpr::launch_em_step(prec, deg, v, items, n, blocks, nb, j, part[a], shift[a], mv, part[b],
@@ -405,6 +429,40 @@ std::vector<char> graph_key(mcpr_ctx *ctx, const Tables &t, int prec, int deg, i
     return k;
 }
 
+// Buffers of the empirical-CDF drift for the concatenated ensembles of t.
+mcpr_status ensure_cdf(mcpr_ctx *ctx, const Tables &t, int prec) {
+    const size_t n = (size_t)t.total_keys, es = prec == 0 ? sizeof(double) : sizeof(float);
+    const int nseg = (int)t.items.size();
+    if (t.total_keys >= ((int64_t)1 << 32) - 1)
+        return fail(ctx, MCPR_E_UNSUPPORTED, "empirical-CDF drift: %lld particles in one launch exceed 2^32 - 1",
+                    (long long)t.total_keys);
+    mcpr_status st;
+    for (int b = 0; b < 2; ++b) {
+        if ((st = ensure(ctx, ctx->cdf_keys[b], n * es)) != MCPR_OK) return st;
+        if ((st = ensure(ctx, ctx->cdf_vals[b], n * sizeof(uint32_t))) != MCPR_OK) return st;
+        if ((st = ensure(ctx, ctx->cdf_fwd[b], n * sizeof(uint32_t))) != MCPR_OK) return st;
+        if ((st = ensure(ctx, ctx->cdf_bwd[b], n * sizeof(uint32_t))) != MCPR_OK) return st;
+    }
+    if ((st = ensure(ctx, ctx->cdf_F, n * es)) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->cdf_seg, 2 * (size_t)nseg * sizeof(uint32_t))) != MCPR_OK) return st;
+    size_t tb = 0;
+    HIP_TRY(mcpr::cdf_scratch_bytes(prec, (uint32_t)n, (uint32_t)nseg, tb));
+    if ((st = ensure(ctx, ctx->cdf_tmp, tb > 0 ? tb : 1)) != MCPR_OK) return st;
+    mcpr::CdfBuffers &c = ctx->cdfb;
+    for (int b = 0; b < 2; ++b) {
+        c.keys[b] = ctx->cdf_keys[b].p;
+        c.vals[b] = (uint32_t *)ctx->cdf_vals[b].p;
+        c.fwd[b] = (uint32_t *)ctx->cdf_fwd[b].p;
+        c.bwd[b] = (uint32_t *)ctx->cdf_bwd[b].p;
+    }
+    c.F = ctx->cdf_F.p;
+    c.seg_begin = (uint32_t *)ctx->cdf_seg.p;
+    c.seg_end = c.seg_begin + nseg;
+    c.tmp = ctx->cdf_tmp.p;
+    c.tmp_bytes = tb;
+    return MCPR_OK;
+}
+
 mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int nreg, const mcpr::Splits &sp,
                           RegionStats *stats, double2 *trace, hipStream_t s) {
     const int n = (int)t.items.size();
@@ -416,6 +474,7 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
     if (stats && (st = ensure_records(ctx, t, nreg)) != MCPR_OK) return st;
     if (trace && (st = ensure(ctx, ctx->trace, (size_t)n * (m + 1) * sizeof(double2))) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->mv, (size_t)n * sizeof(double2))) != MCPR_OK) return st;
+    if (t.items[0].cdf && (st = ensure_cdf(ctx, t, prec)) != MCPR_OK) return st;
     int deg = 1, max_nsc = 0;
     int64_t ps = 0;
     for (const WorkItem &w : t.items) {
@@ -442,7 +501,7 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
         auto it = ctx->tuned.find(tkey);
         if (it != ctx->tuned.end()) {
             variant = it->second;
-        } else if (!ctx->profile && !t.items[0].trig) {
+        } else if (!ctx->profile && !t.items[0].trig && !t.items[0].cdf) {
             tune_now = true;
         }
     }
@@ -498,7 +557,8 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
             MCPR_OK)
             return st;
         ctx->prof_used++;
-    } else if (ctx->graphs) {
+    } else if (ctx->graphs && !t.items[0].cdf) {
+        // (the empirical-CDF sweep runs the library sort eagerly: never captured)
         std::vector<char> key = graph_key(ctx, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr);
         if (!ctx->gexec || key != ctx->gkey) {
             if (ctx->gexec) {
@@ -581,7 +641,10 @@ void mcpr_destroy(mcpr_ctx *ctx) {
                       &ctx->shift[1],      &ctx->rpart,       &ctx->rshift[0],   &ctx->rshift[1],   &ctx->maps,
                       &ctx->recs,          &ctx->adj_ckpt,    &ctx->adj_traj,    &ctx->adj_lam[0],  &ctx->adj_lam[1],
                       &ctx->adj_part[0],   &ctx->adj_part[1], &ctx->adj_acc,     &ctx->adj_trace,   &ctx->adj_grad,
-                      &ctx->adj_sums,      &ctx->adj_items,   &ctx->adj_blocks,  &ctx->trace,       &ctx->mv};
+                      &ctx->adj_sums,      &ctx->adj_items,   &ctx->adj_blocks,  &ctx->trace,       &ctx->mv,
+                      &ctx->cdf_keys[0],   &ctx->cdf_keys[1], &ctx->cdf_vals[0], &ctx->cdf_vals[1], &ctx->cdf_fwd[0],
+                      &ctx->cdf_fwd[1],    &ctx->cdf_bwd[0],  &ctx->cdf_bwd[1],  &ctx->cdf_F,       &ctx->cdf_seg,
+                      &ctx->cdf_tmp};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->staging.p) (void)hipHostFree(ctx->staging.p);
@@ -771,8 +834,8 @@ mcpr_status mcpr_adjoint(mcpr_ctx *ctx, const mcpr_problem *problem, const mcpr_
     if (st != MCPR_OK) return st;
     if (ens->problem != 0) return fail(ctx, MCPR_E_INVALID_ARG, "ensemble must use problem 0");
     if (ens->slice >= problem->n_slices) return fail(ctx, MCPR_E_INVALID_ARG, "first slice beyond n_slices");
-    if (problem->coef.axs != 0.0 || is_trig(*problem) || problem->wrap)
-        return fail(ctx, MCPR_E_UNSUPPORTED, "the adjoint needs axs = ksin = kc = 0 and no wrap");
+    if (problem->coef.axs != 0.0 || is_trig(*problem) || is_cdf(*problem) || problem->wrap)
+        return fail(ctx, MCPR_E_UNSUPPORTED, "the adjoint needs axs = ksin = kc = acdf = 0 and no wrap");
     if (dL_dmoments && !grad_out) return fail(ctx, MCPR_E_INVALID_ARG, "grad_out is null");
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
@@ -1037,6 +1100,13 @@ void moment_rhs(const mcpr_coef &c, int model, int I, const Macro &r, Macro &d) 
         const double bx = c.b1;
         d.M[i] = a + 0.5 * axx * r.V[i];
         d.V[i] = (2.0 * ax + bx * bx) * r.V[i] + b * b;
+        if (c.acdf != 0.0) {
+            // a N(M, V) density: 1 - F is 1/2 at the mean, its slope there
+            // -1/sqrt(2 pi V) and its curvature zero
+            const double vp = r.V[i] > 0.0 ? r.V[i] : 0.0;
+            d.M[i] += 0.5 * c.acdf;
+            d.V[i] += -2.0 * c.acdf * std::sqrt(vp) / std::sqrt(2.0 * 3.141592653589793);
+        }
         d.f[i] = 0.0;
     }
 }

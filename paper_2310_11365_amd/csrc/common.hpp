@@ -52,7 +52,10 @@ struct WorkItem {
     uint32_t key0, key1; // Philox key: seed low and high words
     int32_t wrap;      // 1: shift modulo 2 pi into [0, 2 pi) after every step
     int32_t trig;      // 1: trigonometric drift terms; the step's mean field is (mean sin, mean cos)
-    double c[13];      // a0 a1 a2 a3 am av b0 b1 bm bv axs ksin kc
+    int32_t cdf;       // 1: empirical-CDF drift term (every step ranks the ensemble)
+    int32_t pad;
+    int64_t koff;      // first position of this item in the launch's concatenated sort arrays
+    double c[14];      // a0 a1 a2 a3 am av b0 b1 bm bv axs ksin kc acdf
     double dt, sdt;    // step and its square root
     double p0[5];      // w, mu1, sd1, mu2, sd2
     int64_t traj;      // 0: steps work in place; else step j reads x + j*traj and writes x + (j+1)*traj

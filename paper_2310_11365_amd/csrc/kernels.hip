@@ -538,6 +538,79 @@ __global__ __launch_bounds__(kThreads) void k_em_step_trig(const WorkItem *__res
     if (threadIdx.x == 0) part_out[W.part_off + sc] = make_double2(sm[0], sm[1]);
 }
 
+// One Euler-Maruyama step with the empirical-CDF drift term acdf (1 - F_P(x)):
+// F + koff holds the counts sum_q H(x_p - x_q) of the step's input state
+// (launch_cdf_counts).  The (m, v) partials are formed as in k_em_step, for
+// the trace and the next step's shift.
+template <typename T, int DEG>
+__global__ __launch_bounds__(kThreads) void k_em_step_cdf(const WorkItem *__restrict__ items,
+                                                          const int2 *__restrict__ blocks, int32_t j,
+                                                          const double2 *__restrict__ part_in,
+                                                          const double *__restrict__ shift_in,
+                                                          const T *__restrict__ F, double2 *__restrict__ part_out,
+                                                          double *__restrict__ shift_out,
+                                                          double2 *__restrict__ trace, int32_t m) {
+    __shared__ double lds[8];
+    const int2 bt = blocks[blockIdx.x];
+    const int item = bt.x, sc = bt.y;
+    const WorkItem &W = items[item];
+    T *__restrict__ x = reinterpret_cast<T *>(W.x) + (int64_t)j * W.traj;
+    T *__restrict__ y = x + W.traj;
+    const T *__restrict__ Fi = F + W.koff;
+    const int64_t P = W.P;
+    const int R = W.R;
+    const int64_t base = (int64_t)sc * 4 * kThreads * R;
+    T v[kMaxQuadsPerThread][4], f[kMaxQuadsPerThread][4];
+#pragma unroll
+    for (int g = 0; g < kMaxQuadsPerThread; ++g) {
+        const int64_t p = base + 4 * (int64_t)(g * kThreads + threadIdx.x);
+        if (g < R && p < P) {
+            load_quad(x, p, P, v[g]);
+            load_quad(Fi, p, P, f[g]);
+        }
+    }
+    double S1, S2, mean, var;
+    ensemble_sums(part_in + W.part_off, W.nsc, S1, S2, lds);
+    finish_moments(S1, S2, shift_in[item], (double)P, mean, var);
+    const T shift = (T)mean;
+    if (sc == 0 && threadIdx.x == 0) {
+        shift_out[item] = (double)shift;
+        if (trace) trace[(int64_t)item * (m + 1) + j] = make_double2(mean, var);
+    }
+    const double dt = W.dt, sdt = W.sdt;
+    const T c0 = (T)((W.c[0] + W.c[13]) * dt);
+    const T c1 = (T)(1.0 + W.c[1] * dt), c2 = (T)(W.c[2] * dt), c3 = (T)(W.c[3] * dt);
+    const T kf = (T)(-W.c[13] * dt / (double)P); // the CDF term: acdf dt (1 - cnt / P)
+    const T e0 = (T)(W.c[6] * sdt), e1 = (T)(W.c[7] * sdt);
+    const uint32_t step = (uint32_t)(W.step0 + j);
+    const uint32_t inst = (uint32_t)W.inst;
+    double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+    for (int g = 0; g < kMaxQuadsPerThread; ++g) {
+        const int64_t p = base + 4 * (int64_t)(g * kThreads + threadIdx.x);
+        if (g < R && p < P) {
+            const Words4 w = philox4x32_10((uint32_t)(p >> 2), step, inst, 0u, W.key0, W.key1);
+            T z[4], u[4], d[4];
+            box_muller4(w, z);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const T xv = v[g][e];
+                const T pol0 = (DEG == 1) ? fmaT(c1, xv, c0) : fmaT(fmaT(fmaT(c3, xv, c2), xv, c1), xv, c0);
+                u[e] = fmaT(fmaT(e1, xv, e0), z[e], fmaT(kf, f[g][e], pol0));
+                d[e] = (p + e < P) ? u[e] - shift : (T)0;
+            }
+            store_quad(y, p, P, u);
+            double q1, q2;
+            quad_leaf(d, q1, q2);
+            a1 += q1;
+            a2 += q2;
+        }
+    }
+    double sm[2] = {a1, a2};
+    block_sum<2>(sm, lds);
+    if (threadIdx.x == 0) part_out[W.part_off + sc] = make_double2(sm[0], sm[1]);
+}
+
 // Trace entry m with the trigonometric mean field: the means of sin and cos.
 __global__ __launch_bounds__(kThreads) void k_finish_trig(const WorkItem *__restrict__ items,
                                                           const double2 *__restrict__ part_in,
@@ -1245,6 +1318,27 @@ hipError_t launch_em_step_trig(int prec, int deg, const WorkItem *items, const i
         else
             hipLaunchKernelGGL((k_em_step_trig<float, 3>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
                                part_in, part_out, shift_out, trace, m);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_em_step_cdf(int prec, int deg, const WorkItem *items, const int2 *blocks, int nblocks, int j,
+                              const double2 *part_in, const double *shift_in, const void *F, double2 *part_out,
+                              double *shift_out, double2 *trace, int m, hipStream_t s) {
+    if (prec == 0) {
+        if (deg == 1)
+            hipLaunchKernelGGL((k_em_step_cdf<double, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                               part_in, shift_in, (const double *)F, part_out, shift_out, trace, m);
+        else
+            hipLaunchKernelGGL((k_em_step_cdf<double, 3>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                               part_in, shift_in, (const double *)F, part_out, shift_out, trace, m);
+    } else {
+        if (deg == 1)
+            hipLaunchKernelGGL((k_em_step_cdf<float, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                               part_in, shift_in, (const float *)F, part_out, shift_out, trace, m);
+        else
+            hipLaunchKernelGGL((k_em_step_cdf<float, 3>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                               part_in, shift_in, (const float *)F, part_out, shift_out, trace, m);
     }
     return hipGetLastError();
 }

@@ -51,6 +51,30 @@ hipError_t launch_em_step_trig(int prec, int deg, const WorkItem *items, const i
                                hipStream_t s);
 hipError_t launch_finish_trig(const WorkItem *items, int n_items, const double2 *part_in, double2 *trace, int m,
                               hipStream_t s);
+// Empirical-CDF drift (one launch sequence per step, in cdf.hip): the state of
+// every item is gathered into keys (type of the state) and vals (particle
+// index) at the item's koff, sorted per item (a segmented radix sort), each
+// run of equal keys found by two max-scans, and F[koff + p] set to the count
+// sum_q H(x_p - x_q), H(0) = 1/2.  koff of every item is a multiple of 4;
+// fwd[0] and bwd[0] must be zero at the positions between items.
+struct CdfBuffers {
+    void *keys[2];
+    uint32_t *vals[2];
+    uint32_t *fwd[2], *bwd[2]; // flags and their max-scans
+    void *F;                   // counts, state type
+    uint32_t *seg_begin, *seg_end;
+    void *tmp;
+    size_t tmp_bytes;
+};
+// Once per fine sweep: the segment bounds of every item and zero flags.
+hipError_t launch_cdf_setup(const WorkItem *items, int n_items, uint32_t n, const CdfBuffers &b, hipStream_t s);
+// Bytes of library scratch the sort and the scans need for n positions in nseg segments.
+hipError_t cdf_scratch_bytes(int prec, uint32_t n, uint32_t nseg, size_t &bytes);
+hipError_t launch_cdf_counts(int prec, const WorkItem *items, int n_items, const int2 *blocks, int nblocks, uint32_t n,
+                             int j, const CdfBuffers &b, hipStream_t s);
+hipError_t launch_em_step_cdf(int prec, int deg, const WorkItem *items, const int2 *blocks, int nblocks, int j,
+                              const double2 *part_in, const double *shift_in, const void *F, double2 *part_out,
+                              double *shift_out, double2 *trace, int m, hipStream_t s);
 // out[i] = (1/P) sum Phi(x_p) of item i; part: scratch of one partial per superchunk.
 hipError_t launch_qoi(int prec, int kind, const WorkItem *items, int n_items, const int2 *blocks, int nblocks,
                       double2 *part, double *out, hipStream_t s);

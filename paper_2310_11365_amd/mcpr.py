@@ -32,7 +32,7 @@ class MCPRError(RuntimeError):
 
 class Coef(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs",
-                                               "ksin", "kc")]
+                                               "ksin", "kc", "acdf")]
 
 
 class ProblemC(ctypes.Structure):
@@ -139,7 +139,7 @@ def problem_c(problem, coef=None) -> ProblemC:
     """workloads.Problem (plus optional per-instance coefficients) -> mcpr_problem."""
     c = coef if coef is not None else problem.coef
     s = ProblemC()
-    for n in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs", "ksin", "kc"):
+    for n in ("a0", "a1", "a2", "a3", "am", "av", "b0", "b1", "bm", "bv", "axs", "ksin", "kc", "acdf"):
         setattr(s.coef, n, float(getattr(c, n, 0.0)))
     s.p0_kind = int(problem.p0.kind)
     s.precision = int(problem.precision)

@@ -52,6 +52,7 @@ class Coef:
     axs: float = 0.0  # coefficient of x E[X^2]
     ksin: float = 0.0  # coefficient of sin x
     kc: float = 0.0  # coupling K of the mean field (1/P) sum_q sin(X_q - x)
+    acdf: float = 0.0  # coefficient of 1 - F_P(x), F_P the empirical CDF with H(0) = 1/2
 
     def as_list(self) -> List[float]:
         return [self.a0, self.a1, self.a2, self.a3, self.am, self.av,
@@ -185,6 +186,17 @@ def rotator(P: int = 100_000, precision: int = FP64, N: int = 20, T: float = 10.
     pr.coarse_model = coarse_model
     pr.wrap = wrap
     return Workload("rotator", pr, P, max_iter=N, tol=0.0)
+
+
+def burgers(P: int = 100_000, precision: int = FP64, N: int = 10, T: float = 1.0, dt: float = 1e-3,
+            sigma: float = 1.0, seed: int = 0) -> Workload:
+    """Particle system of the viscous Burgers equation (Sec. 5.2):
+    dX = (1 - F_P(X)) dt + sigma dW, X(0) = 0, F_P the empirical CDF with
+    H(0) = 1/2; the coarse propagator is the Gaussian-density moment model
+    dM = 1/2, dSigma = -(2 / sqrt(2 pi)) sqrt(Sigma) + sigma^2.  sigma and the
+    horizon are not printed: sigma = 1, T = 1, N = 10."""
+    pr = make_problem(Coef(acdf=1.0, b0=sigma), P0(P0_DELTA, 1.0, 0.0, 0.0), T, N, dt, (), seed, 0.05, precision)
+    return Workload("burgers", pr, P, max_iter=N, tol=0.0)
 
 
 def dz_bimodal(P: int = 1_000_000, precision: int = FP32, N: int = 50, T: float = 5.0,

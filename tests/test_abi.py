@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     from paper_2310_11365_amd import mcpr
-    assert ctypes.sizeof(mcpr.ProblemC) == 13 * 8 + 2 * 4 + 6 * 8 + 4 * 4 + 7 * 8 + 8 + 2 * 4
+    assert ctypes.sizeof(mcpr.ProblemC) == 14 * 8 + 2 * 4 + 6 * 8 + 4 * 4 + 7 * 8 + 8 + 2 * 4
     assert ctypes.sizeof(mcpr.EnsembleC) == 32
     assert ctypes.sizeof(mcpr.InstanceC) == 32
     assert mcpr.STATS_DTYPE.itemsize == 48 and mcpr.MAP_DTYPE.itemsize == 32
