@@ -56,7 +56,7 @@ struct mcpr_ctx {
     DevBuf adj_items, adj_blocks; // the backward sweep's work and block tables
     // empirical-CDF drift: sort keys and indices, run flags and scans, counts,
     // segment bounds, library scratch
-    DevBuf cdf_keys[2], cdf_vals[2], cdf_fwd[2], cdf_bwd[2], cdf_F, cdf_seg, cdf_tmp;
+    DevBuf cdf_keys[3], cdf_idx[2], cdf_seg[2], cdf_pos, cdf_beg, cdf_tmp;
     mcpr::CdfBuffers cdfb{};
     HostBuf staging;
     hipEvent_t staged = nullptr; // the last upload from staging has completed
@@ -237,13 +237,13 @@ struct Tables {
     std::vector<WorkItem> items;
     std::vector<int2> blocks; // one entry per superchunk: (item, superchunk)
     int total_sc = 0;
-    int64_t total_keys = 0;   // concatenated sort positions (empirical-CDF drift)
+    int64_t total_dense = 0;  // dense sort positions, the sum of P (empirical-CDF drift)
 };
 
 void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_t n_ens, Tables &t) {
     t.items.resize(n_ens);
     t.blocks.clear();
-    t.total_keys = 0;
+    t.total_dense = 0;
     int off = 0;
     for (int e = 0; e < n_ens; ++e) {
         const mcpr_ensemble &E = ens[e];
@@ -265,8 +265,8 @@ void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_
         w.wrap = p.wrap;
         w.trig = is_trig(p) ? 1 : 0;
         w.cdf = is_cdf(p) ? 1 : 0;
-        w.koff = t.total_keys;
-        t.total_keys += (E.n_particles + 3) / 4 * 4;
+        w.doff = t.total_dense;
+        t.total_dense += E.n_particles;
         w.dt = p.dt;
         w.sdt = std::sqrt(p.dt);
         w.p0[0] = p.p0_w;
@@ -373,8 +373,8 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
     double2 *trace = want_trace ? (double2 *)ctx->trace.p : nullptr;
     const bool trig = t.items[0].trig != 0; // the same for every item of a call
     const bool cdf = t.items[0].cdf != 0;
-    const uint32_t nkeys = (uint32_t)t.total_keys;
-    if (cdf) HIP_TRY(mcpr::launch_cdf_setup(items, n, nkeys, ctx->cdfb, s));
+    const uint32_t ndense = (uint32_t)t.total_dense;
+    if (cdf) HIP_TRY(mcpr::launch_cdf_setup(items, n, ctx->cdfb, s));
     if (trig)
         HIP_TRY(mcpr::launch_sum_init_trig(prec, items, blocks, nb, part[0], shift[0], s));
     else
@@ -388,9 +388,11 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
                             : (variant < 0 ? ctx->tune_cand[0] : variant);
         if (trial) HIP_TRY(hipEventRecord(ctx->tune_ev[0][j], s));
         if (cdf) {
-            HIP_TRY(mcpr::launch_cdf_counts(prec, items, n, blocks, nb, nkeys, j, ctx->cdfb, s));
-            HIP_TRY(mcpr::launch_em_step_cdf(prec, deg, items, blocks, nb, j, part[a], shift[a], ctx->cdfb.F, part[b],
-                                             shift[b], trace, m, s));
+            const void *ks = nullptr;
+            const uint32_t *ix = nullptr;
+            HIP_TRY(mcpr::launch_cdf_sort(prec, items, n, blocks, nb, ndense, j, ctx->cdfb, &ks, &ix, s));
+            HIP_TRY(mcpr::launch_em_step_sorted(prec, deg, items, blocks, nb, j, part[a], shift[a], ks, ix, part[b],
+                                                shift[b], trace, m, s));
         } else if (trig)
             HIP_TRY(mcpr::launch_em_step_trig(prec, deg, items, blocks, nb, j, part[a], part[b], shift[b], trace, m, s));
         else
@@ -431,35 +433,33 @@ std::vector<char> graph_key(mcpr_ctx *ctx, const Tables &t, int prec, int deg, i
 
 // Buffers of the empirical-CDF drift for the concatenated ensembles of t.
 mcpr_status ensure_cdf(mcpr_ctx *ctx, const Tables &t, int prec) {
-    const size_t n = (size_t)t.total_keys, es = prec == 0 ? sizeof(double) : sizeof(float);
+    const size_t n = (size_t)t.total_dense, es = prec == 0 ? sizeof(double) : sizeof(float);
     const int nseg = (int)t.items.size();
-    if (t.total_keys >= ((int64_t)1 << 32) - 1)
+    if (t.total_dense >= ((int64_t)1 << 32) - 1)
         return fail(ctx, MCPR_E_UNSUPPORTED, "empirical-CDF drift: %lld particles in one launch exceed 2^32 - 1",
-                    (long long)t.total_keys);
+                    (long long)t.total_dense);
     mcpr_status st;
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < 3; ++b)
         if ((st = ensure(ctx, ctx->cdf_keys[b], n * es)) != MCPR_OK) return st;
-        if ((st = ensure(ctx, ctx->cdf_vals[b], n * sizeof(uint32_t))) != MCPR_OK) return st;
-        if ((st = ensure(ctx, ctx->cdf_fwd[b], n * sizeof(uint32_t))) != MCPR_OK) return st;
-        if ((st = ensure(ctx, ctx->cdf_bwd[b], n * sizeof(uint32_t))) != MCPR_OK) return st;
+    for (int b = 0; b < 2; ++b) {
+        if ((st = ensure(ctx, ctx->cdf_idx[b], n * sizeof(uint32_t))) != MCPR_OK) return st;
+        if ((st = ensure(ctx, ctx->cdf_seg[b], n * sizeof(uint32_t))) != MCPR_OK) return st;
     }
-    if ((st = ensure(ctx, ctx->cdf_F, n * es)) != MCPR_OK) return st;
-    if ((st = ensure(ctx, ctx->cdf_seg, 2 * (size_t)nseg * sizeof(uint32_t))) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->cdf_pos, n * sizeof(uint32_t))) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->cdf_beg, (size_t)nseg * sizeof(uint32_t))) != MCPR_OK) return st;
     size_t tb = 0;
     HIP_TRY(mcpr::cdf_scratch_bytes(prec, (uint32_t)n, (uint32_t)nseg, tb));
     if ((st = ensure(ctx, ctx->cdf_tmp, tb > 0 ? tb : 1)) != MCPR_OK) return st;
     mcpr::CdfBuffers &c = ctx->cdfb;
+    for (int b = 0; b < 3; ++b) c.keys[b] = ctx->cdf_keys[b].p;
     for (int b = 0; b < 2; ++b) {
-        c.keys[b] = ctx->cdf_keys[b].p;
-        c.vals[b] = (uint32_t *)ctx->cdf_vals[b].p;
-        c.fwd[b] = (uint32_t *)ctx->cdf_fwd[b].p;
-        c.bwd[b] = (uint32_t *)ctx->cdf_bwd[b].p;
+        c.idx[b] = (uint32_t *)ctx->cdf_idx[b].p;
+        c.seg[b] = (uint32_t *)ctx->cdf_seg[b].p;
     }
-    c.F = ctx->cdf_F.p;
-    c.seg_begin = (uint32_t *)ctx->cdf_seg.p;
-    c.seg_end = c.seg_begin + nseg;
+    c.pos = (uint32_t *)ctx->cdf_pos.p;
+    c.seg_begin = (uint32_t *)ctx->cdf_beg.p;
     c.tmp = ctx->cdf_tmp.p;
-    c.tmp_bytes = tb;
+    c.tmp_bytes = ctx->cdf_tmp.cap;
     return MCPR_OK;
 }
 
@@ -642,9 +642,8 @@ void mcpr_destroy(mcpr_ctx *ctx) {
                       &ctx->recs,          &ctx->adj_ckpt,    &ctx->adj_traj,    &ctx->adj_lam[0],  &ctx->adj_lam[1],
                       &ctx->adj_part[0],   &ctx->adj_part[1], &ctx->adj_acc,     &ctx->adj_trace,   &ctx->adj_grad,
                       &ctx->adj_sums,      &ctx->adj_items,   &ctx->adj_blocks,  &ctx->trace,       &ctx->mv,
-                      &ctx->cdf_keys[0],   &ctx->cdf_keys[1], &ctx->cdf_vals[0], &ctx->cdf_vals[1], &ctx->cdf_fwd[0],
-                      &ctx->cdf_fwd[1],    &ctx->cdf_bwd[0],  &ctx->cdf_bwd[1],  &ctx->cdf_F,       &ctx->cdf_seg,
-                      &ctx->cdf_tmp};
+                      &ctx->cdf_keys[0],   &ctx->cdf_keys[1], &ctx->cdf_keys[2], &ctx->cdf_idx[0],  &ctx->cdf_idx[1],
+                      &ctx->cdf_seg[0],    &ctx->cdf_seg[1],  &ctx->cdf_pos,     &ctx->cdf_beg,     &ctx->cdf_tmp};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->staging.p) (void)hipHostFree(ctx->staging.p);

@@ -1,23 +1,26 @@
-// cdf.hip -- ranks for the empirical-CDF drift term (the particle system of
-// the viscous Burgers equation, Sec. 5.2).
+// cdf.hip -- the sorted order the empirical-CDF drift term needs (the
+// particle system of the viscous Burgers equation, Sec. 5.2).
 //
 // The drift acdf (1 - F_P(x_p)) needs, at every step and for every particle,
 // the count sum_q H(x_p - x_q) with H(0) = 1/2: the number of particles below
-// x_p plus half the number equal to it (itself included).  Per step:
-//   1. gather: the state of every item of the launch into one key array (at
-//      the item's offset koff) with the particle index as value;
-//   2. a segmented radix sort of the pairs, one segment per item (rocPRIM);
-//   3. run flags: fwd[i] = i at the first position of a run of equal keys
-//      (a segment start is always one), bwd[n-1-i] = n-1-i at the last one;
-//   4. two inclusive max-scans: fwd gives each position the start of its
-//      run, bwd (indexed from the end) its last position;
-//   5. rank: F[koff + index] = (start - koff) + (end - start + 1) / 2.
-// Runs never cross a segment, so the whole launch is one pair of scans.
+// x_p plus half the number equal to it (itself included).  Each item's states
+// in ascending order give it: position r of a run [lo, hi] of equal keys has
+// the count lo + (hi - lo + 1) / 2 (the step kernel, k_em_step_sorted, finds
+// the run).  The items of a launch are laid end to end in a dense index space
+// (item i at doff_i).  Per step:
+//   1. gather: every item's state into keys[0] at doff + p;
+//   2. one device-wide radix sort of (key, dense index) pairs over all items;
+//   3. with several items: each sorted key's item, then a stable radix sort
+//      by item (a few bits), which leaves each item's keys in ascending order
+//      at [doff, doff + P); keys and indices are permuted into that order.
+// A device-wide sort rather than a segmented one: the segmented sort gives
+// each segment to one workgroup, which leaves the chip idle for the few large
+// ensembles a Parareal sweep batches.
 #include <cstring>
 
 #include <hip/hip_runtime.h>
-#include <rocprim/device/device_scan.hpp>
-#include <rocprim/device/device_segmented_radix_sort.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
 
 #include "common.hpp"
 #include "launch.hpp"
@@ -28,7 +31,7 @@ namespace {
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_cdf_gather(const WorkItem *__restrict__ items,
                                                          const int2 *__restrict__ blocks, int32_t j,
-                                                         T *__restrict__ keys, uint32_t *__restrict__ vals) {
+                                                         T *__restrict__ keys) {
     const int2 bt = blocks[blockIdx.x];
     const WorkItem &W = items[bt.x];
     const T *__restrict__ x = reinterpret_cast<const T *>(W.x) + (int64_t)j * W.traj;
@@ -38,123 +41,105 @@ __global__ __launch_bounds__(kThreads) void k_cdf_gather(const WorkItem *__restr
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int64_t p = base + 4 * (int64_t)(r * kThreads + threadIdx.x) + e;
-            if (p < P) {
-                keys[W.koff + p] = x[p];
-                vals[W.koff + p] = (uint32_t)p;
-            }
+            if (p < P) keys[W.doff + p] = x[p];
         }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cdf_flags(const WorkItem *__restrict__ items,
-                                                        const int2 *__restrict__ blocks,
-                                                        const T *__restrict__ keys, uint32_t n,
-                                                        uint32_t *__restrict__ fwd, uint32_t *__restrict__ bwd) {
-    const int2 bt = blocks[blockIdx.x];
-    const WorkItem &W = items[bt.x];
-    const int64_t P = W.P;
-    const int64_t base = (int64_t)bt.y * 4 * kThreads * W.R;
-    for (int r = 0; r < W.R; ++r)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t rp = base + 4 * (int64_t)(r * kThreads + threadIdx.x) + e;
-            if (rp < P) {
-                const uint32_t i = (uint32_t)(W.koff + rp);
-                const bool first = rp == 0 || keys[i] != keys[i - 1];
-                const bool last = rp == P - 1 || keys[i] != keys[i + 1];
-                fwd[i] = first ? i : 0u;
-                bwd[n - 1u - i] = last ? n - 1u - i : 0u;
-            }
-        }
+// Item of every value-sorted key: the last item whose first dense position is
+// at or below the key's dense index (beg holds n_items ascending starts).
+__global__ __launch_bounds__(kThreads) void k_cdf_segkey(const uint32_t *__restrict__ idx, uint32_t n,
+                                                         const uint32_t *__restrict__ beg, int n_items,
+                                                         uint32_t *__restrict__ seg) {
+    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t g = idx[i];
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (beg[mid] <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    seg[i] = (uint32_t)lo;
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cdf_rank(const WorkItem *__restrict__ items,
-                                                       const int2 *__restrict__ blocks,
-                                                       const uint32_t *__restrict__ vals,
-                                                       const uint32_t *__restrict__ start,
-                                                       const uint32_t *__restrict__ bwd_scan, uint32_t n,
-                                                       T *__restrict__ F) {
-    const int2 bt = blocks[blockIdx.x];
-    const WorkItem &W = items[bt.x];
-    const int64_t P = W.P;
-    const int64_t base = (int64_t)bt.y * 4 * kThreads * W.R;
-    for (int r = 0; r < W.R; ++r)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t rp = base + 4 * (int64_t)(r * kThreads + threadIdx.x) + e;
-            if (rp < P) {
-                const uint32_t i = (uint32_t)(W.koff + rp);
-                const uint32_t s = start[i];
-                const uint32_t last = n - 1u - bwd_scan[n - 1u - i];
-                const double cnt = (double)((int64_t)s - W.koff) + 0.5 * (double)(last - s + 1u);
-                F[W.koff + vals[i]] = (T)cnt;
-            }
-        }
+__global__ __launch_bounds__(kThreads) void k_cdf_permute(const uint32_t *__restrict__ pos, uint32_t n,
+                                                          const T *__restrict__ kin, const uint32_t *__restrict__ iin,
+                                                          T *__restrict__ kout, uint32_t *__restrict__ iout) {
+    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t q = pos[i];
+    kout[i] = kin[q];
+    iout[i] = iin[q];
+}
+
+__global__ __launch_bounds__(kThreads) void k_cdf_setup(const WorkItem *__restrict__ items, int n_items,
+                                                        uint32_t *__restrict__ beg) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n_items) beg[i] = (uint32_t)items[i].doff;
+}
+
+// Bits that hold every item number below n_items.
+unsigned seg_bits(uint32_t n_items) {
+    unsigned b = 1;
+    while (b < 32 && ((uint64_t)1 << b) < n_items) ++b;
+    return b;
 }
 
 template <typename T>
-hipError_t sort_pairs(void *tmp, size_t &bytes, const T *kin, T *kout, const uint32_t *vin, uint32_t *vout,
-                      uint32_t n, uint32_t nseg, const uint32_t *beg, const uint32_t *end, hipStream_t s) {
-    return rocprim::segmented_radix_sort_pairs(tmp, bytes, kin, kout, vin, vout, n, nseg, beg, end, 0,
-                                               (unsigned)(8 * sizeof(T)), s);
+hipError_t sort_values(void *tmp, size_t &bytes, const T *kin, T *kout, uint32_t *iout, uint32_t n, hipStream_t s) {
+    return rocprim::radix_sort_pairs(tmp, bytes, kin, kout, rocprim::counting_iterator<uint32_t>(0u), iout, (size_t)n,
+                                     0u, (unsigned)(8 * sizeof(T)), s);
 }
 
-hipError_t scan_max(void *tmp, size_t &bytes, const uint32_t *in, uint32_t *out, uint32_t n, hipStream_t s) {
-    return rocprim::inclusive_scan(tmp, bytes, in, out, (size_t)n, rocprim::maximum<uint32_t>(), s);
+hipError_t sort_items(void *tmp, size_t &bytes, const uint32_t *sin, uint32_t *sout, uint32_t *pos, uint32_t n,
+                      unsigned bits, hipStream_t s) {
+    return rocprim::radix_sort_pairs(tmp, bytes, sin, sout, rocprim::counting_iterator<uint32_t>(0u), pos, (size_t)n,
+                                     0u, bits, s);
 }
 
 template <typename T>
 hipError_t scratch_bytes(uint32_t n, uint32_t nseg, size_t &bytes) {
     size_t a = 0, b = 0;
-    hipError_t e = sort_pairs<T>(nullptr, a, nullptr, nullptr, nullptr, nullptr, n, nseg, nullptr, nullptr, 0);
+    hipError_t e = sort_values<T>(nullptr, a, nullptr, nullptr, nullptr, n, 0);
     if (e != hipSuccess) return e;
-    e = scan_max(nullptr, b, nullptr, nullptr, n, 0);
-    if (e != hipSuccess) return e;
+    if (nseg > 1 && (e = sort_items(nullptr, b, nullptr, nullptr, nullptr, n, seg_bits(nseg), 0)) != hipSuccess)
+        return e;
     bytes = a > b ? a : b;
     return hipSuccess;
 }
 
 template <typename T>
-hipError_t counts(const WorkItem *items, int n_items, const int2 *blocks, int nblocks, uint32_t n, int j,
-                  const CdfBuffers &b, hipStream_t s) {
-    hipLaunchKernelGGL(k_cdf_gather<T>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j, (T *)b.keys[0],
-                       b.vals[0]);
+hipError_t sorted(const WorkItem *items, int n_items, const int2 *blocks, int nblocks, uint32_t n, int j,
+                  const CdfBuffers &b, const void **ks, const uint32_t **ix, hipStream_t s) {
+    T *k0 = (T *)b.keys[0], *k1 = (T *)b.keys[1], *k2 = (T *)b.keys[2];
+    const dim3 flat((n + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_cdf_gather<T>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j, k0);
     size_t bytes = b.tmp_bytes;
-    hipError_t e = sort_pairs<T>(b.tmp, bytes, (const T *)b.keys[0], (T *)b.keys[1], b.vals[0], b.vals[1], n,
-                                 (uint32_t)n_items, b.seg_begin, b.seg_end, s);
+    hipError_t e = sort_values<T>(b.tmp, bytes, k0, k1, b.idx[0], n, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cdf_flags<T>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, (const T *)b.keys[1], n,
-                       b.fwd[0], b.bwd[0]);
-    bytes = b.tmp_bytes;
-    if ((e = scan_max(b.tmp, bytes, b.fwd[0], b.fwd[1], n, s)) != hipSuccess) return e;
-    bytes = b.tmp_bytes;
-    if ((e = scan_max(b.tmp, bytes, b.bwd[0], b.bwd[1], n, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cdf_rank<T>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, b.vals[1], b.fwd[1],
-                       b.bwd[1], n, (T *)b.F);
+    *ks = k1;
+    *ix = b.idx[0];
+    if (n_items > 1) {
+        hipLaunchKernelGGL(k_cdf_segkey, flat, dim3(kThreads), 0, s, b.idx[0], n, b.seg_begin, n_items, b.seg[0]);
+        bytes = b.tmp_bytes;
+        if ((e = sort_items(b.tmp, bytes, b.seg[0], b.seg[1], b.pos, n, seg_bits((uint32_t)n_items), s)) !=
+            hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_cdf_permute<T>, flat, dim3(kThreads), 0, s, b.pos, n, k1, b.idx[0], k2, b.idx[1]);
+        *ks = k2;
+        *ix = b.idx[1];
+    }
     return hipGetLastError();
-}
-
-__global__ __launch_bounds__(kThreads) void k_cdf_setup(const WorkItem *__restrict__ items, int n_items, uint32_t n,
-                                                        uint32_t *__restrict__ beg, uint32_t *__restrict__ end,
-                                                        uint32_t *__restrict__ fwd, uint32_t *__restrict__ bwd) {
-    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
-    if (i < n) {
-        fwd[i] = 0u;
-        bwd[i] = 0u;
-    }
-    if ((int)i < n_items) {
-        beg[i] = (uint32_t)items[i].koff;
-        end[i] = (uint32_t)(items[i].koff + items[i].P);
-    }
 }
 
 } // namespace
 
-hipError_t launch_cdf_setup(const WorkItem *items, int n_items, uint32_t n, const CdfBuffers &b, hipStream_t s) {
-    const uint32_t cover = n > (uint32_t)n_items ? n : (uint32_t)n_items;
-    hipLaunchKernelGGL(k_cdf_setup, dim3((cover + kThreads - 1) / kThreads), dim3(kThreads), 0, s, items, n_items, n,
-                       b.seg_begin, b.seg_end, b.fwd[0], b.bwd[0]);
+hipError_t launch_cdf_setup(const WorkItem *items, int n_items, const CdfBuffers &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_cdf_setup, dim3((n_items + kThreads - 1) / kThreads), dim3(kThreads), 0, s, items, n_items,
+                       b.seg_begin);
     return hipGetLastError();
 }
 
@@ -162,10 +147,10 @@ hipError_t cdf_scratch_bytes(int prec, uint32_t n, uint32_t nseg, size_t &bytes)
     return prec == 0 ? scratch_bytes<double>(n, nseg, bytes) : scratch_bytes<float>(n, nseg, bytes);
 }
 
-hipError_t launch_cdf_counts(int prec, const WorkItem *items, int n_items, const int2 *blocks, int nblocks, uint32_t n,
-                             int j, const CdfBuffers &b, hipStream_t s) {
-    return prec == 0 ? counts<double>(items, n_items, blocks, nblocks, n, j, b, s)
-                     : counts<float>(items, n_items, blocks, nblocks, n, j, b, s);
+hipError_t launch_cdf_sort(int prec, const WorkItem *items, int n_items, const int2 *blocks, int nblocks, uint32_t n,
+                           int j, const CdfBuffers &b, const void **ks, const uint32_t **ix, hipStream_t s) {
+    return prec == 0 ? sorted<double>(items, n_items, blocks, nblocks, n, j, b, ks, ix, s)
+                     : sorted<float>(items, n_items, blocks, nblocks, n, j, b, ks, ix, s);
 }
 
 } // namespace mcpr

@@ -54,7 +54,7 @@ struct WorkItem {
     int32_t trig;      // 1: trigonometric drift terms; the step's mean field is (mean sin, mean cos)
     int32_t cdf;       // 1: empirical-CDF drift term (every step ranks the ensemble)
     int32_t pad;
-    int64_t koff;      // first position of this item in the launch's concatenated sort arrays
+    int64_t doff;      // first position of this item in the launch's dense sort arrays
     double c[14];      // a0 a1 a2 a3 am av b0 b1 bm bv axs ksin kc acdf
     double dt, sdt;    // step and its square root
     double p0[5];      // w, mu1, sd1, mu2, sd2

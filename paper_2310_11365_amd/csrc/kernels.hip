@@ -538,37 +538,66 @@ __global__ __launch_bounds__(kThreads) void k_em_step_trig(const WorkItem *__res
     if (threadIdx.x == 0) part_out[W.part_off + sc] = make_double2(sm[0], sm[1]);
 }
 
-// One Euler-Maruyama step with the empirical-CDF drift term acdf (1 - F_P(x)):
-// F + koff holds the counts sum_q H(x_p - x_q) of the step's input state
-// (launch_cdf_counts).  The (m, v) partials are formed as in k_em_step, for
-// the trace and the next step's shift.
+template <typename T>
+__device__ __forceinline__ T normal_pick(const Words4 &w, int e);
+template <>
+__device__ __forceinline__ double normal_pick<double>(const Words4 &w, int e) { return normal_of(w, e); }
+template <>
+__device__ __forceinline__ float normal_pick<float>(const Words4 &w, int e) { return normal_of_f(w, e); }
+
+// First (DIR < 0) or last (DIR > 0) position of the run of keys equal to v
+// that contains position r of the ascending array K[0, P): doubling steps
+// away from r while the key still equals v, then bisection of the last step.
+template <int DIR, typename T>
+__device__ __forceinline__ int64_t run_end(const T *__restrict__ K, int64_t P, int64_t r, T v) {
+    int64_t known = r, step = 1;
+    for (;;) {
+        const int64_t probe = known + DIR * step;
+        if (probe < 0 || probe >= P || K[probe] != v) break;
+        known = probe;
+        step <<= 1;
+    }
+    // K[known] == v; the position `step` beyond it is outside [0, P) or differs
+    int64_t out = known + DIR * step;
+    out = out < -1 ? -1 : (out > P ? P : out);
+    while ((out - known) * DIR > 1) {
+        const int64_t mid = known + (out - known) / 2;
+        if (K[mid] == v)
+            known = mid;
+        else
+            out = mid;
+    }
+    return known;
+}
+
+// One Euler-Maruyama step with the empirical-CDF drift term acdf (1 - F_P(x)),
+// taken in the ensemble's ascending order: K (the item's sorted states) and
+// I (their dense indices, doff + p) come from launch_cdf_sort.  Position r of
+// K has sum_q H(x - X_q) = lo + (hi - lo + 1) / 2 for the run [lo, hi] of
+// keys equal to K[r] (distinct neighbours: r + 1/2).  The new state goes to
+// y[p] of particle p, its normal is normal p & 3 of Philox quad p >> 2 as in
+// the particle-order steps.  The (m, v) partials of the new states are summed
+// in sorted order (a fixed order for a given state).
 template <typename T, int DEG>
-__global__ __launch_bounds__(kThreads) void k_em_step_cdf(const WorkItem *__restrict__ items,
-                                                          const int2 *__restrict__ blocks, int32_t j,
-                                                          const double2 *__restrict__ part_in,
-                                                          const double *__restrict__ shift_in,
-                                                          const T *__restrict__ F, double2 *__restrict__ part_out,
-                                                          double *__restrict__ shift_out,
-                                                          double2 *__restrict__ trace, int32_t m) {
+__global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__restrict__ items,
+                                                             const int2 *__restrict__ blocks, int32_t j,
+                                                             const double2 *__restrict__ part_in,
+                                                             const double *__restrict__ shift_in,
+                                                             const T *__restrict__ ks,
+                                                             const uint32_t *__restrict__ ix,
+                                                             double2 *__restrict__ part_out,
+                                                             double *__restrict__ shift_out,
+                                                             double2 *__restrict__ trace, int32_t m) {
     __shared__ double lds[8];
     const int2 bt = blocks[blockIdx.x];
     const int item = bt.x, sc = bt.y;
     const WorkItem &W = items[item];
-    T *__restrict__ x = reinterpret_cast<T *>(W.x) + (int64_t)j * W.traj;
-    T *__restrict__ y = x + W.traj;
-    const T *__restrict__ Fi = F + W.koff;
+    T *__restrict__ y = reinterpret_cast<T *>(W.x) + (int64_t)(j + 1) * W.traj;
+    const T *__restrict__ K = ks + W.doff;
+    const uint32_t *__restrict__ I = ix + W.doff;
     const int64_t P = W.P;
     const int R = W.R;
     const int64_t base = (int64_t)sc * 4 * kThreads * R;
-    T v[kMaxQuadsPerThread][4], f[kMaxQuadsPerThread][4];
-#pragma unroll
-    for (int g = 0; g < kMaxQuadsPerThread; ++g) {
-        const int64_t p = base + 4 * (int64_t)(g * kThreads + threadIdx.x);
-        if (g < R && p < P) {
-            load_quad(x, p, P, v[g]);
-            load_quad(Fi, p, P, f[g]);
-        }
-    }
     double S1, S2, mean, var;
     ensemble_sums(part_in + W.part_off, W.nsc, S1, S2, lds);
     finish_moments(S1, S2, shift_in[item], (double)P, mean, var);
@@ -585,26 +614,32 @@ __global__ __launch_bounds__(kThreads) void k_em_step_cdf(const WorkItem *__rest
     const uint32_t step = (uint32_t)(W.step0 + j);
     const uint32_t inst = (uint32_t)W.inst;
     double a1 = 0.0, a2 = 0.0;
+    for (int g = 0; g < R; ++g) {
+        T d[4];
 #pragma unroll
-    for (int g = 0; g < kMaxQuadsPerThread; ++g) {
-        const int64_t p = base + 4 * (int64_t)(g * kThreads + threadIdx.x);
-        if (g < R && p < P) {
-            const Words4 w = philox4x32_10((uint32_t)(p >> 2), step, inst, 0u, W.key0, W.key1);
-            T z[4], u[4], d[4];
-            box_muller4(w, z);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const T xv = v[g][e];
-                const T pol0 = (DEG == 1) ? fmaT(c1, xv, c0) : fmaT(fmaT(fmaT(c3, xv, c2), xv, c1), xv, c0);
-                u[e] = fmaT(fmaT(e1, xv, e0), z[e], fmaT(kf, f[g][e], pol0));
-                d[e] = (p + e < P) ? u[e] - shift : (T)0;
+        for (int e = 0; e < 4; ++e) {
+            // lane-contiguous positions: every load instruction reads 64 consecutive keys
+            const int64_t r = base + (int64_t)(4 * g + e) * kThreads + threadIdx.x;
+            d[e] = (T)0;
+            if (r < P) {
+                const T v = K[r];
+                int64_t lo = r, hi = r;
+                if (r > 0 && K[r - 1] == v) lo = run_end<-1>(K, P, r, v);
+                if (r + 1 < P && K[r + 1] == v) hi = run_end<1>(K, P, r, v);
+                const T cnt = (T)((double)lo + 0.5 * (double)(hi - lo + 1));
+                const int64_t p = (int64_t)I[r] - W.doff;
+                const Words4 w = philox4x32_10((uint32_t)(p >> 2), step, inst, 0u, W.key0, W.key1);
+                const T z = normal_pick<T>(w, (int)(p & 3));
+                const T pol0 = (DEG == 1) ? fmaT(c1, v, c0) : fmaT(fmaT(fmaT(c3, v, c2), v, c1), v, c0);
+                const T u = fmaT(fmaT(e1, v, e0), z, fmaT(kf, cnt, pol0));
+                y[p] = u;
+                d[e] = u - shift;
             }
-            store_quad(y, p, P, u);
-            double q1, q2;
-            quad_leaf(d, q1, q2);
-            a1 += q1;
-            a2 += q2;
         }
+        double q1, q2;
+        quad_leaf(d, q1, q2);
+        a1 += q1;
+        a2 += q2;
     }
     double sm[2] = {a1, a2};
     block_sum<2>(sm, lds);
@@ -1322,23 +1357,23 @@ hipError_t launch_em_step_trig(int prec, int deg, const WorkItem *items, const i
     return hipGetLastError();
 }
 
-hipError_t launch_em_step_cdf(int prec, int deg, const WorkItem *items, const int2 *blocks, int nblocks, int j,
-                              const double2 *part_in, const double *shift_in, const void *F, double2 *part_out,
-                              double *shift_out, double2 *trace, int m, hipStream_t s) {
+hipError_t launch_em_step_sorted(int prec, int deg, const WorkItem *items, const int2 *blocks, int nblocks, int j,
+                                 const double2 *part_in, const double *shift_in, const void *ks, const uint32_t *ix,
+                                 double2 *part_out, double *shift_out, double2 *trace, int m, hipStream_t s) {
     if (prec == 0) {
         if (deg == 1)
-            hipLaunchKernelGGL((k_em_step_cdf<double, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
-                               part_in, shift_in, (const double *)F, part_out, shift_out, trace, m);
+            hipLaunchKernelGGL((k_em_step_sorted<double, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                               part_in, shift_in, (const double *)ks, ix, part_out, shift_out, trace, m);
         else
-            hipLaunchKernelGGL((k_em_step_cdf<double, 3>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
-                               part_in, shift_in, (const double *)F, part_out, shift_out, trace, m);
+            hipLaunchKernelGGL((k_em_step_sorted<double, 3>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                               part_in, shift_in, (const double *)ks, ix, part_out, shift_out, trace, m);
     } else {
         if (deg == 1)
-            hipLaunchKernelGGL((k_em_step_cdf<float, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
-                               part_in, shift_in, (const float *)F, part_out, shift_out, trace, m);
+            hipLaunchKernelGGL((k_em_step_sorted<float, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                               part_in, shift_in, (const float *)ks, ix, part_out, shift_out, trace, m);
         else
-            hipLaunchKernelGGL((k_em_step_cdf<float, 3>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
-                               part_in, shift_in, (const float *)F, part_out, shift_out, trace, m);
+            hipLaunchKernelGGL((k_em_step_sorted<float, 3>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                               part_in, shift_in, (const float *)ks, ix, part_out, shift_out, trace, m);
     }
     return hipGetLastError();
 }

@@ -51,30 +51,30 @@ hipError_t launch_em_step_trig(int prec, int deg, const WorkItem *items, const i
                                hipStream_t s);
 hipError_t launch_finish_trig(const WorkItem *items, int n_items, const double2 *part_in, double2 *trace, int m,
                               hipStream_t s);
-// Empirical-CDF drift (one launch sequence per step, in cdf.hip): the state of
-// every item is gathered into keys (type of the state) and vals (particle
-// index) at the item's koff, sorted per item (a segmented radix sort), each
-// run of equal keys found by two max-scans, and F[koff + p] set to the count
-// sum_q H(x_p - x_q), H(0) = 1/2.  koff of every item is a multiple of 4;
-// fwd[0] and bwd[0] must be zero at the positions between items.
+// Empirical-CDF drift (in cdf.hip): the states of the items laid end to end
+// (item i at dense offset doff, n positions in all), sorted by value and then
+// stably by item, so that each item's states are ascending at [doff, doff + P)
+// together with their dense indices.
 struct CdfBuffers {
-    void *keys[2];
-    uint32_t *vals[2];
-    uint32_t *fwd[2], *bwd[2]; // flags and their max-scans
-    void *F;                   // counts, state type
-    uint32_t *seg_begin, *seg_end;
+    void *keys[3];      // gathered, sorted by value, sorted by (item, value); state type, n each
+    uint32_t *idx[2];   // dense index of each key after the value sort / after the item sort
+    uint32_t *seg[2];   // item of each value-sorted key, before / after the item sort
+    uint32_t *pos;      // value-sorted position of each (item, value)-sorted key
+    uint32_t *seg_begin; // doff of every item
     void *tmp;
     size_t tmp_bytes;
 };
-// Once per fine sweep: the segment bounds of every item and zero flags.
-hipError_t launch_cdf_setup(const WorkItem *items, int n_items, uint32_t n, const CdfBuffers &b, hipStream_t s);
-// Bytes of library scratch the sort and the scans need for n positions in nseg segments.
+// Once per fine sweep: the dense first position of every item.
+hipError_t launch_cdf_setup(const WorkItem *items, int n_items, const CdfBuffers &b, hipStream_t s);
+// Bytes of library scratch the sorts need for n positions of nseg items.
 hipError_t cdf_scratch_bytes(int prec, uint32_t n, uint32_t nseg, size_t &bytes);
-hipError_t launch_cdf_counts(int prec, const WorkItem *items, int n_items, const int2 *blocks, int nblocks, uint32_t n,
-                             int j, const CdfBuffers &b, hipStream_t s);
-hipError_t launch_em_step_cdf(int prec, int deg, const WorkItem *items, const int2 *blocks, int nblocks, int j,
-                              const double2 *part_in, const double *shift_in, const void *F, double2 *part_out,
-                              double *shift_out, double2 *trace, int m, hipStream_t s);
+// Sorted states of step j's input (*ks, state type) and their dense indices (*ix).
+hipError_t launch_cdf_sort(int prec, const WorkItem *items, int n_items, const int2 *blocks, int nblocks, uint32_t n,
+                           int j, const CdfBuffers &b, const void **ks, const uint32_t **ix, hipStream_t s);
+// The Euler-Maruyama step with the empirical-CDF drift, in sorted order.
+hipError_t launch_em_step_sorted(int prec, int deg, const WorkItem *items, const int2 *blocks, int nblocks, int j,
+                                 const double2 *part_in, const double *shift_in, const void *ks, const uint32_t *ix,
+                                 double2 *part_out, double *shift_out, double2 *trace, int m, hipStream_t s);
 // out[i] = (1/P) sum Phi(x_p) of item i; part: scratch of one partial per superchunk.
 hipError_t launch_qoi(int prec, int kind, const WorkItem *items, int n_items, const int2 *blocks, int nblocks,
                       double2 *part, double *out, hipStream_t s);

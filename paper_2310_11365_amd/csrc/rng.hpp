@@ -75,6 +75,26 @@ __device__ __forceinline__ void box_muller4(const Words4 &w, float z[4]) {
     z[3] = r23 * __builtin_amdgcn_sinf(u3);
 }
 
+// Normal e of the quad, by the same operations as box_muller4 (only its pair).
+__device__ __forceinline__ double normal_of(const Words4 &w, int e) {
+    const double s = 2.3283064365386962890625e-10; // 2^-32
+    const uint32_t wa = e < 2 ? w.w0 : w.w2, wb = e < 2 ? w.w1 : w.w3;
+    const double ua = ((double)wa + 0.5) * s, ub = ((double)wb + 0.5) * s;
+    const double r = sqrt(-2.0 * log(ua));
+    double sn, cs;
+    sincospi(2.0 * ub, &sn, &cs);
+    return (e & 1) ? r * sn : r * cs;
+}
+__device__ __forceinline__ float normal_of_f(const Words4 &w, int e) {
+    const float s = 2.3283064365386963e-10f; // 2^-32
+    const float h = 1.1641532182693481e-10f; // 2^-33
+    const uint32_t wa = e < 2 ? w.w0 : w.w2, wb = e < 2 ? w.w1 : w.w3;
+    const float ua = fmaf((float)wa, s, h), ub = fmaf((float)wb, s, h);
+    const float m2ln2 = -1.3862943611198906f; // -2 ln 2
+    const float r = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(ua));
+    return (e & 1) ? r * __builtin_amdgcn_sinf(ub) : r * __builtin_amdgcn_cosf(ub);
+}
+
 __device__ __forceinline__ double uniform_of(uint32_t w) {
     return ((double)w + 0.5) * 2.3283064365386962890625e-10;
 }
