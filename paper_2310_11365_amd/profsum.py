@@ -17,18 +17,24 @@ import sqlite3
 import statistics
 
 
+def short_name(name: str) -> str:
+    """Kernel name without its argument list, 'void ' and anonymous namespaces."""
+    name = name.replace("(anonymous namespace)::", "").replace("ROCPRIM_400200_NS::detail::", "")
+    return name.split("(")[0].replace("void ", "")
+
+
 def kernel_table(db_path: str, limit: int = 12):
     cur = sqlite3.connect(db_path).cursor()
     rows = list(cur.execute("select name, total_calls, total_duration, average, percentage from top_kernels "
                             "order by total_duration desc limit ?", (limit,)))
-    return [(r[0].split("(")[0].replace("void ", ""), int(r[1]), float(r[2]), float(r[3]), float(r[4])) for r in rows]
+    return [(short_name(r[0]), int(r[1]), float(r[2]), float(r[3]), float(r[4])) for r in rows]
 
 
 def durations(db_path: str, kernel: str):
     cur = sqlite3.connect(db_path).cursor()
     out = []
     for name, d in cur.execute("select name, duration from kernels"):
-        if name.split("(")[0].replace("void ", "").replace("mcpr::", "") == kernel:
+        if short_name(name).replace("mcpr::", "") == kernel:
             out.append(d / 1e3)
     return out
 
@@ -36,7 +42,7 @@ def durations(db_path: str, kernel: str):
 def counter_per_dispatch(db_path: str, kernel: str):
     cur = sqlite3.connect(db_path).cursor()
     q = list(cur.execute("select kernel_name, value from counters_collection"))
-    vals = [v for k, v in q if k.split("(")[0].replace("void ", "").replace("mcpr::", "") == kernel]
+    vals = [v for k, v in q if short_name(k).replace("mcpr::", "") == kernel]
     copies = [v for k, v in q if "copyBuffer" in k]
     return vals, (max(copies) if copies else None)
 
@@ -46,7 +52,7 @@ def counters_of(db_path: str, kernel: str):
     cur = sqlite3.connect(db_path).cursor()
     vals = {}
     for k, name, v in cur.execute("select kernel_name, counter_name, value from counters_collection"):
-        if k.split("(")[0].replace("void ", "").replace("mcpr::", "") == kernel:
+        if short_name(k).replace("mcpr::", "") == kernel:
             vals.setdefault(name, []).append(v)
     return {n: (statistics.mean(v), len(v)) for n, v in vals.items()}
 
