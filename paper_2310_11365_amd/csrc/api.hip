@@ -56,7 +56,7 @@ struct mcpr_ctx {
     DevBuf adj_items, adj_blocks; // the backward sweep's work and block tables
     // empirical-CDF drift: sort keys and indices, run flags and scans, counts,
     // segment bounds, library scratch
-    DevBuf cdf_keys[3], cdf_idx[2], cdf_seg[2], cdf_pos, cdf_beg, cdf_tmp;
+    DevBuf cdf_keys[2], cdf_lab[2], cdf_seg[2], cdf_kl[2], cdf_beg, cdf_tmp;
     mcpr::CdfBuffers cdfb{};
     HostBuf staging;
     hipEvent_t staged = nullptr; // the last upload from staging has completed
@@ -374,7 +374,7 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
     const bool trig = t.items[0].trig != 0; // the same for every item of a call
     const bool cdf = t.items[0].cdf != 0;
     const uint32_t ndense = (uint32_t)t.total_dense;
-    if (cdf) HIP_TRY(mcpr::launch_cdf_setup(items, n, ctx->cdfb, s));
+    if (cdf) HIP_TRY(mcpr::launch_cdf_start(prec, items, n, blocks, nb, ctx->cdfb, s));
     if (trig)
         HIP_TRY(mcpr::launch_sum_init_trig(prec, items, blocks, nb, part[0], shift[0], s));
     else
@@ -388,11 +388,9 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
                             : (variant < 0 ? ctx->tune_cand[0] : variant);
         if (trial) HIP_TRY(hipEventRecord(ctx->tune_ev[0][j], s));
         if (cdf) {
-            const void *ks = nullptr;
-            const uint32_t *ix = nullptr;
-            HIP_TRY(mcpr::launch_cdf_sort(prec, items, n, blocks, nb, ndense, j, ctx->cdfb, &ks, &ix, s));
-            HIP_TRY(mcpr::launch_em_step_sorted(prec, deg, items, blocks, nb, j, part[a], shift[a], ks, ix, part[b],
-                                                shift[b], trace, m, s));
+            HIP_TRY(mcpr::launch_cdf_sort(prec, n, ndense, ctx->cdfb, s));
+            HIP_TRY(mcpr::launch_em_step_sorted(prec, deg, items, n, blocks, nb, j, j == m - 1, part[a], shift[a],
+                                                ctx->cdfb, part[b], shift[b], trace, m, s));
         } else if (trig)
             HIP_TRY(mcpr::launch_em_step_trig(prec, deg, items, blocks, nb, j, part[a], part[b], shift[b], trace, m, s));
         else
@@ -438,25 +436,27 @@ mcpr_status ensure_cdf(mcpr_ctx *ctx, const Tables &t, int prec) {
     if (t.total_dense >= ((int64_t)1 << 32) - 1)
         return fail(ctx, MCPR_E_UNSUPPORTED, "empirical-CDF drift: %lld particles in one launch exceed 2^32 - 1",
                     (long long)t.total_dense);
+    const size_t kls = prec == 0 ? sizeof(mcpr::KeyLabel<double>) : sizeof(mcpr::KeyLabel<float>);
     mcpr_status st;
-    for (int b = 0; b < 3; ++b)
-        if ((st = ensure(ctx, ctx->cdf_keys[b], n * es)) != MCPR_OK) return st;
     for (int b = 0; b < 2; ++b) {
-        if ((st = ensure(ctx, ctx->cdf_idx[b], n * sizeof(uint32_t))) != MCPR_OK) return st;
-        if ((st = ensure(ctx, ctx->cdf_seg[b], n * sizeof(uint32_t))) != MCPR_OK) return st;
+        if ((st = ensure(ctx, ctx->cdf_keys[b], n * es)) != MCPR_OK) return st;
+        if ((st = ensure(ctx, ctx->cdf_lab[b], n * sizeof(uint32_t))) != MCPR_OK) return st;
+        if (nseg > 1) {
+            if ((st = ensure(ctx, ctx->cdf_seg[b], n * sizeof(uint32_t))) != MCPR_OK) return st;
+            if ((st = ensure(ctx, ctx->cdf_kl[b], n * kls)) != MCPR_OK) return st;
+        }
     }
-    if ((st = ensure(ctx, ctx->cdf_pos, n * sizeof(uint32_t))) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->cdf_beg, (size_t)nseg * sizeof(uint32_t))) != MCPR_OK) return st;
     size_t tb = 0;
     HIP_TRY(mcpr::cdf_scratch_bytes(prec, (uint32_t)n, (uint32_t)nseg, tb));
     if ((st = ensure(ctx, ctx->cdf_tmp, tb > 0 ? tb : 1)) != MCPR_OK) return st;
     mcpr::CdfBuffers &c = ctx->cdfb;
-    for (int b = 0; b < 3; ++b) c.keys[b] = ctx->cdf_keys[b].p;
     for (int b = 0; b < 2; ++b) {
-        c.idx[b] = (uint32_t *)ctx->cdf_idx[b].p;
+        c.keys[b] = ctx->cdf_keys[b].p;
+        c.lab[b] = (uint32_t *)ctx->cdf_lab[b].p;
         c.seg[b] = (uint32_t *)ctx->cdf_seg[b].p;
+        c.kl[b] = ctx->cdf_kl[b].p;
     }
-    c.pos = (uint32_t *)ctx->cdf_pos.p;
     c.seg_begin = (uint32_t *)ctx->cdf_beg.p;
     c.tmp = ctx->cdf_tmp.p;
     c.tmp_bytes = ctx->cdf_tmp.cap;
@@ -642,8 +642,8 @@ void mcpr_destroy(mcpr_ctx *ctx) {
                       &ctx->recs,          &ctx->adj_ckpt,    &ctx->adj_traj,    &ctx->adj_lam[0],  &ctx->adj_lam[1],
                       &ctx->adj_part[0],   &ctx->adj_part[1], &ctx->adj_acc,     &ctx->adj_trace,   &ctx->adj_grad,
                       &ctx->adj_sums,      &ctx->adj_items,   &ctx->adj_blocks,  &ctx->trace,       &ctx->mv,
-                      &ctx->cdf_keys[0],   &ctx->cdf_keys[1], &ctx->cdf_keys[2], &ctx->cdf_idx[0],  &ctx->cdf_idx[1],
-                      &ctx->cdf_seg[0],    &ctx->cdf_seg[1],  &ctx->cdf_pos,     &ctx->cdf_beg,     &ctx->cdf_tmp};
+                      &ctx->cdf_keys[0],   &ctx->cdf_keys[1], &ctx->cdf_lab[0],  &ctx->cdf_lab[1],  &ctx->cdf_seg[0],
+                      &ctx->cdf_seg[1],    &ctx->cdf_kl[0],   &ctx->cdf_kl[1],   &ctx->cdf_beg,     &ctx->cdf_tmp};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->staging.p) (void)hipHostFree(ctx->staging.p);

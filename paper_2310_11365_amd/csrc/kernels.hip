@@ -545,24 +545,43 @@ __device__ __forceinline__ double normal_pick<double>(const Words4 &w, int e) { 
 template <>
 __device__ __forceinline__ float normal_pick<float>(const Words4 &w, int e) { return normal_of_f(w, e); }
 
+// Sorted pairs of one item: separate key and label arrays, or packed pairs.
+template <typename T, bool PACKED>
+struct SortedView;
+template <typename T>
+struct SortedView<T, false> {
+    const T *__restrict__ K;
+    const uint32_t *__restrict__ L;
+    __device__ __forceinline__ T key(int64_t r) const { return K[r]; }
+    __device__ __forceinline__ uint32_t label(int64_t r) const { return L[r]; }
+    __device__ __forceinline__ SortedView at(int64_t d) const { return SortedView{K + d, L + d}; }
+};
+template <typename T>
+struct SortedView<T, true> {
+    const KeyLabel<T> *__restrict__ S;
+    __device__ __forceinline__ T key(int64_t r) const { return S[r].k; }
+    __device__ __forceinline__ uint32_t label(int64_t r) const { return S[r].l; }
+    __device__ __forceinline__ SortedView at(int64_t d) const { return SortedView{S + d}; }
+};
+
 // First (DIR < 0) or last (DIR > 0) position of the run of keys equal to v
-// that contains position r of the ascending array K[0, P): doubling steps
-// away from r while the key still equals v, then bisection of the last step.
-template <int DIR, typename T>
-__device__ __forceinline__ int64_t run_end(const T *__restrict__ K, int64_t P, int64_t r, T v) {
+// that contains position r of the ascending keys [0, P): doubling steps away
+// from r while the key still equals v, then bisection of the last step.
+template <int DIR, typename V, typename T>
+__device__ __forceinline__ int64_t run_end(const V &S, int64_t P, int64_t r, T v) {
     int64_t known = r, step = 1;
     for (;;) {
         const int64_t probe = known + DIR * step;
-        if (probe < 0 || probe >= P || K[probe] != v) break;
+        if (probe < 0 || probe >= P || S.key(probe) != v) break;
         known = probe;
         step <<= 1;
     }
-    // K[known] == v; the position `step` beyond it is outside [0, P) or differs
+    // S.key(known) == v; the position `step` beyond it is outside [0, P) or differs
     int64_t out = known + DIR * step;
     out = out < -1 ? -1 : (out > P ? P : out);
     while ((out - known) * DIR > 1) {
         const int64_t mid = known + (out - known) / 2;
-        if (K[mid] == v)
+        if (S.key(mid) == v)
             known = mid;
         else
             out = mid;
@@ -571,20 +590,21 @@ __device__ __forceinline__ int64_t run_end(const T *__restrict__ K, int64_t P, i
 }
 
 // One Euler-Maruyama step with the empirical-CDF drift term acdf (1 - F_P(x)),
-// taken in the ensemble's ascending order: K (the item's sorted states) and
-// I (their dense indices, doff + p) come from launch_cdf_sort.  Position r of
-// K has sum_q H(x - X_q) = lo + (hi - lo + 1) / 2 for the run [lo, hi] of
-// keys equal to K[r] (distinct neighbours: r + 1/2).  The new state goes to
-// y[p] of particle p, its normal is normal p & 3 of Philox quad p >> 2 as in
-// the particle-order steps.  The (m, v) partials of the new states are summed
-// in sorted order (a fixed order for a given state).
-template <typename T, int DEG>
+// taken in the ensemble's ascending order (the sorted pairs of launch_cdf_sort:
+// state and label doff + p).  Position r has sum_q H(x - X_q) = lo + (hi - lo
+// + 1) / 2 for the run [lo, hi] of keys equal to its key (distinct
+// neighbours: r + 1/2).  Particle p's normal is normal p & 3 of Philox quad
+// p >> 2, as in the particle-order steps.  The new state and its label go to
+// position r of ko / lo (the next step's sort input), or on the last step of
+// the sweep to the particle's slot y[p].  The (m, v) partials of the new
+// states are summed in sorted order (a fixed order for a given state).
+template <typename T, int DEG, bool PACKED>
 __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__restrict__ items,
-                                                             const int2 *__restrict__ blocks, int32_t j,
+                                                             const int2 *__restrict__ blocks, int32_t j, int32_t last,
                                                              const double2 *__restrict__ part_in,
                                                              const double *__restrict__ shift_in,
-                                                             const T *__restrict__ ks,
-                                                             const uint32_t *__restrict__ ix,
+                                                             SortedView<T, PACKED> all, T *__restrict__ ko,
+                                                             uint32_t *__restrict__ lo_out,
                                                              double2 *__restrict__ part_out,
                                                              double *__restrict__ shift_out,
                                                              double2 *__restrict__ trace, int32_t m) {
@@ -592,9 +612,8 @@ __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__r
     const int2 bt = blocks[blockIdx.x];
     const int item = bt.x, sc = bt.y;
     const WorkItem &W = items[item];
-    T *__restrict__ y = reinterpret_cast<T *>(W.x) + (int64_t)(j + 1) * W.traj;
-    const T *__restrict__ K = ks + W.doff;
-    const uint32_t *__restrict__ I = ix + W.doff;
+    T *__restrict__ y = reinterpret_cast<T *>(W.x);
+    const SortedView<T, PACKED> S = all.at(W.doff); // this item's pairs
     const int64_t P = W.P;
     const int R = W.R;
     const int64_t base = (int64_t)sc * 4 * kThreads * R;
@@ -618,21 +637,27 @@ __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__r
         T d[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            // lane-contiguous positions: every load instruction reads 64 consecutive keys
+            // lane-contiguous positions: every load instruction reads 64 consecutive pairs
             const int64_t r = base + (int64_t)(4 * g + e) * kThreads + threadIdx.x;
             d[e] = (T)0;
             if (r < P) {
-                const T v = K[r];
+                const T v = S.key(r);
+                const uint32_t lab = S.label(r);
                 int64_t lo = r, hi = r;
-                if (r > 0 && K[r - 1] == v) lo = run_end<-1>(K, P, r, v);
-                if (r + 1 < P && K[r + 1] == v) hi = run_end<1>(K, P, r, v);
+                if (r > 0 && S.key(r - 1) == v) lo = run_end<-1>(S, P, r, v);
+                if (r + 1 < P && S.key(r + 1) == v) hi = run_end<1>(S, P, r, v);
                 const T cnt = (T)((double)lo + 0.5 * (double)(hi - lo + 1));
-                const int64_t p = (int64_t)I[r] - W.doff;
+                const int64_t p = (int64_t)lab - W.doff;
                 const Words4 w = philox4x32_10((uint32_t)(p >> 2), step, inst, 0u, W.key0, W.key1);
                 const T z = normal_pick<T>(w, (int)(p & 3));
                 const T pol0 = (DEG == 1) ? fmaT(c1, v, c0) : fmaT(fmaT(fmaT(c3, v, c2), v, c1), v, c0);
                 const T u = fmaT(fmaT(e1, v, e0), z, fmaT(kf, cnt, pol0));
-                y[p] = u;
+                if (last) {
+                    y[p] = u;
+                } else {
+                    ko[W.doff + r] = u;
+                    lo_out[W.doff + r] = lab;
+                }
                 d[e] = u - shift;
             }
         }
@@ -1357,23 +1382,41 @@ hipError_t launch_em_step_trig(int prec, int deg, const WorkItem *items, const i
     return hipGetLastError();
 }
 
-hipError_t launch_em_step_sorted(int prec, int deg, const WorkItem *items, const int2 *blocks, int nblocks, int j,
-                                 const double2 *part_in, const double *shift_in, const void *ks, const uint32_t *ix,
-                                 double2 *part_out, double *shift_out, double2 *trace, int m, hipStream_t s) {
+template <typename T, int DEG>
+static void em_step_sorted(const WorkItem *items, int n_items, const int2 *blocks, int nblocks, int j, bool last,
+                           const double2 *part_in, const double *shift_in, const CdfBuffers &b, double2 *part_out,
+                           double *shift_out, double2 *trace, int m, hipStream_t s) {
+    if (n_items > 1) {
+        SortedView<T, true> v{(const KeyLabel<T> *)b.kl[1]};
+        hipLaunchKernelGGL((k_em_step_sorted<T, DEG, true>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                           (int32_t)last, part_in, shift_in, v, (T *)b.keys[0], b.lab[0], part_out, shift_out, trace,
+                           m);
+    } else {
+        SortedView<T, false> v{(const T *)b.keys[1], b.lab[1]};
+        hipLaunchKernelGGL((k_em_step_sorted<T, DEG, false>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
+                           (int32_t)last, part_in, shift_in, v, (T *)b.keys[0], b.lab[0], part_out, shift_out, trace,
+                           m);
+    }
+}
+
+hipError_t launch_em_step_sorted(int prec, int deg, const WorkItem *items, int n_items, const int2 *blocks,
+                                 int nblocks, int j, bool last, const double2 *part_in, const double *shift_in,
+                                 const CdfBuffers &b, double2 *part_out, double *shift_out, double2 *trace, int m,
+                                 hipStream_t s) {
     if (prec == 0) {
         if (deg == 1)
-            hipLaunchKernelGGL((k_em_step_sorted<double, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
-                               part_in, shift_in, (const double *)ks, ix, part_out, shift_out, trace, m);
+            em_step_sorted<double, 1>(items, n_items, blocks, nblocks, j, last, part_in, shift_in, b, part_out,
+                                      shift_out, trace, m, s);
         else
-            hipLaunchKernelGGL((k_em_step_sorted<double, 3>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
-                               part_in, shift_in, (const double *)ks, ix, part_out, shift_out, trace, m);
+            em_step_sorted<double, 3>(items, n_items, blocks, nblocks, j, last, part_in, shift_in, b, part_out,
+                                      shift_out, trace, m, s);
     } else {
         if (deg == 1)
-            hipLaunchKernelGGL((k_em_step_sorted<float, 1>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
-                               part_in, shift_in, (const float *)ks, ix, part_out, shift_out, trace, m);
+            em_step_sorted<float, 1>(items, n_items, blocks, nblocks, j, last, part_in, shift_in, b, part_out,
+                                     shift_out, trace, m, s);
         else
-            hipLaunchKernelGGL((k_em_step_sorted<float, 3>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
-                               part_in, shift_in, (const float *)ks, ix, part_out, shift_out, trace, m);
+            em_step_sorted<float, 3>(items, n_items, blocks, nblocks, j, last, part_in, shift_in, b, part_out,
+                                     shift_out, trace, m, s);
     }
     return hipGetLastError();
 }

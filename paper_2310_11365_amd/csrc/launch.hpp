@@ -52,29 +52,38 @@ hipError_t launch_em_step_trig(int prec, int deg, const WorkItem *items, const i
 hipError_t launch_finish_trig(const WorkItem *items, int n_items, const double2 *part_in, double2 *trace, int m,
                               hipStream_t s);
 // Empirical-CDF drift (in cdf.hip): the states of the items laid end to end
-// (item i at dense offset doff, n positions in all), sorted by value and then
-// stably by item, so that each item's states are ascending at [doff, doff + P)
-// together with their dense indices.
+// (item i at dense offset doff, n positions in all) with their labels
+// (doff + p), kept in sorted order through a fine sweep.
+template <typename T>
+struct KeyLabel {
+    T k;
+    uint32_t l;
+};
 struct CdfBuffers {
-    void *keys[3];      // gathered, sorted by value, sorted by (item, value); state type, n each
-    uint32_t *idx[2];   // dense index of each key after the value sort / after the item sort
-    uint32_t *seg[2];   // item of each value-sorted key, before / after the item sort
-    uint32_t *pos;      // value-sorted position of each (item, value)-sorted key
+    void *keys[2];       // state type, n each: [0] the step's output (sort input), [1] sorted by value
+    uint32_t *lab[2];    // their labels
+    uint32_t *seg[2];    // item of each value-sorted pair, before / after the item pass
+    void *kl[2];         // KeyLabel<state type> pairs before / after the item pass
     uint32_t *seg_begin; // doff of every item
     void *tmp;
     size_t tmp_bytes;
 };
-// Once per fine sweep: the dense first position of every item.
-hipError_t launch_cdf_setup(const WorkItem *items, int n_items, const CdfBuffers &b, hipStream_t s);
+// Once per fine sweep: the dense first position of every item; the states and
+// labels into keys[0], lab[0].
+hipError_t launch_cdf_start(int prec, const WorkItem *items, int n_items, const int2 *blocks, int nblocks,
+                            const CdfBuffers &b, hipStream_t s);
 // Bytes of library scratch the sorts need for n positions of nseg items.
 hipError_t cdf_scratch_bytes(int prec, uint32_t n, uint32_t nseg, size_t &bytes);
-// Sorted states of step j's input (*ks, state type) and their dense indices (*ix).
-hipError_t launch_cdf_sort(int prec, const WorkItem *items, int n_items, const int2 *blocks, int nblocks, uint32_t n,
-                           int j, const CdfBuffers &b, const void **ks, const uint32_t **ix, hipStream_t s);
-// The Euler-Maruyama step with the empirical-CDF drift, in sorted order.
-hipError_t launch_em_step_sorted(int prec, int deg, const WorkItem *items, const int2 *blocks, int nblocks, int j,
-                                 const double2 *part_in, const double *shift_in, const void *ks, const uint32_t *ix,
-                                 double2 *part_out, double *shift_out, double2 *trace, int m, hipStream_t s);
+// Sorts (keys[0], lab[0]): each item's pairs ascending at [doff, doff + P) in
+// keys[1], lab[1] (one item) or kl[1] (several items).
+hipError_t launch_cdf_sort(int prec, int n_items, uint32_t n, const CdfBuffers &b, hipStream_t s);
+// The Euler-Maruyama step with the empirical-CDF drift, in sorted order: the
+// new states go to keys[0], lab[0], or on the last step of the sweep to the
+// particles' slots.
+hipError_t launch_em_step_sorted(int prec, int deg, const WorkItem *items, int n_items, const int2 *blocks,
+                                 int nblocks, int j, bool last, const double2 *part_in, const double *shift_in,
+                                 const CdfBuffers &b, double2 *part_out, double *shift_out, double2 *trace, int m,
+                                 hipStream_t s);
 // out[i] = (1/P) sum Phi(x_p) of item i; part: scratch of one partial per superchunk.
 hipError_t launch_qoi(int prec, int kind, const WorkItem *items, int n_items, const int2 *blocks, int nblocks,
                       double2 *part, double *out, hipStream_t s);
