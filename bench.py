@@ -78,9 +78,10 @@ def load_traffic(kernel: str, workload: str):
 
 
 def kernels_sha() -> str:
-    """Hash of the device sources (kernels, RNG, shared types)."""
+    """Hash of the sources the Euler-Maruyama step kernels are built from
+    (kernels, RNG, shared types)."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "cdf.hip", "rng.hpp", "common.hpp"):
+    for f in ("kernels.hip", "rng.hpp", "common.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2310_11365_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
