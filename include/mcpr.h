@@ -78,10 +78,12 @@ typedef struct {
     double ksin, kc;
     /* Empirical-CDF drift term acdf (1 - F_P(x)), F_P(x) = (1/P) sum_q H(x - X_q)
      * with the step function H(0) = 1/2 (the Burgers example of Sec. 5.2:
-     * acdf = 1, b0 = sigma, X(0) = 0).  With acdf nonzero every step ranks the
-     * ensemble (a segmented sort), the problem has one region and the Taylor
-     * (Gaussian-density) coarse model, and the other mean-field coefficients
-     * (am, av, axs, bm, bv, ksin, kc) must be 0, else MCPR_E_UNSUPPORTED.     */
+     * acdf = 1, b0 = sigma, X(0) = 0).  With acdf nonzero every step sorts
+     * each ensemble (a device-wide radix sort; at most 2^32 - 2 particles in
+     * one call, else MCPR_E_UNSUPPORTED), the problem has one region, the
+     * Taylor (Gaussian-density) coarse model and no wrap, and the other
+     * mean-field coefficients (am, av, axs, bm, bv, ksin, kc) must be 0, else
+     * MCPR_E_UNSUPPORTED; the adjoint refuses the problem.                    */
     double acdf;
 } mcpr_coef;
 
@@ -174,8 +176,9 @@ mcpr_status mcpr_profile_read_adjoint(mcpr_ctx *ctx, double *ms, int64_t *launch
  * a fine sweep (step-0 sums, the steps, the final moments and records) is
  * captured once per shape into a graph on a library-owned stream and
  * replayed; the caller's stream waits on it through events.  Results are
- * bitwise the same as direct launches.  mcpr_graph_stats: graphs built and
- * replays so far.                                                           */
+ * bitwise the same as direct launches.  A sweep with the empirical-CDF drift
+ * (acdf != 0) is always launched directly: it calls the library sort.
+ * mcpr_graph_stats: graphs built and replays so far.                        */
 mcpr_status mcpr_set_graphs(mcpr_ctx *ctx, int32_t on);
 
 /* Step-kernel launch variants, all giving the same bits: bit 0 non-temporal
@@ -189,7 +192,8 @@ mcpr_status mcpr_set_graphs(mcpr_ctx *ctx, int32_t on);
  * a candidate other than the first for that shape only if it beats the first
  * by 1 %.  Candidates: 0..3, or only 2 and 3 when an ensemble of the launch
  * has more than 256 superchunks (more than 1048576 particles), where 2 is
- * also the untuned default.  0..3 forces a variant.
+ * also the untuned default.  0..3 forces a variant.  The trigonometric and
+ * empirical-CDF steps have one kernel each: no variants, no trial.
  * mcpr_tuned_variant: the variant chosen for the index-th tuned shape, or -1. */
 mcpr_status mcpr_set_tuning(mcpr_ctx *ctx, int32_t mode);
 int32_t mcpr_tuned_variant(const mcpr_ctx *ctx, int32_t index);
