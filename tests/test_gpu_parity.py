@@ -562,6 +562,35 @@ def test_full_size_bimodal_slice_parity(mc, ctx, oracle):
     assert np.allclose(glob[:, 0], gm, rtol=0, atol=1e-14)
 
 
+def test_full_size_burgers_slice_parity(mc, ctx, oracle):
+    """Burgers workload at full size (P = 1e6, N = 10, fp32) in the launch
+    configuration the benchmark times (init + one iteration; every step sorts
+    the ten ensembles together): the first slice, exact after one iteration,
+    against the oracle's serial slice at P = 1e6 within the fp32 bound (about
+    half a minute of oracle time); every slice by the invariants of the
+    empirical-CDF drift: one region holding every particle, and the average
+    drift of a step is exactly 1/2 (the counts of any ensemble sum to P^2/2),
+    so the mean moves by 1/2 per unit time up to the Monte-Carlo noise."""
+    wl = W.burgers(P=1_000_000, precision=W.FP32)
+    pr = wl.problem
+    para = mc.Parareal([pr], [wl.P], ctx)
+    para.init()
+    para.iterate()
+    rho, glob = para.macro(0)
+    pr64 = W.burgers(P=wl.P, precision=W.FP64).problem
+    xo, _ = oracle.fine(pr64, oracle.sample_p0(pr64, wl.P), 0)
+    o = oracle.restrict(pr64, xo)[0]
+    sc = abs(o["mean"]) + math.sqrt(o["var"])
+    assert abs(rho[1, 0, 1] - o["mean"]) <= FP32_M * sc
+    assert abs(rho[1, 0, 2] - o["var"]) <= FP32_V * o["var"]
+    assert np.all(rho[:, 0, 0] == 1.0)
+    assert np.all(rho[1:, 0, 2] > 0)
+    dT = pr.dt * pr.steps_per_slice
+    t = np.arange(pr.n_slices + 1) * dT
+    se = 6.0 * math.sqrt(t[-1]) / math.sqrt(wl.P)  # sigma = 1: the noise's share of the mean
+    assert np.max(np.abs(glob[:, 0] - 0.5 * t)) <= se
+
+
 # ---------------------------------------------------------------------------- errors
 def test_invalid_arguments_are_rejected(mc, ctx):
     import torch
