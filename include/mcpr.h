@@ -79,8 +79,8 @@ typedef struct {
     /* Empirical-CDF drift term acdf (1 - F_P(x)), F_P(x) = (1/P) sum_q H(x - X_q)
      * with the step function H(0) = 1/2 (the Burgers example of Sec. 5.2:
      * acdf = 1, b0 = sigma, X(0) = 0).  With acdf nonzero every step sorts
-     * each ensemble (a device-wide radix sort; at most 2^32 - 2 particles in
-     * one call, else MCPR_E_UNSUPPORTED), the problem has one region, the
+     * each ensemble (mcpr_set_cdf_sort; at most 2^32 - 2 particles in one
+     * call, else MCPR_E_UNSUPPORTED), the problem has one region, the
      * Taylor (Gaussian-density) coarse model and no wrap, and the other
      * mean-field coefficients (am, av, axs, bm, bv, ksin, kc) must be 0, else
      * MCPR_E_UNSUPPORTED; the adjoint refuses the problem.                    */
@@ -198,6 +198,22 @@ mcpr_status mcpr_set_graphs(mcpr_ctx *ctx, int32_t on);
 mcpr_status mcpr_set_tuning(mcpr_ctx *ctx, int32_t mode);
 int32_t mcpr_tuned_variant(const mcpr_ctx *ctx, int32_t index);
 mcpr_status mcpr_graph_stats(const mcpr_ctx *ctx, int64_t *builds, int64_t *launches);
+
+/* Sort of the empirical-CDF drift (acdf != 0; Sec. 5.2: every step needs
+ * each ensemble in ascending order).  mode 1 (default): the first two steps
+ * of a fine sweep sort with a device-wide radix sort, later steps put the new
+ * states into buckets between the previous step's sorted states (2048 apart
+ * on average) and sort each bucket on chip.  A bucket beyond 4096 states (a
+ * law still spreading fast, as in the first steps from a point mass; a point
+ * mass without noise) makes the sweep run again with the radix sort on its
+ * first 16 steps, and if that overflows too, on all of them.  A call with
+ * this drift synchronises its stream (to read the overflow flag).
+ * mode 0: the radix sort on every step.  Both give the same bits.
+ * mcpr_cdf_stats: sweeps done by the buckets, by the radix sort alone, and
+ * sweeps redone after an overflow, so far (any pointer may be NULL).        */
+mcpr_status mcpr_set_cdf_sort(mcpr_ctx *ctx, int32_t mode);
+mcpr_status mcpr_cdf_stats(const mcpr_ctx *ctx, int64_t *bucket_sweeps, int64_t *library_sweeps,
+                           int64_t *redone_sweeps);
 
 /* ---- hot-path calls ------------------------------------------------------ */
 /* Initial law p0 (Sec. 1.1) sampled into each ensemble (tags 1 and 2). */

@@ -54,10 +54,14 @@ struct mcpr_ctx {
     DevBuf items, blocks, part[2], shift[2], rpart, rshift[2], maps, recs;
     DevBuf adj_ckpt, adj_traj, adj_lam[2], adj_part[2], adj_acc, adj_trace, adj_grad, adj_sums; // adjoint scratch
     DevBuf adj_items, adj_blocks; // the backward sweep's work and block tables
-    // empirical-CDF drift: sort keys and indices, run flags and scans, counts,
-    // segment bounds, library scratch
+    // empirical-CDF drift: states and labels in sorted order, the library
+    // sort's item pass and scratch, the bucket engine's tables and staging
     DevBuf cdf_keys[2], cdf_lab[2], cdf_seg[2], cdf_kl[2], cdf_beg, cdf_tmp;
+    DevBuf cdf_btab, cdf_bcount, cdf_bstart, cdf_stage, cdf_flag;
     mcpr::CdfBuffers cdfb{};
+    uint32_t *cdf_flag_host = nullptr; // pinned copy of the overflow flag
+    int cdf_engine = 1;                // 1: bucket engine after a sweep's first step; 0: library sort every step
+    int64_t cdf_sweeps[3] = {0, 0, 0}; // sweeps by the bucket engine, by the library sort, redone
     HostBuf staging;
     hipEvent_t staged = nullptr; // the last upload from staging has completed
     DevBuf trace; // trace of the last fine sweep (copied to the caller's array)
@@ -238,12 +242,14 @@ struct Tables {
     std::vector<int2> blocks; // one entry per superchunk: (item, superchunk)
     int total_sc = 0;
     int64_t total_dense = 0;  // dense sort positions, the sum of P (empirical-CDF drift)
+    int nbuckets = 0;         // bucket engine: buckets of the launch
 };
 
 void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_t n_ens, Tables &t) {
     t.items.resize(n_ens);
     t.blocks.clear();
     t.total_dense = 0;
+    t.nbuckets = 0;
     int off = 0;
     for (int e = 0; e < n_ens; ++e) {
         const mcpr_ensemble &E = ens[e];
@@ -254,7 +260,10 @@ void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_
         w.P = E.n_particles;
         w.inst = E.instance;
         w.step0 = E.slice * p.steps_per_slice;
-        w.R = mcpr::canonical_quads_per_thread(E.n_particles);
+        // (the empirical-CDF step gathers its states in sorted order and
+        // reserves bucket slots per round: one quad per thread keeps more
+        // blocks in flight; still a function of the ensemble alone)
+        w.R = is_cdf(p) ? 1 : mcpr::canonical_quads_per_thread(E.n_particles);
         w.nsc = (int32_t)mcpr::superchunks(E.n_particles, w.R);
         w.part_off = off;
         w.p0_kind = p.p0_kind;
@@ -267,6 +276,11 @@ void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_
         w.cdf = is_cdf(p) ? 1 : 0;
         w.doff = t.total_dense;
         t.total_dense += E.n_particles;
+        if (w.cdf) {
+            w.nbk = (int32_t)std::max<int64_t>(1, (E.n_particles + mcpr::kCdfBucket - 1) / mcpr::kCdfBucket);
+            w.bbase = t.nbuckets;
+            t.nbuckets += w.nbk;
+        }
         w.dt = p.dt;
         w.sdt = std::sqrt(p.dt);
         w.p0[0] = p.p0_w;
@@ -363,7 +377,8 @@ mcpr_status records(mcpr_ctx *ctx, const Tables &t, int prec, int nreg, const mc
 // each launch bracketed by events (the autotuner's trial; every variant gives
 // the same bits).
 mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int variant, int m, int nreg,
-                         const mcpr::Splits &sp, bool want_stats, bool want_trace, hipStream_t s, bool profile) {
+                         const mcpr::Splits &sp, bool want_stats, bool want_trace, hipStream_t s, bool profile,
+                         int cdf_lib_steps = 0) {
     const int n = (int)t.items.size();
     const WorkItem *items = (const WorkItem *)ctx->items.p;
     const int2 *blocks = (const int2 *)ctx->blocks.p;
@@ -388,9 +403,17 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
                             : (variant < 0 ? ctx->tune_cand[0] : variant);
         if (trial) HIP_TRY(hipEventRecord(ctx->tune_ev[0][j], s));
         if (cdf) {
-            HIP_TRY(mcpr::launch_cdf_sort(prec, n, ndense, ctx->cdfb, s));
-            HIP_TRY(mcpr::launch_em_step_sorted(prec, deg, items, n, blocks, nb, j, j == m - 1, part[a], shift[a],
-                                                ctx->cdfb, part[b], shift[b], trace, m, s));
+            // the library sort on the first cdf_lib_steps steps, else the
+            // buckets the previous step filled (step j's sorted input is the
+            // splitter set of its output)
+            const bool from_buckets = j >= cdf_lib_steps;
+            if (from_buckets)
+                HIP_TRY(mcpr::launch_cdf_buckets(prec, items, n, ctx->cdfb, s));
+            else
+                HIP_TRY(mcpr::launch_cdf_sort(prec, n, ndense, ctx->cdfb, s));
+            const int mode = j == m - 1 ? 2 : (j + 1 >= cdf_lib_steps ? 1 : 0);
+            HIP_TRY(mcpr::launch_em_step_sorted(prec, deg, items, n, blocks, nb, j, mode, !from_buckets && n > 1,
+                                                part[a], shift[a], mv, ctx->cdfb, part[b], shift[b], trace, m, s));
         } else if (trig)
             HIP_TRY(mcpr::launch_em_step_trig(prec, deg, items, blocks, nb, j, part[a], part[b], shift[b], trace, m, s));
         else
@@ -447,6 +470,20 @@ mcpr_status ensure_cdf(mcpr_ctx *ctx, const Tables &t, int prec) {
         }
     }
     if ((st = ensure(ctx, ctx->cdf_beg, (size_t)nseg * sizeof(uint32_t))) != MCPR_OK) return st;
+    const size_t nbk = (size_t)t.nbuckets;
+    if ((st = ensure(ctx, ctx->cdf_btab, nbk * sizeof(int2))) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->cdf_bcount, nbk * sizeof(uint32_t))) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->cdf_flag, sizeof(uint32_t))) != MCPR_OK) return st;
+    if (ctx->cdf_engine) {
+        if ((st = ensure(ctx, ctx->cdf_bstart, nbk * sizeof(uint32_t))) != MCPR_OK) return st;
+        if ((st = ensure(ctx, ctx->cdf_stage, mcpr::stage_bytes(prec, (int)nbk))) != MCPR_OK) return st;
+    }
+    if (!ctx->cdf_flag_host) {
+        void *h = nullptr;
+        if (hipHostMalloc(&h, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
+            return fail(ctx, MCPR_E_OOM, "pinned host allocation failed");
+        ctx->cdf_flag_host = (uint32_t *)h;
+    }
     size_t tb = 0;
     HIP_TRY(mcpr::cdf_scratch_bytes(prec, (uint32_t)n, (uint32_t)nseg, tb));
     if ((st = ensure(ctx, ctx->cdf_tmp, tb > 0 ? tb : 1)) != MCPR_OK) return st;
@@ -460,6 +497,12 @@ mcpr_status ensure_cdf(mcpr_ctx *ctx, const Tables &t, int prec) {
     c.seg_begin = (uint32_t *)ctx->cdf_beg.p;
     c.tmp = ctx->cdf_tmp.p;
     c.tmp_bytes = ctx->cdf_tmp.cap;
+    c.btab = (int2 *)ctx->cdf_btab.p;
+    c.nbuckets = t.nbuckets;
+    c.bcount = (uint32_t *)ctx->cdf_bcount.p;
+    c.bstart = (uint32_t *)ctx->cdf_bstart.p;
+    c.stage = ctx->cdf_stage.p;
+    c.flag = (uint32_t *)ctx->cdf_flag.p;
     return MCPR_OK;
 }
 
@@ -481,6 +524,59 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
         if (w.c[2] != 0.0 || w.c[3] != 0.0) deg = 3;
         ps += w.P;
         max_nsc = std::max(max_nsc, w.nsc);
+    }
+    if (t.items[0].cdf) {
+        // The empirical-CDF sweep: launched directly (no graph, no variants).
+        // With the bucket engine the library sort takes the first two steps
+        // (the input may be a point mass, which gives no splitters); the host
+        // reads the overflow flag after the sweep and, if a bucket overflowed
+        // (a law still spreading fast, as in the first steps from a point
+        // mass), redoes the sweep with the library sort on its first 16 steps,
+        // then on all of them.  The particles are untouched until the sweep's
+        // last step, and an overflowed sweep skips its remaining steps.
+        size_t slot = 0;
+        if (ctx->profile) {
+            if (ctx->prof_used == ctx->prof0.size()) {
+                hipEvent_t e0, e1;
+                HIP_TRY(hipEventCreate(&e0));
+                HIP_TRY(hipEventCreate(&e1));
+                ctx->prof0.push_back(e0);
+                ctx->prof1.push_back(e1);
+                ctx->prof_ps.push_back(0);
+            }
+            slot = ctx->prof_used;
+        }
+        const int tries[3] = {2, 16, m};
+        for (int a = ctx->cdf_engine ? 0 : 2; a < 3; ++a) {
+            const int lib = std::min(tries[a], m);
+            // (the profile events of a later attempt replace those of a failed one)
+            if ((st = enqueue_fine(ctx, t, prec, deg, 0, m, nreg, sp, stats != nullptr, trace != nullptr, s,
+                                   ctx->profile, lib)) != MCPR_OK)
+                return st;
+            if (lib >= m) {
+                ctx->cdf_sweeps[1]++;
+                break;
+            }
+            HIP_TRY(hipMemcpyAsync(ctx->cdf_flag_host, ctx->cdfb.flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (*ctx->cdf_flag_host == 0) {
+                ctx->cdf_sweeps[0]++;
+                break;
+            }
+            ctx->cdf_sweeps[2]++;
+        }
+        if (ctx->profile) {
+            ctx->prof_ps[slot] = ps * m;
+            ctx->prof_launches += m;
+            ctx->prof_used = slot + 1;
+        }
+        if (stats)
+            HIP_TRY(hipMemcpyAsync(stats, ctx->recs.p, (size_t)n * (nreg + 1) * sizeof(RegionStats),
+                                   hipMemcpyDeviceToDevice, s));
+        if (trace)
+            HIP_TRY(hipMemcpyAsync(trace, ctx->trace.p, (size_t)n * (m + 1) * sizeof(double2),
+                                   hipMemcpyDeviceToDevice, s));
+        return MCPR_OK;
     }
     // An ensemble of more than 256 superchunks makes every block of the
     // in-block-combine variants read more than one partial per thread: only
@@ -643,10 +739,12 @@ void mcpr_destroy(mcpr_ctx *ctx) {
                       &ctx->adj_part[0],   &ctx->adj_part[1], &ctx->adj_acc,     &ctx->adj_trace,   &ctx->adj_grad,
                       &ctx->adj_sums,      &ctx->adj_items,   &ctx->adj_blocks,  &ctx->trace,       &ctx->mv,
                       &ctx->cdf_keys[0],   &ctx->cdf_keys[1], &ctx->cdf_lab[0],  &ctx->cdf_lab[1],  &ctx->cdf_seg[0],
-                      &ctx->cdf_seg[1],    &ctx->cdf_kl[0],   &ctx->cdf_kl[1],   &ctx->cdf_beg,     &ctx->cdf_tmp};
+                      &ctx->cdf_seg[1],    &ctx->cdf_kl[0],   &ctx->cdf_kl[1],   &ctx->cdf_beg,     &ctx->cdf_tmp,
+                      &ctx->cdf_btab,      &ctx->cdf_bcount,  &ctx->cdf_bstart,  &ctx->cdf_stage,   &ctx->cdf_flag};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->staging.p) (void)hipHostFree(ctx->staging.p);
+    if (ctx->cdf_flag_host) (void)hipHostFree(ctx->cdf_flag_host);
     if (ctx->staged) (void)hipEventDestroy(ctx->staged);
     for (hipEvent_t e : ctx->prof0) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->prof1) (void)hipEventDestroy(e);
@@ -739,6 +837,21 @@ mcpr_status mcpr_graph_stats(const mcpr_ctx *ctx, int64_t *builds, int64_t *laun
     if (!ctx) return MCPR_E_INVALID_ARG;
     if (builds) *builds = ctx->graph_builds;
     if (launches) *launches = ctx->graph_launches;
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_set_cdf_sort(mcpr_ctx *ctx, int32_t mode) {
+    if (!ctx || mode < 0 || mode > 1) return MCPR_E_INVALID_ARG;
+    ctx->cdf_engine = mode;
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_cdf_stats(const mcpr_ctx *ctx, int64_t *bucket_sweeps, int64_t *library_sweeps,
+                           int64_t *redone_sweeps) {
+    if (!ctx) return MCPR_E_INVALID_ARG;
+    if (bucket_sweeps) *bucket_sweeps = ctx->cdf_sweeps[0];
+    if (library_sweeps) *library_sweeps = ctx->cdf_sweeps[1];
+    if (redone_sweeps) *redone_sweeps = ctx->cdf_sweeps[2];
     return MCPR_OK;
 }
 

@@ -24,9 +24,22 @@
 // A device-wide sort rather than a segmented one: the segmented sort gives
 // each segment to one workgroup, which leaves the chip idle for the few large
 // ensembles a Parareal sweep batches.
+//
+// From the second step of a sweep on, each step's sorted input also serves
+// as the splitter set of its output (the bucket engine): the step kernel puts
+// every new state into the bucket between two sorted inputs at stride
+// kCdfBucket, k_cdf_bscan turns the bucket counts into positions, and
+// k_cdf_bsort sorts each bucket in LDS by (state, previous position), which
+// is the order the stable library sort gives; the library sort then runs only
+// on the first two steps.  (The first step's input may be a point mass, which
+// splits nothing.)  Buckets stay near kCdfBucket states while the law changes
+// little per step; one above kCdfBucketCap marks the sweep, whose remaining
+// steps then do nothing and leave the particles untouched, and the host
+// redoes the sweep with the library sort alone.
 #include <cstring>
 
 #include <hip/hip_runtime.h>
+#include <rocprim/block/block_radix_sort.hpp>
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "common.hpp"
@@ -80,10 +93,181 @@ __global__ __launch_bounds__(kThreads) void k_cdf_pack(const T *__restrict__ key
     kl[i] = v;
 }
 
+// The dense first position of every item; for every bucket its (item,
+// bucket of the item) and a zero count; the overflow flag cleared.
 __global__ __launch_bounds__(kThreads) void k_cdf_setup(const WorkItem *__restrict__ items, int n_items,
-                                                        uint32_t *__restrict__ beg) {
+                                                        uint32_t *__restrict__ beg, int2 *__restrict__ btab,
+                                                        uint32_t *__restrict__ bcount, int nbuckets,
+                                                        uint32_t *__restrict__ flag) {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i < n_items) beg[i] = (uint32_t)items[i].doff;
+    if (i < nbuckets) {
+        int lo = 0, hi = n_items - 1; // the last item whose first bucket is at or below i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].bbase <= i)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        btab[i] = make_int2(lo, i - items[lo].bbase);
+        bcount[i] = 0u;
+    }
+    if (i == 0) *flag = 0u;
+}
+
+// Exclusive scan of one item's bucket counts (one block per item) into the
+// buckets' first positions; a count above the capacity marks the sweep.
+__global__ __launch_bounds__(kThreads) void k_cdf_bscan(const WorkItem *__restrict__ items,
+                                                        const uint32_t *__restrict__ bcount,
+                                                        uint32_t *__restrict__ bstart, uint32_t *__restrict__ flag) {
+    __shared__ uint32_t sh[kThreads];
+    const WorkItem &W = items[blockIdx.x];
+    uint32_t carry = 0;
+    for (int c0 = 0; c0 < W.nbk; c0 += kThreads) {
+        const int k = c0 + (int)threadIdx.x;
+        const uint32_t v = k < W.nbk ? bcount[W.bbase + k] : 0u;
+        if (v > (uint32_t)kCdfBucketCap) *flag = 1u;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < kThreads; off <<= 1) { // inclusive Hillis-Steele scan
+            const uint32_t add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0u;
+            __syncthreads();
+            sh[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (k < W.nbk) bstart[W.bbase + k] = carry + sh[threadIdx.x] - v;
+        carry += sh[kThreads - 1];
+        __syncthreads();
+    }
+}
+
+// Order key of a state: its bits mapped so that unsigned order is numeric
+// order, with -0 taken as +0 (the library sort's convention: equal keys).
+__device__ __forceinline__ uint32_t order_code(float u) {
+    const uint32_t b = __float_as_uint(u == 0.0f ? 0.0f : u);
+    return b ^ ((b >> 31) ? 0xffffffffu : 0x80000000u);
+}
+__device__ __forceinline__ uint64_t order_code(double u) {
+    const uint64_t b = (uint64_t)__double_as_longlong(u == 0.0 ? 0.0 : u);
+    return b ^ ((b >> 63) ? 0xffffffffffffffffull : 0x8000000000000000ull);
+}
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = kCdfBucketCap / kSortThreads;
+constexpr uint32_t kMaxTieRun = 32; // longer runs of equal states mark the sweep (redone by the library)
+
+// One bucket per block: its staged states sorted by order code with a stable
+// block radix sort over the bits in which the bucket's codes differ (input
+// order: the staging slots), then every run of equal
+// codes ordered by the previous position (runs are short: states only tie by
+// rounding once the noise has spread them), written with their labels at the
+// item's positions bstart + t; the bucket's count is cleared for the next
+// step.  The result is the order of the stable library sort.
+template <typename T>
+__global__ __launch_bounds__(kSortThreads) void k_cdf_bsort(const WorkItem *__restrict__ items,
+                                                            const int2 *__restrict__ btab,
+                                                            uint32_t *__restrict__ bcount,
+                                                            const uint32_t *__restrict__ bstart,
+                                                            StageView<T> stage,
+                                                            uint32_t *__restrict__ flag, T *__restrict__ ko,
+                                                            uint32_t *__restrict__ lo) {
+    using Code = decltype(order_code(T()));
+    using Sorter = rocprim::block_radix_sort<Code, kSortThreads, kSortItems, uint32_t>;
+    __shared__ union {
+        typename Sorter::storage_type sort;
+        struct {
+            Code code[kCdfBucketCap];
+            uint32_t slot[kCdfBucketCap];
+        } post;
+    } sh;
+    __shared__ Code s_min, s_max; // the bucket's smallest and largest codes
+    if (*flag) return; // the sweep is redone
+    const int2 bt = btab[blockIdx.x];
+    const WorkItem &W = items[bt.x];
+    const int b = W.bbase + bt.y;
+    const uint32_t n = bcount[b];
+    if (n > (uint32_t)kCdfBucketCap) return; // cannot happen unflagged; keeps LDS indices in range
+    const uint32_t start = bstart[b];
+    const size_t s0 = (size_t)b * kCdfBucketCap; // the bucket's first staging slot
+    const T *__restrict__ su = stage.u + s0;
+    const uint32_t *__restrict__ sl = stage.lab + s0;
+    const uint32_t *__restrict__ sp = stage.pos + s0;
+    if (threadIdx.x == 0) {
+        s_min = ~(Code)0;
+        s_max = 0;
+    }
+    __syncthreads();
+    Code keys[kSortItems];
+    uint32_t vals[kSortItems];
+    Code lmin = ~(Code)0, lmax = 0;
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        // striped loads (coalesced); the input order only decides the order
+        // of equal codes, which the tie pass below sets anyway
+        const uint32_t t = k * kSortThreads + threadIdx.x;
+        keys[k] = t < n ? order_code(su[t]) : (Code)0;
+        vals[k] = t;
+        if (t < n) {
+            lmin = keys[k] < lmin ? keys[k] : lmin;
+            lmax = keys[k] > lmax ? keys[k] : lmax;
+        }
+    }
+    atomicMin(&s_min, lmin);
+    atomicMax(&s_max, lmax);
+    __syncthreads();
+    if (threadIdx.x == 0) bcount[b] = 0u; // every thread has read n
+    // sort keys: code - min for the states, max - min + 1 for the padding
+    // (strictly last), over the bits that hold max - min + 1
+    const Code cmin = s_min, span = s_max - s_min;
+    if (n > 0 && span == ~(Code)0) { // no room above the largest key (a bucket across the whole range)
+        if (threadIdx.x == 0) *flag = 1u;
+        return;
+    }
+    const Code pad = span + 1;
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const uint32_t t = k * kSortThreads + threadIdx.x;
+        keys[k] = t < n ? keys[k] - cmin : pad;
+    }
+    unsigned nbits = 0;
+    for (Code d = pad; d != 0; d >>= 1) ++nbits;
+    Sorter().sort_to_striped(keys, vals, sh.sort, 0u, nbits); // rank k * kSortThreads + t in thread t
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        sh.post.code[k * kSortThreads + threadIdx.x] = keys[k];
+        sh.post.slot[k * kSortThreads + threadIdx.x] = vals[k];
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i + 1 < n; i += kSortThreads) {
+        const Code c = sh.post.code[i];
+        if (sh.post.code[i + 1] != c || (i > 0 && sh.post.code[i - 1] == c)) continue;
+        uint32_t e = i + 1; // the run [i, e]
+        while (e + 1 < n && sh.post.code[e + 1] == c && e - i < kMaxTieRun) ++e;
+        if (e - i >= kMaxTieRun) {
+            *flag = 1u;
+            continue;
+        }
+        for (uint32_t a = i + 1; a <= e; ++a) { // insertion sort of the run by previous position
+            const uint32_t s = sh.post.slot[a], ps = sp[s];
+            uint32_t q = a;
+            while (q > i && sp[sh.post.slot[q - 1]] > ps) {
+                sh.post.slot[q] = sh.post.slot[q - 1];
+                --q;
+            }
+            sh.post.slot[q] = s;
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < n; t += kSortThreads) {
+        const uint32_t g = start + t;
+        if ((int64_t)g < W.P) {
+            const uint32_t e = sh.post.slot[t];
+            ko[W.doff + g] = su[e];
+            lo[W.doff + g] = sl[e];
+        }
+    }
 }
 
 // Bits that hold every item number below n_items.
@@ -137,8 +321,9 @@ hipError_t sorted(int n_items, uint32_t n, const CdfBuffers &b, hipStream_t s) {
 
 hipError_t launch_cdf_start(int prec, const WorkItem *items, int n_items, const int2 *blocks, int nblocks,
                             const CdfBuffers &b, hipStream_t s) {
-    hipLaunchKernelGGL(k_cdf_setup, dim3((n_items + kThreads - 1) / kThreads), dim3(kThreads), 0, s, items, n_items,
-                       b.seg_begin);
+    const int cover = n_items > b.nbuckets ? n_items : b.nbuckets;
+    hipLaunchKernelGGL(k_cdf_setup, dim3((cover + kThreads - 1) / kThreads), dim3(kThreads), 0, s, items, n_items,
+                       b.seg_begin, b.btab, b.bcount, b.nbuckets, b.flag);
     if (prec == 0)
         hipLaunchKernelGGL(k_cdf_gather<double>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks,
                            (double *)b.keys[0], b.lab[0]);
@@ -150,6 +335,17 @@ hipError_t launch_cdf_start(int prec, const WorkItem *items, int n_items, const 
 
 hipError_t cdf_scratch_bytes(int prec, uint32_t n, uint32_t nseg, size_t &bytes) {
     return prec == 0 ? scratch_bytes<double>(n, nseg, bytes) : scratch_bytes<float>(n, nseg, bytes);
+}
+
+hipError_t launch_cdf_buckets(int prec, const WorkItem *items, int n_items, const CdfBuffers &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_cdf_bscan, dim3(n_items), dim3(kThreads), 0, s, items, b.bcount, b.bstart, b.flag);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_cdf_bsort<double>, dim3(b.nbuckets), dim3(kSortThreads), 0, s, items, b.btab, b.bcount,
+                           b.bstart, stage_view<double>(b.stage, b.nbuckets), b.flag, (double *)b.keys[1], b.lab[1]);
+    else
+        hipLaunchKernelGGL(k_cdf_bsort<float>, dim3(b.nbuckets), dim3(kSortThreads), 0, s, items, b.btab, b.bcount,
+                           b.bstart, stage_view<float>(b.stage, b.nbuckets), b.flag, (float *)b.keys[1], b.lab[1]);
+    return hipGetLastError();
 }
 
 hipError_t launch_cdf_sort(int prec, int n_items, uint32_t n, const CdfBuffers &b, hipStream_t s) {

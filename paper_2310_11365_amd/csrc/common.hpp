@@ -53,6 +53,8 @@ struct WorkItem {
     int32_t wrap;      // 1: shift modulo 2 pi into [0, 2 pi) after every step
     int32_t trig;      // 1: trigonometric drift terms; the step's mean field is (mean sin, mean cos)
     int32_t cdf;       // 1: empirical-CDF drift term (every step ranks the ensemble)
+    int32_t nbk;       // empirical-CDF drift: buckets of this item (ceil(P / kCdfBucket))
+    int32_t bbase;     // its first bucket in the launch's bucket tables
     int32_t pad;
     int64_t doff;      // first position of this item in the launch's dense sort arrays
     double c[14];      // a0 a1 a2 a3 am av b0 b1 bm bv axs ksin kc acdf

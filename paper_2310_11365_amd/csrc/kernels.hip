@@ -14,6 +14,8 @@
 // start-up (kernel boundaries order the data; no atomics, no fences, no
 // spinning).  The shift of the sums is the previous step's mean, so the
 // one-pass variance does not cancel.
+#include <limits>
+
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
@@ -589,37 +591,91 @@ __device__ __forceinline__ int64_t run_end(const V &S, int64_t P, int64_t r, T v
     return known;
 }
 
+// Bucket of a new state u: the largest k in [0, nbk) with k == 0 or
+// split(k) <= u, where split(k) is the sorted input's key at position
+// k * kCdfBucket; searched from k0 (the bucket of the state's old position)
+// by doubling steps, then bisection.
+template <typename V, typename T>
+__device__ __forceinline__ int bucket_of(const V &S, int nbk, int k0, T u) {
+    auto ok = [&](int k) { return k == 0 || S.key((uint32_t)k * (uint32_t)kCdfBucket) <= u; };
+    int lo, hi; // ok(lo), !ok(hi) (hi == nbk: past the end)
+    if (ok(k0)) {
+        lo = k0;
+        int step = 1;
+        while (lo + step < nbk && ok(lo + step)) {
+            lo += step;
+            step <<= 1;
+        }
+        hi = lo + step < nbk ? lo + step : nbk;
+    } else {
+        hi = k0;
+        int step = 1;
+        while (hi - step >= 1 && !ok(hi - step)) {
+            hi -= step;
+            step <<= 1;
+        }
+        lo = hi - step >= 1 ? hi - step : 0;
+    }
+    while (hi - lo > 1) {
+        const int mid = lo + (hi - lo) / 2;
+        if (ok(mid))
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 // One Euler-Maruyama step with the empirical-CDF drift term acdf (1 - F_P(x)),
-// taken in the ensemble's ascending order (the sorted pairs of launch_cdf_sort:
-// state and label doff + p).  Position r has sum_q H(x - X_q) = lo + (hi - lo
-// + 1) / 2 for the run [lo, hi] of keys equal to its key (distinct
-// neighbours: r + 1/2).  Particle p's normal is normal p & 3 of Philox quad
-// p >> 2, as in the particle-order steps.  The new state and its label go to
-// position r of ko / lo (the next step's sort input), or on the last step of
-// the sweep to the particle's slot y[p].  The (m, v) partials of the new
-// states are summed in sorted order (a fixed order for a given state).
+// taken in the ensemble's ascending order (the sorted pairs: state and label
+// doff + p); the mean field of the input comes from k_combine.  Position r has sum_q H(x - X_q) = lo + (hi - lo + 1) / 2 for the
+// run [lo, hi] of keys equal to its key (distinct neighbours: r + 1/2).
+// Particle p's normal is normal p & 3 of Philox quad p >> 2, as in the
+// particle-order steps.  The new state goes (mode 0) with its label to
+// position r of keys[0] / lab[0], the next library sort's input; (mode 1)
+// into its bucket, with a slot taken by one atomic per bucket and wave; or
+// (mode 2, the last step of a sweep) to the particle's slot y[p], unless a
+// bucket of the sweep overflowed (the sweep is then redone).  The (m, v)
+// partials of the new states are summed in sorted order.
 template <typename T, int DEG, bool PACKED>
 __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__restrict__ items,
-                                                             const int2 *__restrict__ blocks, int32_t j, int32_t last,
-                                                             const double2 *__restrict__ part_in,
-                                                             const double *__restrict__ shift_in,
+                                                             const int2 *__restrict__ blocks, int32_t j, int32_t mode,
+                                                             const double2 *__restrict__ mv_in,
                                                              SortedView<T, PACKED> all, T *__restrict__ ko,
                                                              uint32_t *__restrict__ lo_out,
+                                                             uint32_t *__restrict__ bcount, StageView<T> stage,
+                                                             uint32_t *__restrict__ flag,
                                                              double2 *__restrict__ part_out,
                                                              double *__restrict__ shift_out,
                                                              double2 *__restrict__ trace, int32_t m) {
+    // mode 1: a round's states (4 * kThreads neighbours in the previous
+    // order) fall into buckets near the one of their first position; kWin
+    // buckets around it are counted in LDS, reserved with one atomic each,
+    // and the states grouped by bucket in LDS and copied out coalesced
+    constexpr int kWin = 64, kBelow = 32, kRound = 4 * kThreads;
+    static_assert(kWin == 64, "one wave scans the window");
     __shared__ double lds[8];
+    __shared__ uint32_t hist[kWin], hbase[kWin], lstart[kWin + 1];
+    __shared__ T spl[kWin + 1]; // the window's splitters (-inf below bucket 1, +inf past the item)
+    __shared__ T su[kRound];
+    __shared__ uint32_t sl[kRound], sp[kRound];
+    __shared__ uint8_t sw[kRound];
+    if (mode != 0 && *flag) return; // a doomed sweep (redone): skip its work, keep the input state
     const int2 bt = blocks[blockIdx.x];
     const int item = bt.x, sc = bt.y;
     const WorkItem &W = items[item];
     T *__restrict__ y = reinterpret_cast<T *>(W.x);
     const SortedView<T, PACKED> S = all.at(W.doff); // this item's pairs
-    const int64_t P = W.P;
+    // item-relative positions fit 32 bits (a launch holds fewer than 2^32 states)
+    const uint32_t P = (uint32_t)W.P;
     const int R = W.R;
-    const int64_t base = (int64_t)sc * 4 * kThreads * R;
-    double S1, S2, mean, var;
-    ensemble_sums(part_in + W.part_off, W.nsc, S1, S2, lds);
-    finish_moments(S1, S2, shift_in[item], (double)P, mean, var);
+    const uint32_t base = (uint32_t)sc * 4u * kThreads * (uint32_t)R;
+    if (mode == 1) {
+        if (threadIdx.x < kWin) hist[threadIdx.x] = 0u;
+        __syncthreads();
+    }
+    const double2 mvv = mv_in[item]; // the step's mean field, from k_combine
+    const double mean = mvv.x, var = mvv.y;
     const T shift = (T)mean;
     if (sc == 0 && threadIdx.x == 0) {
         shift_out[item] = (double)shift;
@@ -634,29 +690,60 @@ __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__r
     const uint32_t inst = (uint32_t)W.inst;
     double a1 = 0.0, a2 = 0.0;
     for (int g = 0; g < R; ++g) {
-        T d[4];
+        T d[4], uu[4];
+        uint32_t ll[4];
+        int bb[4], loc[4];
+        const uint32_t r0 = base + 4u * (uint32_t)g * kThreads; // the round's first position
+        const int kc = ((int)(r0 / kCdfBucket) < W.nbk ? (int)(r0 / kCdfBucket) : W.nbk - 1) - kBelow;
+        if (mode == 1) {
+            if (threadIdx.x <= kWin) {
+                const int k = kc + (int)threadIdx.x;
+                spl[threadIdx.x] = k <= 0 ? -std::numeric_limits<T>::infinity()
+                                          : (k >= W.nbk ? std::numeric_limits<T>::infinity()
+                                                        : S.key((uint32_t)k * (uint32_t)kCdfBucket));
+            }
+            __syncthreads();
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             // lane-contiguous positions: every load instruction reads 64 consecutive pairs
-            const int64_t r = base + (int64_t)(4 * g + e) * kThreads + threadIdx.x;
+            const uint32_t r = base + (uint32_t)(4 * g + e) * kThreads + threadIdx.x;
             d[e] = (T)0;
+            bb[e] = -1;
             if (r < P) {
                 const T v = S.key(r);
                 const uint32_t lab = S.label(r);
                 int64_t lo = r, hi = r;
-                if (r > 0 && S.key(r - 1) == v) lo = run_end<-1>(S, P, r, v);
-                if (r + 1 < P && S.key(r + 1) == v) hi = run_end<1>(S, P, r, v);
+                if (r > 0 && S.key(r - 1) == v) lo = run_end<-1>(S, (int64_t)P, (int64_t)r, v);
+                if (r + 1 < P && S.key(r + 1) == v) hi = run_end<1>(S, (int64_t)P, (int64_t)r, v);
                 const T cnt = (T)((double)lo + 0.5 * (double)(hi - lo + 1));
-                const int64_t p = (int64_t)lab - W.doff;
+                const uint32_t p = lab - (uint32_t)W.doff;
                 const Words4 w = philox4x32_10((uint32_t)(p >> 2), step, inst, 0u, W.key0, W.key1);
                 const T z = normal_pick<T>(w, (int)(p & 3));
                 const T pol0 = (DEG == 1) ? fmaT(c1, v, c0) : fmaT(fmaT(fmaT(c3, v, c2), v, c1), v, c0);
                 const T u = fmaT(fmaT(e1, v, e0), z, fmaT(kf, cnt, pol0));
-                if (last) {
+                if (mode == 2) {
                     y[p] = u;
-                } else {
+                } else if (mode == 0) {
                     ko[W.doff + r] = u;
                     lo_out[W.doff + r] = lab;
+                } else {
+                    // the largest w with spl[w] <= u (spl[w] nondecreasing), by
+                    // halving steps in LDS; outside the window, a search of
+                    // the item's splitters from the state's old bucket
+                    int w = 0;
+#pragma unroll
+                    for (int step = 32; step > 0; step >>= 1)
+                        if (spl[w + step] <= u) w += step;
+                    if (spl[kWin] <= u) w = kWin;
+                    if (spl[0] <= u && w < kWin) {
+                        bb[e] = kc + w;
+                    } else {
+                        const int k0 = (int)(r / kCdfBucket) < W.nbk ? (int)(r / kCdfBucket) : W.nbk - 1;
+                        bb[e] = bucket_of(S, W.nbk, k0, u);
+                    }
+                    uu[e] = u;
+                    ll[e] = lab;
                 }
                 d[e] = u - shift;
             }
@@ -665,6 +752,67 @@ __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__r
         quad_leaf(d, q1, q2);
         a1 += q1;
         a2 += q2;
+        if (mode == 1) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                loc[e] = -1;
+                if (bb[e] >= 0 && bb[e] - kc >= 0 && bb[e] - kc < kWin) loc[e] = (int)atomicAdd(&hist[bb[e] - kc], 1u);
+            }
+            __syncthreads();
+            if (threadIdx.x < kWin) { // wave 0: offsets in the round, slots in the buckets
+                const uint32_t h = hist[threadIdx.x];
+                uint32_t incl = h;
+#pragma unroll
+                for (int off = 1; off < kWin; off <<= 1) {
+                    const uint32_t v = (uint32_t)__shfl_up((int)incl, off);
+                    if ((int)threadIdx.x >= off) incl += v;
+                }
+                lstart[threadIdx.x] = incl - h;
+                if (threadIdx.x == kWin - 1) lstart[kWin] = incl;
+                hbase[threadIdx.x] = h != 0u ? atomicAdd(&bcount[W.bbase + kc + (int)threadIdx.x], h) : 0u;
+                hist[threadIdx.x] = 0u; // for the next round
+            }
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (bb[e] < 0) continue;
+                const uint32_t pos = base + (uint32_t)(4 * g + e) * kThreads + threadIdx.x;
+                if (loc[e] >= 0) {
+                    const int w = bb[e] - kc;
+                    const uint32_t q = lstart[w] + (uint32_t)loc[e];
+                    su[q] = uu[e];
+                    sl[q] = ll[e];
+                    sp[q] = pos;
+                    sw[q] = (uint8_t)w;
+                } else { // outside the window: a slot of its own
+                    const int b = W.bbase + bb[e];
+                    const uint32_t slot = atomicAdd(&bcount[b], 1u);
+                    if (slot < (uint32_t)kCdfBucketCap) {
+                        const size_t i = ((size_t)b << 12) + slot; // kCdfBucketCap == 4096
+                        stage.u[i] = uu[e];
+                        stage.lab[i] = ll[e];
+                        stage.pos[i] = pos;
+                    } else {
+                        *flag = 1u;
+                    }
+                }
+            }
+            __syncthreads();
+            const uint32_t total = lstart[kWin];
+            for (uint32_t q = threadIdx.x; q < total; q += kThreads) {
+                const int w = sw[q];
+                const uint32_t slot = hbase[w] + (q - lstart[w]);
+                if (slot < (uint32_t)kCdfBucketCap) {
+                    const size_t i = ((size_t)(W.bbase + kc + w) << 12) + slot;
+                    stage.u[i] = su[q];
+                    stage.lab[i] = sl[q];
+                    stage.pos[i] = sp[q];
+                } else {
+                    *flag = 1u;
+                }
+            }
+            __syncthreads(); // before the next round reuses the LDS staging
+        }
     }
     double sm[2] = {a1, a2};
     block_sum<2>(sm, lds);
@@ -1383,40 +1531,39 @@ hipError_t launch_em_step_trig(int prec, int deg, const WorkItem *items, const i
 }
 
 template <typename T, int DEG>
-static void em_step_sorted(const WorkItem *items, int n_items, const int2 *blocks, int nblocks, int j, bool last,
-                           const double2 *part_in, const double *shift_in, const CdfBuffers &b, double2 *part_out,
-                           double *shift_out, double2 *trace, int m, hipStream_t s) {
-    if (n_items > 1) {
+static void em_step_sorted(const WorkItem *items, const int2 *blocks, int nblocks, int j, int mode, bool packed,
+                           const double2 *mv, const CdfBuffers &b, double2 *part_out, double *shift_out,
+                           double2 *trace, int m, hipStream_t s) {
+    if (packed) {
         SortedView<T, true> v{(const KeyLabel<T> *)b.kl[1]};
         hipLaunchKernelGGL((k_em_step_sorted<T, DEG, true>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
-                           (int32_t)last, part_in, shift_in, v, (T *)b.keys[0], b.lab[0], part_out, shift_out, trace,
-                           m);
+                           mode, mv, v, (T *)b.keys[0], b.lab[0], b.bcount, stage_view<T>(b.stage, b.nbuckets),
+                           b.flag, part_out, shift_out, trace, m);
     } else {
         SortedView<T, false> v{(const T *)b.keys[1], b.lab[1]};
         hipLaunchKernelGGL((k_em_step_sorted<T, DEG, false>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks, j,
-                           (int32_t)last, part_in, shift_in, v, (T *)b.keys[0], b.lab[0], part_out, shift_out, trace,
-                           m);
+                           mode, mv, v, (T *)b.keys[0], b.lab[0], b.bcount, stage_view<T>(b.stage, b.nbuckets),
+                           b.flag, part_out, shift_out, trace, m);
     }
 }
 
 hipError_t launch_em_step_sorted(int prec, int deg, const WorkItem *items, int n_items, const int2 *blocks,
-                                 int nblocks, int j, bool last, const double2 *part_in, const double *shift_in,
-                                 const CdfBuffers &b, double2 *part_out, double *shift_out, double2 *trace, int m,
-                                 hipStream_t s) {
+                                 int nblocks, int j, int mode, bool packed, const double2 *part_in,
+                                 const double *shift_in, double2 *mv, const CdfBuffers &b, double2 *part_out,
+                                 double *shift_out, double2 *trace, int m, hipStream_t s) {
+    hipLaunchKernelGGL(k_combine, dim3(n_items), dim3(kThreads), 0, s, items, part_in, shift_in, mv);
     if (prec == 0) {
         if (deg == 1)
-            em_step_sorted<double, 1>(items, n_items, blocks, nblocks, j, last, part_in, shift_in, b, part_out,
-                                      shift_out, trace, m, s);
+            em_step_sorted<double, 1>(items, blocks, nblocks, j, mode, packed, mv, b, part_out, shift_out, trace, m,
+                                      s);
         else
-            em_step_sorted<double, 3>(items, n_items, blocks, nblocks, j, last, part_in, shift_in, b, part_out,
-                                      shift_out, trace, m, s);
+            em_step_sorted<double, 3>(items, blocks, nblocks, j, mode, packed, mv, b, part_out, shift_out, trace, m,
+                                      s);
     } else {
         if (deg == 1)
-            em_step_sorted<float, 1>(items, n_items, blocks, nblocks, j, last, part_in, shift_in, b, part_out,
-                                     shift_out, trace, m, s);
+            em_step_sorted<float, 1>(items, blocks, nblocks, j, mode, packed, mv, b, part_out, shift_out, trace, m, s);
         else
-            em_step_sorted<float, 3>(items, n_items, blocks, nblocks, j, last, part_in, shift_in, b, part_out,
-                                     shift_out, trace, m, s);
+            em_step_sorted<float, 3>(items, blocks, nblocks, j, mode, packed, mv, b, part_out, shift_out, trace, m, s);
     }
     return hipGetLastError();
 }

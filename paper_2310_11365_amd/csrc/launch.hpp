@@ -59,6 +59,33 @@ struct KeyLabel {
     T k;
     uint32_t l;
 };
+// Bucket engine of the sort (steps after the first of a sweep): the bucket
+// of a new state is found among the previous step's sorted states at stride
+// kCdfBucket (kCdfBucket states per bucket on average); each bucket holds at
+// most kCdfBucketCap states (else the sweep is marked and redone with the
+// library sort).  The staging area holds, per bucket slot, the state, its
+// label, and its position in the previous step's order (the tie-breaker that
+// makes the order equal to the stable library sort's), as three arrays.
+constexpr int kCdfBucket = 2048;
+constexpr int kCdfBucketCap = 4096;
+static_assert(kCdfBucket == 2048 && kCdfBucketCap == 4096, "the step kernel indexes buckets by shifts");
+template <typename T>
+struct StageView {
+    T *u;
+    uint32_t *lab, *pos;
+};
+template <typename T>
+inline StageView<T> stage_view(void *stage, int nbuckets) {
+    const size_t slots = (size_t)nbuckets * kCdfBucketCap;
+    StageView<T> v;
+    v.u = (T *)stage;
+    v.lab = (uint32_t *)((char *)stage + slots * sizeof(T));
+    v.pos = v.lab + slots;
+    return v;
+}
+inline size_t stage_bytes(int prec, int nbuckets) {
+    return (size_t)nbuckets * kCdfBucketCap * ((prec == 0 ? sizeof(double) : sizeof(float)) + 2 * sizeof(uint32_t));
+}
 struct CdfBuffers {
     void *keys[2];       // state type, n each: [0] the step's output (sort input), [1] sorted by value
     uint32_t *lab[2];    // their labels
@@ -67,23 +94,37 @@ struct CdfBuffers {
     uint32_t *seg_begin; // doff of every item
     void *tmp;
     size_t tmp_bytes;
+    // bucket engine
+    int2 *btab;          // (item, bucket of the item) of every bucket
+    int nbuckets;        // buckets of the launch
+    uint32_t *bcount;    // states per bucket (zero between steps)
+    uint32_t *bstart;    // first position of each bucket in its item's order
+    void *stage;         // staging area (stage_view), kCdfBucketCap slots per bucket
+    uint32_t *flag;      // nonzero once a bucket overflowed in this sweep
 };
 // Once per fine sweep: the dense first position of every item; the states and
-// labels into keys[0], lab[0].
+// labels into keys[0], lab[0]; bucket counts and the overflow flag cleared.
 hipError_t launch_cdf_start(int prec, const WorkItem *items, int n_items, const int2 *blocks, int nblocks,
                             const CdfBuffers &b, hipStream_t s);
 // Bytes of library scratch the sorts need for n positions of nseg items.
 hipError_t cdf_scratch_bytes(int prec, uint32_t n, uint32_t nseg, size_t &bytes);
-// Sorts (keys[0], lab[0]): each item's pairs ascending at [doff, doff + P) in
-// keys[1], lab[1] (one item) or kl[1] (several items).
+// Library engine: sorts (keys[0], lab[0]) so that each item's pairs are
+// ascending at [doff, doff + P) in keys[1], lab[1] (one item) or kl[1]
+// (several items).
 hipError_t launch_cdf_sort(int prec, int n_items, uint32_t n, const CdfBuffers &b, hipStream_t s);
-// The Euler-Maruyama step with the empirical-CDF drift, in sorted order: the
-// new states go to keys[0], lab[0], or on the last step of the sweep to the
-// particles' slots.
+// Bucket engine: the staged states of every bucket sorted by (value,
+// previous position) into keys[1], lab[1] at their item's positions.
+hipError_t launch_cdf_buckets(int prec, const WorkItem *items, int n_items, const CdfBuffers &b, hipStream_t s);
+// The Euler-Maruyama step with the empirical-CDF drift, in sorted order (the
+// pairs in kl[1] if packed, else keys[1], lab[1]); the input's mean field is
+// combined once per item first (into mv).  mode 0: the new states
+// and labels go to keys[0], lab[0] at the sorted positions (the library
+// sort's input); 1: into the buckets; 2 (the last step of the sweep): to the
+// particles' slots, unless the overflow flag is set.
 hipError_t launch_em_step_sorted(int prec, int deg, const WorkItem *items, int n_items, const int2 *blocks,
-                                 int nblocks, int j, bool last, const double2 *part_in, const double *shift_in,
-                                 const CdfBuffers &b, double2 *part_out, double *shift_out, double2 *trace, int m,
-                                 hipStream_t s);
+                                 int nblocks, int j, int mode, bool packed, const double2 *part_in,
+                                 const double *shift_in, double2 *mv, const CdfBuffers &b, double2 *part_out,
+                                 double *shift_out, double2 *trace, int m, hipStream_t s);
 // out[i] = (1/P) sum Phi(x_p) of item i; part: scratch of one partial per superchunk.
 hipError_t launch_qoi(int prec, int kind, const WorkItem *items, int n_items, const int2 *blocks, int nblocks,
                       double2 *part, double *out, hipStream_t s);

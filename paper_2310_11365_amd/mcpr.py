@@ -106,6 +106,10 @@ def lib() -> ctypes.CDLL:
         L.mcpr_tuned_variant.restype = i32
         L.mcpr_graph_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.mcpr_graph_stats.restype = st
+        L.mcpr_set_cdf_sort.argtypes = [vp, i32]
+        L.mcpr_set_cdf_sort.restype = st
+        L.mcpr_cdf_stats.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int64)] * 3
+        L.mcpr_cdf_stats.restype = st
         L.mcpr_adjoint.argtypes = [vp, pP, pE, vp, vp, vp, vp]
         L.mcpr_adjoint.restype = st
         L.mcpr_parareal_create.argtypes = [vp, pP, i32, ctypes.POINTER(InstanceC), i32, i32, ctypes.c_double,
@@ -249,6 +253,17 @@ class Context:
         b, n = ctypes.c_int64(), ctypes.c_int64()
         self._check(lib().mcpr_graph_stats(self._h, ctypes.byref(b), ctypes.byref(n)))
         return b.value, n.value
+
+    def set_cdf_sort(self, mode: int):
+        """Sort of the empirical-CDF drift: 1 buckets after each sweep's first
+        step (default), 0 the radix sort on every step."""
+        self._check(lib().mcpr_set_cdf_sort(self._h, int(mode)))
+
+    def cdf_stats(self):
+        """(bucket sweeps, radix-sort-only sweeps, sweeps redone after an overflow)."""
+        v = [ctypes.c_int64() for _ in range(3)]
+        self._check(lib().mcpr_cdf_stats(self._h, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     def init_particles(self, problems: Sequence[ProblemC], ensembles: Sequence[EnsembleC], stream=None):
         P, E = self._arrays(problems, ensembles)

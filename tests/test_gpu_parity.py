@@ -241,6 +241,90 @@ def test_fine_burgers_batched_ragged(mc, ctx, oracle):
         assert np.max(np.abs(x.cpu().numpy() - ox)) < 1e-11, (i, P)
 
 
+def _burgers_spread(P, N, T, precision, sd=1.0):
+    """The Burgers drift from a spread start X0 ~ N(0, sd^2)."""
+    pr = W.make_problem(W.Coef(acdf=1.0, b0=1.0), W.P0(W.P0_NORMAL, 1.0, 0.0, sd), T, N, 1e-3, (), 0, 0.05,
+                        precision)
+    return pr
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32])
+def test_burgers_bucket_sort_equals_radix_sort_bitwise(mc, prec):
+    """The bucket engine (steps after a sweep's first) gives bit for bit what
+    the radix sort on every step gives: ensembles of 70 001 (four quads per
+    thread), 3 000, 2 048, 1 and 10 007 particles from a spread start in one
+    call, every state and the per-step trace; no sweep is redone."""
+    import torch
+    pr = _burgers_spread(1, 4, 0.4, prec)
+    pc = mc.problem_c(pr)
+    sizes = [70_001, 3_000, 2_048, 1, 10_007]
+    dt = torch.float64 if prec == W.FP64 else torch.float32
+    runs = []
+    for engine in (1, 0):
+        c = mc.Context(0)
+        c.set_cdf_sort(engine)
+        xs = [torch.empty(P, dtype=dt, device="cuda") for P in sizes]
+        c.init_particles([pc], [mc.ensemble(x, i) for i, x in enumerate(xs)])
+        buf = mc.stats_buffer(len(xs), 1)
+        tr = torch.empty(len(xs) * (pr.steps_per_slice + 1) * 2, dtype=torch.float64, device="cuda")
+        for n in range(2):
+            c.fine_propagate([pc], [mc.ensemble(x, i, n) for i, x in enumerate(xs)], buf, tr)
+        torch.cuda.synchronize()
+        runs.append(([x.clone() for x in xs], tr.clone(), buf.clone(), c.cdf_stats()))
+        c.close()
+    (xb, tb, sb, stb), (xl, tl, sl, stl) = runs
+    assert stb == (2, 0, 0) and stl == (0, 2, 0), (stb, stl)
+    for a, b in zip(xb, xl):
+        assert torch.equal(a, b)
+    assert torch.equal(tb, tl) and torch.equal(sb, sl)
+
+
+def test_burgers_bucket_overflow_redoes_the_sweep(mc, oracle):
+    """Without noise a point mass stays one (every state ties at every step):
+    the sorted states give no splitters, a bucket overflows with the library
+    sort on the first 2 steps and on the first 16, and the sweep ends up
+    sorted by the library alone.  From a point mass with noise (P = 2e5) the
+    law spreads fast at first: the edge buckets overflow with 2 library steps
+    (the variance doubles over the first bucket step) but not with 16.  The
+    particles match the oracle either way."""
+    c = mc.Context(0)
+    pr = W.make_problem(W.Coef(acdf=1.0), W.P0(W.P0_DELTA, 1.0, 0.0, 0.0), 1.0, 10, 1e-3, (), 0, 0.05, W.FP64)
+    prop = mc.Propagator(pr, c)
+    x = prop.new_particles(20_000)
+    prop.sample(x)
+    prop.fine([x], [0])
+    assert c.cdf_stats() == (0, 1, 2)
+    ox, _ = oracle.fine(pr, oracle.sample_p0(pr, 20_000), 0)
+    assert np.max(np.abs(x.cpu().numpy() - ox)) < 1e-11
+    wl = W.burgers(P=200_000, N=10, T=1.0)
+    prop = mc.Propagator(wl.problem, c)
+    x = prop.new_particles(wl.P)
+    prop.sample(x)
+    prop.fine([x], [0])
+    assert c.cdf_stats() == (1, 1, 3)
+    ox, _ = oracle.fine(wl.problem, oracle.sample_p0(wl.problem, wl.P), 0)
+    assert np.max(np.abs(x.cpu().numpy() - ox)) < 1e-11
+    c.close()
+
+
+def test_fine_burgers_spread_matches_oracle(mc, ctx, oracle):
+    """The bucket engine against the oracle: a spread start (every step after
+    the first from the buckets), every particle and the trace."""
+    import torch
+    pr = _burgers_spread(1, 10, 1.0, W.FP64)
+    P = 30_011
+    prop = mc.Propagator(pr, ctx)
+    x = prop.new_particles(P)
+    prop.sample(x)
+    before = ctx.cdf_stats()
+    g, tr = prop.fine([x], [2], trace=True)
+    assert ctx.cdf_stats()[0] == before[0] + 1
+    ox, otr = oracle.fine(pr, oracle.sample_p0(pr, P), 2, trace=True)
+    assert np.max(np.abs(x.cpu().numpy() - ox)) < 1e-11
+    assert np.max(np.abs(tr[0, :-1] - otr)) <= TOL64 * (1.0 + np.max(np.abs(otr)))
+    assert_records_close(g[0], oracle.restrict(pr, ox), TOL64)
+
+
 def test_parareal_burgers_fp64_matches_oracle(mc, ctx, oracle):
     """Burgers through the whole Parareal iteration with the Gaussian-density
     moment model (a point mass at t = 0)."""
