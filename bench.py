@@ -296,8 +296,8 @@ def main():
     kernel = f"k_em_step<{tname}, {deg}, {'true' if variant & 1 else 'false'}, {'true' if variant & 2 else 'false'}>"
     if pr.coef.acdf != 0.0:
         # the events bracket every launch of a step: gather, sort, flags, scans, rank, update
-        kernel = (f"empirical-CDF step sequence (k_cdf_gather, radix sort by value, radix pass by ensemble, "
-                  f"k_cdf_permute, k_em_step_sorted<{tname}, {deg}>)")
+        kernel = (f"empirical-CDF step sequence (library radix sort on a sweep's first steps, then buckets: "
+                  f"k_combine, k_em_step_sorted<{tname}, {deg}, false>, k_cdf_bscan, k_cdf_bsort<{tname}>)")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(kernel, wl.name),
                 "kernel": kernel, "avg_launch_us": round(avg_launch_s * 1e6, 2),
