@@ -675,6 +675,75 @@ def test_full_size_burgers_slice_parity(mc, ctx, oracle):
     assert np.max(np.abs(glob[:, 0] - 0.5 * t)) <= se
 
 
+def test_full_size_batched_ou_parity(mc, ctx, oracle):
+    """64 OU instances at full size (P log-uniform in [1e4, 2e6], N = 32,
+    3.7 GB of rings, fp32) in the benchmark's launch configuration: for the
+    smallest, the median and the largest instance, the exact slice after one
+    iteration is bit for bit a lone fine sweep of the same sample, and its
+    moments match the oracle's serial slice at that size within the fp32
+    bound; every instance keeps one region holding all particles."""
+    import torch
+    wl = W.ou_batched()
+    pr = wl.problem
+    sizes = [i["P"] for i in wl.instances]
+    coefs = [i["coef"] for i in wl.instances]
+    para = mc.Parareal([pr], sizes, ctx, coefs=coefs)
+    para.init()
+    para.iterate()
+    pr64 = W.ou_batched(precision=W.FP64).problem
+    order = np.argsort(sizes)
+    for i in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        pc = mc.problem_c(pr, coefs[i])
+        x = torch.empty(sizes[i], dtype=torch.float32, device="cuda")
+        ctx.init_particles([pc], [mc.ensemble(x, i)])
+        ctx.fine_propagate([pc], [mc.ensemble(x, i, 0)], mc.stats_buffer(1, 1))
+        assert torch.equal(x, para.slot(i, 1)), i
+        xo, _ = oracle.fine(pr64, oracle.sample_p0(pr64, sizes[i], inst=i, coef=coefs[i]), 0, inst=i,
+                            coef=coefs[i])
+        o = oracle.restrict(pr64, xo)[0]
+        rho, _ = para.macro(i)
+        sc = abs(o["mean"]) + math.sqrt(o["var"])
+        assert abs(rho[1, 0, 1] - o["mean"]) <= FP32_M * sc, i
+        assert abs(rho[1, 0, 2] - o["var"]) <= FP32_V * o["var"], i
+    for i in range(len(sizes)):
+        rho, glob = para.macro(i)
+        assert np.all(rho[:, 0, 0] == 1.0) and np.all(rho[:, 0, 2] > 0)
+        assert np.array_equal(glob[:, 0], rho[:, 0, 1])
+    para.close()
+
+
+def test_full_size_large_bimodal_parity(mc, ctx, oracle):
+    """The largest workload at full size (P = 1.6e7, N = 256, 16.4 GB ring,
+    fraction learning) in the benchmark's launch configuration: the initial
+    macro state against the oracle's sample at that size within the fp32
+    bound, and the exact slice after one iteration bit for bit a lone fine
+    sweep of the same sample (the lone sweep's kernels are parity-tested
+    against the oracle at smaller sizes)."""
+    import torch
+    wl = W.dz_large()
+    pr = wl.problem
+    para = mc.Parareal([pr], [wl.P], ctx, learning=True, tol=wl.tol)
+    para.init()
+    para.iterate()
+    rho, glob = para.macro(0)
+    pr64 = W.dz_large().problem
+    pr64.precision = W.FP64
+    o = oracle.restrict(pr64, oracle.sample_p0(pr64, wl.P))
+    for i in range(2):
+        assert abs(rho[0, i, 0] * wl.P - o[i]["n"]) <= max(2, 1e-4 * o[i]["n"])
+        sc = abs(o[i]["mean"]) + math.sqrt(o[i]["var"])
+        assert abs(rho[0, i, 1] - o[i]["mean"]) <= FP32_M * sc
+        assert abs(rho[0, i, 2] - o[i]["var"]) <= FP32_V * o[i]["var"]
+    slot1 = para.slot(0, 1).clone()
+    para.close()
+    pc = mc.problem_c(pr)
+    x = torch.empty(wl.P, dtype=torch.float32, device="cuda")
+    ctx.init_particles([pc], [mc.ensemble(x, 0)])
+    ctx.fine_propagate([pc], [mc.ensemble(x, 0, 0)], mc.stats_buffer(1, 2))
+    assert torch.equal(x, slot1)
+    assert np.allclose(rho[:, :, 0].sum(axis=1), 1.0) and np.all(rho[:, :, 2] > 0)
+
+
 # ---------------------------------------------------------------------------- errors
 def test_invalid_arguments_are_rejected(mc, ctx):
     import torch
