@@ -35,7 +35,8 @@
 // splits nothing.)  Buckets stay near kCdfBucket states while the law changes
 // little per step; one above kCdfBucketCap marks the sweep, whose remaining
 // steps then do nothing and leave the particles untouched, and the host
-// redoes the sweep with the library sort alone.
+// redoes the sweep with the library sort on its first 16 steps, and if that
+// overflows too, on all of them.
 #include <cstring>
 
 #include <hip/hip_runtime.h>
