@@ -227,8 +227,8 @@ def main():
                          "reference for the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (slice sharding across GPUs is "
-              "described in DESIGN.md but not implemented); run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path (the fine sweep would shard by slice "
+              "ranges across GPUs; that exchange is not implemented); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     if args.workload.startswith("adjoint_"):
