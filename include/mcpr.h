@@ -59,8 +59,9 @@ enum { MCPR_MAX_REGIONS = 8 };
 enum { MCPR_COARSE_TAYLOR = 0, MCPR_COARSE_GAUSS2 = 1, MCPR_COARSE_GAUSS3 = 2 };
 
 /* Drift and diffusion of the scalar McKean-Vlasov SDE (Sec. 1.1, eq.
- * general_McKean_Vlasov) in the class the build supports: polynomial in the
- * particle position, affine in the ensemble's mean m and variance v.
+ * general_McKean_Vlasov) in the class this library supports: polynomial in
+ * the particle position, affine in the ensemble's mean m and variance v, plus
+ * the terms below (x E[X^2], trigonometric, empirical CDF).
  *   a(x, m, v) = a0 + a1 x + a2 x^2 + a3 x^3 + am m + av v
  *   b(x, m, v) = b0 + b1 x + bm m + bv v                                    */
 typedef struct {
