@@ -57,7 +57,7 @@ struct mcpr_ctx {
     // empirical-CDF drift: states and labels in sorted order, the library
     // sort's item pass and scratch, the bucket engine's tables and staging
     DevBuf cdf_keys[2], cdf_lab[2], cdf_seg[2], cdf_kl[2], cdf_beg, cdf_tmp;
-    DevBuf cdf_btab, cdf_bcount, cdf_bstart, cdf_stage, cdf_flag;
+    DevBuf cdf_bcount, cdf_bmeta, cdf_stage, cdf_flag;
     mcpr::CdfBuffers cdfb{};
     uint32_t *cdf_flag_host = nullptr; // pinned copy of the overflow flag
     int cdf_engine = 1;                // 1: bucket engine after a sweep's first step; 0: library sort every step
@@ -471,11 +471,10 @@ mcpr_status ensure_cdf(mcpr_ctx *ctx, const Tables &t, int prec) {
     }
     if ((st = ensure(ctx, ctx->cdf_beg, (size_t)nseg * sizeof(uint32_t))) != MCPR_OK) return st;
     const size_t nbk = (size_t)t.nbuckets;
-    if ((st = ensure(ctx, ctx->cdf_btab, nbk * sizeof(int2))) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->cdf_bcount, nbk * sizeof(uint32_t))) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->cdf_flag, sizeof(uint32_t))) != MCPR_OK) return st;
     if (ctx->cdf_engine) {
-        if ((st = ensure(ctx, ctx->cdf_bstart, nbk * sizeof(uint32_t))) != MCPR_OK) return st;
+        if ((st = ensure(ctx, ctx->cdf_bmeta, nbk * sizeof(uint2))) != MCPR_OK) return st;
         if ((st = ensure(ctx, ctx->cdf_stage, mcpr::stage_bytes(prec, (int)nbk))) != MCPR_OK) return st;
     }
     if (!ctx->cdf_flag_host) {
@@ -497,10 +496,9 @@ mcpr_status ensure_cdf(mcpr_ctx *ctx, const Tables &t, int prec) {
     c.seg_begin = (uint32_t *)ctx->cdf_beg.p;
     c.tmp = ctx->cdf_tmp.p;
     c.tmp_bytes = ctx->cdf_tmp.cap;
-    c.btab = (int2 *)ctx->cdf_btab.p;
     c.nbuckets = t.nbuckets;
     c.bcount = (uint32_t *)ctx->cdf_bcount.p;
-    c.bstart = (uint32_t *)ctx->cdf_bstart.p;
+    c.bmeta = (uint2 *)ctx->cdf_bmeta.p;
     c.stage = ctx->cdf_stage.p;
     c.flag = (uint32_t *)ctx->cdf_flag.p;
     return MCPR_OK;
@@ -740,7 +738,7 @@ void mcpr_destroy(mcpr_ctx *ctx) {
                       &ctx->adj_sums,      &ctx->adj_items,   &ctx->adj_blocks,  &ctx->trace,       &ctx->mv,
                       &ctx->cdf_keys[0],   &ctx->cdf_keys[1], &ctx->cdf_lab[0],  &ctx->cdf_lab[1],  &ctx->cdf_seg[0],
                       &ctx->cdf_seg[1],    &ctx->cdf_kl[0],   &ctx->cdf_kl[1],   &ctx->cdf_beg,     &ctx->cdf_tmp,
-                      &ctx->cdf_btab,      &ctx->cdf_bcount,  &ctx->cdf_bstart,  &ctx->cdf_stage,   &ctx->cdf_flag};
+                      &ctx->cdf_bcount,    &ctx->cdf_bmeta,   &ctx->cdf_stage,   &ctx->cdf_flag};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->staging.p) (void)hipHostFree(ctx->staging.p);

@@ -94,34 +94,24 @@ __global__ __launch_bounds__(kThreads) void k_cdf_pack(const T *__restrict__ key
     kl[i] = v;
 }
 
-// The dense first position of every item; for every bucket its (item,
-// bucket of the item) and a zero count; the overflow flag cleared.
+// The dense first position of every item; zero bucket counts; the overflow
+// flag cleared.
 __global__ __launch_bounds__(kThreads) void k_cdf_setup(const WorkItem *__restrict__ items, int n_items,
-                                                        uint32_t *__restrict__ beg, int2 *__restrict__ btab,
-                                                        uint32_t *__restrict__ bcount, int nbuckets,
-                                                        uint32_t *__restrict__ flag) {
+                                                        uint32_t *__restrict__ beg, uint32_t *__restrict__ bcount,
+                                                        int nbuckets, uint32_t *__restrict__ flag) {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i < n_items) beg[i] = (uint32_t)items[i].doff;
-    if (i < nbuckets) {
-        int lo = 0, hi = n_items - 1; // the last item whose first bucket is at or below i
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (items[mid].bbase <= i)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        btab[i] = make_int2(lo, i - items[lo].bbase);
-        bcount[i] = 0u;
-    }
+    if (i < nbuckets) bcount[i] = 0u;
     if (i == 0) *flag = 0u;
 }
 
-// Exclusive scan of one item's bucket counts (one block per item) into the
-// buckets' first positions; a count above the capacity marks the sweep.
+// Exclusive scan of one item's bucket counts (one block per item): each
+// bucket's first dense output position and its count, for k_cdf_bsort; the
+// counts cleared for the next step; a count above the capacity marks the
+// sweep.
 __global__ __launch_bounds__(kThreads) void k_cdf_bscan(const WorkItem *__restrict__ items,
-                                                        const uint32_t *__restrict__ bcount,
-                                                        uint32_t *__restrict__ bstart, uint32_t *__restrict__ flag) {
+                                                        uint32_t *__restrict__ bcount, uint2 *__restrict__ bmeta,
+                                                        uint32_t *__restrict__ flag) {
     __shared__ uint32_t sh[kThreads];
     const WorkItem &W = items[blockIdx.x];
     uint32_t carry = 0;
@@ -137,7 +127,10 @@ __global__ __launch_bounds__(kThreads) void k_cdf_bscan(const WorkItem *__restri
             sh[threadIdx.x] += add;
             __syncthreads();
         }
-        if (k < W.nbk) bstart[W.bbase + k] = carry + sh[threadIdx.x] - v;
+        if (k < W.nbk) {
+            bmeta[W.bbase + k] = make_uint2((uint32_t)W.doff + carry + sh[threadIdx.x] - v, v);
+            bcount[W.bbase + k] = 0u;
+        }
         carry += sh[kThreads - 1];
         __syncthreads();
     }
@@ -163,14 +156,9 @@ constexpr uint32_t kMaxTieRun = 32; // longer runs of equal states mark the swee
 // order: the staging slots), then every run of equal
 // codes ordered by the previous position (runs are short: states only tie by
 // rounding once the noise has spread them), written with their labels at the
-// item's positions bstart + t; the bucket's count is cleared for the next
-// step.  The result is the order of the stable library sort.
+// item's positions (bmeta).  The result is the order of the stable library sort.
 template <typename T>
-__global__ __launch_bounds__(kSortThreads) void k_cdf_bsort(const WorkItem *__restrict__ items,
-                                                            const int2 *__restrict__ btab,
-                                                            uint32_t *__restrict__ bcount,
-                                                            const uint32_t *__restrict__ bstart,
-                                                            StageView<T> stage,
+__global__ __launch_bounds__(kSortThreads) void k_cdf_bsort(const uint2 *__restrict__ bmeta, StageView<T> stage,
                                                             uint32_t *__restrict__ flag, T *__restrict__ ko,
                                                             uint32_t *__restrict__ lo) {
     using Code = decltype(order_code(T()));
@@ -183,14 +171,11 @@ __global__ __launch_bounds__(kSortThreads) void k_cdf_bsort(const WorkItem *__re
         } post;
     } sh;
     __shared__ Code s_min, s_max; // the bucket's smallest and largest codes
-    if (*flag) return; // the sweep is redone
-    const int2 bt = btab[blockIdx.x];
-    const WorkItem &W = items[bt.x];
-    const int b = W.bbase + bt.y;
-    const uint32_t n = bcount[b];
+    const uint2 meta = bmeta[blockIdx.x]; // (first dense output position, states)
+    if (*flag) return;                     // the sweep is redone
+    const uint32_t dst = meta.x, n = meta.y;
     if (n > (uint32_t)kCdfBucketCap) return; // cannot happen unflagged; keeps LDS indices in range
-    const uint32_t start = bstart[b];
-    const size_t s0 = (size_t)b * kCdfBucketCap; // the bucket's first staging slot
+    const size_t s0 = (size_t)blockIdx.x * kCdfBucketCap; // the bucket's first staging slot
     const T *__restrict__ su = stage.u + s0;
     const uint32_t *__restrict__ sl = stage.lab + s0;
     const uint32_t *__restrict__ sp = stage.pos + s0;
@@ -217,7 +202,6 @@ __global__ __launch_bounds__(kSortThreads) void k_cdf_bsort(const WorkItem *__re
     atomicMin(&s_min, lmin);
     atomicMax(&s_max, lmax);
     __syncthreads();
-    if (threadIdx.x == 0) bcount[b] = 0u; // every thread has read n
     // sort keys: code - min for the states, max - min + 1 for the padding
     // (strictly last), over the bits that hold max - min + 1
     const Code cmin = s_min, span = s_max - s_min;
@@ -262,12 +246,9 @@ __global__ __launch_bounds__(kSortThreads) void k_cdf_bsort(const WorkItem *__re
     }
     __syncthreads();
     for (uint32_t t = threadIdx.x; t < n; t += kSortThreads) {
-        const uint32_t g = start + t;
-        if ((int64_t)g < W.P) {
-            const uint32_t e = sh.post.slot[t];
-            ko[W.doff + g] = su[e];
-            lo[W.doff + g] = sl[e];
-        }
+        const uint32_t e = sh.post.slot[t];
+        ko[dst + t] = su[e];
+        lo[dst + t] = sl[e];
     }
 }
 
@@ -324,7 +305,7 @@ hipError_t launch_cdf_start(int prec, const WorkItem *items, int n_items, const 
                             const CdfBuffers &b, hipStream_t s) {
     const int cover = n_items > b.nbuckets ? n_items : b.nbuckets;
     hipLaunchKernelGGL(k_cdf_setup, dim3((cover + kThreads - 1) / kThreads), dim3(kThreads), 0, s, items, n_items,
-                       b.seg_begin, b.btab, b.bcount, b.nbuckets, b.flag);
+                       b.seg_begin, b.bcount, b.nbuckets, b.flag);
     if (prec == 0)
         hipLaunchKernelGGL(k_cdf_gather<double>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks,
                            (double *)b.keys[0], b.lab[0]);
@@ -339,13 +320,13 @@ hipError_t cdf_scratch_bytes(int prec, uint32_t n, uint32_t nseg, size_t &bytes)
 }
 
 hipError_t launch_cdf_buckets(int prec, const WorkItem *items, int n_items, const CdfBuffers &b, hipStream_t s) {
-    hipLaunchKernelGGL(k_cdf_bscan, dim3(n_items), dim3(kThreads), 0, s, items, b.bcount, b.bstart, b.flag);
+    hipLaunchKernelGGL(k_cdf_bscan, dim3(n_items), dim3(kThreads), 0, s, items, b.bcount, b.bmeta, b.flag);
     if (prec == 0)
-        hipLaunchKernelGGL(k_cdf_bsort<double>, dim3(b.nbuckets), dim3(kSortThreads), 0, s, items, b.btab, b.bcount,
-                           b.bstart, stage_view<double>(b.stage, b.nbuckets), b.flag, (double *)b.keys[1], b.lab[1]);
+        hipLaunchKernelGGL(k_cdf_bsort<double>, dim3(b.nbuckets), dim3(kSortThreads), 0, s, b.bmeta,
+                           stage_view<double>(b.stage, b.nbuckets), b.flag, (double *)b.keys[1], b.lab[1]);
     else
-        hipLaunchKernelGGL(k_cdf_bsort<float>, dim3(b.nbuckets), dim3(kSortThreads), 0, s, items, b.btab, b.bcount,
-                           b.bstart, stage_view<float>(b.stage, b.nbuckets), b.flag, (float *)b.keys[1], b.lab[1]);
+        hipLaunchKernelGGL(k_cdf_bsort<float>, dim3(b.nbuckets), dim3(kSortThreads), 0, s, b.bmeta,
+                           stage_view<float>(b.stage, b.nbuckets), b.flag, (float *)b.keys[1], b.lab[1]);
     return hipGetLastError();
 }
 

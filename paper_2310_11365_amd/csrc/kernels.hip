@@ -695,6 +695,16 @@ __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__r
         int bb[4], loc[4];
         const uint32_t r0 = base + 4u * (uint32_t)g * kThreads; // the round's first position
         const int kc = ((int)(r0 / kCdfBucket) < W.nbk ? (int)(r0 / kCdfBucket) : W.nbk - 1) - kBelow;
+        T vv[4];
+        uint32_t lb[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) { // the round's sorted pairs, loaded before the window's barrier
+            const uint32_t r = r0 + (uint32_t)e * kThreads + threadIdx.x;
+            if (r < P) {
+                vv[e] = S.key(r);
+                lb[e] = S.label(r);
+            }
+        }
         if (mode == 1) {
             if (threadIdx.x <= kWin) {
                 const int k = kc + (int)threadIdx.x;
@@ -711,8 +721,8 @@ __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__r
             d[e] = (T)0;
             bb[e] = -1;
             if (r < P) {
-                const T v = S.key(r);
-                const uint32_t lab = S.label(r);
+                const T v = vv[e];
+                const uint32_t lab = lb[e];
                 int64_t lo = r, hi = r;
                 if (r > 0 && S.key(r - 1) == v) lo = run_end<-1>(S, (int64_t)P, (int64_t)r, v);
                 if (r + 1 < P && S.key(r + 1) == v) hi = run_end<1>(S, (int64_t)P, (int64_t)r, v);

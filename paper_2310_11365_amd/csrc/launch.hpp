@@ -95,10 +95,9 @@ struct CdfBuffers {
     void *tmp;
     size_t tmp_bytes;
     // bucket engine
-    int2 *btab;          // (item, bucket of the item) of every bucket
     int nbuckets;        // buckets of the launch
     uint32_t *bcount;    // states per bucket (zero between steps)
-    uint32_t *bstart;    // first position of each bucket in its item's order
+    uint2 *bmeta;        // per bucket: first dense output position and states (k_cdf_bscan)
     void *stage;         // staging area (stage_view), kCdfBucketCap slots per bucket
     uint32_t *flag;      // nonzero once a bucket overflowed in this sweep
 };
