@@ -177,6 +177,8 @@ mcpr_status check_problem(mcpr_ctx *ctx, const mcpr_problem &p, int idx) {
     const double *c = &p.coef.a0;
     for (int i = 0; i < 14; ++i)
         if (!std::isfinite(c[i])) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: coefficient %d not finite", idx, i);
+    // invalid values first, then combinations the kernels do not support
+    if (p.wrap != 0 && p.wrap != 1) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: wrap must be 0 or 1", idx);
     if (is_cdf(p) && (p.coef.am != 0.0 || p.coef.av != 0.0 || p.coef.axs != 0.0 || p.coef.bm != 0.0 ||
                       p.coef.bv != 0.0 || is_trig(p) || p.wrap != 0 || p.n_regions != 1 ||
                       p.coarse_model != MCPR_COARSE_TAYLOR))
@@ -184,7 +186,6 @@ mcpr_status check_problem(mcpr_ctx *ctx, const mcpr_problem &p, int idx) {
                     "problem %d: the empirical-CDF drift needs one region, the Taylor model and no other "
                     "mean-field coefficient",
                     idx);
-    if (p.wrap != 0 && p.wrap != 1) return fail(ctx, MCPR_E_INVALID_ARG, "problem %d: wrap must be 0 or 1", idx);
     if (is_trig(p) && (p.coef.am != 0.0 || p.coef.av != 0.0 || p.coef.axs != 0.0 || p.coef.bm != 0.0 ||
                        p.coef.bv != 0.0))
         return fail(ctx, MCPR_E_UNSUPPORTED,

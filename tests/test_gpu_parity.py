@@ -770,6 +770,44 @@ def test_invalid_arguments_are_rejected(mc, ctx):
     assert torch.count_nonzero(x) == 0  # nothing launched
 
 
+def test_unsupported_coefficient_mixes_are_rejected(mc, ctx):
+    """The empirical-CDF and trigonometric terms only come with what their
+    kernels and coarse models support: any other mix is MCPR_E_UNSUPPORTED
+    (status -5) before anything is launched; a non-finite coefficient and an
+    out-of-range wrap flag are invalid arguments (status -1)."""
+    import torch
+    x = torch.zeros(1024, dtype=torch.float64, device="cuda")
+    base = W.burgers(P=1024, N=4, T=0.4).problem
+    cases = []
+    for field, value in (("am", 0.5), ("axs", 0.1), ("ksin", -1.0), ("bm", 0.1)):
+        c = mc.problem_c(base)
+        setattr(c.coef, field, value)
+        cases.append((c, -5))
+    c = mc.problem_c(base)
+    c.wrap = 1
+    cases.append((c, -5))
+    c = mc.problem_c(base)
+    c.coarse_model = W.COARSE_GAUSS3
+    cases.append((c, -5))
+    two = W.burgers(P=1024, N=4, T=0.4).problem
+    two.splits = (0.0,)
+    cases.append((mc.problem_c(two), -5))
+    rot = mc.problem_c(W.rotator(P=1024, N=4, T=0.4).problem)
+    rot.coef.am = 0.3
+    cases.append((rot, -5))
+    c = mc.problem_c(base)
+    c.coef.acdf = float("nan")
+    cases.append((c, -1))
+    c = mc.problem_c(base)
+    c.wrap = 2
+    cases.append((c, -1))
+    for i, (c, status) in enumerate(cases):
+        with pytest.raises(mc.MCPRError) as e:
+            ctx.fine_propagate([c], [mc.ensemble(x)])
+        assert e.value.status == status, (i, e.value)
+    assert torch.count_nonzero(x) == 0
+
+
 # ---------------------------------------------------------------------------- adjoint
 def _adj_problem(kind, prec, T=0.2, N=4, dt=1e-2):
     if kind == "ou":
