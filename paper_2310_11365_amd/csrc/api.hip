@@ -60,7 +60,8 @@ struct mcpr_ctx {
     DevBuf cdf_bcount, cdf_bmeta, cdf_stage, cdf_flag;
     mcpr::CdfBuffers cdfb{};
     uint32_t *cdf_flag_host = nullptr; // pinned copy of the overflow flag
-    int cdf_engine = 1;                // 1: bucket engine after a sweep's first step; 0: library sort every step
+    int cdf_engine = 1; // 1: bucket engine after a sweep's first steps; 2: the same, radix sort in every tile;
+                        // 0: library sort every step
     int64_t cdf_sweeps[3] = {0, 0, 0}; // sweeps by the bucket engine, by the library sort, redone
     HostBuf staging;
     hipEvent_t staged = nullptr; // the last upload from staging has completed
@@ -377,9 +378,13 @@ mcpr_status records(mcpr_ctx *ctx, const Tables &t, int prec, int nreg, const mc
 // variant < 0: the first tune_steps steps run the candidate variants in turn,
 // each launch bracketed by events (the autotuner's trial; every variant gives
 // the same bits).
+// j0, j1: only steps [j0, j1) (the empirical-CDF sweep is enqueued in parts);
+// the sums of step 0 come with the first part, the moments and records with
+// the last.
 mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int variant, int m, int nreg,
                          const mcpr::Splits &sp, bool want_stats, bool want_trace, hipStream_t s, bool profile,
-                         int cdf_lib_steps = 0) {
+                         int cdf_lib_steps = 0, int j0 = 0, int j1 = -1) {
+    if (j1 < 0) j1 = m;
     const int n = (int)t.items.size();
     const WorkItem *items = (const WorkItem *)ctx->items.p;
     const int2 *blocks = (const int2 *)ctx->blocks.p;
@@ -390,14 +395,16 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
     const bool trig = t.items[0].trig != 0; // the same for every item of a call
     const bool cdf = t.items[0].cdf != 0;
     const uint32_t ndense = (uint32_t)t.total_dense;
-    if (cdf) HIP_TRY(mcpr::launch_cdf_start(prec, items, n, blocks, nb, ctx->cdfb, s));
-    if (trig)
-        HIP_TRY(mcpr::launch_sum_init_trig(prec, items, blocks, nb, part[0], shift[0], s));
-    else
-        HIP_TRY(mcpr::launch_sum_init(prec, items, blocks, nb, part[0], shift[0], s));
-    if (profile) HIP_TRY(hipEventRecord(ctx->prof0[ctx->prof_used], s));
+    if (j0 == 0) {
+        if (cdf) HIP_TRY(mcpr::launch_cdf_start(prec, items, n, blocks, nb, ctx->cdfb, s));
+        if (trig)
+            HIP_TRY(mcpr::launch_sum_init_trig(prec, items, blocks, nb, part[0], shift[0], s));
+        else
+            HIP_TRY(mcpr::launch_sum_init(prec, items, blocks, nb, part[0], shift[0], s));
+        if (profile) HIP_TRY(hipEventRecord(ctx->prof0[ctx->prof_used], s));
+    }
     double2 *mv = (double2 *)ctx->mv.p;
-    for (int j = 0; j < m; ++j) {
+    for (int j = j0; j < j1; ++j) {
         const int a = j & 1, b = a ^ 1;
         const bool trial = variant < 0 && j < ctx->tune_steps;
         const int v = trial ? ctx->tune_cand[j / (ctx->tune_steps / ctx->tune_nc)]
@@ -422,6 +429,7 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
                                          shift[b], trace, m, s));
         if (trial) HIP_TRY(hipEventRecord(ctx->tune_ev[1][j], s));
     }
+    if (j1 < m) return MCPR_OK;
     if (profile) HIP_TRY(hipEventRecord(ctx->prof1[ctx->prof_used], s));
     if (trace) {
         if (trig)
@@ -501,6 +509,7 @@ mcpr_status ensure_cdf(mcpr_ctx *ctx, const Tables &t, int prec) {
     c.bcount = (uint32_t *)ctx->cdf_bcount.p;
     c.bmeta = (uint2 *)ctx->cdf_bmeta.p;
     c.stage = ctx->cdf_stage.p;
+    c.radix_tiles = ctx->cdf_engine == 2 ? 1 : 0;
     c.flag = (uint32_t *)ctx->cdf_flag.p;
     return MCPR_OK;
 }
@@ -528,11 +537,12 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
         // The empirical-CDF sweep: launched directly (no graph, no variants).
         // With the bucket engine the library sort takes the first two steps
         // (the input may be a point mass, which gives no splitters); the host
-        // reads the overflow flag after the sweep and, if a bucket overflowed
-        // (a law still spreading fast, as in the first steps from a point
-        // mass), redoes the sweep with the library sort on its first 16 steps,
-        // then on all of them.  The particles are untouched until the sweep's
-        // last step, and an overflowed sweep skips its remaining steps.
+        // reads the overflow flag after the first bucket step and after the
+        // sweep and, if a bucket overflowed (a law still spreading fast, as in
+        // the first steps from a point mass), redoes the sweep with the library
+        // sort on its first 8 steps, then 32, then all of them.  The particles
+        // are untouched until the sweep's last step, and the steps of an
+        // overflowed sweep that are already enqueued do nothing.
         size_t slot = 0;
         if (ctx->profile) {
             if (ctx->prof_used == ctx->prof0.size()) {
@@ -545,20 +555,31 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
             }
             slot = ctx->prof_used;
         }
-        const int tries[3] = {2, 16, m};
-        for (int a = ctx->cdf_engine ? 0 : 2; a < 3; ++a) {
+        const int tries[4] = {2, 8, 32, m};
+        for (int a = ctx->cdf_engine ? 0 : 3; a < 4; ++a) {
             const int lib = std::min(tries[a], m);
             // (the profile events of a later attempt replace those of a failed one)
-            if ((st = enqueue_fine(ctx, t, prec, deg, 0, m, nreg, sp, stats != nullptr, trace != nullptr, s,
-                                   ctx->profile, lib)) != MCPR_OK)
-                return st;
             if (lib >= m) {
+                if ((st = enqueue_fine(ctx, t, prec, deg, 0, m, nreg, sp, stats != nullptr, trace != nullptr, s,
+                                       ctx->profile, lib)) != MCPR_OK)
+                    return st;
                 ctx->cdf_sweeps[1]++;
                 break;
             }
-            HIP_TRY(hipMemcpyAsync(ctx->cdf_flag_host, ctx->cdfb.flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            if (*ctx->cdf_flag_host == 0) {
+            const int mid = lib + 1; // through the first bucket step, then the rest
+            bool over = false;
+            for (int part = 0; part < 2 && !over; ++part) {
+                const int j0 = part == 0 ? 0 : mid, j1 = part == 0 ? mid : m;
+                if (j0 >= j1) continue;
+                if ((st = enqueue_fine(ctx, t, prec, deg, 0, m, nreg, sp, stats != nullptr, trace != nullptr, s,
+                                       ctx->profile, lib, j0, j1)) != MCPR_OK)
+                    return st;
+                HIP_TRY(hipMemcpyAsync(ctx->cdf_flag_host, ctx->cdfb.flag, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                       s));
+                HIP_TRY(hipStreamSynchronize(s));
+                over = *ctx->cdf_flag_host != 0;
+            }
+            if (!over) {
                 ctx->cdf_sweeps[0]++;
                 break;
             }
@@ -840,7 +861,7 @@ mcpr_status mcpr_graph_stats(const mcpr_ctx *ctx, int64_t *builds, int64_t *laun
 }
 
 mcpr_status mcpr_set_cdf_sort(mcpr_ctx *ctx, int32_t mode) {
-    if (!ctx || mode < 0 || mode > 1) return MCPR_E_INVALID_ARG;
+    if (!ctx || mode < 0 || mode > 2) return MCPR_E_INVALID_ARG;
     ctx->cdf_engine = mode;
     return MCPR_OK;
 }

@@ -652,8 +652,8 @@ __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__r
     // order) fall into buckets near the one of their first position; kWin
     // buckets around it are counted in LDS, reserved with one atomic each,
     // and the states grouped by bucket in LDS and copied out coalesced
-    constexpr int kWin = 64, kBelow = 32, kRound = 4 * kThreads;
-    static_assert(kWin == 64, "one wave scans the window");
+    constexpr int kWin = 128, kBelow = 64, kRound = 4 * kThreads;
+    static_assert(kWin == 2 * 64 && kWin <= kThreads, "one wave scans the window, two buckets per lane");
     __shared__ double lds[8];
     __shared__ uint32_t hist[kWin], hbase[kWin], lstart[kWin + 1];
     __shared__ T spl[kWin + 1]; // the window's splitters (-inf below bucket 1, +inf past the item)
@@ -695,15 +695,20 @@ __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__r
         int bb[4], loc[4];
         const uint32_t r0 = base + 4u * (uint32_t)g * kThreads; // the round's first position
         const int kc = ((int)(r0 / kCdfBucket) < W.nbk ? (int)(r0 / kCdfBucket) : W.nbk - 1) - kBelow;
-        T vv[4];
+        T vv[4], kb[4], ka[4];
         uint32_t lb[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) { // the round's sorted pairs, loaded before the window's barrier
+        for (int e = 0; e < 4; ++e) {
+            // the round's sorted pairs and their neighbours' keys, loaded
+            // before the window's barrier; positions clamped into [0, P) so
+            // that every load issues without a branch (the values of clamped
+            // positions are not used)
             const uint32_t r = r0 + (uint32_t)e * kThreads + threadIdx.x;
-            if (r < P) {
-                vv[e] = S.key(r);
-                lb[e] = S.label(r);
-            }
+            const uint32_t rc = r < P ? r : P - 1u;
+            vv[e] = S.key(rc);
+            lb[e] = S.label(rc);
+            kb[e] = S.key(rc > 0u ? rc - 1u : 0u);
+            ka[e] = S.key(rc + 1u < P ? rc + 1u : rc);
         }
         if (mode == 1) {
             if (threadIdx.x <= kWin) {
@@ -724,8 +729,8 @@ __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__r
                 const T v = vv[e];
                 const uint32_t lab = lb[e];
                 int64_t lo = r, hi = r;
-                if (r > 0 && S.key(r - 1) == v) lo = run_end<-1>(S, (int64_t)P, (int64_t)r, v);
-                if (r + 1 < P && S.key(r + 1) == v) hi = run_end<1>(S, (int64_t)P, (int64_t)r, v);
+                if (r > 0 && kb[e] == v) lo = run_end<-1>(S, (int64_t)P, (int64_t)r, v);
+                if (r + 1 < P && ka[e] == v) hi = run_end<1>(S, (int64_t)P, (int64_t)r, v);
                 const T cnt = (T)((double)lo + 0.5 * (double)(hi - lo + 1));
                 const uint32_t p = lab - (uint32_t)W.doff;
                 const Words4 w = philox4x32_10((uint32_t)(p >> 2), step, inst, 0u, W.key0, W.key1);
@@ -743,7 +748,7 @@ __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__r
                     // the item's splitters from the state's old bucket
                     int w = 0;
 #pragma unroll
-                    for (int step = 32; step > 0; step >>= 1)
+                    for (int step = kWin / 2; step > 0; step >>= 1)
                         if (spl[w + step] <= u) w += step;
                     if (spl[kWin] <= u) w = kWin;
                     if (spl[0] <= u && w < kWin) {
@@ -769,18 +774,22 @@ __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__r
                 if (bb[e] >= 0 && bb[e] - kc >= 0 && bb[e] - kc < kWin) loc[e] = (int)atomicAdd(&hist[bb[e] - kc], 1u);
             }
             __syncthreads();
-            if (threadIdx.x < kWin) { // wave 0: offsets in the round, slots in the buckets
-                const uint32_t h = hist[threadIdx.x];
+            if (threadIdx.x < kWin / 2) { // wave 0: offsets in the round, slots in the buckets
+                const int k = 2 * (int)threadIdx.x; // this lane's buckets k, k + 1
+                const uint32_t h0 = hist[k], h1 = hist[k + 1], h = h0 + h1;
                 uint32_t incl = h;
 #pragma unroll
-                for (int off = 1; off < kWin; off <<= 1) {
+                for (int off = 1; off < kWin / 2; off <<= 1) {
                     const uint32_t v = (uint32_t)__shfl_up((int)incl, off);
                     if ((int)threadIdx.x >= off) incl += v;
                 }
-                lstart[threadIdx.x] = incl - h;
-                if (threadIdx.x == kWin - 1) lstart[kWin] = incl;
-                hbase[threadIdx.x] = h != 0u ? atomicAdd(&bcount[W.bbase + kc + (int)threadIdx.x], h) : 0u;
-                hist[threadIdx.x] = 0u; // for the next round
+                lstart[k] = incl - h;
+                lstart[k + 1] = incl - h1;
+                if (k + 2 == kWin) lstart[kWin] = incl;
+                hbase[k] = h0 != 0u ? atomicAdd(&bcount[W.bbase + kc + k], h0) : 0u;
+                hbase[k + 1] = h1 != 0u ? atomicAdd(&bcount[W.bbase + kc + k + 1], h1) : 0u;
+                hist[k] = 0u; // for the next round
+                hist[k + 1] = 0u;
             }
             __syncthreads();
 #pragma unroll

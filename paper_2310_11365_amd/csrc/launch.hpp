@@ -66,9 +66,14 @@ struct KeyLabel {
 // library sort).  The staging area holds, per bucket slot, the state, its
 // label, and its position in the previous step's order (the tie-breaker that
 // makes the order equal to the stable library sort's), as three arrays.
-constexpr int kCdfBucket = 2048;
+// The stride leaves room for the count of a bucket to drift by a few
+// standard deviations while the law changes from step to step, so that
+// nearly every bucket fits the bucket sort's smaller tile (kCdfTileSmall).
+constexpr int kCdfBucket = 1792;
 constexpr int kCdfBucketCap = 4096;
-static_assert(kCdfBucket == 2048 && kCdfBucketCap == 4096, "the step kernel indexes buckets by shifts");
+constexpr int kCdfTileSmall = 2048;
+static_assert(kCdfBucketCap == 4096, "the step kernel indexes staging slots by shifts");
+static_assert(kCdfBucket < kCdfTileSmall && kCdfTileSmall < kCdfBucketCap, "tile sizes");
 template <typename T>
 struct StageView {
     T *u;
@@ -99,6 +104,7 @@ struct CdfBuffers {
     uint32_t *bcount;    // states per bucket (zero between steps)
     uint2 *bmeta;        // per bucket: first dense output position and states (k_cdf_bscan)
     void *stage;         // staging area (stage_view), kCdfBucketCap slots per bucket
+    int radix_tiles;     // nonzero: every bucket by the block radix sort (no one-pass bins)
     uint32_t *flag;      // nonzero once a bucket overflowed in this sweep
 };
 // Once per fine sweep: the dense first position of every item; the states and

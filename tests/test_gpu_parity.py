@@ -250,17 +250,19 @@ def _burgers_spread(P, N, T, precision, sd=1.0):
 
 @pytest.mark.parametrize("prec", [W.FP64, W.FP32])
 def test_burgers_bucket_sort_equals_radix_sort_bitwise(mc, prec):
-    """The bucket engine (steps after a sweep's first) gives bit for bit what
-    the radix sort on every step gives: ensembles of 70 001 (four quads per
-    thread), 3 000, 2 048, 1 and 10 007 particles from a spread start in one
-    call, every state and the per-step trace; no sweep is redone."""
+    """The bucket engine (steps after a sweep's first two), with the one-pass
+    bins in the buckets that suit them and with the block radix sort in every
+    bucket, gives bit for bit what the radix sort on every step gives:
+    ensembles of 70 001 (four quads per thread), 3 000, 2 048, 1 and 10 007
+    particles from a spread start in one call, every state and the per-step
+    trace; no sweep is redone."""
     import torch
     pr = _burgers_spread(1, 4, 0.4, prec)
     pc = mc.problem_c(pr)
     sizes = [70_001, 3_000, 2_048, 1, 10_007]
     dt = torch.float64 if prec == W.FP64 else torch.float32
     runs = []
-    for engine in (1, 0):
+    for engine in (1, 2, 0):
         c = mc.Context(0)
         c.set_cdf_sort(engine)
         xs = [torch.empty(P, dtype=dt, device="cuda") for P in sizes]
@@ -272,28 +274,57 @@ def test_burgers_bucket_sort_equals_radix_sort_bitwise(mc, prec):
         torch.cuda.synchronize()
         runs.append(([x.clone() for x in xs], tr.clone(), buf.clone(), c.cdf_stats()))
         c.close()
-    (xb, tb, sb, stb), (xl, tl, sl, stl) = runs
-    assert stb == (2, 0, 0) and stl == (0, 2, 0), (stb, stl)
-    for a, b in zip(xb, xl):
+    (xl, tl, sl, stl) = runs[-1]
+    assert stl == (0, 2, 0), stl
+    for xb, tb, sb, stb in runs[:-1]:
+        assert stb == (2, 0, 0), stb
+        for a, b in zip(xb, xl):
+            assert torch.equal(a, b)
+        assert torch.equal(tb, tl) and torch.equal(sb, sl)
+
+
+def test_burgers_bucket_with_far_outliers_bitwise(mc):
+    """A law with a far component (0.1 % of the particles near 1000): the top
+    bucket of each ensemble spans the gap, so its states crowd a few of the
+    one-pass bins and it takes the block radix sort; the result is still bit
+    for bit the radix sort's on every step."""
+    import torch
+    pr = W.make_problem(W.Coef(acdf=1.0, b0=1.0), W.P0(W.P0_MIXTURE, 0.999, 0.0, 1.0, 1000.0, 1.0), 0.4, 4, 1e-3,
+                        (), 0, 0.05, W.FP32)
+    pc = mc.problem_c(pr)
+    sizes = [20_011, 5_003]
+    runs = []
+    for engine in (1, 0):
+        c = mc.Context(0)
+        c.set_cdf_sort(engine)
+        xs = [torch.empty(P, dtype=torch.float32, device="cuda") for P in sizes]
+        c.init_particles([pc], [mc.ensemble(x, i) for i, x in enumerate(xs)])
+        assert all(float(x.max()) > 900.0 for x in xs)
+        for n in range(2):
+            c.fine_propagate([pc], [mc.ensemble(x, i, n) for i, x in enumerate(xs)], None, None)
+        torch.cuda.synchronize()
+        runs.append(([x.clone() for x in xs], c.cdf_stats()))
+        c.close()
+    assert runs[0][1] == (2, 0, 0) and runs[1][1] == (0, 2, 0), (runs[0][1], runs[1][1])
+    for a, b in zip(runs[0][0], runs[1][0]):
         assert torch.equal(a, b)
-    assert torch.equal(tb, tl) and torch.equal(sb, sl)
 
 
 def test_burgers_bucket_overflow_redoes_the_sweep(mc, oracle):
     """Without noise a point mass stays one (every state ties at every step):
     the sorted states give no splitters, a bucket overflows with the library
-    sort on the first 2 steps and on the first 16, and the sweep ends up
-    sorted by the library alone.  From a point mass with noise (P = 2e5) the
-    law spreads fast at first: the edge buckets overflow with 2 library steps
-    (the variance doubles over the first bucket step) but not with 16.  The
-    particles match the oracle either way."""
+    sort on the first 2 steps, on the first 8 and on the first 32, and the
+    sweep ends up sorted by the library alone.  From a point mass with noise
+    (P = 2e5) the law spreads fast at first: the edge buckets overflow with 2
+    library steps (the variance doubles over the first bucket step) but not
+    with 8.  The particles match the oracle either way."""
     c = mc.Context(0)
     pr = W.make_problem(W.Coef(acdf=1.0), W.P0(W.P0_DELTA, 1.0, 0.0, 0.0), 1.0, 10, 1e-3, (), 0, 0.05, W.FP64)
     prop = mc.Propagator(pr, c)
     x = prop.new_particles(20_000)
     prop.sample(x)
     prop.fine([x], [0])
-    assert c.cdf_stats() == (0, 1, 2)
+    assert c.cdf_stats() == (0, 1, 3)
     ox, _ = oracle.fine(pr, oracle.sample_p0(pr, 20_000), 0)
     assert np.max(np.abs(x.cpu().numpy() - ox)) < 1e-11
     wl = W.burgers(P=200_000, N=10, T=1.0)
@@ -301,7 +332,7 @@ def test_burgers_bucket_overflow_redoes_the_sweep(mc, oracle):
     x = prop.new_particles(wl.P)
     prop.sample(x)
     prop.fine([x], [0])
-    assert c.cdf_stats() == (1, 1, 3)
+    assert c.cdf_stats() == (1, 1, 4)
     ox, _ = oracle.fine(wl.problem, oracle.sample_p0(wl.problem, wl.P), 0)
     assert np.max(np.abs(x.cpu().numpy() - ox)) < 1e-11
     c.close()
