@@ -204,16 +204,14 @@ mcpr_status mcpr_graph_stats(const mcpr_ctx *ctx, int64_t *builds, int64_t *laun
  * each ensemble in ascending order).  mode 1 (default): the first two steps
  * of a fine sweep sort with a device-wide radix sort, later steps put the new
  * states into buckets between the previous step's sorted states (1792 apart
- * on average) and sort each bucket on chip (a bucket of up to 2048 states by
- * one counting pass over bins linear in the state, else, and where the bins
- * do not suit it, by a block radix sort).  A bucket beyond 4096 states (a
+ * on average) and sort each bucket on chip (a block radix sort in a tile of
+ * 2048 states, or of 4096 for a larger bucket).  A bucket beyond 4096 states (a
  * law still spreading fast, as in the first steps from a point mass; a point
  * mass without noise) makes the sweep run again with the radix sort on its
  * first 8 steps, then 32, then all of them; the overflow flag is read after
  * the first bucket step and at the end of the sweep.  A call with this drift
  * synchronises its stream (to read the flag).
- * mode 2: as mode 1 with the block radix sort in every bucket.  mode 0: the
- * device-wide radix sort on every step.  All give the same bits.
+ * mode 0: the device-wide radix sort on every step.  Both give the same bits.
  * mcpr_cdf_stats: sweeps done by the buckets, by the radix sort alone, and
  * sweeps redone after an overflow, so far (any pointer may be NULL).        */
 mcpr_status mcpr_set_cdf_sort(mcpr_ctx *ctx, int32_t mode);

@@ -60,8 +60,7 @@ struct mcpr_ctx {
     DevBuf cdf_bcount, cdf_bmeta, cdf_stage, cdf_flag;
     mcpr::CdfBuffers cdfb{};
     uint32_t *cdf_flag_host = nullptr; // pinned copy of the overflow flag
-    int cdf_engine = 1; // 1: bucket engine after a sweep's first steps; 2: the same, radix sort in every tile;
-                        // 0: library sort every step
+    int cdf_engine = 1;                // 1: bucket engine after a sweep's first steps; 0: library sort every step
     int64_t cdf_sweeps[3] = {0, 0, 0}; // sweeps by the bucket engine, by the library sort, redone
     HostBuf staging;
     hipEvent_t staged = nullptr; // the last upload from staging has completed
@@ -509,7 +508,6 @@ mcpr_status ensure_cdf(mcpr_ctx *ctx, const Tables &t, int prec) {
     c.bcount = (uint32_t *)ctx->cdf_bcount.p;
     c.bmeta = (uint2 *)ctx->cdf_bmeta.p;
     c.stage = ctx->cdf_stage.p;
-    c.radix_tiles = ctx->cdf_engine == 2 ? 1 : 0;
     c.flag = (uint32_t *)ctx->cdf_flag.p;
     return MCPR_OK;
 }
@@ -861,7 +859,7 @@ mcpr_status mcpr_graph_stats(const mcpr_ctx *ctx, int64_t *builds, int64_t *laun
 }
 
 mcpr_status mcpr_set_cdf_sort(mcpr_ctx *ctx, int32_t mode) {
-    if (!ctx || mode < 0 || mode > 2) return MCPR_E_INVALID_ARG;
+    if (!ctx || mode < 0 || mode > 1) return MCPR_E_INVALID_ARG;
     ctx->cdf_engine = mode;
     return MCPR_OK;
 }

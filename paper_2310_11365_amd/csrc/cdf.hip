@@ -37,10 +37,9 @@
 // steps then do nothing and leave the particles untouched, and the host
 // redoes the sweep with the library sort on its first 8 steps, then 32, then
 // all of them.  Each bucket is sorted in a tile of kCdfTileSmall states when
-// it fits, else of kCdfBucketCap.
+// it fits, else of kCdfBucketCap (measured against one counting pass over
+// bins linear in the state: no faster here, so not kept).
 #include <cstring>
-#include <limits>
-#include <type_traits>
 
 #include <hip/hip_runtime.h>
 #include <rocprim/block/block_radix_sort.hpp>
@@ -150,78 +149,63 @@ __device__ __forceinline__ uint64_t order_code(double u) {
     return b ^ ((b >> 63) ? 0xffffffffffffffffull : 0x8000000000000000ull);
 }
 
-// The state of an order code (the inverse of order_code, -0 aside).
-__device__ __forceinline__ float state_of(uint32_t c) { return __uint_as_float((c >> 31) ? c ^ 0x80000000u : ~c); }
-__device__ __forceinline__ double state_of(uint64_t c) {
-    return __longlong_as_double((long long)((c >> 63) ? c ^ 0x8000000000000000ull : ~c));
-}
-
 constexpr int kSortThreads = 256;
 constexpr uint32_t kMaxTieRun = 32; // longer runs of equal states mark the sweep (redone by the library)
 
 template <typename T, int ITEMS>
 using BucketSorter = rocprim::block_radix_sort<decltype(order_code(T())), kSortThreads, ITEMS, uint32_t>;
 
-// LDS of the bucket sort, smaller tile: the bucket's states, labels and
-// previous positions by staging slot from the start; then either the bins
-// (counts, then starts, 16 bits each; the slots in sorted order) or the
-// block radix sort's storage and, in its place, the sorted slots.
-constexpr int kBins = kCdfTileSmall;   // bins of the one-pass sort, linear in the state
-constexpr uint32_t kMaxBin = 32;       // a fuller bin sends the bucket to the radix sort
+// LDS of the bucket sort: the block radix sort's storage for either tile,
+// then the sorted codes and staging slots; the bucket's smallest and largest
+// codes before the sort.
 template <typename T>
-struct SmallTileShared {
-    T u[kCdfTileSmall];
-    uint32_t lab[kCdfTileSmall], pos[kCdfTileSmall];
-    union {
-        struct {
-            uint32_t cnt[kBins / 2];
-            uint32_t order[kCdfTileSmall];
-        } bins;
-        typename BucketSorter<T, kCdfTileSmall / kSortThreads>::storage_type sort;
-        uint32_t slot[kCdfTileSmall];
-    } s;
-    decltype(order_code(T())) range[2]; // the bucket's smallest and largest codes
-    uint32_t wsum[kSortThreads / 64];
-    uint32_t full; // a bin above kMaxBin
-};
-// Full tile: the block radix sort's storage, then the sorted codes and slots.
-template <typename T>
-union FullTileShared {
-    decltype(order_code(T())) range[2]; // the bucket's smallest and largest codes (before the sort)
-    typename BucketSorter<T, kCdfBucketCap / kSortThreads>::storage_type sort;
+union BucketShared {
+    using Code = decltype(order_code(T()));
+    Code range[2];
+    typename BucketSorter<T, kCdfTileSmall / kSortThreads>::storage_type small;
+    typename BucketSorter<T, kCdfBucketCap / kSortThreads>::storage_type large;
     struct {
-        decltype(order_code(T())) code[kCdfBucketCap];
+        Code code[kCdfBucketCap];
         uint32_t slot[kCdfBucketCap];
     } post;
 };
 
-// Stable block radix sort of the keys (order codes of the bucket's states,
-// blocked by thread in stripes: element k of thread t is staging slot
-// k * kSortThreads + t) with their slots as values, over the bits in which
-// the bucket's codes differ: code - min for the states, max - min + 1 for the
-// padding (strictly last).  On return thread t holds ranks k * kSortThreads
-// + t.  False (the sweep marked) when no key is left above the largest code.
-template <typename T, int ITEMS, typename Storage, typename Code>
-__device__ __forceinline__ bool sort_codes(Storage &st, Code (&keys)[ITEMS], uint32_t (&vals)[ITEMS], Code *range,
-                                           uint32_t n, uint32_t *__restrict__ flag) {
+// The n <= ITEMS * kSortThreads staged states of one bucket sorted by order
+// code with a stable block radix sort over the bits in which the bucket's
+// codes differ: code - min for the states, max - min + 1 for the padding
+// (strictly last); the input order (the staging slots) only decides the
+// order of equal codes, which the tie pass then sets: every run of equal
+// codes ordered by the previous position (runs are short: states only tie by
+// rounding once the noise has spread them; a run longer than kMaxTieRun
+// marks the sweep).  Written with their labels from dst on.
+template <typename T, int ITEMS, typename Storage>
+__device__ __forceinline__ void sort_bucket(Storage &st, BucketShared<T> &sh, uint32_t n, uint32_t dst,
+                                            const T *__restrict__ su, const uint32_t *__restrict__ sl,
+                                            const uint32_t *__restrict__ sp, uint32_t *__restrict__ flag,
+                                            T *__restrict__ ko, uint32_t *__restrict__ lo) {
+    using Code = decltype(order_code(T()));
+    Code keys[ITEMS];
+    uint32_t vals[ITEMS];
     Code lmin = ~(Code)0, lmax = 0;
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
+        // striped, coalesced loads without a branch (every slot below
+        // kCdfBucketCap is the bucket's own; those at or past n are not used)
         const uint32_t t = k * kSortThreads + threadIdx.x;
+        const T a = su[t];
+        keys[k] = order_code(a);
         vals[k] = t;
-        if (t < n) {
-            lmin = keys[k] < lmin ? keys[k] : lmin;
-            lmax = keys[k] > lmax ? keys[k] : lmax;
-        }
+        lmin = t < n && keys[k] < lmin ? keys[k] : lmin;
+        lmax = t < n && keys[k] > lmax ? keys[k] : lmax;
     }
-    atomicMin(&range[0], lmin);
-    atomicMax(&range[1], lmax);
+    atomicMin(&sh.range[0], lmin);
+    atomicMax(&sh.range[1], lmax);
     __syncthreads();
-    const Code cmin = range[0], span = range[1] - range[0];
+    const Code cmin = sh.range[0], span = sh.range[1] - sh.range[0];
     __syncthreads(); // (the sort storage overlays the range)
     if (n > 0 && span == ~(Code)0) { // no room above the largest key (a bucket across the whole range)
         if (threadIdx.x == 0) *flag = 1u;
-        return false;
+        return;
     }
     const Code pad = span + 1;
 #pragma unroll
@@ -231,213 +215,7 @@ __device__ __forceinline__ bool sort_codes(Storage &st, Code (&keys)[ITEMS], uin
     }
     unsigned nbits = 0;
     for (Code d = pad; d != 0; d >>= 1) ++nbits;
-    BucketSorter<T, ITEMS>().sort_to_striped(keys, vals, st, 0u, nbits);
-    return true;
-}
-
-// Every run of equal codes among the n sorted ranks (runs are short: states
-// only tie by rounding once the noise has spread them) put in the order of
-// the previous position, pos_of(slot); a run longer than kMaxTieRun marks
-// the sweep.  code_at(i): the code at rank i (while runs are reordered, any
-// slot of a run gives the run's code).
-template <typename CodeAt, typename PosOf>
-__device__ __forceinline__ void order_ties(CodeAt code_at, uint32_t *slots, uint32_t n, PosOf pos_of,
-                                           uint32_t *__restrict__ flag) {
-    for (uint32_t i = threadIdx.x; i + 1 < n; i += kSortThreads) {
-        const auto c = code_at(i);
-        if (code_at(i + 1) != c || (i > 0 && code_at(i - 1) == c)) continue;
-        uint32_t e = i + 1; // the run [i, e]
-        while (e + 1 < n && code_at(e + 1) == c && e - i < kMaxTieRun) ++e;
-        if (e - i >= kMaxTieRun) {
-            *flag = 1u;
-            continue;
-        }
-        for (uint32_t a = i + 1; a <= e; ++a) { // insertion sort of the run by previous position
-            const uint32_t s = slots[a], ps = pos_of(s);
-            uint32_t q = a;
-            while (q > i && pos_of(slots[q - 1]) > ps) {
-                slots[q] = slots[q - 1];
-                --q;
-            }
-            slots[q] = s;
-        }
-    }
-}
-
-// A bucket of up to kCdfTileSmall states.  States, labels and previous
-// positions are read once, coalesced, into LDS.  The states of a bucket lie
-// in a short interval, nearly uniformly: one counting pass over kBins bins
-// linear in the state (bin = (u - min) * kBins / (max - min), rounded down:
-// nondecreasing in u, equal for equal states) places them, and each bin
-// (about one state) is ordered by (order code, previous position) by
-// insertion.  A bucket whose range is empty or not finite, or with a bin
-// above kMaxBin, takes the block radix sort and the tie pass instead (every
-// bucket does when radix is set).
-template <typename T>
-__device__ __forceinline__ void sort_bucket_small(SmallTileShared<T> &sh, uint32_t n, uint32_t dst,
-                                                  const T *__restrict__ su, const uint32_t *__restrict__ sl,
-                                                  const uint32_t *__restrict__ sp, bool radix, uint32_t *__restrict__ flag,
-                                                  T *__restrict__ ko, uint32_t *__restrict__ lo) {
-    using Code = decltype(order_code(T()));
-    constexpr int ITEMS = kCdfTileSmall / kSortThreads, WAVES = kSortThreads / 64;
-    // (every load and LDS store without a branch, so that they issue
-    // together: slots n .. kCdfTileSmall - 1 lie inside the bucket's staging
-    // slots too, and their values are never used)
-    T uv[ITEMS];
-    Code lmin = ~(Code)0, lmax = 0;
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t t = k * kSortThreads + threadIdx.x;
-        const T a = su[t];
-        const uint32_t l = sl[t], q = sp[t];
-        sh.u[t] = a;
-        sh.lab[t] = l;
-        sh.pos[t] = q;
-        const bool in = t < n;
-        uv[k] = in ? a : (T)0;
-        const Code c = order_code(uv[k]);
-        lmin = in && c < lmin ? c : lmin;
-        lmax = in && c > lmax ? c : lmax;
-    }
-    for (int i = threadIdx.x; i < kBins / 2; i += kSortThreads) sh.s.bins.cnt[i] = 0u;
-    if (threadIdx.x == 0) sh.full = 0u;
-    atomicMin(&sh.range[0], lmin);
-    atomicMax(&sh.range[1], lmax);
-    __syncthreads();
-    const T umin = state_of(sh.range[0]), width = state_of(sh.range[1]) - umin;
-    const T scale = (T)kBins / width;
-    // (the same for every thread: the block takes one path)
-    const bool linear = !radix && n > 0 && width > (T)0 && scale > (T)0 && scale <= std::numeric_limits<T>::max();
-    if (linear) {
-        // counting pass: each state's bin and its place among the bin's states
-        uint32_t loc[ITEMS];
-        int bin[ITEMS];
-#pragma unroll
-        for (int k = 0; k < ITEMS; ++k) { // (padding slots add 0 to bin 0)
-            const uint32_t t = k * kSortThreads + threadIdx.x;
-            const bool in = t < n;
-            const T f = in ? (uv[k] - umin) * scale : (T)0; // in [0, kBins], up to rounding
-            const int b = f < (T)(kBins - 1) ? (int)f : kBins - 1;
-            const uint32_t sh16 = 16u * (uint32_t)(b & 1);
-            loc[k] = (atomicAdd(&sh.s.bins.cnt[b >> 1], in ? 1u << sh16 : 0u) >> sh16) & 0xffffu;
-            bin[k] = in ? b : -1;
-        }
-        __syncthreads();
-        // bin starts: thread t owns bins 8t .. 8t + 7 (block exclusive scan)
-        uint32_t c[8], st[8], sum = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint32_t w = sh.s.bins.cnt[4 * threadIdx.x + i];
-            c[2 * i] = w & 0xffffu;
-            c[2 * i + 1] = w >> 16;
-        }
-        bool full = false;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            sum += c[i];
-            full |= c[i] > kMaxBin;
-        }
-        if (full) sh.full = 1u;
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        uint32_t incl = sum;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t v = (uint32_t)__shfl_up((int)incl, off);
-            if (lane >= off) incl += v;
-        }
-        if (lane == 63) sh.wsum[wave] = incl;
-        __syncthreads();
-        uint32_t run = incl - sum;
-        for (int w = 0; w < wave; ++w) run += sh.wsum[w];
-        const uint32_t end = run + sum; // the end of this thread's last bin
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            st[i] = run;
-            run += c[i];
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) sh.s.bins.cnt[4 * threadIdx.x + i] = st[2 * i] | (st[2 * i + 1] << 16);
-        __syncthreads();
-        if (!sh.full) {
-            uint32_t at[ITEMS];
-#pragma unroll
-            for (int k = 0; k < ITEMS; ++k) { // the starts read first, together
-                const int b = bin[k] < 0 ? 0 : bin[k];
-                const uint32_t sh16 = 16u * (uint32_t)(b & 1);
-                at[k] = ((sh.s.bins.cnt[b >> 1] >> sh16) & 0xffffu) + loc[k];
-            }
-#pragma unroll
-            for (int k = 0; k < ITEMS; ++k)
-                if (bin[k] >= 0) sh.s.bins.order[at[k]] = k * kSortThreads + threadIdx.x;
-            __syncthreads();
-            uint32_t *ord = sh.s.bins.order;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) { // insertion sort of each of this thread's bins
-                const uint32_t b0 = st[i], b1 = i < 7 ? st[i + 1] : end;
-                for (uint32_t a = b0 + 1; a < b1; ++a) {
-                    const uint32_t s = ord[a], ps = sh.pos[s];
-                    const Code cs = order_code(sh.u[s]);
-                    uint32_t q = a;
-                    while (q > b0) {
-                        const uint32_t r = ord[q - 1];
-                        const Code cr = order_code(sh.u[r]);
-                        if (cr < cs || (cr == cs && sh.pos[r] < ps)) break;
-                        ord[q] = r;
-                        --q;
-                    }
-                    ord[q] = s;
-                }
-            }
-            __syncthreads();
-            for (uint32_t t = threadIdx.x; t < n; t += kSortThreads) {
-                const uint32_t e = ord[t];
-                ko[dst + t] = sh.u[e];
-                lo[dst + t] = sh.lab[e];
-            }
-            return;
-        }
-    }
-    // the block radix sort over the bits of the codes' span, then the tie pass
-    uint32_t vals[ITEMS];
-    Code keys[ITEMS];
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) keys[k] = order_code(uv[k]);
-    if (!sort_codes<T, ITEMS>(sh.s.sort, keys, vals, sh.range, n, flag)) return;
-    __syncthreads(); // the sort storage is free: the sorted slots in its place
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) sh.s.slot[k * kSortThreads + threadIdx.x] = vals[k];
-    __syncthreads();
-    const T *ut = sh.u;
-    const uint32_t *pt = sh.pos, *st = sh.s.slot;
-    order_ties([ut, st](uint32_t i) { return order_code(ut[st[i]]); }, sh.s.slot, n,
-               [pt](uint32_t q) { return pt[q]; }, flag);
-    __syncthreads();
-    for (uint32_t t = threadIdx.x; t < n; t += kSortThreads) {
-        const uint32_t e = sh.s.slot[t];
-        ko[dst + t] = sh.u[e];
-        lo[dst + t] = sh.lab[e];
-    }
-}
-
-// A bucket of up to kCdfBucketCap states: the states read for the sort, the
-// previous positions (ties only) and the output gathered from the staging
-// area.
-template <typename T>
-__device__ __forceinline__ void sort_bucket_large(FullTileShared<T> &sh, uint32_t n, uint32_t dst,
-                                                  const T *__restrict__ su, const uint32_t *__restrict__ sl,
-                                                  const uint32_t *__restrict__ sp, uint32_t *__restrict__ flag,
-                                                  T *__restrict__ ko, uint32_t *__restrict__ lo) {
-    using Code = decltype(order_code(T()));
-    constexpr int ITEMS = kCdfBucketCap / kSortThreads;
-    Code keys[ITEMS];
-    uint32_t vals[ITEMS];
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) { // (every slot below kCdfBucketCap is the bucket's: loads without a branch)
-        const uint32_t t = k * kSortThreads + threadIdx.x;
-        const T a = su[t];
-        keys[k] = t < n ? order_code(a) : (Code)0;
-    }
-    if (!sort_codes<T, ITEMS>(sh.sort, keys, vals, sh.range, n, flag)) return;
+    BucketSorter<T, ITEMS>().sort_to_striped(keys, vals, st, 0u, nbits); // rank k * kSortThreads + t in thread t
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
@@ -445,8 +223,25 @@ __device__ __forceinline__ void sort_bucket_large(FullTileShared<T> &sh, uint32_
         sh.post.slot[k * kSortThreads + threadIdx.x] = vals[k];
     }
     __syncthreads();
-    const Code *ct = sh.post.code;
-    order_ties([ct](uint32_t i) { return ct[i]; }, sh.post.slot, n, [sp](uint32_t q) { return sp[q]; }, flag);
+    for (uint32_t i = threadIdx.x; i + 1 < n; i += kSortThreads) {
+        const Code c = sh.post.code[i];
+        if (sh.post.code[i + 1] != c || (i > 0 && sh.post.code[i - 1] == c)) continue;
+        uint32_t e = i + 1; // the run [i, e]
+        while (e + 1 < n && sh.post.code[e + 1] == c && e - i < kMaxTieRun) ++e;
+        if (e - i >= kMaxTieRun) {
+            *flag = 1u;
+            continue;
+        }
+        for (uint32_t a = i + 1; a <= e; ++a) { // insertion sort of the run by previous position
+            const uint32_t s = sh.post.slot[a], ps = sp[s];
+            uint32_t q = a;
+            while (q > i && sp[sh.post.slot[q - 1]] > ps) {
+                sh.post.slot[q] = sh.post.slot[q - 1];
+                --q;
+            }
+            sh.post.slot[q] = s;
+        }
+    }
     __syncthreads();
     for (uint32_t t = threadIdx.x; t < n; t += kSortThreads) {
         const uint32_t e = sh.post.slot[t];
@@ -455,37 +250,32 @@ __device__ __forceinline__ void sort_bucket_large(FullTileShared<T> &sh, uint32_
     }
 }
 
-// One bucket per block: its staged states sorted by order code with a stable
-// block radix sort (input order: the staging slots; the input order only
-// decides the order of equal codes, which the tie pass then sets), every run
-// of equal codes ordered by the previous position, written with their labels
-// at the item's positions (bmeta).  The result is the order of the stable
-// library sort.  Two kernels, each over every bucket, sort the buckets that
-// fit the smaller tile (nearly all: the bucket stride leaves that margin)
-// and the others; each has the registers and LDS of its own tile.
-template <typename T, bool SMALL>
+// One bucket per block, sorted in the smaller tile when it fits (nearly
+// always: the bucket stride leaves that margin), else in the full one; the
+// result is the order of the stable library sort, at the item's positions
+// (bmeta).
+template <typename T>
 __global__ __launch_bounds__(kSortThreads) void k_cdf_bsort(const uint2 *__restrict__ bmeta, StageView<T> stage,
-                                                            int radix, uint32_t *__restrict__ flag,
-                                                            T *__restrict__ ko, uint32_t *__restrict__ lo) {
+                                                            uint32_t *__restrict__ flag, T *__restrict__ ko,
+                                                            uint32_t *__restrict__ lo) {
     using Code = decltype(order_code(T()));
-    using Shared = typename std::conditional<SMALL, SmallTileShared<T>, FullTileShared<T>>::type;
-    __shared__ Shared sh;
+    __shared__ BucketShared<T> sh;
     const uint2 meta = bmeta[blockIdx.x]; // (first dense output position, states)
+    if (*flag) return;                     // the sweep is redone
     const uint32_t dst = meta.x, n = meta.y;
-    if ((n <= (uint32_t)kCdfTileSmall) != SMALL) return; // the other kernel's bucket
-    if (*flag) return;                                   // the sweep is redone
     if (n > (uint32_t)kCdfBucketCap) return; // cannot happen unflagged; keeps LDS indices in range
     const size_t s0 = (size_t)blockIdx.x * kCdfBucketCap; // the bucket's first staging slot
-    Code *range = sh.range;
     if (threadIdx.x == 0) {
-        range[0] = ~(Code)0;
-        range[1] = 0;
+        sh.range[0] = ~(Code)0;
+        sh.range[1] = 0;
     }
     __syncthreads();
-    if constexpr (SMALL)
-        sort_bucket_small<T>(sh, n, dst, stage.u + s0, stage.lab + s0, stage.pos + s0, radix != 0, flag, ko, lo);
+    if (n <= (uint32_t)kCdfTileSmall) // (n is the same for the whole block)
+        sort_bucket<T, kCdfTileSmall / kSortThreads>(sh.small, sh, n, dst, stage.u + s0, stage.lab + s0,
+                                                     stage.pos + s0, flag, ko, lo);
     else
-        sort_bucket_large<T>(sh, n, dst, stage.u + s0, stage.lab + s0, stage.pos + s0, flag, ko, lo);
+        sort_bucket<T, kCdfBucketCap / kSortThreads>(sh.large, sh, n, dst, stage.u + s0, stage.lab + s0,
+                                                     stage.pos + s0, flag, ko, lo);
 }
 
 // Bits that hold every item number below n_items.
@@ -557,19 +347,12 @@ hipError_t cdf_scratch_bytes(int prec, uint32_t n, uint32_t nseg, size_t &bytes)
 
 hipError_t launch_cdf_buckets(int prec, const WorkItem *items, int n_items, const CdfBuffers &b, hipStream_t s) {
     hipLaunchKernelGGL(k_cdf_bscan, dim3(n_items), dim3(kThreads), 0, s, items, b.bcount, b.bmeta, b.flag);
-    if (prec == 0) {
-        const StageView<double> sv = stage_view<double>(b.stage, b.nbuckets);
-        hipLaunchKernelGGL((k_cdf_bsort<double, false>), dim3(b.nbuckets), dim3(kSortThreads), 0, s, b.bmeta, sv,
-                           b.radix_tiles, b.flag, (double *)b.keys[1], b.lab[1]);
-        hipLaunchKernelGGL((k_cdf_bsort<double, true>), dim3(b.nbuckets), dim3(kSortThreads), 0, s, b.bmeta, sv,
-                           b.radix_tiles, b.flag, (double *)b.keys[1], b.lab[1]);
-    } else {
-        const StageView<float> sv = stage_view<float>(b.stage, b.nbuckets);
-        hipLaunchKernelGGL((k_cdf_bsort<float, false>), dim3(b.nbuckets), dim3(kSortThreads), 0, s, b.bmeta, sv,
-                           b.radix_tiles, b.flag, (float *)b.keys[1], b.lab[1]);
-        hipLaunchKernelGGL((k_cdf_bsort<float, true>), dim3(b.nbuckets), dim3(kSortThreads), 0, s, b.bmeta, sv,
-                           b.radix_tiles, b.flag, (float *)b.keys[1], b.lab[1]);
-    }
+    if (prec == 0)
+        hipLaunchKernelGGL(k_cdf_bsort<double>, dim3(b.nbuckets), dim3(kSortThreads), 0, s, b.bmeta,
+                           stage_view<double>(b.stage, b.nbuckets), b.flag, (double *)b.keys[1], b.lab[1]);
+    else
+        hipLaunchKernelGGL(k_cdf_bsort<float>, dim3(b.nbuckets), dim3(kSortThreads), 0, s, b.bmeta,
+                           stage_view<float>(b.stage, b.nbuckets), b.flag, (float *)b.keys[1], b.lab[1]);
     return hipGetLastError();
 }
 

@@ -104,7 +104,6 @@ struct CdfBuffers {
     uint32_t *bcount;    // states per bucket (zero between steps)
     uint2 *bmeta;        // per bucket: first dense output position and states (k_cdf_bscan)
     void *stage;         // staging area (stage_view), kCdfBucketCap slots per bucket
-    int radix_tiles;     // nonzero: every bucket by the block radix sort (no one-pass bins)
     uint32_t *flag;      // nonzero once a bucket overflowed in this sweep
 };
 // Once per fine sweep: the dense first position of every item; the states and

@@ -256,8 +256,8 @@ class Context:
 
     def set_cdf_sort(self, mode: int):
         """Sort of the empirical-CDF drift: 1 buckets after each sweep's first
-        steps (default), 2 the same with the block radix sort in every bucket,
-        0 the radix sort on every step (all give the same bits)."""
+        steps (default), 0 the radix sort on every step (both give the same
+        bits)."""
         self._check(lib().mcpr_set_cdf_sort(self._h, int(mode)))
 
     def cdf_stats(self):

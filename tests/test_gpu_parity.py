@@ -250,19 +250,17 @@ def _burgers_spread(P, N, T, precision, sd=1.0):
 
 @pytest.mark.parametrize("prec", [W.FP64, W.FP32])
 def test_burgers_bucket_sort_equals_radix_sort_bitwise(mc, prec):
-    """The bucket engine (steps after a sweep's first two), with the one-pass
-    bins in the buckets that suit them and with the block radix sort in every
-    bucket, gives bit for bit what the radix sort on every step gives:
-    ensembles of 70 001 (four quads per thread), 3 000, 2 048, 1 and 10 007
-    particles from a spread start in one call, every state and the per-step
-    trace; no sweep is redone."""
+    """The bucket engine (steps after a sweep's first two) gives bit for bit
+    what the radix sort on every step gives: ensembles of 70 001 (four quads
+    per thread), 3 000, 2 048, 1 and 10 007 particles from a spread start in
+    one call, every state and the per-step trace; no sweep is redone."""
     import torch
     pr = _burgers_spread(1, 4, 0.4, prec)
     pc = mc.problem_c(pr)
     sizes = [70_001, 3_000, 2_048, 1, 10_007]
     dt = torch.float64 if prec == W.FP64 else torch.float32
     runs = []
-    for engine in (1, 2, 0):
+    for engine in (1, 0):
         c = mc.Context(0)
         c.set_cdf_sort(engine)
         xs = [torch.empty(P, dtype=dt, device="cuda") for P in sizes]
@@ -285,9 +283,9 @@ def test_burgers_bucket_sort_equals_radix_sort_bitwise(mc, prec):
 
 def test_burgers_bucket_with_far_outliers_bitwise(mc):
     """A law with a far component (0.1 % of the particles near 1000): the top
-    bucket of each ensemble spans the gap, so its states crowd a few of the
-    one-pass bins and it takes the block radix sort; the result is still bit
-    for bit the radix sort's on every step."""
+    bucket of each ensemble spans the gap, so its codes differ in far more
+    bits than an interior bucket's; the result is still bit for bit the radix
+    sort's on every step."""
     import torch
     pr = W.make_problem(W.Coef(acdf=1.0, b0=1.0), W.P0(W.P0_MIXTURE, 0.999, 0.0, 1.0, 1000.0, 1.0), 0.4, 4, 1e-3,
                         (), 0, 0.05, W.FP32)
