@@ -512,6 +512,18 @@ mcpr_status ensure_cdf(mcpr_ctx *ctx, const Tables &t, int prec) {
     return MCPR_OK;
 }
 
+// An event pair for the next profiled run of step launches (slot prof_used).
+mcpr_status next_prof_slot(mcpr_ctx *ctx) {
+    if (ctx->prof_used < ctx->prof0.size()) return MCPR_OK;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    ctx->prof0.push_back(e0);
+    ctx->prof1.push_back(e1);
+    ctx->prof_ps.push_back(0);
+    return MCPR_OK;
+}
+
 mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int nreg, const mcpr::Splits &sp,
                           RegionStats *stats, double2 *trace, hipStream_t s) {
     const int n = (int)t.items.size();
@@ -543,14 +555,7 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
         // overflowed sweep that are already enqueued do nothing.
         size_t slot = 0;
         if (ctx->profile) {
-            if (ctx->prof_used == ctx->prof0.size()) {
-                hipEvent_t e0, e1;
-                HIP_TRY(hipEventCreate(&e0));
-                HIP_TRY(hipEventCreate(&e1));
-                ctx->prof0.push_back(e0);
-                ctx->prof1.push_back(e1);
-                ctx->prof_ps.push_back(0);
-            }
+            if ((st = next_prof_slot(ctx)) != MCPR_OK) return st;
             slot = ctx->prof_used;
         }
         const int tries[4] = {2, 8, 32, m};
@@ -657,14 +662,7 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
             if (tv[c] < 0.99f * tv[0] && tv[c] < tv[pick]) pick = c;
         ctx->tuned[tkey] = ctx->tune_cand[pick];
     } else if (ctx->profile) {
-        if (ctx->prof_used == ctx->prof0.size()) {
-            hipEvent_t e0, e1;
-            HIP_TRY(hipEventCreate(&e0));
-            HIP_TRY(hipEventCreate(&e1));
-            ctx->prof0.push_back(e0);
-            ctx->prof1.push_back(e1);
-            ctx->prof_ps.push_back(0);
-        }
+        if ((st = next_prof_slot(ctx)) != MCPR_OK) return st;
         ctx->prof_ps[ctx->prof_used] = ps * m;
         ctx->prof_launches += m;
         if ((st = enqueue_fine(ctx, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr, s, true)) !=
