@@ -262,9 +262,10 @@ void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_
         w.inst = E.instance;
         w.step0 = E.slice * p.steps_per_slice;
         // (the empirical-CDF step gathers its states in sorted order and
-        // reserves bucket slots per round: one quad per thread keeps more
-        // blocks in flight; still a function of the ensemble alone)
-        w.R = is_cdf(p) ? 1 : mcpr::canonical_quads_per_thread(E.n_particles);
+        // reserves bucket slots per round of 1024 states: two rounds per
+        // block amortise a block's start, more would leave fewer blocks in
+        // flight; still a function of the ensemble alone)
+        w.R = is_cdf(p) ? 2 : mcpr::canonical_quads_per_thread(E.n_particles);
         w.nsc = (int32_t)mcpr::superchunks(E.n_particles, w.R);
         w.part_off = off;
         w.p0_kind = p.p0_kind;
