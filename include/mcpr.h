@@ -73,7 +73,7 @@ typedef struct {
     /* Trigonometric drift terms ksin sin x + kc E_q[sin(X_q - x)], where the
      * mean-field average is (1/P) sum_q sin(X_q - x) = S cos x - C sin x with
      * S, C the population means of sin X and cos X (the plane rotator of
-     * Sec. 5.2: ksin = -1, kc = K).  With either nonzero the per-step mean
+     * Sec. 5.1: ksin = -1, kc = K).  With either nonzero the per-step mean
      * field is (S, C) instead of (m, v), so am, av, axs, bm and bv must be 0
      * (else MCPR_E_UNSUPPORTED), and the adjoint refuses the problem.        */
     double ksin, kc;
@@ -150,7 +150,7 @@ const char *mcpr_last_error(const mcpr_ctx *ctx);
 const char *mcpr_version(void);
 
 /* Quantity of interest (Sec. 1.1: the sample average of Phi over the
- * ensemble; Sec. 5.2 uses Phi(x) = sin(x^2) for the geometric Brownian motion
+ * ensemble; Sec. 5.1 uses Phi(x) = sin(x^2) for the geometric Brownian motion
  * example): out[e] = (1/P) sum_p Phi(x_p) of ensemble e, Phi evaluated in
  * fp64 from the state, summed in the canonical order.  out: device array
  * [n_ens].  Asynchronous.  Errors: MCPR_E_INVALID_ARG for an unknown kind or
@@ -329,7 +329,7 @@ mcpr_status mcpr_parareal_qoi(mcpr_parareal *pr, int32_t inst, int32_t kind, dou
 mcpr_status mcpr_parareal_track_qoi(mcpr_parareal *pr, int32_t on);
 
 /* Given particle fractions for instance inst (the reference variant of
- * Sec. 5.4 that uses the exact particle fractions, e.g. those of a serial
+ * Sec. 5.3 that uses the exact particle fractions, e.g. those of a serial
  * fine solution, in place of the Parareal approximations): fractions is a
  * host array [(N+1)][I], copied.  From the next mcpr_parareal_init or
  * mcpr_parareal_iterate on, every macro state rho^k_n carries fractions[n]

@@ -19,7 +19,7 @@
  *                      numbers in every iteration (Property "Exactness of
  *                      MC-moments Parareal", Sec. 5 protocol).
  *   or_normals4        Box-Muller on the four words of one Philox call.
- *   or_sample_p0       initial law p0 of the SDE (Sec. 1.1, Sec. 5.4 setups).
+ *   or_sample_p0       initial law p0 of the SDE (Sec. 1.1, Sec. 5.3 setups).
  *   or_qoi             empirical mean of a quantity of interest Phi (Sec. 1.1;
  *                      Phi(x) = sin(x^2) in the geometric Brownian motion
  *                      example of Sec. 5.2).
@@ -39,7 +39,7 @@
  *                      multimodal MC-moments iterators (Definitions of Sec. 3.4),
  *                      the learning extension (Sec. 3.6) and the reference
  *                      variant with given (exact) particle fractions (the
- *                      variants listed in Sec. 5.4).
+ *                      variants listed in Sec. 5.3).
  *   or_fraction_fit    least-squares fit of the two-region rate model
  *                      (eq. exponential_for_particle_fractions, App. H).
  *   or_adjoint         pathwise gradient of a moment-misfit through the
@@ -65,7 +65,7 @@ typedef struct {
     double axs;
     /* trigonometric drift ksin sin x + kc (1/P) sum_q sin(X_q - x), the
        second written as kc (S cos x - C sin x) with S, C the population means
-       of sin X and cos X (plane rotator of Sec. 5.2)                         */
+       of sin X and cos X (plane rotator of Sec. 5.1)                         */
     double ksin, kc;
     /* empirical-CDF drift acdf (1 - F_P(x)), F_P(x) = (1/P) sum_q H(x - X_q),
        H(0) = 1/2 (Burgers example of Sec. 5.2)                              */
@@ -210,7 +210,7 @@ void or_moments(const double *x, int64_t P, double *mean, double *var)
 
 /* Empirical mean of a quantity of interest over the ensemble, (1/P) sum
    Phi(x_p) (Sec. 1.1, the sample average of Phi; the nonlinear QoI of the
-   geometric Brownian motion example of Sec. 5.2 is Phi(x) = sin(x^2)).
+   geometric Brownian motion example of Sec. 5.1 is Phi(x) = sin(x^2)).
    kind 0: x, 1: x^2, 2: sin(x^2).                                            */
 double or_qoi(const double *x, int64_t P, int32_t kind)
 {

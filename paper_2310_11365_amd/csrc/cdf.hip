@@ -261,7 +261,13 @@ __global__ __launch_bounds__(kSortThreads) void k_cdf_bsort(const uint2 *__restr
     using Code = decltype(order_code(T()));
     __shared__ BucketShared<T> sh;
     const uint2 meta = bmeta[blockIdx.x]; // (first dense output position, states)
-    if (*flag) return;                     // the sweep is redone
+    // The sweep is redone once any block has set the flag.  Other blocks of
+    // this launch may set it while this one starts, so one thread reads it
+    // and the whole block takes that one decision.
+    __shared__ uint32_t skip;
+    if (threadIdx.x == 0) skip = *flag;
+    __syncthreads();
+    if (skip) return;
     const uint32_t dst = meta.x, n = meta.y;
     if (n > (uint32_t)kCdfBucketCap) return; // cannot happen unflagged; keeps LDS indices in range
     const size_t s0 = (size_t)blockIdx.x * kCdfBucketCap; // the bucket's first staging slot

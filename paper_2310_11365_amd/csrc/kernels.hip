@@ -405,7 +405,7 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
 }
 
 // ----------------------------------------------------------------------------
-// Trigonometric mean field (plane rotator, Sec. 5.2): the drift
+// Trigonometric mean field (plane rotator, Sec. 5.1): the drift
 //   a(x) = a0 + a1 x + a2 x^2 + a3 x^3 + ksin sin x + kc (1/P) sum_q sin(X_q - x)
 // with (1/P) sum_q sin(X_q - x) = S cos x - C sin x, S and C the population
 // means of sin X and cos X.  The per-step mean field is (S, C): every launch
@@ -660,7 +660,15 @@ __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__r
     __shared__ T su[kRound];
     __shared__ uint32_t sl[kRound], sp[kRound];
     __shared__ uint8_t sw[kRound];
-    if (mode != 0 && *flag) return; // a doomed sweep (redone): skip its work, keep the input state
+    // A doomed sweep (redone): skip its work, keep the input state.  Blocks
+    // of this launch may set the flag while this one starts, so one thread
+    // reads it and the whole block takes that one decision.
+    if (mode != 0) {
+        __shared__ uint32_t skip;
+        if (threadIdx.x == 0) skip = *flag;
+        __syncthreads();
+        if (skip) return;
+    }
     const int2 bt = blocks[blockIdx.x];
     const int item = bt.x, sc = bt.y;
     const WorkItem &W = items[item];

@@ -11,7 +11,7 @@ workload, taken from numpy's seeded PCG64 generator.
 
 The workloads stand in for the paper's experiments (Sec. 5): the linear
 mean-field Ornstein-Uhlenbeck case (exact moment model, Lemma on exactness of
-the Taylor model), the bimodal double-well case of Sec. 5.4 in its
+the Taylor model), the bimodal double-well case of Sec. 5.3 in its
 Desai-Zwanzig mean-field form, a batch of independent OU instances, and the
 large bimodal case with the particle-fraction learning of Sec. 3.6.
 """
@@ -146,7 +146,7 @@ def ou_linear(P: int = 10_000, precision: int = FP64, N: int = 10, T: float = 1.
 
 def gbm_coef() -> Coef:
     """Geometric Brownian motion with interaction (the nonlinear-QoI example of
-    Sec. 5.2): dX = (alpha X + beta E[X] + a) dt + (sigma X + omega E[X] + b) dW,
+    Sec. 5.1): dX = (alpha X + beta E[X] + a) dt + (sigma X + omega E[X] + b) dW,
     alpha = -1/2, beta = 4/5, a = 1/3, sigma = omega = (1/2) sqrt(1/2), b = 1/6."""
     s = 0.5 * math.sqrt(0.5)
     return Coef(a0=1.0 / 3.0, a1=-0.5, am=0.8, b0=1.0 / 6.0, b1=s, bm=s)
@@ -176,7 +176,7 @@ def polydrift(P: int = 100_000, precision: int = FP64, N: int = 10, T: float = 2
 
 def rotator(P: int = 100_000, precision: int = FP64, N: int = 20, T: float = 10.0, dt: float = 1e-3,
             K: float = 1.0, kT: float = 0.5, wrap: int = 1, seed: int = 0, coarse_model: int = 0) -> Workload:
-    """Plane rotator (Sec. 5.2): dX = [K E_q[sin(X_q - X)] - sin X] dt + sqrt(2 kB T) dW,
+    """Plane rotator (Sec. 5.1): dX = [K E_q[sin(X_q - X)] - sin X] dt + sqrt(2 kB T) dW,
     X0 ~ N(pi/4, 3 pi/4) (variance 3 pi/4), shifted modulo 2 pi into [0, 2 pi)
     after every step; T = 10, dt = 1e-3, 1e5 particles as in the paper.  K and
     kB T are not printed: K = 1, kB T = 1/2 (unit noise)."""

@@ -525,7 +525,7 @@ def test_parareal_bimodal_fp64_matches_oracle(mc, ctx, oracle, model):
 
 def test_parareal_unimodal_coarse_on_bimodal_fp64(mc, ctx, oracle):
     """The unimodal variant on the bimodal problem (one region, Gaussian
-    coarse model with three sigma points; the first variant of Sec. 5.4)."""
+    coarse model with three sigma points; the first variant of Sec. 5.3)."""
     wl = W.dz_bimodal(P=20_000, N=8, T=2.0, precision=W.FP64)
     wl.problem.splits = ()
     wl.problem.coarse_model = W.COARSE_GAUSS3
@@ -535,7 +535,7 @@ def test_parareal_unimodal_coarse_on_bimodal_fp64(mc, ctx, oracle):
 @pytest.mark.parametrize("model", [W.COARSE_TAYLOR, W.COARSE_GAUSS2, W.COARSE_GAUSS3])
 def test_parareal_gbm_qoi_fp64_matches_oracle(mc, ctx, oracle, model):
     """Geometric Brownian motion with interaction (multiplicative noise in x and
-    E[X]) and the QoI sin(x^2) of Sec. 5.2, with the three coarse models: every
+    E[X]) and the QoI sin(x^2) of Sec. 5.1, with the three coarse models: every
     iterate's macro states and the QoI of every slice against the oracle, and
     the QoI of the slices already exact equal to the serial solution's."""
     wl = W.gbm(P=20_000, N=6, T=0.6, coarse_model=model)

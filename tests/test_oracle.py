@@ -610,7 +610,7 @@ def test_parareal_exactness_bimodal(oracle):
 
 def test_parareal_exact_fractions_variant(oracle):
     """Reference variant with the serial solution's particle fractions (the
-    exact-fraction variant of Sec. 5.4): exactness still holds bit for bit,
+    exact-fraction variant of Sec. 5.3): exactness still holds bit for bit,
     every macro state carries the given fractions at every iteration, and the
     first iterate differs from the plain variant's (the fractions enter the
     coarse model's mean-field arguments)."""
