@@ -564,14 +564,14 @@ def test_transform_acceptance_is_per_particle(oracle):
 
 
 # --------------------------------------------------------------------------- driver
-def _invariant_check(oracle, wl, K, exact_fractions=False):
+def _invariant_check(oracle, wl, K, exact_fractions=False, learning=False):
     pr = wl.problem
     u0 = oracle.sample_p0(pr, wl.P)
     xs, st_serial = oracle.serial(pr, u0)
     fr = None
     if exact_fractions:
         fr = st_serial[:, :pr.n_regions]["n"] / wl.P
-    res = oracle.parareal(pr, u0, K, keep_states=True, fractions=fr)
+    res = oracle.parareal(pr, u0, K, keep_states=True, fractions=fr, learning=learning)
     # serial states, slice by slice
     ser = [u0.copy()]
     x = u0.copy()
@@ -689,6 +689,202 @@ def test_fraction_fit_recovers_exponential(oracle):
     w12 = kappa - w21
     A = np.array([[-w12, w21], [w12, -w21]])
     assert np.allclose(A.sum(axis=0), 0.0)
+
+
+def _relaxing_bimodal(P=1500, N=8, T=4.0):
+    """Two-region double well whose particle fractions relax: an uneven
+    mixture (95 % in the left well) with strong noise, so particles cross the
+    barrier and the left fraction falls from 0.95 to about 0.73 over the horizon."""
+    c = W.dz_coef(sigma=0.9)
+    pr = W.make_problem(c, W.P0(W.P0_MIXTURE, 0.95, -1.0, 0.1, 1.0, 0.1), T, N, 1e-2, (0.0,))
+    pr.coarse_model = W.COARSE_GAUSS3
+    return W.Workload("relaxing_bimodal", pr, P, max_iter=N, learning=True)
+
+
+def test_parareal_learning_keeps_exactness(oracle):
+    """Learning-based MC-moments Parareal (Sec. 3.6): the extrapolated
+    fractions touch only slices beyond the exact ones, so the exactness
+    property still holds bit for bit and every exact slice takes the
+    I(a, b, a) branch; and learning does change the slices beyond."""
+    wl = _relaxing_bimodal()
+    res, st = _invariant_check(oracle, wl, wl.problem.n_slices, learning=True)
+    fl = res["flags"]
+    for k in range(fl.shape[0]):
+        assert np.all(fl[k, :k + 1] == 0), k
+    fr = st[:, 0]["n"] / wl.P
+    assert fr[0] - fr[-1] > 0.15  # the fractions do relax
+    u0 = oracle.sample_p0(wl.problem, wl.P)
+    plain = oracle.parareal(wl.problem, u0, 3)
+    assert not np.array_equal(plain["rho"][2, :, :, 0], res["rho"][2, :, :, 0])
+
+
+def test_parareal_learning_extrapolates_an_independent_fit(oracle):
+    """After the fine sweep of iteration k the slices 0..k+1 are exact; their
+    left-region fractions are fitted by the two-region rate model of App. H,
+    P_1(t) = P* + (P_1(0) - P*) exp(-kappa t), and every later slice n of
+    rho^{k+1} carries P* + (P_{1,k+1} - P*) exp(-kappa (t_n - t_{k+1})) in region
+    0 and its complement in region 1.  The fit here is scipy's bounded
+    trust-region least squares on the serial solution's fractions, a fitter
+    and a data path that share nothing with the oracle's driver."""
+    from scipy.optimize import least_squares
+    wl = _relaxing_bimodal()
+    pr, P, N = wl.problem, wl.P, wl.problem.n_slices
+    u0 = oracle.sample_p0(pr, P)
+    _, st = oracle.serial(pr, u0)
+    y = st[:, 0]["n"] / P
+    t = np.arange(N + 1) * pr.slice_length
+    res = oracle.parareal(pr, u0, N, learning=True)
+    checked = 0
+    for k in range(1, res["iterations"]):
+        tt, yy = t[:k + 2], y[:k + 2]
+        fit = least_squares(lambda q: q[1] + (yy[0] - q[1]) * np.exp(-q[0] * tt) - yy,
+                            x0=[1.0, 0.5], bounds=([0.0, 0.0], [np.inf, 1.0]),
+                            xtol=1e-15, ftol=1e-15, gtol=1e-15, method="trf")
+        kappa, pstar = fit.x
+        for n in range(k + 2, N + 1):
+            if res["flags"][k, n - 1, 0] == 0:
+                continue  # (an I(a, b, a) short cut keeps the fine fractions)
+            want = pstar + (yy[-1] - pstar) * math.exp(-kappa * (t[n] - t[k + 1]))
+            rho = res["rho"][k + 1, n]
+            assert abs(rho[0, 0] - want) <= 1e-8, (k, n, rho[0, 0], want)
+            assert rho[1, 0] == 1.0 - rho[0, 0], (k, n)
+            checked += 1
+    assert checked >= 10
+
+
+def test_parareal_learning_one_region_is_plain(oracle):
+    """The fraction model needs two regions: with one region learning is a
+    no-op, bit for bit."""
+    wl = W.ou_linear(P=400, N=5)
+    pr = wl.problem
+    u0 = oracle.sample_p0(pr, wl.P)
+    a = oracle.parareal(pr, u0, 4, keep_states=True)
+    b = oracle.parareal(pr, u0, 4, keep_states=True, learning=True)
+    for key in ("rho", "glob", "flags", "delta", "states"):
+        np.testing.assert_array_equal(a[key], b[key])
+
+
+@pytest.mark.parametrize("model,npts", [(W.COARSE_GAUSS2, 2), (W.COARSE_GAUSS3, 3)])
+def test_gaussian_trig_field_hermite_nodes(oracle, model, npts):
+    """Gaussian models of the plane rotator with two regions of positive
+    variance: every expectation over N(M_i, V_i) -- the drift's own sin x term,
+    the mean field's S = sum_i f_i E_i[sin X] and C = sum_i f_i E_i[cos X], and
+    the moment equations' E[a], E[(x - M) a], E[b^2] -- taken with numpy's
+    probabilists' Gauss-Hermite rule of the same order; the oracle's RK4
+    against a tight solve of that system."""
+    from numpy.polynomial.hermite_e import hermegauss
+    K, kT = 1.2, 0.3
+    pr = W.rotator(K=K, kT=kT, N=1, T=0.2).problem
+    pr.splits = (math.pi,)
+    pr.coarse_model = model
+    pr.coarse_substeps = 40
+    z, wz = hermegauss(npts)
+    wz = wz / wz.sum()
+    f = np.array([0.4, 0.6])
+    y0 = np.array([1.0, 0.25, 4.0, 0.4])
+    b = math.sqrt(2 * kT)
+
+    def rhs(t, u):
+        M, V = u[0::2], u[1::2]
+        xs = [M[i] + np.sqrt(V[i]) * z for i in range(2)]
+        S = sum(f[i] * wz @ np.sin(xs[i]) for i in range(2))
+        C = sum(f[i] * wz @ np.cos(xs[i]) for i in range(2))
+        out = []
+        for i in range(2):
+            a = -np.sin(xs[i]) + K * (S * np.cos(xs[i]) - C * np.sin(xs[i]))
+            out += [wz @ a, 2 * wz @ ((xs[i] - M[i]) * a) + b * b]
+        return out
+    sol = solve_ivp(rhs, (0, pr.slice_length), y0, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(oracle.coarse(pr, f, y0), sol.y[:, -1], rtol=1e-9, atol=1e-12)
+    # the rule matters: the point-mass field (the Taylor model's) is far off
+    pr.coarse_model = W.COARSE_TAYLOR
+    assert np.max(np.abs(oracle.coarse(pr, f, y0) - sol.y[:, -1])) > 1e-3
+
+
+# --------------------------------------------------------------------------- classical Parareal
+def test_classical_parareal_dahlquist(oracle):
+    """A one-particle ensemble without noise is classical Parareal on the
+    Dahlquist equation x' = lambda x (Sec. 4.2: R and M are the identity for a
+    single particle): the fine propagator is explicit Euler, F = (1 + lambda
+    dt)^m, the coarse one RK4, G = R(lambda h)^s with the RK4 stability
+    polynomial.  Every iterate equals the textbook recursion
+    U^{k+1}_{n+1} = G U^{k+1}_n + F U^k_n - G U^k_n, and at k = N the fine
+    solution F^n U_0 is reached (Sec. 4.4)."""
+    lam = -4.0
+    N = 8
+    pr = W.make_problem(W.Coef(a1=lam), W.P0(W.P0_DELTA, 1.0, 1.3, 0.0), 2.0, N, 0.05, coarse_h=0.25)
+    assert pr.steps_per_slice == 5 and pr.coarse_substeps == 1
+    m, s = pr.steps_per_slice, pr.coarse_substeps
+    F = (1.0 + lam * pr.dt) ** m
+    h = pr.slice_length / s
+    z = lam * h
+    G = (1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24) ** s
+    u0 = oracle.sample_p0(pr, 1)
+    assert u0[0] == 1.3
+    res = oracle.parareal(pr, u0, N)
+    assert res["iterations"] == N
+    U = np.array([1.3 * G ** n for n in range(N + 1)])  # iteration 0: the coarse sweep
+    fine = np.array([1.3 * F ** n for n in range(N + 1)])
+    for k in range(N + 1):
+        np.testing.assert_allclose(res["glob"][k, :, 0], U, rtol=1e-12, atol=0)
+        assert np.all(res["glob"][k, :, 1] == 0.0)
+        if k < N:
+            Un = U.copy()
+            for n in range(N):
+                Un[n + 1] = G * Un[n] + F * U[n] - G * U[n]
+            U = Un
+    np.testing.assert_allclose(res["glob"][N, :, 0], fine, rtol=1e-12)
+    # before k = N the coarse error is still visible at the last slice
+    assert abs(res["glob"][N // 2, N, 0] - fine[N]) > 1e-3 * abs(fine[N])
+
+
+def test_noisy_parareal_error_recursion_and_bounds(oracle):
+    """MC-moments Parareal on the linear mean-field OU with the exact (Taylor)
+    moment model: its mean is noisy classical Parareal (Lemma on the error
+    recursion with noise).  The fine propagator maps slice means as
+    M -> F M + f + eps_n, with eps_n the slice's statistical error (the
+    per-realisation identity of the Euler-Maruyama mean), the coarse one as
+    M -> G M + g.  Against the noise-free fine solution u_n (eps = 0) the mean
+    iterates follow U^{k+1}_{n+1} = G U^{k+1}_n + g + F U^k_n + f + eps_n -
+    (G U^k_n + g), and their error obeys the superlinear and the linear bound
+    of the Lemma on Parareal with noise, with eps = max_n |eps_n|."""
+    wl = W.ou_linear(P=2000, N=10, T=2.0)
+    pr, P, N = wl.problem, wl.P, wl.problem.n_slices
+    c = pr.coef
+    lam, dt, m = c.a1 + c.am, pr.dt, pr.steps_per_slice
+    F = (1.0 + lam * dt) ** m
+    f = c.a0 * dt * sum((1.0 + lam * dt) ** j for j in range(m))
+    h = pr.slice_length / pr.coarse_substeps
+    z = lam * h
+    R = 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+    G = R ** pr.coarse_substeps
+    g = 0.0  # (a0 = 0)
+    assert c.a0 == 0.0
+    u0 = oracle.sample_p0(pr, P)
+    _, st = oracle.serial(pr, u0)
+    ms = np.array([s["mean"] for s in st[:, -1]])
+    eps = ms[1:] - (F * ms[:-1] + f)
+    res = oracle.parareal(pr, u0, N)
+    assert np.all(res["flags"] <= 1)  # every region matched or short cut
+    u = np.array([ms[0] * F ** n for n in range(N + 1)])  # noise-free fine solution (f = 0)
+    U = res["glob"][0, :, 0].copy()
+    xi0 = np.max(np.abs(U - u))
+    E = np.max(np.abs(eps))
+    for k in range(res["iterations"] + 1):
+        got = res["glob"][k, :, 0]
+        np.testing.assert_allclose(got, U, rtol=1e-11, atol=1e-13)
+        xi = np.max(np.abs(got - u))
+        sup = (abs(F - G) ** k / math.factorial(k) * math.prod(N - j for j in range(1, k + 1)) * xi0
+               + E * (1 - abs(G) ** N) / (1 - abs(G)) * sum(abs(F - G) ** j * math.comb(N - 1, j)
+                                                         for j in range(k)))
+        q = abs(F - G) / (1 - abs(G))
+        lin = q ** k * xi0 + E / (1 - abs(G)) * sum(q ** j for j in range(k))
+        assert xi <= sup * (1 + 1e-9) + 1e-14, (k, xi, sup)
+        assert xi <= lin * (1 + 1e-9) + 1e-14, (k, xi, lin)
+        Un = U.copy()
+        for n in range(N):
+            Un[n + 1] = (G * Un[n] + g) + (F * U[n] + f + eps[n]) - (G * U[n] + g)
+        U = Un
 
 
 # --------------------------------------------------------------------------- adjoint
