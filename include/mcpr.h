@@ -44,7 +44,8 @@ typedef enum {
     MCPR_E_OOM = -2,
     MCPR_E_DEVICE = -3,
     MCPR_E_NONFINITE = -4,
-    MCPR_E_UNSUPPORTED = -5
+    MCPR_E_UNSUPPORTED = -5,
+    MCPR_E_NOT_RESERVED = -6 /* the context's scratch is smaller than the call needs: see mcpr_reserve */
 } mcpr_status;
 
 enum { MCPR_FP64 = 0, MCPR_FP32 = 1 }; /* FP32: fp32 particles, fp64 reductions and matching */
@@ -142,12 +143,46 @@ typedef struct {
 } mcpr_region_map;
 
 /* ---- context ------------------------------------------------------------ */
-/* Creates a context on a HIP device; it owns reduction scratch, staging and
- * per-call tables, grown on demand and reused (no allocation once warm). */
+/* Creates a context on a HIP device; it owns the scratch of the calls
+ * (reduction partials, work tables, pinned staging of the tables, the
+ * adjoint's checkpoints), sized by mcpr_reserve: the calls below never
+ * allocate, synchronise the device or free memory for scratch; a call that
+ * needs more than is reserved returns MCPR_E_NOT_RESERVED and launches
+ * nothing.  (Events of the profiling hooks and of the launch-variant trial,
+ * and the graph of a new launch shape, are created on first use.)          */
 mcpr_status mcpr_create(mcpr_ctx **ctx, int32_t device);
 void mcpr_destroy(mcpr_ctx *ctx);
 const char *mcpr_last_error(const mcpr_ctx *ctx);
 const char *mcpr_version(void);
+
+/* Sizes the context's scratch for later calls of the kinds in `calls` on the
+ * given ensembles, or on any set that needs no more (fewer or smaller
+ * ensembles of the same layout): allocates device and pinned host memory and
+ * may synchronise the device, so call it outside the hot path.  Buffers only
+ * grow; a reserve that fits what is held allocates nothing.  Kinds:
+ *   MCPR_RESERVE_INIT     mcpr_init_particles
+ *   MCPR_RESERVE_MOMENTS  mcpr_moments
+ *   MCPR_RESERVE_QOI      mcpr_qoi
+ *   MCPR_RESERVE_FINE     mcpr_fine_propagate, with records and trace
+ *   MCPR_RESERVE_MATCH    mcpr_match, with the dry-run probe
+ *   MCPR_RESERVE_ADJOINT  mcpr_adjoint from each given ensemble (its slice to
+ *                         n_slices), with the backward sweep
+ * mcpr_parareal_create reserves everything its driver needs itself.  Errors:
+ * as the calls (arguments), MCPR_E_OOM when an allocation fails.           */
+enum {
+    MCPR_RESERVE_INIT = 1,
+    MCPR_RESERVE_MOMENTS = 2,
+    MCPR_RESERVE_QOI = 4,
+    MCPR_RESERVE_FINE = 8,
+    MCPR_RESERVE_MATCH = 16,
+    MCPR_RESERVE_ADJOINT = 32,
+    MCPR_RESERVE_ALL = 63
+};
+mcpr_status mcpr_reserve(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems, const mcpr_ensemble *ens,
+                         int32_t n_ens, int32_t calls);
+/* Allocations the context (and its Parareal drivers) has made so far: device
+ * and pinned host buffers, and their bytes (either pointer may be NULL).    */
+mcpr_status mcpr_alloc_stats(const mcpr_ctx *ctx, int64_t *allocations, int64_t *bytes);
 
 /* Quantity of interest (Sec. 1.1: the sample average of Phi over the
  * ensemble; Sec. 5.1 uses Phi(x) = sin(x^2) for the geometric Brownian motion
@@ -338,6 +373,22 @@ mcpr_status mcpr_parareal_track_qoi(mcpr_parareal *pr, int32_t on);
  * branch.  NULL returns to the method's own fractions.  Errors:
  * MCPR_E_INVALID_ARG for a bad instance or a negative or non-finite value. */
 mcpr_status mcpr_parareal_set_fractions(mcpr_parareal *pr, int32_t inst, const double *fractions);
+
+/* Checkpoint and resume between iterations.  The driver's state is its host
+ * state (this call) plus the instances' rings, which are caller-owned device
+ * memory: a caller saves the rings (slots of slices k..N of each instance,
+ * or simply the whole ring) with the state and copies them back before
+ * mcpr_parareal_restore.  Random numbers are counter-based, so iterations
+ * after a restore give the same bits as an uninterrupted run.
+ * mcpr_parareal_save: *bytes receives the state's size; with buf != NULL and
+ * capacity >= that size the state is written to buf (host).  Call between
+ * iterations; it waits for the QoI still in flight.
+ * mcpr_parareal_restore: loads a state saved from a driver created with the
+ * same problems, instances (particle counts, RNG streams), N, m, regions and
+ * precision, in this process or another; anything else returns
+ * MCPR_E_INVALID_ARG and leaves the driver as it was.                       */
+mcpr_status mcpr_parareal_save(mcpr_parareal *pr, void *buf, size_t capacity, size_t *bytes);
+mcpr_status mcpr_parareal_restore(mcpr_parareal *pr, const void *buf, size_t bytes);
 
 /* Macro state of instance i (host arrays): rho [(N+1)][I][3] = (fraction,
  * mean, variance) per region; glob [(N+1)][2] = mixture mean and variance

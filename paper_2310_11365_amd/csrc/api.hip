@@ -45,6 +45,8 @@ struct HostBuf {
 
 // Launches in the step-variant autotuner's trial (at most 4 candidates x 4).
 constexpr int kTuneSteps = 16;
+// Instantiated fine sweeps kept per context.
+constexpr size_t kGraphCache = 8;
 // The adjoint's backward steps use one-quad superchunks below this many particles.
 constexpr int64_t kAdjointSmall = 262144;
 
@@ -81,9 +83,20 @@ struct mcpr_ctx {
     bool graphs = true;
     hipStream_t gstream = nullptr;
     hipEvent_t gin = nullptr, gout = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    std::vector<char> gkey;
+    // instantiated sweeps by launch shape, least recently used evicted first
+    // (a Parareal step alternates lifting and sweep shapes, the adjoint its
+    // traced forward sweeps and the recomputations)
+    struct GraphEntry {
+        std::vector<char> key;
+        hipGraphExec_t exec = nullptr;
+        int64_t used = 0;
+    };
+    std::vector<GraphEntry> graphs_cached;
     int64_t graph_builds = 0, graph_launches = 0;
+    // the adjoint's second stream (recomputation of slice n-1 while the
+    // backward steps of slice n run) and its events
+    hipStream_t astream = nullptr;
+    hipEvent_t a_fwd = nullptr, a_rec[2] = {}, a_bwd[2] = {};
     // step-kernel variant per launch shape: -1 autotune, 0..3 forced
     int tuning = -1;
     std::map<std::vector<char>, int> tuned;
@@ -92,6 +105,11 @@ struct mcpr_ctx {
     int tune_cand[4] = {0, 1, 2, 3}; // variants of the trial, the first is the reference
     int tune_nc = 4;
     DevBuf mv; // per-item (mean, variance) of the separate-combine variant
+    // scratch sizing: buffers grow only inside mcpr_reserve (and the Parareal
+    // driver's create); a hot-path call that needs more fails with
+    // MCPR_E_NOT_RESERVED before launching anything
+    bool growing = false;
+    int64_t allocs = 0, alloc_bytes = 0; // device and pinned allocations made so far
 };
 
 namespace {
@@ -112,8 +130,15 @@ mcpr_status fail(mcpr_ctx *ctx, mcpr_status st, const char *fmt, ...) {
         if (e_ != hipSuccess) return fail(ctx, MCPR_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));         \
     } while (0)
 
+// Scratch buffer b of at least `bytes`: grown (with a device synchronisation)
+// only while the context is sizing, else MCPR_E_NOT_RESERVED.
 mcpr_status ensure(mcpr_ctx *ctx, DevBuf &b, size_t bytes) {
     if (bytes <= b.cap) return MCPR_OK;
+    if (!ctx->growing)
+        return fail(ctx, MCPR_E_NOT_RESERVED,
+                    "%zu bytes of scratch needed where %zu are reserved: call mcpr_reserve with this call's "
+                    "ensembles first",
+                    bytes, b.cap);
     size_t want = std::max(bytes, b.cap * 3 / 2);
     want = (want + 255) & ~(size_t)255;
     if (b.p) {
@@ -127,22 +152,44 @@ mcpr_status ensure(mcpr_ctx *ctx, DevBuf &b, size_t bytes) {
         return fail(ctx, MCPR_E_OOM, "device allocation of %zu bytes failed", want);
     }
     b.cap = want;
+    ctx->allocs++;
+    ctx->alloc_bytes += (int64_t)want;
     return MCPR_OK;
 }
 
+// Pinned host buffer of at least `bytes`, under the same rule as ensure().
+mcpr_status ensure_host(mcpr_ctx *ctx, HostBuf &b, size_t bytes) {
+    if (bytes <= b.cap) return MCPR_OK;
+    if (!ctx->growing)
+        return fail(ctx, MCPR_E_NOT_RESERVED,
+                    "%zu bytes of pinned staging needed where %zu are reserved: call mcpr_reserve first", bytes,
+                    b.cap);
+    if (b.p) HIP_TRY(hipHostFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+    const size_t want = std::max(bytes, (size_t)1 << 16);
+    if (hipHostMalloc(&b.p, want, hipHostMallocDefault) != hipSuccess) {
+        b.p = nullptr;
+        return fail(ctx, MCPR_E_OOM, "pinned allocation of %zu bytes failed", want);
+    }
+    b.cap = want;
+    ctx->allocs++;
+    ctx->alloc_bytes += (int64_t)want;
+    return MCPR_OK;
+}
+
+// Sizing mode for the duration of a scope (mcpr_reserve, the driver's create).
+struct Growing {
+    mcpr_ctx *ctx;
+    explicit Growing(mcpr_ctx *c) : ctx(c) { ctx->growing = true; }
+    ~Growing() { ctx->growing = false; }
+};
+
 // Host staging of the per-call tables (pinned, reused once its last upload is done).
 mcpr_status stage(mcpr_ctx *ctx, size_t bytes, char **out) {
+    mcpr_status st = ensure_host(ctx, ctx->staging, bytes);
+    if (st != MCPR_OK) return st;
     HIP_TRY(hipEventSynchronize(ctx->staged));
-    if (bytes > ctx->staging.cap) {
-        if (ctx->staging.p) HIP_TRY(hipHostFree(ctx->staging.p));
-        ctx->staging.p = nullptr;
-        size_t want = std::max(bytes, (size_t)1 << 16);
-        if (hipHostMalloc(&ctx->staging.p, want, hipHostMallocDefault) != hipSuccess) {
-            ctx->staging.cap = 0;
-            return fail(ctx, MCPR_E_OOM, "pinned allocation of %zu bytes failed", want);
-        }
-        ctx->staging.cap = want;
-    }
     *out = (char *)ctx->staging.p;
     return MCPR_OK;
 }
@@ -202,9 +249,10 @@ bool same_layout(const mcpr_problem &a, const mcpr_problem &b) {
     return true;
 }
 
-mcpr_status check_call(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems, const mcpr_ensemble *ens,
+// Arguments of a call on ensembles (ctx may be NULL: errors then go to the
+// calling thread's context-free error text).
+mcpr_status check_args(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems, const mcpr_ensemble *ens,
                        int32_t n_ens) {
-    if (!ctx) return MCPR_E_INVALID_ARG;
     if (!problems || n_problems < 1) return fail(ctx, MCPR_E_INVALID_ARG, "no problems");
     if (!ens || n_ens < 1) return fail(ctx, MCPR_E_INVALID_ARG, "no ensembles");
     for (int i = 0; i < n_problems; ++i) {
@@ -233,6 +281,12 @@ mcpr_status check_call(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_pr
     }
     if (total_sc > 0x7fffffffLL) return fail(ctx, MCPR_E_INVALID_ARG, "too many particles in one call");
     return MCPR_OK;
+}
+
+mcpr_status check_call(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems, const mcpr_ensemble *ens,
+                       int32_t n_ens) {
+    if (!ctx) return MCPR_E_INVALID_ARG;
+    return check_args(ctx, problems, n_problems, ens, n_ens);
 }
 
 // ----------------------------------------------------------------------------
@@ -298,13 +352,21 @@ void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_
 
 // Upload items and blocks (and optionally maps) through the pinned staging
 // buffer, into the given device buffers.
-mcpr_status upload_into(mcpr_ctx *ctx, const Tables &t, DevBuf &ditems, DevBuf &dblocks, const void *maps,
-                        size_t map_bytes, hipStream_t s) {
+// Buffers of an upload of the tables t (and map_bytes of maps).
+mcpr_status size_upload(mcpr_ctx *ctx, const Tables &t, DevBuf &ditems, DevBuf &dblocks, size_t map_bytes) {
     const size_t ib = t.items.size() * sizeof(WorkItem), bb = t.blocks.size() * sizeof(int2);
     mcpr_status st;
     if ((st = ensure(ctx, ditems, ib)) != MCPR_OK) return st;
     if ((st = ensure(ctx, dblocks, bb)) != MCPR_OK) return st;
     if (map_bytes && (st = ensure(ctx, ctx->maps, map_bytes)) != MCPR_OK) return st;
+    return ensure_host(ctx, ctx->staging, align256(ib) + align256(bb) + align256(map_bytes));
+}
+
+mcpr_status upload_into(mcpr_ctx *ctx, const Tables &t, DevBuf &ditems, DevBuf &dblocks, const void *maps,
+                        size_t map_bytes, hipStream_t s) {
+    const size_t ib = t.items.size() * sizeof(WorkItem), bb = t.blocks.size() * sizeof(int2);
+    mcpr_status st;
+    if ((st = size_upload(ctx, t, ditems, dblocks, map_bytes)) != MCPR_OK) return st;
     char *h;
     if ((st = stage(ctx, align256(ib) + align256(bb) + align256(map_bytes), &h)) != MCPR_OK) return st;
     std::memcpy(h, t.items.data(), ib);
@@ -342,15 +404,46 @@ mcpr_status ensure_records(mcpr_ctx *ctx, const Tables &t, int nreg) {
     return MCPR_OK;
 }
 
-mcpr_status enqueue_records(mcpr_ctx *ctx, const Tables &t, int prec, int nreg, const mcpr::Splits &sp,
-                            const double *shift, bool two_pass, int mode, const RegionMap *maps, RegionStats *out,
-                            hipStream_t s) {
+// Device scratch of one fine sweep or restriction: the work and block
+// tables, the step partials and shifts (ping-pong), the per-item mean field,
+// the region partials and shifts, and where the records and the trace go.
+struct Bufs {
+    const WorkItem *items;
+    const int2 *blocks;
+    double2 *part[2];
+    double *shift[2];
+    double2 *mv;
+    RegionPartial *rpart;
+    double *rshift[2];
+    RegionStats *recs;
+    double2 *trace;
+};
+
+Bufs ctx_bufs(mcpr_ctx *ctx) {
+    Bufs b;
+    b.items = (const WorkItem *)ctx->items.p;
+    b.blocks = (const int2 *)ctx->blocks.p;
+    for (int k = 0; k < 2; ++k) {
+        b.part[k] = (double2 *)ctx->part[k].p;
+        b.shift[k] = (double *)ctx->shift[k].p;
+        b.rshift[k] = (double *)ctx->rshift[k].p;
+    }
+    b.mv = (double2 *)ctx->mv.p;
+    b.rpart = (RegionPartial *)ctx->rpart.p;
+    b.recs = (RegionStats *)ctx->recs.p;
+    b.trace = (double2 *)ctx->trace.p;
+    return b;
+}
+
+mcpr_status enqueue_records(mcpr_ctx *ctx, const Bufs &bf, const Tables &t, int prec, int nreg,
+                            const mcpr::Splits &sp, const double *shift, bool two_pass, int mode,
+                            const RegionMap *maps, RegionStats *out, hipStream_t s) {
     const int nr = nreg + 1, n = (int)t.items.size();
-    const WorkItem *items = (const WorkItem *)ctx->items.p;
-    const int2 *blocks = (const int2 *)ctx->blocks.p;
+    const WorkItem *items = bf.items;
+    const int2 *blocks = bf.blocks;
     const int nb = (int)t.blocks.size();
-    double *rs0 = (double *)ctx->rshift[0].p, *rs1 = (double *)ctx->rshift[1].p;
-    RegionPartial *rp = (RegionPartial *)ctx->rpart.p;
+    double *rs0 = bf.rshift[0], *rs1 = bf.rshift[1];
+    RegionPartial *rp = bf.rpart;
     HIP_TRY(mcpr::launch_fill_shift(prec, nr, items, n, shift, rs0, s));
     if (two_pass) {
         // first pass: region means only; second pass about each region's mean
@@ -369,7 +462,7 @@ mcpr_status records(mcpr_ctx *ctx, const Tables &t, int prec, int nreg, const mc
                     bool two_pass, int mode, const RegionMap *maps, RegionStats *out, hipStream_t s) {
     mcpr_status st = ensure_records(ctx, t, nreg);
     if (st != MCPR_OK) return st;
-    return enqueue_records(ctx, t, prec, nreg, sp, shift, two_pass, mode, maps, out, s);
+    return enqueue_records(ctx, ctx_bufs(ctx), t, prec, nreg, sp, shift, two_pass, mode, maps, out, s);
 }
 
 // The step sequence of the fine propagator on already uploaded tables:
@@ -381,17 +474,17 @@ mcpr_status records(mcpr_ctx *ctx, const Tables &t, int prec, int nreg, const mc
 // j0, j1: only steps [j0, j1) (the empirical-CDF sweep is enqueued in parts);
 // the sums of step 0 come with the first part, the moments and records with
 // the last.
-mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int variant, int m, int nreg,
-                         const mcpr::Splits &sp, bool want_stats, bool want_trace, hipStream_t s, bool profile,
-                         int cdf_lib_steps = 0, int j0 = 0, int j1 = -1) {
+mcpr_status enqueue_fine(mcpr_ctx *ctx, const Bufs &bf, const Tables &t, int prec, int deg, int variant, int m,
+                         int nreg, const mcpr::Splits &sp, bool want_stats, bool want_trace, hipStream_t s,
+                         bool profile, int cdf_lib_steps = 0, int j0 = 0, int j1 = -1) {
     if (j1 < 0) j1 = m;
     const int n = (int)t.items.size();
-    const WorkItem *items = (const WorkItem *)ctx->items.p;
-    const int2 *blocks = (const int2 *)ctx->blocks.p;
+    const WorkItem *items = bf.items;
+    const int2 *blocks = bf.blocks;
     const int nb = (int)t.blocks.size();
-    double2 *part[2] = {(double2 *)ctx->part[0].p, (double2 *)ctx->part[1].p};
-    double *shift[2] = {(double *)ctx->shift[0].p, (double *)ctx->shift[1].p};
-    double2 *trace = want_trace ? (double2 *)ctx->trace.p : nullptr;
+    double2 *const *part = bf.part;
+    double *const *shift = bf.shift;
+    double2 *trace = want_trace ? bf.trace : nullptr;
     const bool trig = t.items[0].trig != 0; // the same for every item of a call
     const bool cdf = t.items[0].cdf != 0;
     const uint32_t ndense = (uint32_t)t.total_dense;
@@ -403,7 +496,7 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
             HIP_TRY(mcpr::launch_sum_init(prec, items, blocks, nb, part[0], shift[0], s));
         if (profile) HIP_TRY(hipEventRecord(ctx->prof0[ctx->prof_used], s));
     }
-    double2 *mv = (double2 *)ctx->mv.p;
+    double2 *mv = bf.mv;
     for (int j = j0; j < j1; ++j) {
         const int a = j & 1, b = a ^ 1;
         const bool trial = variant < 0 && j < ctx->tune_steps;
@@ -440,8 +533,8 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int 
     if (want_stats) {
         // shift of the record sums: the mean the last step used (with the
         // trigonometric mean field there is none: two passes then)
-        return enqueue_records(ctx, t, prec, nreg, sp, shift[m & 1], nreg > 1 || trig, 0, nullptr,
-                               (RegionStats *)ctx->recs.p, s);
+        return enqueue_records(ctx, bf, t, prec, nreg, sp, shift[m & 1], nreg > 1 || trig, 0, nullptr, bf.recs,
+                               s);
     }
     return MCPR_OK;
 }
@@ -487,10 +580,14 @@ mcpr_status ensure_cdf(mcpr_ctx *ctx, const Tables &t, int prec) {
         if ((st = ensure(ctx, ctx->cdf_stage, mcpr::stage_bytes(prec, (int)nbk))) != MCPR_OK) return st;
     }
     if (!ctx->cdf_flag_host) {
+        if (!ctx->growing)
+            return fail(ctx, MCPR_E_NOT_RESERVED, "empirical-CDF drift: call mcpr_reserve for this call first");
         void *h = nullptr;
         if (hipHostMalloc(&h, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
             return fail(ctx, MCPR_E_OOM, "pinned host allocation failed");
         ctx->cdf_flag_host = (uint32_t *)h;
+        ctx->allocs++;
+        ctx->alloc_bytes += (int64_t)sizeof(uint32_t);
     }
     size_t tb = 0;
     HIP_TRY(mcpr::cdf_scratch_bytes(prec, (uint32_t)n, (uint32_t)nseg, tb));
@@ -525,8 +622,8 @@ mcpr_status next_prof_slot(mcpr_ctx *ctx) {
     return MCPR_OK;
 }
 
-mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int nreg, const mcpr::Splits &sp,
-                          RegionStats *stats, double2 *trace, hipStream_t s) {
+// Buffers of a fine sweep of the tables t (records and trace if wanted).
+mcpr_status size_fine(mcpr_ctx *ctx, const Tables &t, int prec, int m, int nreg, bool stats, bool trace) {
     const int n = (int)t.items.size();
     mcpr_status st;
     for (int b = 0; b < 2; ++b) {
@@ -537,6 +634,15 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
     if (trace && (st = ensure(ctx, ctx->trace, (size_t)n * (m + 1) * sizeof(double2))) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->mv, (size_t)n * sizeof(double2))) != MCPR_OK) return st;
     if (t.items[0].cdf && (st = ensure_cdf(ctx, t, prec)) != MCPR_OK) return st;
+    return MCPR_OK;
+}
+
+mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int nreg, const mcpr::Splits &sp,
+                          RegionStats *stats, double2 *trace, hipStream_t s) {
+    const int n = (int)t.items.size();
+    mcpr_status st;
+    if ((st = size_fine(ctx, t, prec, m, nreg, stats != nullptr, trace != nullptr)) != MCPR_OK) return st;
+    const Bufs bf = ctx_bufs(ctx);
     int deg = 1, max_nsc = 0;
     int64_t ps = 0;
     for (const WorkItem &w : t.items) {
@@ -564,7 +670,7 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
             const int lib = std::min(tries[a], m);
             // (the profile events of a later attempt replace those of a failed one)
             if (lib >= m) {
-                if ((st = enqueue_fine(ctx, t, prec, deg, 0, m, nreg, sp, stats != nullptr, trace != nullptr, s,
+                if ((st = enqueue_fine(ctx, bf, t, prec, deg, 0, m, nreg, sp, stats != nullptr, trace != nullptr, s,
                                        ctx->profile, lib)) != MCPR_OK)
                     return st;
                 ctx->cdf_sweeps[1]++;
@@ -575,7 +681,7 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
             for (int part = 0; part < 2 && !over; ++part) {
                 const int j0 = part == 0 ? 0 : mid, j1 = part == 0 ? mid : m;
                 if (j0 >= j1) continue;
-                if ((st = enqueue_fine(ctx, t, prec, deg, 0, m, nreg, sp, stats != nullptr, trace != nullptr, s,
+                if ((st = enqueue_fine(ctx, bf, t, prec, deg, 0, m, nreg, sp, stats != nullptr, trace != nullptr, s,
                                        ctx->profile, lib, j0, j1)) != MCPR_OK)
                     return st;
                 HIP_TRY(hipMemcpyAsync(ctx->cdf_flag_host, ctx->cdfb.flag, sizeof(uint32_t), hipMemcpyDeviceToHost,
@@ -646,8 +752,8 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
         if (!ctx->tune_ev[0][0])
             for (int k = 0; k < 2; ++k)
                 for (int j = 0; j < kTuneSteps; ++j) HIP_TRY(hipEventCreate(&ctx->tune_ev[k][j]));
-        if ((st = enqueue_fine(ctx, t, prec, deg, -1, m, nreg, sp, stats != nullptr, trace != nullptr, s, false)) !=
-            MCPR_OK)
+        if ((st = enqueue_fine(ctx, bf, t, prec, deg, -1, m, nreg, sp, stats != nullptr, trace != nullptr, s,
+                               false)) != MCPR_OK)
             return st;
         HIP_TRY(hipEventSynchronize(ctx->tune_ev[1][ctx->tune_steps - 1]));
         float tv[4] = {0, 0, 0, 0};
@@ -666,47 +772,53 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
         if ((st = next_prof_slot(ctx)) != MCPR_OK) return st;
         ctx->prof_ps[ctx->prof_used] = ps * m;
         ctx->prof_launches += m;
-        if ((st = enqueue_fine(ctx, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr, s, true)) !=
-            MCPR_OK)
+        if ((st = enqueue_fine(ctx, bf, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr, s,
+                               true)) != MCPR_OK)
             return st;
         ctx->prof_used++;
     } else if (ctx->graphs && !t.items[0].cdf) {
         // (the empirical-CDF sweep runs the library sort eagerly: never captured)
         std::vector<char> key = graph_key(ctx, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr);
-        if (!ctx->gexec || key != ctx->gkey) {
-            if (ctx->gexec) {
+        mcpr_ctx::GraphEntry *ge = nullptr;
+        for (auto &e : ctx->graphs_cached)
+            if (e.key == key) ge = &e;
+        if (!ge) {
+            if (ctx->graphs_cached.size() >= kGraphCache) {
+                // evict the least recently used sweep (after the graph stream drains)
+                size_t lru = 0;
+                for (size_t i = 1; i < ctx->graphs_cached.size(); ++i)
+                    if (ctx->graphs_cached[i].used < ctx->graphs_cached[lru].used) lru = i;
                 HIP_TRY(hipStreamSynchronize(ctx->gstream));
-                HIP_TRY(hipGraphExecDestroy(ctx->gexec));
-                ctx->gexec = nullptr;
+                HIP_TRY(hipGraphExecDestroy(ctx->graphs_cached[lru].exec));
+                ctx->graphs_cached.erase(ctx->graphs_cached.begin() + lru);
             }
             hipGraph_t g = nullptr;
             HIP_TRY(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
-            st = enqueue_fine(ctx, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr, ctx->gstream,
-                              false);
+            st = enqueue_fine(ctx, bf, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr,
+                              ctx->gstream, false);
             hipError_t ec = hipStreamEndCapture(ctx->gstream, &g);
             if (st != MCPR_OK) {
                 if (g) (void)hipGraphDestroy(g);
                 return st;
             }
             if (ec != hipSuccess) return fail(ctx, MCPR_E_DEVICE, "graph capture: %s", hipGetErrorString(ec));
-            hipError_t ei = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+            hipGraphExec_t exec = nullptr;
+            hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
-            if (ei != hipSuccess) {
-                ctx->gexec = nullptr;
-                return fail(ctx, MCPR_E_DEVICE, "graph instantiate: %s", hipGetErrorString(ei));
-            }
-            ctx->gkey = key;
+            if (ei != hipSuccess) return fail(ctx, MCPR_E_DEVICE, "graph instantiate: %s", hipGetErrorString(ei));
+            ctx->graphs_cached.push_back(mcpr_ctx::GraphEntry{key, exec, 0});
+            ge = &ctx->graphs_cached.back();
             ctx->graph_builds++;
         }
+        ge->used = ++ctx->graph_launches;
         HIP_TRY(hipEventRecord(ctx->gin, s));
         HIP_TRY(hipStreamWaitEvent(ctx->gstream, ctx->gin, 0));
-        HIP_TRY(hipGraphLaunch(ctx->gexec, ctx->gstream));
+        HIP_TRY(hipGraphLaunch(ge->exec, ctx->gstream));
         HIP_TRY(hipEventRecord(ctx->gout, ctx->gstream));
         HIP_TRY(hipStreamWaitEvent(s, ctx->gout, 0));
-        ctx->graph_launches++;
     } else {
-        if ((st = enqueue_fine(ctx, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr, s, false)) !=
-            MCPR_OK)
+        if ((st = enqueue_fine(ctx, bf, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr, s,
+                               false)) != MCPR_OK)
             return st;
     }
     if (stats)
@@ -714,6 +826,78 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
                                hipMemcpyDeviceToDevice, s));
     if (trace)
         HIP_TRY(hipMemcpyAsync(trace, ctx->trace.p, (size_t)n * (m + 1) * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    return MCPR_OK;
+}
+
+} // namespace
+
+namespace {
+
+// Tables of the adjoint's backward steps from those of the recomputed slice:
+// the backward steps have sums of their own (the adjoint's ensemble sums and
+// the gradient sums), so they need not share the forward superchunks; one quad
+// per thread below 262144 particles, where a single ensemble's launch is
+// latency bound and short blocks finish sooner.
+Tables backward_tables(const Tables &tt, int64_t P) {
+    Tables tb = tt;
+    WorkItem &w = tb.items[0];
+    w.R = P < kAdjointSmall ? 1 : mcpr::kMaxQuadsPerThread;
+    w.nsc = (int32_t)mcpr::superchunks(P, w.R);
+    tb.blocks.clear();
+    for (int sc = 0; sc < w.nsc; ++sc) tb.blocks.push_back(make_int2(0, sc));
+    tb.total_sc = w.nsc;
+    return tb;
+}
+
+// Buffers of mcpr_adjoint on ensemble e (problem p): the forward sweeps with
+// their trace and checkpoints and, with the backward sweep, the recomputed
+// trajectory, the adjoint state and the gradient sums.
+mcpr_status size_adjoint(mcpr_ctx *ctx, const mcpr_problem &p, const mcpr_ensemble &e, bool backward) {
+    const int m = p.steps_per_slice, NS = p.n_slices - e.slice;
+    const int64_t P = e.n_particles, Ps = (P + 3) / 4 * 4;
+    const size_t esz = p.precision == MCPR_FP64 ? 8 : 4;
+    mcpr_ensemble one = e;
+    one.problem = 0;
+    Tables t;
+    build_tables(&p, &one, 1, t);
+    mcpr_status st;
+    if ((st = size_upload(ctx, t, ctx->items, ctx->blocks, 0)) != MCPR_OK) return st;
+    if ((st = size_fine(ctx, t, p.precision, m, p.n_regions, false, true)) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->adj_ckpt, (size_t)(NS + 1) * Ps * esz)) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->adj_trace, (size_t)NS * (m + 1) * 2 * sizeof(double))) != MCPR_OK) return st;
+    if (!backward) return MCPR_OK;
+    if ((st = ensure(ctx, ctx->adj_traj, 2 * (size_t)(m + 1) * Ps * esz)) != MCPR_OK) return st;
+    const Tables tb = backward_tables(t, P);
+    const int nsc = tb.total_sc;
+    if ((st = size_upload(ctx, tb, ctx->adj_items, ctx->adj_blocks, 0)) != MCPR_OK) return st;
+    for (int b = 0; b < 2; ++b) {
+        if ((st = ensure(ctx, ctx->adj_lam[b], (size_t)Ps * sizeof(double))) != MCPR_OK) return st;
+        if ((st = ensure(ctx, ctx->adj_part[b], (size_t)nsc * sizeof(double2))) != MCPR_OK) return st;
+    }
+    if ((st = ensure(ctx, ctx->adj_acc, (size_t)nsc * 10 * sizeof(double))) != MCPR_OK) return st;
+    if ((st = ensure(ctx, ctx->adj_grad, 10 * sizeof(double))) != MCPR_OK) return st;
+    return ensure(ctx, ctx->adj_sums, sizeof(double2));
+}
+
+// Buffers of the calls named in `calls` (MCPR_RESERVE_*) on the ensembles of
+// t (problems: the call's problems, for the adjoint).
+mcpr_status size_calls(mcpr_ctx *ctx, const Tables &t, const mcpr_problem *problems, const mcpr_ensemble *ens,
+                       int32_t calls, size_t map_bytes) {
+    const mcpr_problem &p = problems[ens[0].problem];
+    mcpr_status st;
+    if ((st = size_upload(ctx, t, ctx->items, ctx->blocks, map_bytes)) != MCPR_OK) return st;
+    if ((calls & (MCPR_RESERVE_MOMENTS | MCPR_RESERVE_MATCH)) && (st = ensure_records(ctx, t, p.n_regions)) != MCPR_OK)
+        return st;
+    if ((calls & MCPR_RESERVE_QOI) &&
+        (st = ensure(ctx, ctx->part[0], (size_t)t.total_sc * sizeof(double2))) != MCPR_OK)
+        return st;
+    if ((calls & MCPR_RESERVE_FINE) &&
+        (st = size_fine(ctx, t, p.precision, p.steps_per_slice, p.n_regions, true, true)) != MCPR_OK)
+        return st;
+    if (calls & MCPR_RESERVE_ADJOINT) {
+        for (size_t e = 0; e < t.items.size(); ++e)
+            if ((st = size_adjoint(ctx, problems[ens[e].problem], ens[e], true)) != MCPR_OK) return st;
+    }
     return MCPR_OK;
 }
 
@@ -738,7 +922,13 @@ mcpr_status mcpr_create(mcpr_ctx **out, int32_t device) {
     if (hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->gin, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->gout, hipEventDisableTiming) != hipSuccess ||
-        hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->astream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->a_fwd, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->a_rec[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->a_rec[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->a_bwd[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->a_bwd[1], hipEventDisableTiming) != hipSuccess) {
         mcpr_destroy(ctx);
         return MCPR_E_DEVICE;
     }
@@ -770,7 +960,10 @@ void mcpr_destroy(mcpr_ctx *ctx) {
     for (int k = 0; k < 2; ++k)
         for (int j = 0; j < kTuneSteps; ++j)
             if (ctx->tune_ev[k][j]) (void)hipEventDestroy(ctx->tune_ev[k][j]);
-    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    for (auto &e : ctx->graphs_cached) (void)hipGraphExecDestroy(e.exec);
+    if (ctx->astream) (void)hipStreamDestroy(ctx->astream);
+    for (hipEvent_t e : {ctx->a_fwd, ctx->a_rec[0], ctx->a_rec[1], ctx->a_bwd[0], ctx->a_bwd[1]})
+        if (e) (void)hipEventDestroy(e);
     if (ctx->gin) (void)hipEventDestroy(ctx->gin);
     if (ctx->gout) (void)hipEventDestroy(ctx->gout);
     if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
@@ -872,6 +1065,34 @@ mcpr_status mcpr_cdf_stats(const mcpr_ctx *ctx, int64_t *bucket_sweeps, int64_t 
     return MCPR_OK;
 }
 
+mcpr_status mcpr_reserve(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems, const mcpr_ensemble *ens,
+                         int32_t n_ens, int32_t calls) {
+    mcpr_status st = check_call(ctx, problems, n_problems, ens, n_ens);
+    if (st != MCPR_OK) return st;
+    if (calls <= 0 || (calls & ~MCPR_RESERVE_ALL))
+        return fail(ctx, MCPR_E_INVALID_ARG, "calls %d: a nonempty mask of MCPR_RESERVE_*", calls);
+    if (calls & MCPR_RESERVE_ADJOINT)
+        for (int e = 0; e < n_ens; ++e) {
+            const mcpr_problem &p = problems[ens[e].problem];
+            if (ens[e].slice >= p.n_slices)
+                return fail(ctx, MCPR_E_INVALID_ARG, "ensemble %d: first slice beyond n_slices", e);
+            if (p.coef.axs != 0.0 || is_trig(p) || is_cdf(p) || p.wrap)
+                return fail(ctx, MCPR_E_UNSUPPORTED, "the adjoint needs axs = ksin = kc = acdf = 0 and no wrap");
+        }
+    HIP_TRY(hipSetDevice(ctx->device));
+    Tables t;
+    build_tables(problems, ens, n_ens, t);
+    Growing grow(ctx);
+    return size_calls(ctx, t, problems, ens, calls, 0);
+}
+
+mcpr_status mcpr_alloc_stats(const mcpr_ctx *ctx, int64_t *allocations, int64_t *bytes) {
+    if (!ctx) return MCPR_E_INVALID_ARG;
+    if (allocations) *allocations = ctx->allocs;
+    if (bytes) *bytes = ctx->alloc_bytes;
+    return MCPR_OK;
+}
+
 // ============================================================================
 // C ABI: hot-path calls
 // ============================================================================
@@ -899,6 +1120,7 @@ mcpr_status mcpr_moments(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_
     const mcpr_problem &p = problems[ens[0].problem];
     Tables t;
     build_tables(problems, ens, n_ens, t);
+    if ((st = ensure_records(ctx, t, p.n_regions)) != MCPR_OK) return st;
     if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
     return records(ctx, t, p.precision, p.n_regions, splits_of(p), nullptr, true, 0, nullptr, (RegionStats *)stats, s);
 }
@@ -913,8 +1135,8 @@ mcpr_status mcpr_qoi(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_prob
     hipStream_t s = (hipStream_t)stream;
     Tables t;
     build_tables(problems, ens, n_ens, t);
-    if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->part[0], (size_t)t.total_sc * sizeof(double2))) != MCPR_OK) return st;
+    if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
     HIP_TRY(mcpr::launch_qoi(problems[ens[0].problem].precision, kind, (const WorkItem *)ctx->items.p, n_ens,
                              (const int2 *)ctx->blocks.p, (int)t.blocks.size(), (double2 *)ctx->part[0].p, out, s));
     return MCPR_OK;
@@ -930,6 +1152,9 @@ mcpr_status mcpr_fine_propagate(mcpr_ctx *ctx, const mcpr_problem *problems, int
     const mcpr_problem &p = problems[ens[0].problem];
     Tables t;
     build_tables(problems, ens, n_ens, t);
+    if ((st = size_fine(ctx, t, p.precision, p.steps_per_slice, p.n_regions, stats != nullptr, trace != nullptr)) !=
+        MCPR_OK)
+        return st;
     if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
     return fine_sequence(ctx, t, p.precision, p.steps_per_slice, p.n_regions, splits_of(p), (RegionStats *)stats,
                          (double2 *)trace, s);
@@ -947,6 +1172,7 @@ mcpr_status mcpr_match(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_pr
     const mcpr_problem &p = problems[ens[0].problem];
     Tables t;
     build_tables(problems, ens, n_ens, t);
+    if (dry_run && (st = ensure_records(ctx, t, p.n_regions)) != MCPR_OK) return st;
     if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
     if (dry_run)
         return records(ctx, t, p.precision, p.n_regions, splits_of(p), nullptr, true, 1, (const RegionMap *)maps,
@@ -974,6 +1200,7 @@ mcpr_status mcpr_adjoint(mcpr_ctx *ctx, const mcpr_problem *problem, const mcpr_
     const int prec = p.precision;
     const size_t esz = prec == MCPR_FP64 ? 8 : 4;
     const mcpr::Splits sp = splits_of(p);
+    if ((st = size_adjoint(ctx, p, *ens, dL_dmoments != nullptr)) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->adj_ckpt, (size_t)(NS + 1) * Ps * esz)) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->adj_trace, (size_t)NS * (m + 1) * 2 * sizeof(double))) != MCPR_OK) return st;
     char *ckpt = (char *)ctx->adj_ckpt.p;
@@ -1006,26 +1233,24 @@ mcpr_status mcpr_adjoint(mcpr_ctx *ctx, const mcpr_problem *problem, const mcpr_
         }
     if (!dL_dmoments) return MCPR_OK;
 
-    // backward sweep over slices in reverse, each recomputed from its checkpoint
+    // Backward sweep over the slices in reverse.  Each slice's trajectory is
+    // recomputed from its checkpoint, out of place, on the context's second
+    // stream into one of two buffers, so that the recomputation of slice n-1
+    // runs while the backward steps of slice n do (the two chains are
+    // independent; each is a run of latency-bound launches).
+    const size_t tstride = (size_t)(m + 1) * Ps * esz;
+    if ((st = ensure(ctx, ctx->adj_traj, 2 * tstride)) != MCPR_OK) return st;
+    char *trajb[2] = {(char *)ctx->adj_traj.p, (char *)ctx->adj_traj.p + tstride};
     Tables tt;
     mcpr_ensemble et = *ens;
-    if ((st = ensure(ctx, ctx->adj_traj, (size_t)(m + 1) * Ps * esz)) != MCPR_OK) return st;
-    et.x = ctx->adj_traj.p;
+    et.x = trajb[0];
     build_tables(problem, &et, 1, tt);
     tt.items[0].traj = Ps;
     // The backward steps have sums of their own (the adjoint's ensemble sums
     // and the gradient sums), so they need not share the forward superchunks:
     // one quad per thread below 262144 particles, where a single ensemble's
     // launch is latency bound and short blocks finish sooner.
-    Tables tb = tt;
-    {
-        WorkItem &w = tb.items[0];
-        w.R = P < kAdjointSmall ? 1 : mcpr::kMaxQuadsPerThread;
-        w.nsc = (int32_t)mcpr::superchunks(P, w.R);
-        tb.blocks.clear();
-        for (int sc = 0; sc < w.nsc; ++sc) tb.blocks.push_back(make_int2(0, sc));
-        tb.total_sc = w.nsc;
-    }
+    const Tables tb = backward_tables(tt, P);
     const int nsc = tb.total_sc;
     for (int b = 0; b < 2; ++b) {
         if ((st = ensure(ctx, ctx->adj_lam[b], (size_t)Ps * sizeof(double))) != MCPR_OK) return st;
@@ -1055,12 +1280,29 @@ mcpr_status mcpr_adjoint(mcpr_ctx *ctx, const mcpr_problem *problem, const mcpr_
         a.step = (n0 + NS) * m;
         HIP_TRY(mcpr::launch_adj_init(prec, items, blocks, nb, ckpt + (size_t)NS * Ps * esz, lam[cur], a, apart[pc], s));
     }
-    char *traj = (char *)ctx->adj_traj.p;
-    for (int n = NS - 1; n >= 0; --n) {
-        HIP_TRY(hipMemcpyAsync(traj, ckpt + (size_t)n * Ps * esz, (size_t)P * esz, hipMemcpyDeviceToDevice, s));
+    hipStream_t r = ctx->astream;
+    HIP_TRY(hipEventRecord(ctx->a_fwd, s)); // the forward sweeps (and their use of the work table) are done
+    HIP_TRY(hipStreamWaitEvent(r, ctx->a_fwd, 0));
+    auto recompute = [&](int n) -> mcpr_status {
+        char *tj = trajb[n & 1];
+        HIP_TRY(hipMemcpyAsync(tj, ckpt + (size_t)n * Ps * esz, (size_t)P * esz, hipMemcpyDeviceToDevice, r));
+        tt.items[0].x = tj;
         tt.items[0].step0 = (n0 + n) * m;
-        if ((st = upload(ctx, tt, nullptr, 0, s)) != MCPR_OK) return st;
-        if ((st = fine_sequence(ctx, tt, prec, m, p.n_regions, sp, nullptr, nullptr, s)) != MCPR_OK) return st;
+        mcpr_status st2;
+        if ((st2 = upload(ctx, tt, nullptr, 0, r)) != MCPR_OK) return st2;
+        if ((st2 = fine_sequence(ctx, tt, prec, m, p.n_regions, sp, nullptr, nullptr, r)) != MCPR_OK) return st2;
+        HIP_TRY(hipEventRecord(ctx->a_rec[n & 1], r));
+        return MCPR_OK;
+    };
+    if ((st = recompute(NS - 1)) != MCPR_OK) return st;
+    for (int n = NS - 1; n >= 0; --n) {
+        if (n >= 1) {
+            // buffer (n - 1) & 1 was last read by the backward steps of slice n + 1
+            if (n + 1 < NS) HIP_TRY(hipStreamWaitEvent(r, ctx->a_bwd[(n + 1) & 1], 0));
+            if ((st = recompute(n - 1)) != MCPR_OK) return st;
+        }
+        HIP_TRY(hipStreamWaitEvent(s, ctx->a_rec[n & 1], 0));
+        char *traj = trajb[n & 1];
         const bool prof = ctx->profile;
         if (prof) {
             if (ctx->aprof_used == ctx->aprof0.size()) {
@@ -1090,6 +1332,7 @@ mcpr_status mcpr_adjoint(mcpr_ctx *ctx, const mcpr_problem *problem, const mcpr_
             cur ^= 1;
             pc ^= 1;
         }
+        HIP_TRY(hipEventRecord(ctx->a_bwd[n & 1], s));
         if (prof) {
             HIP_TRY(hipEventRecord(ctx->aprof1[ctx->aprof_used], s));
             ctx->aprof_used++;
@@ -1388,7 +1631,6 @@ char *slot_ptr(const mcpr_parareal *pr, const Instance &in, int n, int k) {
     return in.ring + (size_t)idx * in.stride * pr->esize;
 }
 
-mcpr_status pr_fail(mcpr_parareal *pr, mcpr_status st, const char *msg) { return fail(pr->ctx, st, "%s", msg); }
 
 // Fetch device records [n][I+1] into host memory (synchronises the stream).
 mcpr_status fetch(mcpr_parareal *pr, size_t count, std::vector<RegionStats> &out, hipStream_t s) {
@@ -1433,15 +1675,7 @@ mcpr_status queue_exact_qoi(mcpr_parareal *pr, const std::vector<int> &insts, mc
         pr->hq_who.emplace_back(insts[j], in.k);
     }
     if ((st = ensure(ctx, pr->dq, bytes)) != MCPR_OK) return st;
-    if (bytes > pr->hq.cap) {
-        if (pr->hq.p) HIP_TRY(hipHostFree(pr->hq.p));
-        pr->hq.p = nullptr;
-        pr->hq.cap = 0;
-        if (hipHostMalloc(&pr->hq.p, bytes, hipHostMallocDefault) != hipSuccess)
-            return fail(ctx, MCPR_E_OOM, "pinned allocation of %zu bytes failed", bytes);
-        pr->hq.cap = bytes;
-    }
-    if (!pr->hq_done) HIP_TRY(hipEventCreateWithFlags(&pr->hq_done, hipEventDisableTiming));
+    if ((st = ensure_host(ctx, pr->hq, bytes)) != MCPR_OK) return st;
     for (int kind = 0; kind < 3; ++kind)
         if ((st = mcpr_qoi(ctx, probs.data(), (int)cnt, ens.data(), (int)cnt, kind, (double *)pr->dq.p + kind * cnt,
                            stream)) != MCPR_OK)
@@ -1501,6 +1735,43 @@ mcpr_status mcpr_parareal_create(mcpr_ctx *ctx, const mcpr_problem *problems, in
         in.rec.resize((size_t)(pr->N + 1) * (pr->I + 1));
         in.flags.assign((size_t)pr->N * pr->I, 0);
         in.qcache.assign((size_t)(pr->N + 1) * 3, 0.0);
+    }
+    // Every buffer of init, iterate and qoi is sized here, for the largest
+    // batch they use (every slot of every instance: the lifting writes slices
+    // 1..N, the first iteration propagates slices 0..N-1, the QoI of one
+    // instance reads slices k..N), so those calls allocate nothing.
+    mcpr_status st = MCPR_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) st = fail(ctx, MCPR_E_DEVICE, "hipSetDevice(%d) failed", ctx->device);
+    if (st == MCPR_OK) {
+        Growing grow(ctx);
+        const int N = pr->N, I = pr->I;
+        std::vector<mcpr_problem> probs(n_inst);
+        std::vector<mcpr_ensemble> all;
+        for (int i = 0; i < n_inst; ++i) {
+            const Instance &in = pr->inst[i];
+            probs[i] = in.pb;
+            for (int n = 0; n <= N; ++n)
+                all.push_back(mcpr_ensemble{in.ring + (size_t)n * in.stride * pr->esize, in.P, in.inst, n, i, 0});
+        }
+        Tables t;
+        build_tables(probs.data(), all.data(), (int)all.size(), t);
+        const size_t nmaps = all.size() * I * sizeof(RegionMap);
+        const size_t nstats = std::max(all.size() * (I + 1) * sizeof(RegionStats), (size_t)(N + 1) * sizeof(double));
+        const size_t nq = 3 * (size_t)n_inst * sizeof(double);
+        const int32_t calls = MCPR_RESERVE_INIT | MCPR_RESERVE_MOMENTS | MCPR_RESERVE_QOI | MCPR_RESERVE_FINE |
+                              MCPR_RESERVE_MATCH;
+        if ((st = size_calls(ctx, t, probs.data(), all.data(), calls, nmaps)) == MCPR_OK &&
+            (st = ensure(ctx, pr->dstats, nstats)) == MCPR_OK && (st = ensure(ctx, pr->dmaps, nmaps)) == MCPR_OK &&
+            (st = ensure_host(ctx, pr->hmaps, nmaps)) == MCPR_OK && (st = ensure(ctx, pr->dq, nq)) == MCPR_OK &&
+            (st = ensure_host(ctx, pr->hq, nq)) == MCPR_OK) {
+            if (hipEventCreateWithFlags(&pr->hmaps_done, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&pr->hq_done, hipEventDisableTiming) != hipSuccess)
+                st = fail(ctx, MCPR_E_DEVICE, "event creation failed");
+        }
+    }
+    if (st != MCPR_OK) {
+        mcpr_parareal_destroy(pr);
+        return st;
     }
     *out = pr;
     return MCPR_OK;
@@ -1788,16 +2059,8 @@ mcpr_status mcpr_parareal_iterate(mcpr_parareal *pr, double *delta_out, mcpr_str
         const size_t mb = mmaps.size() * sizeof(RegionMap);
         if ((st = ensure(ctx, pr->dmaps, mb)) != MCPR_OK) return st;
         // through a pinned buffer, so that the call can return before the copy ends
-        if (!pr->hmaps_done) HIP_TRY(hipEventCreateWithFlags(&pr->hmaps_done, hipEventDisableTiming));
+        if ((st = ensure_host(ctx, pr->hmaps, mb)) != MCPR_OK) return st;
         HIP_TRY(hipEventSynchronize(pr->hmaps_done));
-        if (mb > pr->hmaps.cap) {
-            if (pr->hmaps.p) HIP_TRY(hipHostFree(pr->hmaps.p));
-            pr->hmaps.p = nullptr;
-            pr->hmaps.cap = 0;
-            if (hipHostMalloc(&pr->hmaps.p, mb, hipHostMallocDefault) != hipSuccess)
-                return fail(ctx, MCPR_E_OOM, "pinned allocation of %zu bytes failed", mb);
-            pr->hmaps.cap = mb;
-        }
         std::memcpy(pr->hmaps.p, mmaps.data(), mb);
         HIP_TRY(hipMemcpyAsync(pr->dmaps.p, pr->hmaps.p, mb, hipMemcpyHostToDevice, s));
         HIP_TRY(hipEventRecord(pr->hmaps_done, s));
@@ -1863,6 +2126,138 @@ mcpr_status mcpr_parareal_set_fractions(mcpr_parareal *pr, int32_t inst, const d
         if (!(fractions[j] >= 0.0) || !std::isfinite(fractions[j]))
             return fail(pr->ctx, MCPR_E_INVALID_ARG, "fraction %zu is negative or not finite", j);
     in.fgiven.assign(fractions, fractions + n);
+    return MCPR_OK;
+}
+
+} // extern "C"
+
+// ---- checkpoint and resume of the driver's host state ----------------------
+namespace {
+
+constexpr char kStateMagic[8] = {'M', 'C', 'P', 'R', 'S', 'T', '0', '1'};
+
+// Appends (or, reading, takes) plain values and arrays in a fixed order.
+struct Blob {
+    char *out = nullptr;       // writing: destination (NULL: count only)
+    const char *in = nullptr;  // reading: source
+    size_t pos = 0, cap = 0;
+    bool ok = true;
+    void raw(void *p, size_t n) {
+        if (in) {
+            if (pos + n > cap) {
+                ok = false;
+                return;
+            }
+            std::memcpy(p, in + pos, n);
+        } else if (out) {
+            std::memcpy(out + pos, p, n);
+        }
+        pos += n;
+    }
+    template <typename T> void val(T &v) { raw(&v, sizeof v); }
+    template <typename T> void vec(std::vector<T> &v) {
+        uint64_t n = v.size();
+        val(n);
+        if (in) {
+            if (!ok || n > (cap - pos) / std::max<size_t>(sizeof(T), 1)) {
+                ok = false;
+                return;
+            }
+            v.resize(n);
+        }
+        if (n) raw(v.data(), n * sizeof(T));
+    }
+};
+
+// The driver's host state in a fixed order: a header that identifies the
+// driver's shape, then per instance its iteration count, stop flag, fraction
+// fit, macro states, cached coarse outputs, records, iterator flags, QoI of
+// the exact slices and given fractions.
+void state_fields(mcpr_parareal *pr, Blob &b) {
+    char magic[8];
+    std::memcpy(magic, kStateMagic, 8);
+    b.raw(magic, 8);
+    if (b.in && std::memcmp(magic, kStateMagic, 8) != 0) b.ok = false;
+    int32_t shape[5] = {pr->N, pr->m, pr->I, pr->prec, (int32_t)pr->inst.size()};
+    int32_t got[5];
+    std::memcpy(got, shape, sizeof shape);
+    b.raw(got, sizeof got);
+    if (b.in && std::memcmp(got, shape, sizeof shape) != 0) b.ok = false;
+    int32_t k = pr->k;
+    b.val(k);
+    for (Instance &in : pr->inst) {
+        int64_t id[2] = {in.P, in.inst};
+        int64_t gid[2] = {id[0], id[1]};
+        b.raw(gid, sizeof gid);
+        if (b.in && (gid[0] != id[0] || gid[1] != id[1])) b.ok = false;
+        int32_t flags3[3] = {in.k, in.done ? 1 : 0, in.have_fit ? 1 : 0};
+        b.raw(flags3, sizeof flags3);
+        double fit[2] = {in.kappa, in.pstar};
+        b.raw(fit, sizeof fit);
+        b.vec(in.rho);
+        b.vec(in.cache);
+        b.vec(in.rec);
+        b.vec(in.st0);
+        b.vec(in.flags);
+        b.vec(in.qcache);
+        b.vec(in.fgiven);
+        if (b.in && b.ok) {
+            in.k = flags3[0];
+            in.done = flags3[1] != 0;
+            in.have_fit = flags3[2] != 0;
+            in.kappa = fit[0];
+            in.pstar = fit[1];
+        }
+    }
+    if (b.in && b.ok) pr->k = k;
+}
+
+} // namespace
+
+extern "C" {
+
+mcpr_status mcpr_parareal_save(mcpr_parareal *pr, void *buf, size_t capacity, size_t *bytes) {
+    if (!pr || !bytes) return MCPR_E_INVALID_ARG;
+    mcpr_ctx *ctx = pr->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    mcpr_status st;
+    if ((st = harvest_qoi(pr)) != MCPR_OK) return st; // the QoI still in flight belongs to the state
+    Blob count;
+    state_fields(pr, count);
+    *bytes = count.pos;
+    if (!buf) return MCPR_OK;
+    if (capacity < count.pos) return fail(ctx, MCPR_E_INVALID_ARG, "state needs %zu bytes, %zu given", count.pos, capacity);
+    Blob w;
+    w.out = (char *)buf;
+    state_fields(pr, w);
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_parareal_restore(mcpr_parareal *pr, const void *buf, size_t bytes) {
+    if (!pr || !buf) return MCPR_E_INVALID_ARG;
+    mcpr_ctx *ctx = pr->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    mcpr_status st;
+    if ((st = harvest_qoi(pr)) != MCPR_OK) return st;
+    // read into a copy first, so that a bad blob leaves the driver as it was
+    std::vector<Instance> keep = pr->inst;
+    const int k_keep = pr->k;
+    Blob r;
+    r.in = (const char *)buf;
+    r.cap = bytes;
+    state_fields(pr, r);
+    const size_t N = pr->N, I = pr->I;
+    for (const Instance &in : pr->inst)
+        if (in.rho.size() != N + 1 || in.cache.size() != N || in.rec.size() != (N + 1) * (I + 1) ||
+            in.st0.size() != (in.k > 0 || !in.st0.empty() ? I + 1 : 0) || in.flags.size() != N * I ||
+            in.qcache.size() != (N + 1) * 3 || (!in.fgiven.empty() && in.fgiven.size() != (N + 1) * I) ||
+            in.k < 0 || in.k > (int)N)
+            r.ok = false;
+    if (!r.ok || r.pos != bytes) {
+        pr->inst = keep;
+        pr->k = k_keep;
+        return fail(ctx, MCPR_E_INVALID_ARG, "not a state of this driver (shape, particle counts or length differ)");
+    }
     return MCPR_OK;
 }
 

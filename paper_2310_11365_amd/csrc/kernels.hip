@@ -162,15 +162,21 @@ __device__ __forceinline__ int region_of(double x, const Splits &sp) {
 }
 
 // ----------------------------------------------------------------------------
-// Canonical leaf of the per-step sums: one quad, d_e = x_e - shift in the state
-// type (shift is a value of that type, so it is exact in fp64 as well):
+// Canonical leaf of the per-step sums: one quad, d_e = x_e - shift formed in
+// fp64 from the state value and the shift (a value of the state type, so in
+// fp32 the difference of the two widened values is exact unless their
+// exponents are more than 29 apart):
 //   q1 = (d0 + d1) + (d2 + d3),   q2 = fma(d3, d3, fma(d2, d2, fma(d1, d1, d0 * d0)))
-// Absent particles have d = 0.  From the quad level up every sum is fp64.
+// Absent particles have d = 0.  Every sum over particles is fp64 from the
+// particle up, in fp32-state mode as well.
 // ----------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void quad_leaf(const T d[4], double &q1, double &q2) {
-    q1 = (double)((d[0] + d[1]) + (d[2] + d[3]));
-    q2 = (double)fmaT(d[3], d[3], fmaT(d[2], d[2], fmaT(d[1], d[1], d[0] * d[0])));
+__device__ __forceinline__ double leaf_diff(T x, T shift) {
+    return (double)x - (double)shift;
+}
+__device__ __forceinline__ void quad_leaf(const double d[4], double &q1, double &q2) {
+    q1 = (d[0] + d[1]) + (d[2] + d[3]);
+    q2 = fma(d[3], d[3], fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0])));
 }
 
 // Vector access to one quad through the global address space (full quads).
@@ -234,10 +240,11 @@ __global__ __launch_bounds__(kThreads) void k_sum_init(const WorkItem *__restric
     const T *xs = x + base;
     if (base + (int64_t)4 * kThreads * R <= P) {
         for (int r = 0; r < R; ++r) {
-            T v[4], d[4];
+            T v[4];
+            double d[4];
             gload_quad<false>(xs, (uint32_t)(r * kThreads + threadIdx.x), v);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) d[e] = v[e] - shift;
+            for (int e = 0; e < 4; ++e) d[e] = leaf_diff(v[e], shift);
             double q1, q2;
             quad_leaf(d, q1, q2);
             a1 += q1;
@@ -247,10 +254,11 @@ __global__ __launch_bounds__(kThreads) void k_sum_init(const WorkItem *__restric
         for (int r = 0; r < R; ++r) {
             const int64_t p = base + 4 * (int64_t)(r * kThreads + threadIdx.x);
             if (p < P) {
-                T v[4], d[4];
+                T v[4];
+                double d[4];
                 load_quad(x, p, P, v);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) d[e] = (p + e < P) ? v[e] - shift : (T)0;
+                for (int e = 0; e < 4; ++e) d[e] = (p + e < P) ? leaf_diff(v[e], shift) : 0.0;
                 double q1, q2;
                 quad_leaf(d, q1, q2);
                 a1 += q1;
@@ -363,12 +371,13 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
         for (int g = 0; g < kMaxQuadsPerThread; ++g) {
             if (g < R) {
                 const Words4 w = philox4x32_10(qb + (uint32_t)(g * kThreads), step, inst, 0u, k0, k1);
-                T z[4], d[4];
+                T z[4];
+                double d[4];
                 box_muller4(w, z);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     v[g][e] = em_update<T, DEG>(v[g][e], z[e], c0, c1, c2, c3, e0, e1);
-                    d[e] = v[g][e] - shift;
+                    d[e] = leaf_diff(v[g][e], shift);
                 }
                 gstore_quad<NT>(ys, (uint32_t)(g * kThreads + threadIdx.x), v[g]);
                 double q1, q2;
@@ -382,14 +391,15 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
         for (int r = 0; r < R; ++r) {
             const int64_t p = base + 4 * (int64_t)(r * kThreads + threadIdx.x);
             if (p < P) {
-                T v[4], z[4], d[4];
+                T v[4], z[4];
+                double d[4];
                 load_quad(x, p, P, v);
                 const Words4 w = philox4x32_10((uint32_t)(p >> 2), step, inst, 0u, k0, k1);
                 box_muller4(w, z);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     v[e] = em_update<T, DEG>(v[e], z[e], c0, c1, c2, c3, e0, e1);
-                    d[e] = (p + e < P) ? v[e] - shift : (T)0;
+                    d[e] = (p + e < P) ? leaf_diff(v[e], shift) : 0.0;
                 }
                 store_quad(y, p, P, v);
                 double q1, q2;
@@ -410,7 +420,7 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
 // with (1/P) sum_q sin(X_q - x) = S cos x - C sin x, S and C the population
 // means of sin X and cos X.  The per-step mean field is (S, C): every launch
 // writes per-superchunk partials (sum sin x, sum cos x) of its output in the
-// canonical order (quad leaf in the state type, fp64 from the quad up), and
+// canonical order (sin and cos in the state type, summed in fp64), and
 // the next launch combines them.  wrap: x <- x - 2 pi floor(x / (2 pi)).
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ void sincos_T(float x, float &s, float &c) {
@@ -436,8 +446,8 @@ __device__ __forceinline__ void trig_leaf(const T v[4], int64_t p, int64_t P, do
         sincos_T(v[e], s[e], c[e]);
         if (p + e >= P) s[e] = c[e] = (T)0;
     }
-    q1 = (double)((s[0] + s[1]) + (s[2] + s[3]));
-    q2 = (double)((c[0] + c[1]) + (c[2] + c[3]));
+    q1 = ((double)s[0] + (double)s[1]) + ((double)s[2] + (double)s[3]);
+    q2 = ((double)c[0] + (double)c[1]) + ((double)c[2] + (double)c[3]);
 }
 
 // Step-0 trigonometric sums of each superchunk.
@@ -698,7 +708,8 @@ __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__r
     const uint32_t inst = (uint32_t)W.inst;
     double a1 = 0.0, a2 = 0.0;
     for (int g = 0; g < R; ++g) {
-        T d[4], uu[4];
+        T uu[4];
+        double d[4];
         uint32_t ll[4];
         int bb[4], loc[4];
         const uint32_t r0 = base + 4u * (uint32_t)g * kThreads; // the round's first position
@@ -731,7 +742,7 @@ __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__r
         for (int e = 0; e < 4; ++e) {
             // lane-contiguous positions: every load instruction reads 64 consecutive pairs
             const uint32_t r = base + (uint32_t)(4 * g + e) * kThreads + threadIdx.x;
-            d[e] = (T)0;
+            d[e] = 0.0;
             bb[e] = -1;
             if (r < P) {
                 const T v = vv[e];
@@ -768,7 +779,7 @@ __global__ __launch_bounds__(kThreads) void k_em_step_sorted(const WorkItem *__r
                     uu[e] = u;
                     ll[e] = lab;
                 }
-                d[e] = u - shift;
+                d[e] = leaf_diff(u, shift);
             }
         }
         double q1, q2;

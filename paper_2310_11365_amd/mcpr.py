@@ -21,7 +21,8 @@ QOI_X, QOI_X2, QOI_SIN_X2 = 0, 1, 2
 MAX_REGIONS = 8
 
 STATUS = {0: "MCPR_OK", -1: "MCPR_E_INVALID_ARG", -2: "MCPR_E_OOM", -3: "MCPR_E_DEVICE",
-          -4: "MCPR_E_NONFINITE", -5: "MCPR_E_UNSUPPORTED"}
+          -4: "MCPR_E_NONFINITE", -5: "MCPR_E_UNSUPPORTED", -6: "MCPR_E_NOT_RESERVED"}
+RESERVE_INIT, RESERVE_MOMENTS, RESERVE_QOI, RESERVE_FINE, RESERVE_MATCH, RESERVE_ADJOINT = 1, 2, 4, 8, 16, 32
 
 
 class MCPRError(RuntimeError):
@@ -81,6 +82,10 @@ def lib() -> ctypes.CDLL:
         L.mcpr_last_error.argtypes = [vp]
         L.mcpr_last_error.restype = ctypes.c_char_p
         L.mcpr_version.restype = ctypes.c_char_p
+        L.mcpr_reserve.argtypes = [vp, pP, i32, pE, i32, i32]
+        L.mcpr_reserve.restype = st
+        L.mcpr_alloc_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.mcpr_alloc_stats.restype = st
         L.mcpr_init_particles.argtypes = [vp, pP, i32, pE, i32, vp]
         L.mcpr_init_particles.restype = st
         L.mcpr_moments.argtypes = [vp, pP, i32, pE, i32, vp, vp]
@@ -133,6 +138,10 @@ def lib() -> ctypes.CDLL:
         L.mcpr_parareal_set_fractions.restype = st
         L.mcpr_parareal_flags.argtypes = [vp, i32, vp]
         L.mcpr_parareal_flags.restype = st
+        L.mcpr_parareal_save.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+        L.mcpr_parareal_save.restype = st
+        L.mcpr_parareal_restore.argtypes = [vp, vp, ctypes.c_size_t]
+        L.mcpr_parareal_restore.restype = st
         L.mcpr_parareal_slot.argtypes = [vp, i32, i32, ctypes.POINTER(vp)]
         L.mcpr_parareal_slot.restype = st
         _lib = L
@@ -266,24 +275,43 @@ class Context:
         self._check(lib().mcpr_cdf_stats(self._h, *[ctypes.byref(x) for x in v]))
         return tuple(x.value for x in v)
 
+    def reserve(self, problems, ensembles, calls: int):
+        """mcpr_reserve: size the context's scratch for later calls of the
+        kinds in calls (RESERVE_*) on these ensembles (allocates only what is
+        not held yet)."""
+        P, E = self._arrays(problems, ensembles)
+        self._check(lib().mcpr_reserve(self._h, P, len(problems), E, len(ensembles), int(calls)))
+
+    def alloc_stats(self):
+        """(allocations, bytes) the context and its drivers have made so far."""
+        n, b = ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().mcpr_alloc_stats(self._h, ctypes.byref(n), ctypes.byref(b)))
+        return n.value, b.value
+
+    # The methods below reserve before each call (a no-op once the scratch
+    # suffices), so that Python callers need not size the context themselves.
     def init_particles(self, problems: Sequence[ProblemC], ensembles: Sequence[EnsembleC], stream=None):
         P, E = self._arrays(problems, ensembles)
+        self._check(lib().mcpr_reserve(self._h, P, len(problems), E, len(ensembles), RESERVE_INIT))
         self._check(lib().mcpr_init_particles(self._h, P, len(problems), E, len(ensembles), _stream(stream)))
 
     def moments(self, problems, ensembles, stats_dev, stream=None):
         """stats_dev: a device tensor of >= n_ens*(I+1)*48 bytes."""
         P, E = self._arrays(problems, ensembles)
+        self._check(lib().mcpr_reserve(self._h, P, len(problems), E, len(ensembles), RESERVE_MOMENTS))
         self._check(lib().mcpr_moments(self._h, P, len(problems), E, len(ensembles), _ptr(stats_dev),
                                        _stream(stream)))
 
     def qoi(self, problems, ensembles, kind: int, out_dev, stream=None):
         """out_dev: a float64 device tensor of >= n_ens entries; out[e] = (1/P) sum Phi(x)."""
         P, E = self._arrays(problems, ensembles)
+        self._check(lib().mcpr_reserve(self._h, P, len(problems), E, len(ensembles), RESERVE_QOI))
         self._check(lib().mcpr_qoi(self._h, P, len(problems), E, len(ensembles), int(kind), _ptr(out_dev),
                                    _stream(stream)))
 
     def fine_propagate(self, problems, ensembles, stats_dev=None, trace_dev=None, stream=None):
         P, E = self._arrays(problems, ensembles)
+        self._check(lib().mcpr_reserve(self._h, P, len(problems), E, len(ensembles), RESERVE_FINE))
         self._check(lib().mcpr_fine_propagate(self._h, P, len(problems), E, len(ensembles),
                                               _ptr(stats_dev) if stats_dev is not None else None,
                                               _ptr(trace_dev) if trace_dev is not None else None,
@@ -291,6 +319,7 @@ class Context:
 
     def match(self, problems, ensembles, maps_dev, dry_run=False, probe_dev=None, stream=None):
         P, E = self._arrays(problems, ensembles)
+        self._check(lib().mcpr_reserve(self._h, P, len(problems), E, len(ensembles), RESERVE_MATCH))
         self._check(lib().mcpr_match(self._h, P, len(problems), E, len(ensembles), _ptr(maps_dev),
                                      1 if dry_run else 0,
                                      _ptr(probe_dev) if probe_dev is not None else None, _stream(stream)))
@@ -388,6 +417,7 @@ def adjoint(ctx: Context, problem_struct: ProblemC, x0, dL_dmoments=None, instan
     e = ensemble(x0, instance, first_slice)
     P = (ProblemC * 1)(problem_struct)
     E = (EnsembleC * 1)(e)
+    ctx._check(lib().mcpr_reserve(ctx.handle, P, 1, E, 1, RESERVE_ADJOINT))
     if dL_dmoments is None:
         ctx._check(lib().mcpr_adjoint(ctx.handle, P, E, None, mom.ctypes.data, None, _stream(stream)))
         return mom, None
@@ -513,6 +543,19 @@ class Parareal:
         f = np.zeros((self.N, self.I), dtype=np.int32)
         self.ctx._check(lib().mcpr_parareal_flags(self._h, i, f.ctypes.data))
         return f
+
+    def save(self) -> bytes:
+        """The driver's host state (mcpr_parareal_save); the rings are the caller's."""
+        n = ctypes.c_size_t()
+        self.ctx._check(lib().mcpr_parareal_save(self._h, None, 0, ctypes.byref(n)))
+        buf = (ctypes.c_char * n.value)()
+        self.ctx._check(lib().mcpr_parareal_save(self._h, buf, n.value, ctypes.byref(n)))
+        return bytes(buf)
+
+    def restore(self, state: bytes):
+        """mcpr_parareal_restore (copy the rings back first)."""
+        buf = ctypes.create_string_buffer(state, len(state))
+        self.ctx._check(lib().mcpr_parareal_restore(self._h, buf, len(state)))
 
     def slot(self, i: int, n: int):
         """Tensor view of u^k_n of instance i."""

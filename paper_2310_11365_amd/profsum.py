@@ -30,13 +30,40 @@ def kernel_table(db_path: str, limit: int = 12):
     return [(short_name(r[0]), int(r[1]), float(r[2]), float(r[3]), float(r[4])) for r in rows]
 
 
-def durations(db_path: str, kernel: str):
+def grid_column(cur):
+    """Name of the kernels view's column holding the grid's x extent (in work items)."""
+    cols = [r[1] for r in cur.execute("pragma table_info(kernels)")]
+    for c in cols:
+        lc = c.lower()
+        if "grid" in lc and lc.endswith("x"):
+            return c
+    return None
+
+
+def durations(db_path: str, kernel: str, grid=None):
+    """Durations (us) of every dispatch of kernel; grid: only dispatches with
+    that x extent of the grid (work items)."""
     cur = sqlite3.connect(db_path).cursor()
+    gc = grid_column(cur)
     out = []
-    for name, d in cur.execute("select name, duration from kernels"):
-        if short_name(name).replace("mcpr::", "") == kernel:
+    q = f"select name, duration, {gc} from kernels" if gc else "select name, duration, 0 from kernels"
+    for name, d, g in cur.execute(q):
+        if short_name(name).replace("mcpr::", "") == kernel and (grid is None or int(g) == grid):
             out.append(d / 1e3)
     return out
+
+
+def grid_groups(db_path: str, kernel: str):
+    """{grid x extent: dispatch count} of kernel."""
+    cur = sqlite3.connect(db_path).cursor()
+    gc = grid_column(cur)
+    if not gc:
+        return {}
+    groups = {}
+    for name, g in cur.execute(f"select name, {gc} from kernels"):
+        if short_name(name).replace("mcpr::", "") == kernel:
+            groups[int(g)] = groups.get(int(g), 0) + 1
+    return groups
 
 
 def counter_per_dispatch(db_path: str, kernel: str):
@@ -68,6 +95,7 @@ def main():
     t = sub.add_parser("trace")
     t.add_argument("db")
     t.add_argument("--kernel", default=None)
+    t.add_argument("--grid", type=int, default=None, help="also the dispatches of --kernel with this grid x extent")
     t.add_argument("--bench-log", default=None)
     c = sub.add_parser("traffic")
     c.add_argument("fetch_db")
@@ -90,6 +118,19 @@ def main():
             if d:
                 print(f"\n`{a.kernel}`: {len(d)} dispatches, mean {statistics.mean(d):.2f} us, median "
                       f"{statistics.median(d):.2f} us, min {min(d):.2f} us, max {max(d):.2f} us")
+            groups = grid_groups(a.db, a.kernel)
+            if len(groups) > 1 or a.grid:
+                print("\n| grid (work items) | dispatches | mean us | median us |")
+                print("|---|---|---|---|")
+                for g in sorted(groups, reverse=True)[:8]:
+                    dg = durations(a.db, a.kernel, g)
+                    print(f"| {g} | {len(dg)} | {statistics.mean(dg):.2f} | {statistics.median(dg):.2f} |")
+            if a.grid:
+                dg = durations(a.db, a.kernel, a.grid)
+                if dg:
+                    print(f"\n`{a.kernel}` at grid {a.grid} (the launches of the timed steps' full sweeps): "
+                          f"{len(dg)} dispatches, mean {statistics.mean(dg):.2f} us, median "
+                          f"{statistics.median(dg):.2f} us")
         if a.bench_log:
             for line in open(a.bench_log):
                 if line.startswith("{"):

@@ -22,6 +22,18 @@ def test_header_declares_the_hot_path():
         assert n in names
 
 
+def test_header_declares_reserve_and_allocation_counter():
+    """The scratch is sized outside the hot path (mcpr_reserve) and the
+    allocations a context makes are counted (mcpr_alloc_stats); a call on an
+    unreserved shape is refused with its own status."""
+    names = declared_functions()
+    assert "mcpr_reserve" in names and "mcpr_alloc_stats" in names
+    src = open(HEADER).read()
+    assert "MCPR_E_NOT_RESERVED = -6" in src
+    for k in ("INIT", "MOMENTS", "QOI", "FINE", "MATCH", "ADJOINT"):
+        assert f"MCPR_RESERVE_{k}" in src
+
+
 def test_library_exports_every_declared_symbol():
     from paper_2310_11365_amd import mcpr
     if not os.path.exists(mcpr.LIB_PATH):

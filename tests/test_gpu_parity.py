@@ -745,9 +745,13 @@ def test_full_size_large_bimodal_parity(mc, ctx, oracle):
     """The largest workload at full size (P = 1.6e7, N = 256, 16.4 GB ring,
     fraction learning) in the benchmark's launch configuration: the initial
     macro state against the oracle's sample at that size within the fp32
-    bound, and the exact slice after one iteration bit for bit a lone fine
-    sweep of the same sample (the lone sweep's kernels are parity-tested
-    against the oracle at smaller sizes)."""
+    bound; the exact slice after one iteration bit for bit a lone fine sweep
+    of the same sample, and that slice (79 steps of 1.6e7 particles) against
+    the oracle's serial slice at full size within the fp32 bound (about a
+    minute of oracle time).  The step kernel's own fp64 sums of the final
+    state (the traced moments) are checked against the oracle's long-double
+    moments of the very same fp32 values: that isolates the reductions from
+    the fp32 state, and they must agree to 1e-13."""
     import torch
     wl = W.dz_large()
     pr = wl.problem
@@ -765,12 +769,39 @@ def test_full_size_large_bimodal_parity(mc, ctx, oracle):
         assert abs(rho[0, i, 2] - o[i]["var"]) <= FP32_V * o[i]["var"]
     slot1 = para.slot(0, 1).clone()
     para.close()
+    del para
     pc = mc.problem_c(pr)
     x = torch.empty(wl.P, dtype=torch.float32, device="cuda")
     ctx.init_particles([pc], [mc.ensemble(x, 0)])
-    ctx.fine_propagate([pc], [mc.ensemble(x, 0, 0)], mc.stats_buffer(1, 2))
+    m = pr.steps_per_slice
+    buf = mc.stats_buffer(1, 2)
+    tr = torch.empty((m + 1) * 2, dtype=torch.float64, device="cuda")
+    ctx.fine_propagate([pc], [mc.ensemble(x, 0, 0)], buf, tr)
     assert torch.equal(x, slot1)
     assert np.allclose(rho[:, :, 0].sum(axis=1), 1.0) and np.all(rho[:, :, 2] > 0)
+    g = mc.stats_to_numpy(buf, 1, 2)[0]
+    trace = tr.cpu().numpy().reshape(m + 1, 2)
+    # the step kernel's sums of the final fp32 state against exact moments of the same values
+    xh = x.cpu().numpy().astype(np.float64)
+    em, ev = oracle.moments(xh)
+    sd = math.sqrt(ev)
+    red_m, red_v = abs(trace[m, 0] - em) / sd, abs(trace[m, 1] - ev) / ev
+    print(f"fp64 step sums of the fp32 state at P=1.6e7: mean {red_m:.2e} (of sd), var {red_v:.2e}")
+    assert red_m <= 1e-13 and red_v <= 1e-13
+    # the same state's restriction records (their own fp64 pass) against the oracle's
+    assert_records_close(g, oracle.restrict(pr64, xh), 1e-13, "restriction of the fp32 state")
+    # the exact slice against the oracle's serial slice at full size
+    xo, _ = oracle.fine(pr64, oracle.sample_p0(pr64, wl.P), 0)
+    o1 = oracle.restrict(pr64, xo)
+    del xo
+    worst_m = worst_v = 0.0
+    for i in range(3):
+        assert abs(int(g[i]["n"]) - int(o1[i]["n"])) <= max(2, 1e-4 * o1[i]["n"])
+        sc = abs(o1[i]["mean"]) + math.sqrt(o1[i]["var"])
+        worst_m = max(worst_m, abs(g[i]["mean"] - o1[i]["mean"]) / sc)
+        worst_v = max(worst_v, abs(g[i]["var"] - o1[i]["var"]) / o1[i]["var"])
+    print(f"fp32 exact slice vs oracle at P=1.6e7: mean {worst_m:.2e}, var {worst_v:.2e}")
+    assert worst_m <= FP32_M and worst_v <= FP32_V
 
 
 # ---------------------------------------------------------------------------- errors
@@ -797,6 +828,195 @@ def test_invalid_arguments_are_rejected(mc, ctx):
     with pytest.raises(mc.MCPRError):
         ctx.fine_propagate([pc], [e0])
     assert torch.count_nonzero(x) == 0  # nothing launched
+
+
+def test_nonfinite_particles_are_reported(mc):
+    """A NaN or an infinity in an ensemble is flagged in its restriction
+    records (nonfinite != 0), and the Parareal driver stops with
+    MCPR_E_NONFINITE (status -4): at init for a NaN in u0, at iterate for a
+    NaN in a slice's start state (carried through its fine sweep).  A context
+    of its own: the refused calls leave the driver where they stopped."""
+    import torch
+    ctx = mc.Context(0)
+    wl = W.ou_linear(P=5000, N=4, T=0.4, precision=W.FP64)
+    pr = wl.problem
+    prop = mc.Propagator(pr, ctx)
+    x = prop.new_particles(wl.P)
+    prop.sample(x)
+    assert np.all(prop.moments([x])[0]["nonfinite"] == 0)
+    x[1234] = float("nan")
+    assert np.all(prop.moments([x])[0]["nonfinite"] != 0)
+    y = prop.new_particles(wl.P)
+    prop.sample(y)
+    y[wl.P - 1] = float("inf")
+    assert np.all(prop.moments([y])[0]["nonfinite"] != 0)
+    para = mc.Parareal([pr], [wl.P], ctx)
+    para.init()
+    para.slot(0, 0)[17] = float("nan")  # u0 (slot of slice 0 at k = 0)
+    with pytest.raises(mc.MCPRError) as e:
+        para.init(sample_u0=False)
+    assert e.value.status == -4
+    para.init()
+    para.slot(0, 2)[5] = float("nan")  # the lifted start state of slice 2
+    with pytest.raises(mc.MCPRError) as e:
+        para.iterate()
+    assert e.value.status == -4
+    torch.cuda.synchronize()
+    para.close()
+    ctx.close()
+
+
+def test_hot_path_allocates_nothing_after_reserve(mc):
+    """A call on a context whose scratch was not reserved for it is refused
+    with MCPR_E_NOT_RESERVED (status -6) before anything is launched; after
+    mcpr_reserve the same call (and smaller ones) runs without a single new
+    allocation; a Parareal driver sizes everything at create, so init and K
+    iterations (with QoI tracking and the resample probe) allocate nothing;
+    the adjoint likewise after its reserve."""
+    import ctypes
+
+    import torch
+    L = mc.lib()
+    ctx = mc.Context(0)
+    wl = W.dz_bimodal(P=100_003, N=6, T=0.3, precision=W.FP32)
+    pr = wl.problem
+    pc = mc.problem_c(pr)
+    x = torch.zeros(wl.P, dtype=torch.float32, device="cuda")
+    P_, E_ = ctx._arrays([pc], [mc.ensemble(x, 0, 0)])
+    buf = mc.stats_buffer(1, pr.n_regions)
+    st = L.mcpr_fine_propagate(ctx.handle, P_, 1, E_, 1, buf.data_ptr(), None, None)
+    assert st == -6, st
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(x)) == 0  # nothing launched
+    ctx.reserve([pc], [mc.ensemble(x, 0, 0)], mc.RESERVE_INIT | mc.RESERVE_FINE)
+    before = ctx.alloc_stats()
+    L.mcpr_init_particles(ctx.handle, P_, 1, E_, 1, None)
+    for n in range(3):
+        E_[0].slice = n
+        assert L.mcpr_fine_propagate(ctx.handle, P_, 1, E_, 1, buf.data_ptr(), None, None) == 0
+    small = torch.empty(5000, dtype=torch.float32, device="cuda")
+    Ps, Es = ctx._arrays([pc], [mc.ensemble(small, 0, 0)])
+    assert L.mcpr_init_particles(ctx.handle, Ps, 1, Es, 1, None) == 0
+    assert L.mcpr_fine_propagate(ctx.handle, Ps, 1, Es, 1, buf.data_ptr(), None, None) == 0
+    torch.cuda.synchronize()
+    assert ctx.alloc_stats() == before
+    # the driver: everything sized at create
+    para = mc.Parareal([pr], [wl.P, 70_001], ctx, learning=True)
+    para.track_qoi(True)
+    after_create = ctx.alloc_stats()
+    para.init()
+    for _ in range(4):
+        para.iterate()
+    para.qoi(mc.QOI_SIN_X2, 1)
+    torch.cuda.synchronize()
+    assert ctx.alloc_stats() == after_create
+    para.close()
+    # a point mass takes the resample branch (its dry-run probe) without allocating
+    pm = W.make_problem(W.dz_coef(), W.P0(W.P0_DELTA, 1.0, 0.5, 0.0), 0.2, 4, 1e-2, (0.0,), precision=W.FP64)
+    para = mc.Parareal([pm], [20_000], ctx)
+    a0 = ctx.alloc_stats()
+    para.init()
+    para.iterate()
+    para.iterate()
+    torch.cuda.synchronize()
+    assert ctx.alloc_stats() == a0
+    para.close()
+    # the adjoint after its reserve
+    pa = W.adjoint_case("dz", P=30_000, precision=W.FP32).problem
+    pac = mc.problem_c(pa)
+    xa = torch.empty(30_000, dtype=torch.float32, device="cuda")
+    ctx.init_particles([pac], [mc.ensemble(xa)])
+    Pa, Ea = ctx._arrays([pac], [mc.ensemble(xa)])
+    dl = np.ones((pa.n_slices, 2))
+    g = np.zeros(10)
+    mom = np.zeros((pa.n_slices, 2))
+    st = L.mcpr_adjoint(ctx.handle, Pa, Ea, dl.ctypes.data, mom.ctypes.data, g.ctypes.data, None)
+    assert st == -6, st
+    ctx.reserve([pac], [mc.ensemble(xa)], mc.RESERVE_ADJOINT)
+    a1 = ctx.alloc_stats()
+    for _ in range(2):
+        assert L.mcpr_adjoint(ctx.handle, Pa, Ea, dl.ctypes.data, mom.ctypes.data, g.ctypes.data, None) == 0
+    assert ctx.alloc_stats() == a1 and np.all(np.isfinite(g))
+    ctx.close()
+
+
+_RESUME_CHILD = r"""
+import sys, numpy as np, torch
+sys.path.insert(0, sys.argv[1])
+from paper_2310_11365_amd import mcpr, workloads as W
+wl = W.dz_bimodal(P=20_003, N=8, T=0.8, precision=W.FP32)
+para = mcpr.Parareal([wl.problem], [wl.P, 9_001], mcpr.Context(0), learning=True)
+para.track_qoi(True)
+para.init()
+for _ in range(3):
+    para.iterate()
+state = para.save()
+torch.cuda.synchronize()
+open(sys.argv[2] + ".state", "wb").write(state)
+for i in range(2):
+    np.save(sys.argv[2] + f".ring{i}.npy", para.rings[i].cpu().numpy())
+import os
+os._exit(9)  # the process ends between iterations without closing anything
+"""
+
+
+def test_parareal_resume_after_a_killed_process_is_bitwise(mc, ctx, tmp_path):
+    """Checkpoint and resume between iterations: a child process runs init
+    and three iterations of a two-instance bimodal driver with learning and
+    QoI tracking, saves the driver's state and its rings, and dies without
+    cleaning up; this process restores them into a fresh driver and runs
+    three more iterations.  Every macro state, iterator flag, QoI and ring
+    slot equals that of an uninterrupted run bit for bit (the random numbers
+    are counter-based).  A state from a differently shaped driver is refused
+    and leaves the driver unchanged."""
+    import os
+    import subprocess
+    import sys
+
+    import torch
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    base = str(tmp_path / "ckpt")
+    r = subprocess.run([sys.executable, "-c", _RESUME_CHILD, root, base], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 9, r.stderr[-2000:]
+    wl = W.dz_bimodal(P=20_003, N=8, T=0.8, precision=W.FP32)
+    sizes = [wl.P, 9_001]
+    ref = mc.Parareal([wl.problem], sizes, ctx, learning=True)
+    ref.track_qoi(True)
+    ref.init()
+    for _ in range(3):
+        ref.iterate()
+    ctx2 = mc.Context(0)
+    res = mc.Parareal([wl.problem], sizes, ctx2, learning=True)
+    res.track_qoi(True)
+    for i in range(2):
+        res.rings[i].copy_(torch.from_numpy(np.load(base + f".ring{i}.npy")).cuda())
+    res.restore(open(base + ".state", "rb").read())
+    assert res.iteration == ref.iteration == 3
+    for _ in range(3):
+        ref.iterate()
+        res.iterate()
+        torch.cuda.synchronize()
+        for i in range(2):
+            ra, ga = ref.macro(i)
+            rb, gb = res.macro(i)
+            assert np.array_equal(ra, rb) and np.array_equal(ga, gb)
+            assert np.array_equal(ref.flags(i), res.flags(i))
+            assert torch.equal(ref.rings[i], res.rings[i])
+    for i in range(2):
+        assert np.array_equal(ref.qoi(mc.QOI_SIN_X2, i), res.qoi(mc.QOI_SIN_X2, i))
+    # a state of another shape is refused; the driver keeps its own
+    other = mc.Parareal([W.dz_bimodal(P=1000, N=4, T=0.4, precision=W.FP32).problem], [1000], ctx2)
+    other.init()
+    before = res.macro(0)
+    with pytest.raises(mc.MCPRError) as e:
+        res.restore(other.save())
+    assert e.value.status == -1
+    assert all(np.array_equal(a, b) for a, b in zip(before, res.macro(0)))
+    other.close()
+    ref.close()
+    res.close()
+    ctx2.close()
 
 
 def test_unsupported_coefficient_mixes_are_rejected(mc, ctx):
@@ -944,6 +1164,54 @@ def test_adjoint_config_scale_zero_and_fd(mc, ctx, prec):
             tol = 1e-5 if prec == W.FP64 else 2e-2
             print(kind, prec, name, fd, g[i])
             assert abs(fd - g[i]) <= tol * max(abs(g[i]), 1e-8), (kind, name, fd, g[i])
+
+
+@pytest.mark.parametrize("kind", ["ou", "dz"])
+def test_adjoint_config_scale_matches_oracle(mc, ctx, oracle, kind):
+    """The adjoint workload at its own scale (P = 1e5, T = 2, dt = 1e-3,
+    N = 20, checkpoints at the slice starts every 100 steps), OU and double
+    well, fixed targets: J and dJ/d(a0..bv) in fp64 against the oracle's
+    adjoint (rtol 1e-9), and the fp32-state adjoint against the same fp64
+    oracle.  fp32: J is a sum of squared misfits, so the tested fp32 bound of
+    the slice moments (FP32_M, FP32_V) bounds its error by
+    sum_n 2 |m_n - M_n| dm_n + 2 |v_n - V_n| dv_n; the gradient's error is
+    printed and held below 1e-3 of its largest component (measured 3.1e-4
+    for OU, 5e-5 for the double well: like J's, it scales with the moment
+    error over the misfit)."""
+    wl = W.adjoint_case(kind, P=100_000, precision=W.FP64)
+    pr = wl.problem
+    t = np.arange(1, pr.n_slices + 1) * pr.dt * pr.steps_per_slice
+    if kind == "ou":
+        Mh, Vh = 0.95 * np.exp(-0.5 * t), 0.04 + 0.0 * t
+    else:
+        Mh, Vh = 0.05 + 0.0 * t, 0.9 + 0.0 * t
+    xo = oracle.sample_p0(pr, wl.P)
+    Jo, go = oracle.adjoint(pr, xo, Mh, Vh)
+    del xo
+    scale = np.max(np.abs(go))
+    for prec in (W.FP64, W.FP32):
+        prp = W.adjoint_case(kind, P=wl.P, precision=prec).problem
+        prop = mc.Propagator(prp, ctx)
+        x = prop.new_particles(wl.P)
+        prop.sample(x)
+        pc = mc.problem_c(prp)
+        mom, _ = mc.adjoint(ctx, pc, x)
+        dl = np.stack([2 * (mom[:, 0] - Mh), 2 * (mom[:, 1] - Vh)], axis=1)
+        _, g = mc.adjoint(ctx, pc, x, dl)
+        J = float(np.sum((mom[:, 0] - Mh) ** 2 + (mom[:, 1] - Vh) ** 2))
+        err_j = abs(J - Jo) / abs(Jo)
+        err_g = float(np.max(np.abs(g - go)) / scale)
+        print(f"adjoint {kind} {'fp64' if prec == W.FP64 else 'fp32'}: J rel err {err_j:.2e}, "
+              f"grad max abs err / max |grad| {err_g:.2e}")
+        if prec == W.FP64:
+            assert err_j <= 1e-10
+            np.testing.assert_allclose(g, go, rtol=1e-9, atol=1e-11 * scale)
+        else:
+            dm = FP32_M * (np.abs(mom[:, 0]) + np.sqrt(mom[:, 1]))
+            dv = FP32_V * mom[:, 1]
+            tol_j = float(np.sum(2 * np.abs(mom[:, 0] - Mh) * dm + dm ** 2 + 2 * np.abs(mom[:, 1] - Vh) * dv + dv ** 2))
+            assert abs(J - Jo) <= tol_j, (J, Jo, tol_j)
+            assert err_g <= 1e-3
 
 
 def test_adjoint_autograd_function(mc, ctx):
