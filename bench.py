@@ -129,9 +129,16 @@ def host_threads() -> int:
         return os.cpu_count() or 1
 
 
-def make_workload(name: str):
-    """(workload, per-instance particle counts, coefficient overrides, description)."""
+def make_workload(name: str, particles: int = 0):
+    """(workload, per-instance particle counts, coefficient overrides, description).
+    particles > 0 replaces the particle count of a one-instance workload."""
     from paper_2310_11365_amd import workloads as W
+    if particles > 0:
+        if name == "ou_batched":
+            raise SystemExit("--particles applies to one-instance workloads")
+        wl, _, coefs, desc = make_workload(name)
+        wl = dataclasses.replace(wl, P=particles)
+        return wl, [particles], coefs, desc + f"; particle count replaced: P={particles}"
     if name == "dz_bimodal":
         wl = W.dz_bimodal()
         return wl, [wl.P], None, ("dz_bimodal: Desai-Zwanzig dX=(X-X^3-0.5(X-E[X]))dt+0.5dW, "
@@ -219,7 +226,7 @@ def cpu_baseline(workload: str, steps: int):
 # ---------------------------------------------------------------------------
 # GPU measurements
 # ---------------------------------------------------------------------------
-def throughput(name: str, steps: int, warmup: int, variant: int):
+def throughput(name: str, steps: int, warmup: int, variant: int, particles: int = 0):
     """Whole hot-path steps (init + one iteration) of a workload: wall clock
     over the timed steps, and the step kernel's mean launch time by HIP
     events inside the timed region.  A context of its own, so that its
@@ -228,7 +235,7 @@ def throughput(name: str, steps: int, warmup: int, variant: int):
 
     from paper_2310_11365_amd import mcpr
     from paper_2310_11365_amd import workloads as W
-    wl, sizes, coefs, desc = make_workload(name)
+    wl, sizes, coefs, desc = make_workload(name, particles)
     pr = wl.problem
     N, m = pr.n_slices, pr.steps_per_slice
     ps_per_step = N * m * sum(sizes)
@@ -547,6 +554,9 @@ def main():
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD,
                     choices=["dz_large", "dz_bimodal", "ou_batched", "ou_linear", "gbm", "burgers", "adjoint_ou",
                              "adjoint_dz"])
+    ap.add_argument("--particles", type=int, default=0,
+                    help="replace the particle count of a one-instance workload (e.g. to move its ring across "
+                         "the Infinity Cache size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parareal", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
@@ -578,7 +588,7 @@ def main():
     if args.workload.startswith("adjoint_"):
         return bench_adjoint(args)
 
-    default = args.workload == DEFAULT_WORKLOAD
+    default = args.workload == DEFAULT_WORKLOAD and args.particles == 0
     cpu = None
     if default and not args.no_cpu_baseline:
         # first, before this process touches the GPU: the oracle runs in child processes
@@ -603,14 +613,14 @@ def main():
         print(f"# copy probe: {n * 4} bytes read, {n * 4} bytes written", flush=True)
         del src, dst
 
-    main_res = throughput(args.workload, args.steps, args.warmup, args.variant)
+    main_res = throughput(args.workload, args.steps, args.warmup, args.variant, args.particles)
     out = {"metric": "fine-propagator particle-steps/sec", "value": main_res["value"], "unit": "particle-steps/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_res["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": main_res["dtype"],
            "data": "synthetic", "config": main_res["config"], "roofline": main_res["roofline"]}
 
     ctx = mcpr.Context(0)
-    if not args.no_parareal:
+    if not args.no_parareal and args.particles == 0:
         out["parareal"] = parareal_section(ctx, args.workload, args.parareal_max_s, args.parareal_iters)
 
     if default and not args.no_secondary:

@@ -1002,7 +1002,10 @@ def test_parareal_resume_after_a_killed_process_is_bitwise(mc, ctx, tmp_path):
             rb, gb = res.macro(i)
             assert np.array_equal(ra, rb) and np.array_equal(ga, gb)
             assert np.array_equal(ref.flags(i), res.flags(i))
-            assert torch.equal(ref.rings[i], res.rings[i])
+            # every slot's particles (the padding of each slot to a multiple of 4 holds nothing)
+            va = ref.rings[i].view(ref.N + 1, ref.strides[i])[:, : sizes[i]]
+            vb = res.rings[i].view(res.N + 1, res.strides[i])[:, : sizes[i]]
+            assert torch.equal(va, vb)
     for i in range(2):
         assert np.array_equal(ref.qoi(mc.QOI_SIN_X2, i), res.qoi(mc.QOI_SIN_X2, i))
     # a state of another shape is refused; the driver keeps its own
