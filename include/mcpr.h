@@ -152,7 +152,7 @@ typedef struct {
  * and the graph of a new launch shape, are created on first use.)          */
 mcpr_status mcpr_create(mcpr_ctx **ctx, int32_t device);
 void mcpr_destroy(mcpr_ctx *ctx);
-const char *mcpr_last_error(const mcpr_ctx *ctx);
+const char *mcpr_last_error(const mcpr_ctx *ctx); /* NULL: the calling thread's last context-free call */
 const char *mcpr_version(void);
 
 /* Sizes the context's scratch for later calls of the kinds in `calls` on the
@@ -280,6 +280,31 @@ mcpr_status mcpr_moments(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_
 mcpr_status mcpr_fine_propagate(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems,
                                 const mcpr_ensemble *ens, int32_t n_ens, mcpr_region_stats *stats,
                                 double *trace, mcpr_stream stream);
+
+/* The fine propagator of mcpr_fine_propagate for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels, launch order and
+ * results bit for bit (the untuned default launch variant, no graph replay),
+ * with every scratch buffer in a static device array of the library
+ * (4 MiB per device, held until the process ends; its address is looked up
+ * once per device on the first call there) instead of a context.  Takes no
+ * context; the work tables are written by kernels from their arguments, so
+ * nothing is copied from host memory.  stats and trace (may be NULL) are
+ * written directly, same layout as mcpr_fine_propagate.  Asynchronous on
+ * stream, on the calling thread's current device.
+ * Limits: the scratch must hold 256-byte-aligned parts of n_ens work items
+ * (264 B each), and per superchunk (4096 particles, or 1024 below 65536
+ * particles) 40 B plus, with stats, 40 B per region and one more: about
+ * 1.4e8 particles in one call with stats and one region, 1e8 with two.  A
+ * call needing more returns MCPR_E_INVALID_ARG and launches nothing; the
+ * empirical-CDF drift
+ * (acdf != 0) returns MCPR_E_UNSUPPORTED.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (two host threads, two streams) race and give wrong results.
+ * Errors: as mcpr_fine_propagate; the text is mcpr_last_error(NULL), per host
+ * thread.                                                                    */
+mcpr_status mcpr_fine_propagate_static(const mcpr_problem *problems, int32_t n_problems, const mcpr_ensemble *ens,
+                                       int32_t n_ens, mcpr_region_stats *stats, double *trace, mcpr_stream stream);
 
 /* Matching T per region (eq. multimodal_M), in place.  maps: device,
  * [n_ens][n_regions].  dry_run != 0: nothing is written; probe (device,

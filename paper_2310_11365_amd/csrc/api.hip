@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -114,13 +115,20 @@ struct mcpr_ctx {
 
 namespace {
 
+// Error text of the calls that take no context (mcpr_fine_propagate_static),
+// per host thread.
+thread_local char g_static_err[512] = "no error";
+
 mcpr_status fail(mcpr_ctx *ctx, mcpr_status st, const char *fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    if (ctx) ctx->err = buf;
+    if (ctx)
+        ctx->err = buf;
+    else
+        std::memcpy(g_static_err, buf, sizeof buf);
     return st;
 }
 
@@ -904,6 +912,49 @@ mcpr_status size_calls(mcpr_ctx *ctx, const Tables &t, const mcpr_problem *probl
 } // namespace
 
 // ============================================================================
+// Static scratch of mcpr_fine_propagate_static (no allocation on any call)
+// ============================================================================
+// Holds the work and block tables, the step partials and shifts, the mean
+// field and the region partials of one call; each device has its own copy,
+// which lives until the process ends.  Nothing in it needs clearing: every
+// part is written before it is read within a call.
+constexpr size_t kStaticScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (the current device), looked up
+// once per device: the array's name in host code is not a device address.
+mcpr_status static_scratch(int dev, char **out) {
+    mcpr_ctx *ctx = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return fail(ctx, MCPR_E_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(ctx, MCPR_E_DEVICE, "no device address for the static scratch");
+        g_scratch_ptr[dev] = (char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MCPR_OK;
+}
+
+// Work item e (by value) and its block-table entries (e, s), s < nsc, at its
+// first superchunk.
+__global__ __launch_bounds__(mcpr::kThreads) void k_put_item(WorkItem w, int32_t e, WorkItem *__restrict__ items,
+                                                            int2 *__restrict__ blocks) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) items[e] = w;
+    for (int sc = blockIdx.x * mcpr::kThreads + threadIdx.x; sc < w.nsc; sc += gridDim.x * mcpr::kThreads)
+        blocks[w.part_off + sc] = make_int2(e, sc);
+}
+
+} // namespace
+
+// ============================================================================
 // C ABI: context
 // ============================================================================
 extern "C" {
@@ -970,7 +1021,7 @@ void mcpr_destroy(mcpr_ctx *ctx) {
     delete ctx;
 }
 
-const char *mcpr_last_error(const mcpr_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char *mcpr_last_error(const mcpr_ctx *ctx) { return ctx ? ctx->err.c_str() : g_static_err; }
 
 mcpr_status mcpr_profile_enable(mcpr_ctx *ctx, int32_t on) {
     if (!ctx) return MCPR_E_INVALID_ARG;
@@ -1158,6 +1209,76 @@ mcpr_status mcpr_fine_propagate(mcpr_ctx *ctx, const mcpr_problem *problems, int
     if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
     return fine_sequence(ctx, t, p.precision, p.steps_per_slice, p.n_regions, splits_of(p), (RegionStats *)stats,
                          (double2 *)trace, s);
+}
+
+mcpr_status mcpr_fine_propagate_static(const mcpr_problem *problems, int32_t n_problems, const mcpr_ensemble *ens,
+                                       int32_t n_ens, mcpr_region_stats *stats, double *trace, mcpr_stream stream) {
+    mcpr_ctx *ctx = nullptr; // errors go to the calling thread's context-free error text
+    mcpr_status st = check_args(ctx, problems, n_problems, ens, n_ens);
+    if (st != MCPR_OK) return st;
+    const mcpr_problem &p = problems[ens[0].problem];
+    if (is_cdf(p))
+        return fail(ctx, MCPR_E_UNSUPPORTED, "the empirical-CDF drift sorts every step and needs a context's buffers");
+    Tables t;
+    build_tables(problems, ens, n_ens, t);
+    const int n = n_ens, nr = p.n_regions + 1, m = p.steps_per_slice;
+    // the scratch layout of this call, every part 256-byte aligned
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t o_items = take((size_t)n * sizeof(WorkItem)), o_blocks = take((size_t)t.total_sc * sizeof(int2));
+    const size_t o_part0 = take((size_t)t.total_sc * sizeof(double2)), o_part1 = take((size_t)t.total_sc * sizeof(double2));
+    const size_t o_shift0 = take((size_t)n * sizeof(double)), o_shift1 = take((size_t)n * sizeof(double));
+    const size_t o_mv = take((size_t)n * sizeof(double2));
+    size_t o_rpart = 0, o_rs0 = 0, o_rs1 = 0;
+    if (stats) {
+        o_rpart = take((size_t)t.total_sc * nr * sizeof(RegionPartial));
+        o_rs0 = take((size_t)n * nr * sizeof(double));
+        o_rs1 = take((size_t)n * nr * sizeof(double));
+    }
+    if (off > kStaticScratchBytes)
+        return fail(ctx, MCPR_E_INVALID_ARG,
+                    "the call needs %zu bytes of scratch (%d superchunks, %d ensembles, %d regions); the static "
+                    "scratch holds %zu",
+                    off, t.total_sc, n, nr - 1, kStaticScratchBytes);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    char *base = nullptr;
+    if ((st = static_scratch(dev, &base)) != MCPR_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Bufs bf;
+    WorkItem *items = (WorkItem *)(base + o_items);
+    int2 *blocks = (int2 *)(base + o_blocks);
+    bf.items = items;
+    bf.blocks = blocks;
+    bf.part[0] = (double2 *)(base + o_part0);
+    bf.part[1] = (double2 *)(base + o_part1);
+    bf.shift[0] = (double *)(base + o_shift0);
+    bf.shift[1] = (double *)(base + o_shift1);
+    bf.mv = (double2 *)(base + o_mv);
+    bf.rpart = stats ? (RegionPartial *)(base + o_rpart) : nullptr;
+    bf.rshift[0] = stats ? (double *)(base + o_rs0) : nullptr;
+    bf.rshift[1] = stats ? (double *)(base + o_rs1) : nullptr;
+    bf.recs = (RegionStats *)stats;  // the records and the trace go straight to the caller's arrays
+    bf.trace = (double2 *)trace;
+    // the work and block tables are written by kernels from their arguments (nothing is copied from the host)
+    for (int e = 0; e < n; ++e) {
+        const int grid = std::max(1, std::min(1024, (t.items[e].nsc + mcpr::kThreads - 1) / mcpr::kThreads));
+        hipLaunchKernelGGL(k_put_item, dim3(grid), dim3(mcpr::kThreads), 0, s, t.items[e], e, items, blocks);
+        HIP_TRY(hipGetLastError());
+    }
+    int deg = 1, max_nsc = 0;
+    for (const WorkItem &w : t.items) {
+        if (w.c[2] != 0.0 || w.c[3] != 0.0) deg = 3;
+        max_nsc = std::max(max_nsc, w.nsc);
+    }
+    // the untuned default launch variant (every variant gives the same bits)
+    const int variant = max_nsc > mcpr::kThreads ? 2 : 0;
+    return enqueue_fine(ctx, bf, t, p.precision, deg, variant, m, p.n_regions, splits_of(p), stats != nullptr,
+                        trace != nullptr, s, false);
 }
 
 mcpr_status mcpr_match(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems, const mcpr_ensemble *ens,

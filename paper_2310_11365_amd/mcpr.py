@@ -94,6 +94,8 @@ def lib() -> ctypes.CDLL:
         L.mcpr_qoi.restype = st
         L.mcpr_fine_propagate.argtypes = [vp, pP, i32, pE, i32, vp, vp, vp]
         L.mcpr_fine_propagate.restype = st
+        L.mcpr_fine_propagate_static.argtypes = [pP, i32, pE, i32, vp, vp, vp]
+        L.mcpr_fine_propagate_static.restype = st
         L.mcpr_match.argtypes = [vp, pP, i32, pE, i32, vp, i32, vp, vp]
         L.mcpr_match.restype = st
         L.mcpr_profile_enable.argtypes = [vp, i32]
@@ -323,6 +325,19 @@ class Context:
         self._check(lib().mcpr_match(self._h, P, len(problems), E, len(ensembles), _ptr(maps_dev),
                                      1 if dry_run else 0,
                                      _ptr(probe_dev) if probe_dev is not None else None, _stream(stream)))
+
+
+def fine_propagate_static(problems, ensembles, stats_dev=None, trace_dev=None, stream=None):
+    """mcpr_fine_propagate_static: the fine propagator with its scratch in the
+    library's static device array (no context, no allocation)."""
+    L = lib()
+    P = (ProblemC * len(problems))(*problems)
+    E = (EnsembleC * len(ensembles))(*ensembles)
+    st = L.mcpr_fine_propagate_static(P, len(problems), E, len(ensembles),
+                                      _ptr(stats_dev) if stats_dev is not None else None,
+                                      _ptr(trace_dev) if trace_dev is not None else None, _stream(stream))
+    if st != 0:
+        raise MCPRError(st, L.mcpr_last_error(None).decode())
 
 
 def ensemble(x, instance=0, slice_index=0, problem=0, n=None) -> EnsembleC:
