@@ -614,6 +614,20 @@ def main():
         del src, dst
 
     main_res = throughput(args.workload, args.steps, args.warmup, args.variant, args.particles)
+    if main_res["roofline"]["bound"] == "hbm":
+        # what the memory system sustains for the step kernel's access pattern
+        # over as many bytes as the ring (in-place read and write, no arithmetic)
+        n = main_res["config"]["state_bytes"] // 4 // 4096 * 4096
+        probe = torch.ones(n, dtype=torch.float32, device="cuda")
+        ms = mcpr.stream_probe(probe, 20)
+        del probe
+        ceil = 8.0 * n / (ms / 1e3) / 1e9
+        main_res["roofline"]["stream_ceiling"] = {
+            "achieved": round(ceil, 1), "unit": "GB/s", "frac_of_peak": round(ceil / HBM_PEAK_GBS, 4),
+            "kernel_frac_of_ceiling": round(main_res["roofline"]["achieved"] / ceil, 4),
+            "what": f"mcpr_stream_probe: in-place read and write of {8 * n / 1e9:.3g} GB with the step kernel's "
+                    f"block shape and non-temporal access, no arithmetic (mean of 20 passes)"}
+        print(f"# stream ceiling {ceil:.1f} GB/s", flush=True)
     out = {"metric": "fine-propagator particle-steps/sec", "value": main_res["value"], "unit": "particle-steps/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_res["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": main_res["dtype"],

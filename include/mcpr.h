@@ -208,7 +208,17 @@ mcpr_status mcpr_profile_read(mcpr_ctx *ctx, double *em_ms, int64_t *em_launches
 mcpr_status mcpr_profile_read_adjoint(mcpr_ctx *ctx, double *ms, int64_t *launches, int64_t *particle_steps,
                                       int32_t reset);
 
-/* hipGraph replay of the fine sweep (on by default): the launch sequence of
+/* Measurement: the HBM streaming ceiling of the step kernel's access pattern
+ * (the bound its roofline fraction is read against besides the vendor
+ * peak).  reps in-place passes x <- 1.0f * x over n floats (device, 16-byte
+ * aligned, n a multiple of 4096; contents unchanged) with the step kernel's
+ * block shape (256 threads x 4 quads, non-temporal loads and stores), after
+ * one warm-up pass; ms_per_pass (host) receives the mean time of a pass,
+ * i.e. 8 n bytes moved.  Takes no context; synchronises the stream; errors
+ * as the context-free calls (mcpr_last_error(NULL)).                        */
+mcpr_status mcpr_stream_probe(void *x, int64_t n, int32_t reps, mcpr_stream stream, double *ms_per_pass);
+
+/* hipGraph replay of the fine sweep (on by default): the launch sequence of/* hipGraph replay of the fine sweep (on by default): the launch sequence of
  * a fine sweep (step-0 sums, the steps, the final moments and records) is
  * captured once per shape into a graph on a library-owned stream and
  * replayed; the caller's stream waits on it through events.  Results are

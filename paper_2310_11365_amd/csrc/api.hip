@@ -56,7 +56,9 @@ struct mcpr_ctx {
     std::string err;
     DevBuf items, blocks, part[2], shift[2], rpart, rshift[2], maps, recs;
     DevBuf adj_ckpt, adj_traj, adj_lam[2], adj_part[2], adj_acc, adj_trace, adj_grad, adj_sums; // adjoint scratch
-    DevBuf adj_items, adj_blocks; // the backward sweep's work and block tables
+    DevBuf adj_tables; // the adjoint's work tables (every slice's), block tables and upstream derivatives
+    hipGraphExec_t adj_exec = nullptr; // the adjoint's whole launch sequence, for the shape in adj_key
+    std::vector<char> adj_key;
     // empirical-CDF drift: states and labels in sorted order, the library
     // sort's item pass and scratch, the bucket engine's tables and staging
     DevBuf cdf_keys[2], cdf_lab[2], cdf_seg[2], cdf_kl[2], cdf_beg, cdf_tmp;
@@ -857,6 +859,228 @@ Tables backward_tables(const Tables &tt, int64_t P) {
     return tb;
 }
 
+// ---- adjoint: one launch sequence over device tables, run directly or replayed from a graph ----
+// Shape of an adjoint call and its host tables (counts and flags only: the
+// kernels read every per-slice item from the device).
+struct AdjPlan {
+    int prec = 0, deg = 1, variant = 0, m = 0, NS = 0, n0 = 0, nreg = 1;
+    int64_t P = 0, Ps = 0;
+    size_t esz = 4;
+    mcpr::Splits sp{};
+    bool grad = false;
+    Tables t1; // one forward or recomputed slice (one item)
+    Tables tb; // the backward steps' item
+};
+
+AdjPlan adjoint_plan(mcpr_ctx *ctx, const mcpr_problem &p, const mcpr_ensemble &e, bool grad) {
+    AdjPlan pl;
+    pl.prec = p.precision;
+    pl.m = p.steps_per_slice;
+    pl.n0 = e.slice;
+    pl.NS = p.n_slices - e.slice;
+    pl.nreg = p.n_regions;
+    pl.P = e.n_particles;
+    pl.Ps = (pl.P + 3) / 4 * 4;
+    pl.esz = p.precision == MCPR_FP64 ? 8 : 4;
+    pl.sp = splits_of(p);
+    pl.grad = grad;
+    mcpr_ensemble one = e;
+    one.problem = 0;
+    build_tables(&p, &one, 1, pl.t1);
+    pl.deg = (p.coef.a2 != 0.0 || p.coef.a3 != 0.0) ? 3 : 1;
+    // the step variant this launch shape was tuned to, else the untuned default
+    std::vector<char> tkey(6 * sizeof(int64_t));
+    const int64_t tk[6] = {pl.prec, pl.deg, 1, (int64_t)pl.t1.blocks.size(), pl.t1.total_sc, pl.P};
+    std::memcpy(tkey.data(), tk, sizeof tk);
+    const bool many = pl.t1.items[0].nsc > mcpr::kThreads;
+    pl.variant = many ? 2 : 0;
+    if (ctx->tuning >= 0) {
+        pl.variant = ctx->tuning & 3;
+    } else {
+        auto it = ctx->tuned.find(tkey);
+        if (it != ctx->tuned.end()) pl.variant = it->second;
+    }
+    Tables tt = pl.t1;
+    tt.items[0].traj = pl.Ps;
+    pl.tb = backward_tables(tt, pl.P);
+    return pl;
+}
+
+// Staging layout of the adjoint's tables: forward items [NS], recomputed
+// items [NS], the slice block table, the backward item and block table, the
+// upstream derivatives [NS][2].
+struct AdjLayout {
+    size_t fitems, ritems, fblocks, bitem, bblocks, dl, total;
+};
+AdjLayout adjoint_layout(const AdjPlan &pl) {
+    AdjLayout L;
+    size_t o = 0;
+    auto take = [&o](size_t b) {
+        const size_t r = o;
+        o += align256(b);
+        return r;
+    };
+    L.fitems = take((size_t)pl.NS * sizeof(WorkItem));
+    L.ritems = take((size_t)pl.NS * sizeof(WorkItem));
+    L.fblocks = take(pl.t1.blocks.size() * sizeof(int2));
+    L.bitem = take(sizeof(WorkItem));
+    L.bblocks = take(pl.tb.blocks.size() * sizeof(int2));
+    L.dl = take((size_t)pl.NS * 2 * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+mcpr_status upload_adjoint(mcpr_ctx *ctx, const AdjPlan &pl, const mcpr_problem &p, const mcpr_ensemble &e,
+                           const double *dL, hipStream_t s) {
+    const AdjLayout L = adjoint_layout(pl);
+    char *h;
+    mcpr_status st;
+    if ((st = stage(ctx, L.total, &h)) != MCPR_OK) return st;
+    std::memset(h, 0, L.total);
+    char *ckpt = (char *)ctx->adj_ckpt.p;
+    const size_t tstride = (size_t)(pl.m + 1) * pl.Ps * pl.esz;
+    WorkItem *fi = (WorkItem *)(h + L.fitems), *ri = (WorkItem *)(h + L.ritems);
+    for (int n = 0; n < pl.NS; ++n) {
+        fi[n] = pl.t1.items[0];
+        fi[n].x = ckpt + (size_t)(n + 1) * pl.Ps * pl.esz; // slice n runs in place on the copy of its start
+        fi[n].step0 = (pl.n0 + n) * pl.m;
+        ri[n] = pl.t1.items[0];
+        ri[n].x = (char *)ctx->adj_traj.p + (size_t)(n & 1) * tstride; // recomputed out of place
+        ri[n].traj = pl.Ps;
+        ri[n].step0 = (pl.n0 + n) * pl.m;
+    }
+    std::memcpy(h + L.fblocks, pl.t1.blocks.data(), pl.t1.blocks.size() * sizeof(int2));
+    std::memcpy(h + L.bitem, pl.tb.items.data(), sizeof(WorkItem));
+    std::memcpy(h + L.bblocks, pl.tb.blocks.data(), pl.tb.blocks.size() * sizeof(int2));
+    if (dL) std::memcpy(h + L.dl, dL, (size_t)pl.NS * 2 * sizeof(double));
+    (void)p;
+    (void)e;
+    HIP_TRY(hipMemcpyAsync(ctx->adj_tables.p, h, L.total, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(ctx->staged, s));
+    return MCPR_OK;
+}
+
+// Everything a captured adjoint depends on besides the tables' contents.
+std::vector<char> adjoint_key(mcpr_ctx *ctx, const AdjPlan &pl) {
+    const void *ptrs[] = {ctx->adj_tables.p, ctx->adj_ckpt.p, ctx->adj_traj.p, ctx->adj_trace.p, ctx->adj_lam[0].p,
+                          ctx->adj_lam[1].p, ctx->adj_part[0].p, ctx->adj_part[1].p, ctx->adj_acc.p, ctx->adj_grad.p,
+                          ctx->adj_sums.p, ctx->part[0].p, ctx->part[1].p, ctx->shift[0].p, ctx->shift[1].p, ctx->mv.p};
+    const int64_t ints[] = {pl.prec, pl.deg, pl.variant, pl.m, pl.NS, pl.n0, pl.nreg, pl.P, pl.grad ? 1 : 0};
+    std::vector<char> k(sizeof ptrs + sizeof ints + sizeof pl.sp);
+    std::memcpy(k.data(), ptrs, sizeof ptrs);
+    std::memcpy(k.data() + sizeof ptrs, ints, sizeof ints);
+    std::memcpy(k.data() + sizeof ptrs + sizeof ints, &pl.sp, sizeof pl.sp);
+    return k;
+}
+
+// The adjoint's launch sequence on stream s (forward, then the backward steps)
+// and r (the recomputations, overlapped with the backward steps of the next
+// slice).  Every scalar the kernels need comes from device memory (tables,
+// trace, upstream derivatives), so the sequence can be captured once and
+// replayed.  Forward: each slice copies its start to its checkpoint slot and
+// runs in place there with its moments traced.  Backward: see mcpr_adjoint.
+mcpr_status enqueue_adjoint(mcpr_ctx *ctx, const AdjPlan &pl, hipStream_t s, hipStream_t r, bool profile) {
+    const AdjLayout L = adjoint_layout(pl);
+    char *tab = (char *)ctx->adj_tables.p;
+    const WorkItem *fitems = (const WorkItem *)(tab + L.fitems), *ritems = (const WorkItem *)(tab + L.ritems);
+    const int2 *fblocks = (const int2 *)(tab + L.fblocks);
+    const WorkItem *bitem = (const WorkItem *)(tab + L.bitem);
+    const int2 *bblocks = (const int2 *)(tab + L.bblocks);
+    const double *dl = (const double *)(tab + L.dl);
+    const int m = pl.m, NS = pl.NS, n0 = pl.n0;
+    const size_t esz = pl.esz, slot = (size_t)pl.Ps * esz, tstride = (size_t)(m + 1) * slot;
+    char *ckpt = (char *)ctx->adj_ckpt.p;
+    char *trajb[2] = {(char *)ctx->adj_traj.p, (char *)ctx->adj_traj.p + tstride};
+    double2 *trace = (double2 *)ctx->adj_trace.p;
+    Bufs bf = ctx_bufs(ctx);
+    bf.blocks = fblocks;
+    mcpr_status st;
+    for (int n = 0; n < NS; ++n) {
+        HIP_TRY(hipMemcpyAsync(ckpt + (size_t)(n + 1) * slot, ckpt + (size_t)n * slot, (size_t)pl.P * esz,
+                               hipMemcpyDeviceToDevice, s));
+        bf.items = fitems + n;
+        bf.trace = trace + (size_t)n * (m + 1);
+        if ((st = enqueue_fine(ctx, bf, pl.t1, pl.prec, pl.deg, pl.variant, m, pl.nreg, pl.sp, false, true, s,
+                               false)) != MCPR_OK)
+            return st;
+    }
+    if (!pl.grad) return MCPR_OK;
+
+    const int nsc = pl.tb.total_sc, nb = (int)pl.tb.blocks.size();
+    double2 *sums = nsc > mcpr::kThreads ? (double2 *)ctx->adj_sums.p : nullptr;
+    double *lam[2] = {(double *)ctx->adj_lam[0].p, (double *)ctx->adj_lam[1].p};
+    double2 *apart[2] = {(double2 *)ctx->adj_part[0].p, (double2 *)ctx->adj_part[1].p};
+    double *acc = (double *)ctx->adj_acc.p;
+    const bool zprev = pl.tb.items[0].c[8] != 0.0 || pl.tb.items[0].c[9] != 0.0;
+    const double invP = 1.0 / (double)pl.P;
+    HIP_TRY(mcpr::launch_zero(acc, (int64_t)nsc * 10, s));
+    int cur = 0, pc = 0;
+    {
+        // lambda at the final state: the slice-end term of the last slice
+        mcpr::AdjRef a{nullptr, dl + 2 * (NS - 1), trace + (size_t)(NS - 1) * (m + 1) + m, invP, (n0 + NS) * m,
+                       0, 0, 0};
+        HIP_TRY(mcpr::launch_adj_init(pl.prec, bitem, bblocks, nb, ckpt + (size_t)NS * slot, lam[cur], a, apart[pc],
+                                      s));
+    }
+    // the forward sweeps (and their use of the slice scratch) are done
+    HIP_TRY(hipEventRecord(ctx->a_fwd, s));
+    HIP_TRY(hipStreamWaitEvent(r, ctx->a_fwd, 0));
+    Bufs rb = ctx_bufs(ctx);
+    rb.blocks = fblocks;
+    rb.trace = nullptr;
+    auto recompute = [&](int n) -> mcpr_status {
+        HIP_TRY(hipMemcpyAsync(trajb[n & 1], ckpt + (size_t)n * slot, (size_t)pl.P * esz, hipMemcpyDeviceToDevice, r));
+        rb.items = ritems + n;
+        mcpr_status st2;
+        if ((st2 = enqueue_fine(ctx, rb, pl.t1, pl.prec, pl.deg, pl.variant, m, pl.nreg, pl.sp, false, false, r,
+                                false)) != MCPR_OK)
+            return st2;
+        HIP_TRY(hipEventRecord(ctx->a_rec[n & 1], r));
+        return MCPR_OK;
+    };
+    if ((st = recompute(NS - 1)) != MCPR_OK) return st;
+    for (int n = NS - 1; n >= 0; --n) {
+        if (n >= 1) {
+            // buffer (n - 1) & 1 was last read by the backward steps of slice n + 1
+            if (n + 1 < NS) HIP_TRY(hipStreamWaitEvent(r, ctx->a_bwd[(n + 1) & 1], 0));
+            if ((st = recompute(n - 1)) != MCPR_OK) return st;
+        }
+        HIP_TRY(hipStreamWaitEvent(s, ctx->a_rec[n & 1], 0));
+        char *traj = trajb[n & 1];
+        if (profile) {
+            if (ctx->aprof_used == ctx->aprof0.size()) {
+                hipEvent_t e0, e1;
+                HIP_TRY(hipEventCreate(&e0));
+                HIP_TRY(hipEventCreate(&e1));
+                ctx->aprof0.push_back(e0);
+                ctx->aprof1.push_back(e1);
+            }
+            HIP_TRY(hipEventRecord(ctx->aprof0[ctx->aprof_used], s));
+        }
+        for (int j = m - 1; j >= 0; --j) {
+            mcpr::AdjRef a{trace + (size_t)n * (m + 1) + j, nullptr, nullptr, invP, (n0 + n) * m + j,
+                           (zprev && (n > 0 || j > 0)) ? 1 : 0, 1, 0};
+            if (j == 0 && n > 0) { // slice end n-1 (the state that starts slice n)
+                a.dl = dl + 2 * (n - 1);
+                a.end = trace + (size_t)(n - 1) * (m + 1) + m;
+            }
+            HIP_TRY(mcpr::launch_adj_step(pl.prec, bitem, 1, bblocks, nb, traj + (size_t)j * slot, lam[cur],
+                                          lam[cur ^ 1], a, apart[pc], sums, apart[pc ^ 1], acc, s));
+            cur ^= 1;
+            pc ^= 1;
+        }
+        HIP_TRY(hipEventRecord(ctx->a_bwd[n & 1], s));
+        if (profile) {
+            HIP_TRY(hipEventRecord(ctx->aprof1[ctx->aprof_used], s));
+            ctx->aprof_used++;
+            ctx->aprof_launches += m;
+            ctx->aprof_ps += pl.P * m;
+        }
+    }
+    HIP_TRY(mcpr::launch_adj_reduce(bitem, 1, acc, (double *)ctx->adj_grad.p, s));
+    return MCPR_OK;
+}
+
 // Buffers of mcpr_adjoint on ensemble e (problem p): the forward sweeps with
 // their trace and checkpoints and, with the backward sweep, the recomputed
 // trajectory, the adjoint state and the gradient sums.
@@ -869,21 +1093,30 @@ mcpr_status size_adjoint(mcpr_ctx *ctx, const mcpr_problem &p, const mcpr_ensemb
     Tables t;
     build_tables(&p, &one, 1, t);
     mcpr_status st;
-    if ((st = size_upload(ctx, t, ctx->items, ctx->blocks, 0)) != MCPR_OK) return st;
+    // the slice scratch of the forward sweeps and the recomputations
     if ((st = size_fine(ctx, t, p.precision, m, p.n_regions, false, true)) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->adj_ckpt, (size_t)(NS + 1) * Ps * esz)) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->adj_trace, (size_t)NS * (m + 1) * 2 * sizeof(double))) != MCPR_OK) return st;
-    if (!backward) return MCPR_OK;
+    Tables tt = t;
+    tt.items[0].traj = Ps;
+    const Tables tb = backward_tables(tt, P);
+    AdjPlan pl;
+    pl.m = m;
+    pl.NS = NS;
+    pl.t1 = t;
+    pl.tb = tb;
+    const AdjLayout L = adjoint_layout(pl);
+    if ((st = ensure(ctx, ctx->adj_tables, L.total)) != MCPR_OK) return st;
+    if ((st = ensure_host(ctx, ctx->staging, L.total)) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->adj_traj, 2 * (size_t)(m + 1) * Ps * esz)) != MCPR_OK) return st;
-    const Tables tb = backward_tables(t, P);
     const int nsc = tb.total_sc;
-    if ((st = size_upload(ctx, tb, ctx->adj_items, ctx->adj_blocks, 0)) != MCPR_OK) return st;
     for (int b = 0; b < 2; ++b) {
         if ((st = ensure(ctx, ctx->adj_lam[b], (size_t)Ps * sizeof(double))) != MCPR_OK) return st;
         if ((st = ensure(ctx, ctx->adj_part[b], (size_t)nsc * sizeof(double2))) != MCPR_OK) return st;
     }
     if ((st = ensure(ctx, ctx->adj_acc, (size_t)nsc * 10 * sizeof(double))) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->adj_grad, 10 * sizeof(double))) != MCPR_OK) return st;
+    (void)backward; // the backward buffers are sized always: a context that has run the forward alone can differentiate
     return ensure(ctx, ctx->adj_sums, sizeof(double2));
 }
 
@@ -995,7 +1228,7 @@ void mcpr_destroy(mcpr_ctx *ctx) {
                       &ctx->shift[1],      &ctx->rpart,       &ctx->rshift[0],   &ctx->rshift[1],   &ctx->maps,
                       &ctx->recs,          &ctx->adj_ckpt,    &ctx->adj_traj,    &ctx->adj_lam[0],  &ctx->adj_lam[1],
                       &ctx->adj_part[0],   &ctx->adj_part[1], &ctx->adj_acc,     &ctx->adj_trace,   &ctx->adj_grad,
-                      &ctx->adj_sums,      &ctx->adj_items,   &ctx->adj_blocks,  &ctx->trace,       &ctx->mv,
+                      &ctx->adj_sums,      &ctx->adj_tables,  &ctx->trace,       &ctx->mv,
                       &ctx->cdf_keys[0],   &ctx->cdf_keys[1], &ctx->cdf_lab[0],  &ctx->cdf_lab[1],  &ctx->cdf_seg[0],
                       &ctx->cdf_seg[1],    &ctx->cdf_kl[0],   &ctx->cdf_kl[1],   &ctx->cdf_beg,     &ctx->cdf_tmp,
                       &ctx->cdf_bcount,    &ctx->cdf_bmeta,   &ctx->cdf_stage,   &ctx->cdf_flag};
@@ -1012,6 +1245,7 @@ void mcpr_destroy(mcpr_ctx *ctx) {
         for (int j = 0; j < kTuneSteps; ++j)
             if (ctx->tune_ev[k][j]) (void)hipEventDestroy(ctx->tune_ev[k][j]);
     for (auto &e : ctx->graphs_cached) (void)hipGraphExecDestroy(e.exec);
+    if (ctx->adj_exec) (void)hipGraphExecDestroy(ctx->adj_exec);
     if (ctx->astream) (void)hipStreamDestroy(ctx->astream);
     for (hipEvent_t e : {ctx->a_fwd, ctx->a_rec[0], ctx->a_rec[1], ctx->a_bwd[0], ctx->a_bwd[1]})
         if (e) (void)hipEventDestroy(e);
@@ -1072,6 +1306,31 @@ mcpr_status mcpr_profile_read_adjoint(mcpr_ctx *ctx, double *ms, int64_t *launch
         ctx->aprof_launches = 0;
         ctx->aprof_ps = 0;
     }
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_stream_probe(void *x, int64_t n, int32_t reps, mcpr_stream stream, double *ms_per_pass) {
+    mcpr_ctx *ctx = nullptr;
+    if (!x || ((uintptr_t)x & 15) || n < 4096 || n % 4096 || n / 4 > 0xffffffffLL || reps < 1 || !ms_per_pass)
+        return fail(ctx, MCPR_E_INVALID_ARG, "stream probe: a 16-byte aligned array of a multiple of 4096 floats");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(ctx, MCPR_E_DEVICE, "event creation failed");
+    }
+    hipError_t e = mcpr::launch_stream_inplace((float *)x, n, s); // warm-up pass
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = mcpr::launch_stream_inplace((float *)x, n, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(ctx, MCPR_E_DEVICE, "stream probe: %s", hipGetErrorString(e));
+    *ms_per_pass = (double)ms / reps;
     return MCPR_OK;
 }
 
@@ -1315,155 +1574,59 @@ mcpr_status mcpr_adjoint(mcpr_ctx *ctx, const mcpr_problem *problem, const mcpr_
     if (dL_dmoments && !grad_out) return fail(ctx, MCPR_E_INVALID_ARG, "grad_out is null");
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    const mcpr_problem &p = *problem;
-    const int m = p.steps_per_slice, n0 = ens->slice, NS = p.n_slices - n0;
-    const int64_t P = ens->n_particles, Ps = (P + 3) / 4 * 4;
-    const int prec = p.precision;
-    const size_t esz = prec == MCPR_FP64 ? 8 : 4;
-    const mcpr::Splits sp = splits_of(p);
-    if ((st = size_adjoint(ctx, p, *ens, dL_dmoments != nullptr)) != MCPR_OK) return st;
-    if ((st = ensure(ctx, ctx->adj_ckpt, (size_t)(NS + 1) * Ps * esz)) != MCPR_OK) return st;
-    if ((st = ensure(ctx, ctx->adj_trace, (size_t)NS * (m + 1) * 2 * sizeof(double))) != MCPR_OK) return st;
-    char *ckpt = (char *)ctx->adj_ckpt.p;
-    double *trace_d = (double *)ctx->adj_trace.p;
-
-    // forward: checkpoint every slice start, trace every step's moments
-    HIP_TRY(hipMemcpyAsync(ckpt, ens->x, (size_t)P * esz, hipMemcpyDeviceToDevice, s));
-    for (int n = 0; n < NS; ++n) {
-        char *dst = ckpt + (size_t)(n + 1) * Ps * esz;
-        HIP_TRY(hipMemcpyAsync(dst, ckpt + (size_t)n * Ps * esz, (size_t)P * esz, hipMemcpyDeviceToDevice, s));
-        mcpr_ensemble e = *ens;
-        e.x = dst;
-        e.slice = n0 + n;
-        Tables t;
-        build_tables(problem, &e, 1, t);
-        if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
-        if ((st = fine_sequence(ctx, t, prec, m, p.n_regions, sp, nullptr,
-                                (double2 *)(trace_d + (size_t)n * (m + 1) * 2), s)) != MCPR_OK)
-            return st;
+    if ((st = size_adjoint(ctx, *problem, *ens, dL_dmoments != nullptr)) != MCPR_OK) return st;
+    AdjPlan pl = adjoint_plan(ctx, *problem, *ens, dL_dmoments != nullptr);
+    const int m = pl.m, NS = pl.NS;
+    // the work tables of every forward and recomputed slice, the backward
+    // item and the upstream derivatives: one upload
+    if ((st = upload_adjoint(ctx, pl, *problem, *ens, dL_dmoments, s)) != MCPR_OK) return st;
+    HIP_TRY(hipMemcpyAsync(ctx->adj_ckpt.p, ens->x, (size_t)pl.P * pl.esz, hipMemcpyDeviceToDevice, s));
+    if (ctx->graphs && !ctx->profile) {
+        // the whole sequence from one graph, instantiated once per shape
+        std::vector<char> key = adjoint_key(ctx, pl);
+        if (!ctx->adj_exec || key != ctx->adj_key) {
+            if (ctx->adj_exec) {
+                HIP_TRY(hipStreamSynchronize(ctx->gstream));
+                HIP_TRY(hipGraphExecDestroy(ctx->adj_exec));
+                ctx->adj_exec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
+            st = enqueue_adjoint(ctx, pl, ctx->gstream, ctx->astream, false);
+            hipError_t ec = hipStreamEndCapture(ctx->gstream, &g);
+            if (st != MCPR_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (ec != hipSuccess) return fail(ctx, MCPR_E_DEVICE, "adjoint graph capture: %s", hipGetErrorString(ec));
+            hipError_t ei = hipGraphInstantiate(&ctx->adj_exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ei != hipSuccess) {
+                ctx->adj_exec = nullptr;
+                return fail(ctx, MCPR_E_DEVICE, "adjoint graph instantiate: %s", hipGetErrorString(ei));
+            }
+            ctx->adj_key = key;
+            ctx->graph_builds++;
+        }
+        HIP_TRY(hipEventRecord(ctx->gin, s));
+        HIP_TRY(hipStreamWaitEvent(ctx->gstream, ctx->gin, 0));
+        HIP_TRY(hipGraphLaunch(ctx->adj_exec, ctx->gstream));
+        HIP_TRY(hipEventRecord(ctx->gout, ctx->gstream));
+        HIP_TRY(hipStreamWaitEvent(s, ctx->gout, 0));
+        ctx->graph_launches++;
+    } else if ((st = enqueue_adjoint(ctx, pl, s, ctx->astream, ctx->profile)) != MCPR_OK) {
+        return st;
     }
     std::vector<double> tr((size_t)NS * (m + 1) * 2);
-    HIP_TRY(hipMemcpyAsync(tr.data(), trace_d, tr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(tr.data(), ctx->adj_trace.p, tr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (dL_dmoments)
+        HIP_TRY(hipMemcpyAsync(grad_out, ctx->adj_grad.p, 10 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    auto tm = [&](int n, int j) { return tr[((size_t)n * (m + 1) + j) * 2]; };
-    auto tv = [&](int n, int j) { return tr[((size_t)n * (m + 1) + j) * 2 + 1]; };
     if (moments_out)
         for (int n = 0; n < NS; ++n) {
-            moments_out[2 * n] = tm(n, m);
-            moments_out[2 * n + 1] = tv(n, m);
+            moments_out[2 * n] = tr[((size_t)n * (m + 1) + m) * 2];
+            moments_out[2 * n + 1] = tr[((size_t)n * (m + 1) + m) * 2 + 1];
         }
-    if (!dL_dmoments) return MCPR_OK;
-
-    // Backward sweep over the slices in reverse.  Each slice's trajectory is
-    // recomputed from its checkpoint, out of place, on the context's second
-    // stream into one of two buffers, so that the recomputation of slice n-1
-    // runs while the backward steps of slice n do (the two chains are
-    // independent; each is a run of latency-bound launches).
-    const size_t tstride = (size_t)(m + 1) * Ps * esz;
-    if ((st = ensure(ctx, ctx->adj_traj, 2 * tstride)) != MCPR_OK) return st;
-    char *trajb[2] = {(char *)ctx->adj_traj.p, (char *)ctx->adj_traj.p + tstride};
-    Tables tt;
-    mcpr_ensemble et = *ens;
-    et.x = trajb[0];
-    build_tables(problem, &et, 1, tt);
-    tt.items[0].traj = Ps;
-    // The backward steps have sums of their own (the adjoint's ensemble sums
-    // and the gradient sums), so they need not share the forward superchunks:
-    // one quad per thread below 262144 particles, where a single ensemble's
-    // launch is latency bound and short blocks finish sooner.
-    const Tables tb = backward_tables(tt, P);
-    const int nsc = tb.total_sc;
-    for (int b = 0; b < 2; ++b) {
-        if ((st = ensure(ctx, ctx->adj_lam[b], (size_t)Ps * sizeof(double))) != MCPR_OK) return st;
-        if ((st = ensure(ctx, ctx->adj_part[b], (size_t)nsc * sizeof(double2))) != MCPR_OK) return st;
-    }
-    if ((st = ensure(ctx, ctx->adj_acc, (size_t)nsc * 10 * sizeof(double))) != MCPR_OK) return st;
-    if ((st = ensure(ctx, ctx->adj_grad, 10 * sizeof(double))) != MCPR_OK) return st;
-    if ((st = ensure(ctx, ctx->adj_sums, sizeof(double2))) != MCPR_OK) return st;
-    // more than 256 superchunks: one launch forms the adjoint's ensemble sums
-    double2 *sums = nsc > mcpr::kThreads ? (double2 *)ctx->adj_sums.p : nullptr;
-    if ((st = upload_into(ctx, tb, ctx->adj_items, ctx->adj_blocks, nullptr, 0, s)) != MCPR_OK) return st;
-    HIP_TRY(hipMemsetAsync(ctx->adj_acc.p, 0, (size_t)nsc * 10 * sizeof(double), s));
-    const WorkItem *items = (const WorkItem *)ctx->adj_items.p;
-    const int2 *blocks = (const int2 *)ctx->adj_blocks.p;
-    const int nb = (int)tb.blocks.size();
-    double *lam[2] = {(double *)ctx->adj_lam[0].p, (double *)ctx->adj_lam[1].p};
-    double2 *apart[2] = {(double2 *)ctx->adj_part[0].p, (double2 *)ctx->adj_part[1].p};
-    const bool zprev = p.coef.bm != 0.0 || p.coef.bv != 0.0;
-    const double invP = 1.0 / (double)P;
-    int cur = 0, pc = 0;
-    {
-        // lambda at the final state: the slice-end term of the last slice
-        mcpr::AdjStep a{};
-        a.dm = dL_dmoments[2 * (NS - 1)] * invP;
-        a.dv = 2.0 * dL_dmoments[2 * (NS - 1) + 1] * invP;
-        a.mdir = tm(NS - 1, m);
-        a.step = (n0 + NS) * m;
-        HIP_TRY(mcpr::launch_adj_init(prec, items, blocks, nb, ckpt + (size_t)NS * Ps * esz, lam[cur], a, apart[pc], s));
-    }
-    hipStream_t r = ctx->astream;
-    HIP_TRY(hipEventRecord(ctx->a_fwd, s)); // the forward sweeps (and their use of the work table) are done
-    HIP_TRY(hipStreamWaitEvent(r, ctx->a_fwd, 0));
-    auto recompute = [&](int n) -> mcpr_status {
-        char *tj = trajb[n & 1];
-        HIP_TRY(hipMemcpyAsync(tj, ckpt + (size_t)n * Ps * esz, (size_t)P * esz, hipMemcpyDeviceToDevice, r));
-        tt.items[0].x = tj;
-        tt.items[0].step0 = (n0 + n) * m;
-        mcpr_status st2;
-        if ((st2 = upload(ctx, tt, nullptr, 0, r)) != MCPR_OK) return st2;
-        if ((st2 = fine_sequence(ctx, tt, prec, m, p.n_regions, sp, nullptr, nullptr, r)) != MCPR_OK) return st2;
-        HIP_TRY(hipEventRecord(ctx->a_rec[n & 1], r));
-        return MCPR_OK;
-    };
-    if ((st = recompute(NS - 1)) != MCPR_OK) return st;
-    for (int n = NS - 1; n >= 0; --n) {
-        if (n >= 1) {
-            // buffer (n - 1) & 1 was last read by the backward steps of slice n + 1
-            if (n + 1 < NS) HIP_TRY(hipStreamWaitEvent(r, ctx->a_bwd[(n + 1) & 1], 0));
-            if ((st = recompute(n - 1)) != MCPR_OK) return st;
-        }
-        HIP_TRY(hipStreamWaitEvent(s, ctx->a_rec[n & 1], 0));
-        char *traj = trajb[n & 1];
-        const bool prof = ctx->profile;
-        if (prof) {
-            if (ctx->aprof_used == ctx->aprof0.size()) {
-                hipEvent_t e0, e1;
-                HIP_TRY(hipEventCreate(&e0));
-                HIP_TRY(hipEventCreate(&e1));
-                ctx->aprof0.push_back(e0);
-                ctx->aprof1.push_back(e1);
-            }
-            HIP_TRY(hipEventRecord(ctx->aprof0[ctx->aprof_used], s));
-        }
-        for (int j = m - 1; j >= 0; --j) {
-            mcpr::AdjStep a{};
-            a.m = tm(n, j);
-            a.v = tv(n, j);
-            a.step = (n0 + n) * m + j;
-            a.grad = 1;
-            a.zprev = (zprev && (n > 0 || j > 0)) ? 1 : 0;
-            if (j == 0 && n > 0) { // slice end n-1 (the state that starts slice n)
-                a.dm = dL_dmoments[2 * (n - 1)] * invP;
-                a.dv = 2.0 * dL_dmoments[2 * (n - 1) + 1] * invP;
-                a.mdir = tm(n - 1, m);
-            }
-            HIP_TRY(mcpr::launch_adj_step(prec, items, 1, blocks, nb, traj + (size_t)j * Ps * esz, lam[cur],
-                                          lam[cur ^ 1], a, apart[pc], sums, apart[pc ^ 1], (double *)ctx->adj_acc.p,
-                                          s));
-            cur ^= 1;
-            pc ^= 1;
-        }
-        HIP_TRY(hipEventRecord(ctx->a_bwd[n & 1], s));
-        if (prof) {
-            HIP_TRY(hipEventRecord(ctx->aprof1[ctx->aprof_used], s));
-            ctx->aprof_used++;
-            ctx->aprof_launches += m;
-            ctx->aprof_ps += P * m;
-        }
-    }
-    HIP_TRY(mcpr::launch_adj_reduce(items, 1, (const double *)ctx->adj_acc.p, (double *)ctx->adj_grad.p, s));
-    HIP_TRY(hipMemcpyAsync(grad_out, ctx->adj_grad.p, 10 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
     return MCPR_OK;
 }
 

@@ -16,6 +16,8 @@
 
 #include <cstdint>
 
+#include <hip/hip_runtime.h>
+
 namespace mcpr {
 
 constexpr int kThreads = 256;        // threads per block; fixed by the canonical tree
@@ -91,6 +93,23 @@ struct AdjStep {
     int32_t step;     // global step index s
     int32_t zprev;    // 1: form sum lambda_s z_{s-1} for the next launch
     int32_t grad;     // 1: accumulate the parameter gradient of step s
+    int32_t pad;
+};
+
+// Where the scalars of a backward step live on the device, so that a whole
+// adjoint can be replayed from a graph while they change from call to call:
+// the step's traced moments (m_s, v_s) (NULL: none, the initial step), and
+// for a step at a slice end the upstream derivatives dL/d(m, v) of that end
+// (NULL: no direct term) and its traced (mean, variance).  The step's
+// AdjStep follows as dm = dl[0] invP, dv = 2 dl[1] invP, mdir = end->x.
+struct AdjRef {
+    const double2 *mv;
+    const double *dl;
+    const double2 *end;
+    double invP;
+    int32_t step;
+    int32_t zprev;
+    int32_t grad;
     int32_t pad;
 };
 

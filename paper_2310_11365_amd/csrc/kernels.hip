@@ -951,13 +951,33 @@ __global__ __launch_bounds__(kThreads) void k_finish(const WorkItem *__restrict_
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ double adj_leaf(const double d[4]) { return (d[0] + d[1]) + (d[2] + d[3]); }
 
+// The step's scalars from where they live on the device (uniform loads).
+__device__ __forceinline__ AdjStep resolve_adj(const AdjRef &r) {
+    AdjStep a{};
+    a.step = r.step;
+    a.zprev = r.zprev;
+    a.grad = r.grad;
+    if (r.mv) {
+        const double2 t = *r.mv;
+        a.m = t.x;
+        a.v = t.y;
+    }
+    if (r.dl) {
+        a.dm = r.dl[0] * r.invP;
+        a.dv = 2.0 * r.dl[1] * r.invP;
+        a.mdir = r.end->x;
+    }
+    return a;
+}
+
 // lambda_S = direct term at the final state; partials for step S-1.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_adj_init(const WorkItem *__restrict__ items,
                                                        const int2 *__restrict__ blocks, const T *__restrict__ xS,
-                                                       double *__restrict__ lam, AdjStep a,
+                                                       double *__restrict__ lam, AdjRef ar,
                                                        double2 *__restrict__ part_out) {
     __shared__ double lds[8];
+    const AdjStep a = resolve_adj(ar);
     const int2 bt = blocks[blockIdx.x];
     const WorkItem &W = items[bt.x];
     const int64_t P = W.P;
@@ -1011,11 +1031,12 @@ template <typename T, bool PRE>
 __global__ __launch_bounds__(kThreads) void k_adj_step(const WorkItem *__restrict__ items,
                                                        const int2 *__restrict__ blocks, const T *__restrict__ xs_,
                                                        const double *__restrict__ lam_in,
-                                                       double *__restrict__ lam_out, AdjStep a,
+                                                       double *__restrict__ lam_out, AdjRef ar,
                                                        const double2 *__restrict__ part_in,
                                                        const double2 *__restrict__ sums,
                                                        double2 *__restrict__ part_out, double *__restrict__ acc) {
     __shared__ double lds[4 * 8];
+    const AdjStep a = resolve_adj(ar);
     const int2 bt = blocks[blockIdx.x];
     const WorkItem &W = items[bt.x];
     const int64_t P = W.P;
@@ -1120,6 +1141,35 @@ __global__ __launch_bounds__(kThreads) void k_adj_step(const WorkItem *__restric
             ac[9] += sdt * a.v * sm[4];
         }
     }
+}
+
+// The streaming ceiling of the step kernel's access pattern: every block
+// reads its superchunk of 256 x 4 quads (non-temporal, all loads issued before
+// any store), multiplies by a and writes it back in place.  No arithmetic of
+// the method; a measurement of what the memory system sustains for it.
+__global__ __launch_bounds__(kThreads) void k_stream_inplace(float *__restrict__ x, float a) {
+    const uint32_t q0 = blockIdx.x * (uint32_t)(kThreads * kMaxQuadsPerThread) + threadIdx.x;
+    float v[kMaxQuadsPerThread][4];
+#pragma unroll
+    for (int g = 0; g < kMaxQuadsPerThread; ++g) gload_quad<true>(x, q0 + (uint32_t)(g * kThreads), v[g]);
+#pragma unroll
+    for (int g = 0; g < kMaxQuadsPerThread; ++g) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[g][e] *= a;
+        gstore_quad<true>(x, q0 + (uint32_t)(g * kThreads), v[g]);
+    }
+}
+
+hipError_t launch_stream_inplace(float *x, int64_t n, hipStream_t s) {
+    const int64_t per_block = (int64_t)4 * kThreads * kMaxQuadsPerThread;
+    hipLaunchKernelGGL(k_stream_inplace, dim3((unsigned)(n / per_block)), dim3(kThreads), 0, s, x, 1.0f);
+    return hipGetLastError();
+}
+
+// n doubles set to zero (a kernel, not a memset, so that it can be replayed from a graph).
+__global__ __launch_bounds__(kThreads) void k_zero(double *__restrict__ x, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        x[i] = 0.0;
 }
 
 // Sum of the per-superchunk gradient accumulators of one item (one block).
@@ -1640,7 +1690,7 @@ hipError_t launch_finish(const WorkItem *items, int n_items, const double2 *part
 }
 
 hipError_t launch_adj_init(int prec, const WorkItem *items, const int2 *blocks, int nblocks, const void *xS,
-                           double *lam, const AdjStep &a, double2 *part_out, hipStream_t s) {
+                           double *lam, const AdjRef &a, double2 *part_out, hipStream_t s) {
     if (prec == 0)
         hipLaunchKernelGGL(k_adj_init<double>, dim3(nblocks), dim3(kThreads), 0, s, items, blocks, (const double *)xS,
                            lam, a, part_out);
@@ -1652,7 +1702,7 @@ hipError_t launch_adj_init(int prec, const WorkItem *items, const int2 *blocks, 
 
 template <typename T>
 static void adj_step_variant(bool pre, const WorkItem *items, const int2 *blocks, int nblocks, const void *xs,
-                             const double *lam_in, double *lam_out, const AdjStep &a, const double2 *part_in,
+                             const double *lam_in, double *lam_out, const AdjRef &a, const double2 *part_in,
                              const double2 *sums, double2 *part_out, double *acc, hipStream_t s) {
     if (pre)
         hipLaunchKernelGGL((k_adj_step<T, true>), dim3(nblocks), dim3(kThreads), 0, s, items, blocks,
@@ -1663,7 +1713,7 @@ static void adj_step_variant(bool pre, const WorkItem *items, const int2 *blocks
 }
 
 hipError_t launch_adj_step(int prec, const WorkItem *items, int n_items, const int2 *blocks, int nblocks,
-                           const void *xs, const double *lam_in, double *lam_out, const AdjStep &a,
+                           const void *xs, const double *lam_in, double *lam_out, const AdjRef &a,
                            const double2 *part_in, double2 *sums, double2 *part_out, double *acc, hipStream_t s) {
     if (sums) hipLaunchKernelGGL(k_item_sums, dim3(n_items), dim3(kThreads), 0, s, items, part_in, sums);
     if (prec == 0)
@@ -1672,6 +1722,12 @@ hipError_t launch_adj_step(int prec, const WorkItem *items, int n_items, const i
     else
         adj_step_variant<float>(sums != nullptr, items, blocks, nblocks, xs, lam_in, lam_out, a, part_in, sums,
                                 part_out, acc, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double *x, int64_t n, hipStream_t s) {
+    const int64_t nb = (n + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)(nb < 1024 ? (nb > 0 ? nb : 1) : 1024)), dim3(kThreads), 0, s, x, n);
     return hipGetLastError();
 }
 

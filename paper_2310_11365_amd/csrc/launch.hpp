@@ -21,14 +21,19 @@ hipError_t launch_em_step(int prec, int deg, int variant, const WorkItem *items,
 hipError_t launch_finish(const WorkItem *items, int n_items, const double2 *part_in, const double *shift_in,
                          double2 *trace, int m, hipStream_t s);
 hipError_t launch_adj_init(int prec, const WorkItem *items, const int2 *blocks, int nblocks, const void *xS,
-                           double *lam, const AdjStep &a, double2 *part_out, hipStream_t s);
+                           double *lam, const AdjRef &a, double2 *part_out, hipStream_t s);
 // sums: scratch of n_items entries; when given, the two ensemble sums of the
 // adjoint are formed once per item by a separate launch (for ensembles of many
 // superchunks) instead of by every block.
 hipError_t launch_adj_step(int prec, const WorkItem *items, int n_items, const int2 *blocks, int nblocks,
-                           const void *xs, const double *lam_in, double *lam_out, const AdjStep &a,
+                           const void *xs, const double *lam_in, double *lam_out, const AdjRef &a,
                            const double2 *part_in, double2 *sums, double2 *part_out, double *acc, hipStream_t s);
 hipError_t launch_adj_reduce(const WorkItem *items, int n_items, const double *acc, double *out, hipStream_t s);
+// In-place streaming pass over n floats (n a multiple of 4096) with the step
+// kernel's block shape (the measurement behind mcpr_stream_probe).
+hipError_t launch_stream_inplace(float *x, int64_t n, hipStream_t s);
+// x[0..n) = 0 (a kernel: safe to replay from a graph)
+hipError_t launch_zero(double *x, int64_t n, hipStream_t s);
 // Restriction: nr = regions + 1 (record stride).  full = false: region counts
 // and means only (a first pass, whose combine writes the region means to
 // rshift_next); full = true: complete records.

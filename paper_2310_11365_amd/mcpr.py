@@ -105,6 +105,8 @@ def lib() -> ctypes.CDLL:
         L.mcpr_profile_read.restype = st
         L.mcpr_profile_read_adjoint.argtypes = L.mcpr_profile_read.argtypes
         L.mcpr_profile_read_adjoint.restype = st
+        L.mcpr_stream_probe.argtypes = [vp, ctypes.c_int64, i32, vp, ctypes.POINTER(ctypes.c_double)]
+        L.mcpr_stream_probe.restype = st
         L.mcpr_set_graphs.argtypes = [vp, i32]
         L.mcpr_set_graphs.restype = st
         L.mcpr_set_tuning.argtypes = [vp, i32]
@@ -338,6 +340,17 @@ def fine_propagate_static(problems, ensembles, stats_dev=None, trace_dev=None, s
                                       _ptr(trace_dev) if trace_dev is not None else None, _stream(stream))
     if st != 0:
         raise MCPRError(st, L.mcpr_last_error(None).decode())
+
+
+def stream_probe(x, reps: int = 20, stream=None) -> float:
+    """mcpr_stream_probe on a float32 device tensor (numel a multiple of
+    4096): mean ms of one in-place streaming pass (8 bytes per float)."""
+    L = lib()
+    ms = ctypes.c_double()
+    st = L.mcpr_stream_probe(_ptr(x), int(x.numel()), int(reps), _stream(stream), ctypes.byref(ms))
+    if st != 0:
+        raise MCPRError(st, L.mcpr_last_error(None).decode())
+    return ms.value
 
 
 def ensemble(x, instance=0, slice_index=0, problem=0, n=None) -> EnsembleC:

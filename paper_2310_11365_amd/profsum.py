@@ -66,20 +66,22 @@ def grid_groups(db_path: str, kernel: str):
     return groups
 
 
-def counter_per_dispatch(db_path: str, kernel: str):
+def counter_per_dispatch(db_path: str, kernel: str, grid=None):
+    """Counter values of kernel's dispatches (grid: only those with that x
+    extent in work items) and the largest value of a library copy."""
     cur = sqlite3.connect(db_path).cursor()
-    q = list(cur.execute("select kernel_name, value from counters_collection"))
-    vals = [v for k, v in q if short_name(k).replace("mcpr::", "") == kernel]
-    copies = [v for k, v in q if "copyBuffer" in k]
+    q = list(cur.execute("select kernel_name, value, grid_size_x from counters_collection"))
+    vals = [v for k, v, g in q if short_name(k).replace("mcpr::", "") == kernel and (grid is None or int(g) == grid)]
+    copies = [v for k, v, g in q if "copyBuffer" in k]
     return vals, (max(copies) if copies else None)
 
 
-def counters_of(db_path: str, kernel: str):
+def counters_of(db_path: str, kernel: str, grid=None):
     """Mean value per dispatch of every counter collected for kernel."""
     cur = sqlite3.connect(db_path).cursor()
     vals = {}
-    for k, name, v in cur.execute("select kernel_name, counter_name, value from counters_collection"):
-        if short_name(k).replace("mcpr::", "") == kernel:
+    for k, name, v, g in cur.execute("select kernel_name, counter_name, value, grid_size_x from counters_collection"):
+        if short_name(k).replace("mcpr::", "") == kernel and (grid is None or int(g) == grid):
             vals.setdefault(name, []).append(v)
     return {n: (statistics.mean(v), len(v)) for n, v in vals.items()}
 
@@ -103,10 +105,12 @@ def main():
     c.add_argument("--kernel", required=True)
     c.add_argument("--copy-mib", type=int, default=1024)
     c.add_argument("--algorithmic-bytes", type=float, required=True)
+    c.add_argument("--grid", type=int, default=None, help="only dispatches with this grid x extent (work items)")
     v = sub.add_parser("valu")
     v.add_argument("db")
     v.add_argument("--kernel", required=True)
     v.add_argument("--trace-us", type=float, required=True, help="mean duration of the kernel (kernel trace)")
+    v.add_argument("--grid", type=int, default=None, help="only dispatches with this grid x extent (work items)")
     a = ap.parse_args()
     if a.cmd == "trace":
         print("| kernel | calls | total us | mean us | % |")
@@ -138,7 +142,7 @@ def main():
                     print(f"\nbench.py, same run: {r['kernel']} mean {r['avg_launch_us']} us per launch by HIP events, "
                           f"{r['achieved']} GB/s algorithmic")
     elif a.cmd == "valu":
-        cs = counters_of(a.db, a.kernel)
+        cs = counters_of(a.db, a.kernel, a.grid)
         print("| counter | mean per dispatch | dispatches |")
         print("|---|---|---|")
         for name in sorted(cs):
@@ -153,7 +157,7 @@ def main():
         kib = a.copy_mib * 1024.0
         out = {}
         for name, db in (("FETCH_SIZE", a.fetch_db), ("WRITE_SIZE", a.write_db)):
-            vals, copy = counter_per_dispatch(db, a.kernel)
+            vals, copy = counter_per_dispatch(db, a.kernel, a.grid)
             scale = kib / copy
             out[name] = dict(n=len(vals), raw_kib=statistics.mean(vals), copy_kib=copy, scale=scale,
                              bytes=statistics.mean(vals) * scale * 1024.0)
