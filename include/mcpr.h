@@ -333,10 +333,16 @@ mcpr_status mcpr_match(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_pr
  * reports the (mean, variance) at each slice end (host moments_out
  * [n][2], may be NULL).  If dL_dmoments (host [n][2], upstream derivatives
  * of a scalar L with respect to those moments) is given, the backward sweep
- * recomputes each slice once from its checkpoint and writes
- * grad_out (host [10]) = dL/d(a0, a1, a2, a3, am, av, b0, b1, bm, bv).
- * fp64 adjoint state and reductions; synchronises the stream.  Scratch of
- * (n + 1) + (m + 1) states and two fp64 arrays of P is held by the context. */
+ * recomputes each slice once from its checkpoint (on the context's second
+ * stream, overlapped with the backward steps of the following slice) and
+ * writes grad_out (host [10]) = dL/d(a0, a1, a2, a3, am, av, b0, b1, bm, bv).
+ * With graphs on (mcpr_set_graphs) and profiling off, the whole launch
+ * sequence is captured once per shape and replayed; every per-call value
+ * (work tables, moments, dL_dmoments) is read from device memory, so the
+ * results are those of direct launches.  fp64 adjoint state and reductions;
+ * synchronises the stream.  Scratch (sized by mcpr_reserve with
+ * MCPR_RESERVE_ADJOINT): (n + 1) + 2 (m + 1) states, two fp64 arrays of P,
+ * the per-slice work tables.                                                 */
 mcpr_status mcpr_adjoint(mcpr_ctx *ctx, const mcpr_problem *problem, const mcpr_ensemble *ens,
                          const double *dL_dmoments, double *moments_out, double *grad_out, mcpr_stream stream);
 
