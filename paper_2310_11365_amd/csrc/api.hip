@@ -57,8 +57,6 @@ struct mcpr_ctx {
     DevBuf items, blocks, part[2], shift[2], rpart, rshift[2], maps, recs;
     DevBuf adj_ckpt, adj_traj, adj_lam[2], adj_part[2], adj_acc, adj_trace, adj_grad, adj_sums; // adjoint scratch
     DevBuf adj_tables; // the adjoint's work tables (every slice's), block tables and upstream derivatives
-    hipGraphExec_t adj_exec = nullptr; // the adjoint's whole launch sequence, for the shape in adj_key
-    std::vector<char> adj_key;
     // empirical-CDF drift: states and labels in sorted order, the library
     // sort's item pass and scratch, the bucket engine's tables and staging
     DevBuf cdf_keys[2], cdf_lab[2], cdf_seg[2], cdf_kl[2], cdf_beg, cdf_tmp;
@@ -647,6 +645,50 @@ mcpr_status size_fine(mcpr_ctx *ctx, const Tables &t, int prec, int m, int nreg,
     return MCPR_OK;
 }
 
+// Replays the graph cached under key on the library's graph stream, ordered
+// after the work on s and before s's later work; on a miss the sequence that
+// enqueue puts on the stream it is given is captured and instantiated first
+// (the least recently used graph is evicted when the cache is full).
+template <typename Enqueue>
+mcpr_status replay(mcpr_ctx *ctx, const std::vector<char> &key, hipStream_t s, Enqueue enqueue) {
+    mcpr_ctx::GraphEntry *ge = nullptr;
+    for (auto &e : ctx->graphs_cached)
+        if (e.key == key) ge = &e;
+    if (!ge) {
+        if (ctx->graphs_cached.size() >= kGraphCache) {
+            size_t lru = 0;
+            for (size_t i = 1; i < ctx->graphs_cached.size(); ++i)
+                if (ctx->graphs_cached[i].used < ctx->graphs_cached[lru].used) lru = i;
+            HIP_TRY(hipStreamSynchronize(ctx->gstream)); // (the evicted graph may still run)
+            HIP_TRY(hipGraphExecDestroy(ctx->graphs_cached[lru].exec));
+            ctx->graphs_cached.erase(ctx->graphs_cached.begin() + lru);
+        }
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
+        mcpr_status st = enqueue(ctx->gstream);
+        hipError_t ec = hipStreamEndCapture(ctx->gstream, &g);
+        if (st != MCPR_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (ec != hipSuccess) return fail(ctx, MCPR_E_DEVICE, "graph capture: %s", hipGetErrorString(ec));
+        hipGraphExec_t exec = nullptr;
+        hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return fail(ctx, MCPR_E_DEVICE, "graph instantiate: %s", hipGetErrorString(ei));
+        ctx->graphs_cached.push_back(mcpr_ctx::GraphEntry{key, exec, 0});
+        ge = &ctx->graphs_cached.back();
+        ctx->graph_builds++;
+    }
+    ge->used = ++ctx->graph_launches;
+    HIP_TRY(hipEventRecord(ctx->gin, s));
+    HIP_TRY(hipStreamWaitEvent(ctx->gstream, ctx->gin, 0));
+    HIP_TRY(hipGraphLaunch(ge->exec, ctx->gstream));
+    HIP_TRY(hipEventRecord(ctx->gout, ctx->gstream));
+    HIP_TRY(hipStreamWaitEvent(s, ctx->gout, 0));
+    return MCPR_OK;
+}
+
 mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int nreg, const mcpr::Splits &sp,
                           RegionStats *stats, double2 *trace, hipStream_t s) {
     const int n = (int)t.items.size();
@@ -789,43 +831,12 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
     } else if (ctx->graphs && !t.items[0].cdf) {
         // (the empirical-CDF sweep runs the library sort eagerly: never captured)
         std::vector<char> key = graph_key(ctx, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr);
-        mcpr_ctx::GraphEntry *ge = nullptr;
-        for (auto &e : ctx->graphs_cached)
-            if (e.key == key) ge = &e;
-        if (!ge) {
-            if (ctx->graphs_cached.size() >= kGraphCache) {
-                // evict the least recently used sweep (after the graph stream drains)
-                size_t lru = 0;
-                for (size_t i = 1; i < ctx->graphs_cached.size(); ++i)
-                    if (ctx->graphs_cached[i].used < ctx->graphs_cached[lru].used) lru = i;
-                HIP_TRY(hipStreamSynchronize(ctx->gstream));
-                HIP_TRY(hipGraphExecDestroy(ctx->graphs_cached[lru].exec));
-                ctx->graphs_cached.erase(ctx->graphs_cached.begin() + lru);
-            }
-            hipGraph_t g = nullptr;
-            HIP_TRY(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
-            st = enqueue_fine(ctx, bf, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr,
-                              ctx->gstream, false);
-            hipError_t ec = hipStreamEndCapture(ctx->gstream, &g);
-            if (st != MCPR_OK) {
-                if (g) (void)hipGraphDestroy(g);
-                return st;
-            }
-            if (ec != hipSuccess) return fail(ctx, MCPR_E_DEVICE, "graph capture: %s", hipGetErrorString(ec));
-            hipGraphExec_t exec = nullptr;
-            hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (ei != hipSuccess) return fail(ctx, MCPR_E_DEVICE, "graph instantiate: %s", hipGetErrorString(ei));
-            ctx->graphs_cached.push_back(mcpr_ctx::GraphEntry{key, exec, 0});
-            ge = &ctx->graphs_cached.back();
-            ctx->graph_builds++;
-        }
-        ge->used = ++ctx->graph_launches;
-        HIP_TRY(hipEventRecord(ctx->gin, s));
-        HIP_TRY(hipStreamWaitEvent(ctx->gstream, ctx->gin, 0));
-        HIP_TRY(hipGraphLaunch(ge->exec, ctx->gstream));
-        HIP_TRY(hipEventRecord(ctx->gout, ctx->gstream));
-        HIP_TRY(hipStreamWaitEvent(s, ctx->gout, 0));
+        if ((st = replay(ctx, key, s,
+                         [&](hipStream_t gs) {
+                             return enqueue_fine(ctx, bf, t, prec, deg, variant, m, nreg, sp, stats != nullptr,
+                                                 trace != nullptr, gs, false);
+                         })) != MCPR_OK)
+            return st;
     } else {
         if ((st = enqueue_fine(ctx, bf, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr, s,
                                false)) != MCPR_OK)
@@ -965,7 +976,8 @@ std::vector<char> adjoint_key(mcpr_ctx *ctx, const AdjPlan &pl) {
     const void *ptrs[] = {ctx->adj_tables.p, ctx->adj_ckpt.p, ctx->adj_traj.p, ctx->adj_trace.p, ctx->adj_lam[0].p,
                           ctx->adj_lam[1].p, ctx->adj_part[0].p, ctx->adj_part[1].p, ctx->adj_acc.p, ctx->adj_grad.p,
                           ctx->adj_sums.p, ctx->part[0].p, ctx->part[1].p, ctx->shift[0].p, ctx->shift[1].p, ctx->mv.p};
-    const int64_t ints[] = {pl.prec, pl.deg, pl.variant, pl.m, pl.NS, pl.n0, pl.nreg, pl.P, pl.grad ? 1 : 0};
+    const int64_t ints[] = {-1 /* an adjoint, not a sweep */, pl.prec, pl.deg, pl.variant, pl.m, pl.NS, pl.n0,
+                            pl.nreg, pl.P, pl.grad ? 1 : 0};
     std::vector<char> k(sizeof ptrs + sizeof ints + sizeof pl.sp);
     std::memcpy(k.data(), ptrs, sizeof ptrs);
     std::memcpy(k.data() + sizeof ptrs, ints, sizeof ints);
@@ -1245,7 +1257,6 @@ void mcpr_destroy(mcpr_ctx *ctx) {
         for (int j = 0; j < kTuneSteps; ++j)
             if (ctx->tune_ev[k][j]) (void)hipEventDestroy(ctx->tune_ev[k][j]);
     for (auto &e : ctx->graphs_cached) (void)hipGraphExecDestroy(e.exec);
-    if (ctx->adj_exec) (void)hipGraphExecDestroy(ctx->adj_exec);
     if (ctx->astream) (void)hipStreamDestroy(ctx->astream);
     for (hipEvent_t e : {ctx->a_fwd, ctx->a_rec[0], ctx->a_rec[1], ctx->a_bwd[0], ctx->a_bwd[1]})
         if (e) (void)hipEventDestroy(e);
@@ -1583,37 +1594,9 @@ mcpr_status mcpr_adjoint(mcpr_ctx *ctx, const mcpr_problem *problem, const mcpr_
     HIP_TRY(hipMemcpyAsync(ctx->adj_ckpt.p, ens->x, (size_t)pl.P * pl.esz, hipMemcpyDeviceToDevice, s));
     if (ctx->graphs && !ctx->profile) {
         // the whole sequence from one graph, instantiated once per shape
-        std::vector<char> key = adjoint_key(ctx, pl);
-        if (!ctx->adj_exec || key != ctx->adj_key) {
-            if (ctx->adj_exec) {
-                HIP_TRY(hipStreamSynchronize(ctx->gstream));
-                HIP_TRY(hipGraphExecDestroy(ctx->adj_exec));
-                ctx->adj_exec = nullptr;
-            }
-            hipGraph_t g = nullptr;
-            HIP_TRY(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
-            st = enqueue_adjoint(ctx, pl, ctx->gstream, ctx->astream, false);
-            hipError_t ec = hipStreamEndCapture(ctx->gstream, &g);
-            if (st != MCPR_OK) {
-                if (g) (void)hipGraphDestroy(g);
-                return st;
-            }
-            if (ec != hipSuccess) return fail(ctx, MCPR_E_DEVICE, "adjoint graph capture: %s", hipGetErrorString(ec));
-            hipError_t ei = hipGraphInstantiate(&ctx->adj_exec, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (ei != hipSuccess) {
-                ctx->adj_exec = nullptr;
-                return fail(ctx, MCPR_E_DEVICE, "adjoint graph instantiate: %s", hipGetErrorString(ei));
-            }
-            ctx->adj_key = key;
-            ctx->graph_builds++;
-        }
-        HIP_TRY(hipEventRecord(ctx->gin, s));
-        HIP_TRY(hipStreamWaitEvent(ctx->gstream, ctx->gin, 0));
-        HIP_TRY(hipGraphLaunch(ctx->adj_exec, ctx->gstream));
-        HIP_TRY(hipEventRecord(ctx->gout, ctx->gstream));
-        HIP_TRY(hipStreamWaitEvent(s, ctx->gout, 0));
-        ctx->graph_launches++;
+        if ((st = replay(ctx, adjoint_key(ctx, pl), s,
+                         [&](hipStream_t gs) { return enqueue_adjoint(ctx, pl, gs, ctx->astream, false); })) != MCPR_OK)
+            return st;
     } else if ((st = enqueue_adjoint(ctx, pl, s, ctx->astream, ctx->profile)) != MCPR_OK) {
         return st;
     }
