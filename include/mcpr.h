@@ -249,8 +249,9 @@ mcpr_status mcpr_graph_stats(const mcpr_ctx *ctx, int64_t *builds, int64_t *laun
  * each ensemble in ascending order).  mode 1 (default): the first two steps
  * of a fine sweep sort with a device-wide radix sort, later steps put the new
  * states into buckets between the previous step's sorted states (1792 apart
- * on average) and sort each bucket on chip (a block radix sort in a tile of
- * 2048 states, or of 4096 for a larger bucket).  A bucket beyond 4096 states (a
+ * on average) and sort each bucket on chip (a bitonic network in one
+ * wavefront's registers for a bucket of up to 2048 states, in one block for a
+ * larger one).  A bucket beyond 4096 states (a
  * law still spreading fast, as in the first steps from a point mass; a point
  * mass without noise) makes the sweep run again with the radix sort on its
  * first 8 steps, then 32, then all of them; the overflow flag is read after

@@ -60,7 +60,7 @@ struct mcpr_ctx {
     // empirical-CDF drift: states and labels in sorted order, the library
     // sort's item pass and scratch, the bucket engine's tables and staging
     DevBuf cdf_keys[2], cdf_lab[2], cdf_seg[2], cdf_kl[2], cdf_beg, cdf_tmp;
-    DevBuf cdf_bcount, cdf_bmeta, cdf_stage, cdf_flag;
+    DevBuf cdf_bcount, cdf_bmeta, cdf_stage, cdf_flag, cdf_defer;
     mcpr::CdfBuffers cdfb{};
     uint32_t *cdf_flag_host = nullptr; // pinned copy of the overflow flag
     int cdf_engine = 1;                // 1: bucket engine after a sweep's first steps; 0: library sort every step
@@ -586,6 +586,7 @@ mcpr_status ensure_cdf(mcpr_ctx *ctx, const Tables &t, int prec) {
     if (ctx->cdf_engine) {
         if ((st = ensure(ctx, ctx->cdf_bmeta, nbk * sizeof(uint2))) != MCPR_OK) return st;
         if ((st = ensure(ctx, ctx->cdf_stage, mcpr::stage_bytes(prec, (int)nbk))) != MCPR_OK) return st;
+        if ((st = ensure(ctx, ctx->cdf_defer, (nbk + 1) * sizeof(uint32_t))) != MCPR_OK) return st;
     }
     if (!ctx->cdf_flag_host) {
         if (!ctx->growing)
@@ -614,6 +615,7 @@ mcpr_status ensure_cdf(mcpr_ctx *ctx, const Tables &t, int prec) {
     c.bcount = (uint32_t *)ctx->cdf_bcount.p;
     c.bmeta = (uint2 *)ctx->cdf_bmeta.p;
     c.stage = ctx->cdf_stage.p;
+    c.defer = (uint32_t *)ctx->cdf_defer.p;
     c.flag = (uint32_t *)ctx->cdf_flag.p;
     return MCPR_OK;
 }
@@ -1243,7 +1245,7 @@ void mcpr_destroy(mcpr_ctx *ctx) {
                       &ctx->adj_sums,      &ctx->adj_tables,  &ctx->trace,       &ctx->mv,
                       &ctx->cdf_keys[0],   &ctx->cdf_keys[1], &ctx->cdf_lab[0],  &ctx->cdf_lab[1],  &ctx->cdf_seg[0],
                       &ctx->cdf_seg[1],    &ctx->cdf_kl[0],   &ctx->cdf_kl[1],   &ctx->cdf_beg,     &ctx->cdf_tmp,
-                      &ctx->cdf_bcount,    &ctx->cdf_bmeta,   &ctx->cdf_stage,   &ctx->cdf_flag};
+                      &ctx->cdf_bcount,    &ctx->cdf_bmeta,   &ctx->cdf_stage,   &ctx->cdf_flag,    &ctx->cdf_defer};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->staging.p) (void)hipHostFree(ctx->staging.p);

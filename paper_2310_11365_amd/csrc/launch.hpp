@@ -109,6 +109,7 @@ struct CdfBuffers {
     uint32_t *bcount;    // states per bucket (zero between steps)
     uint2 *bmeta;        // per bucket: first dense output position and states (k_cdf_bscan)
     void *stage;         // staging area (stage_view), kCdfBucketCap slots per bucket
+    uint32_t *defer;     // [0] count, [1..] buckets left to the block sort (k_cdf_wsort appends, k_cdf_bscan clears)
     uint32_t *flag;      // nonzero once a bucket overflowed in this sweep
 };
 // Once per fine sweep: the dense first position of every item; the states and
