@@ -266,6 +266,7 @@ def throughput(name: str, steps: int, warmup: int, variant: int, particles: int 
     em_ms, em_launches, em_ps = ctx.profile_read(reset=True)
     ctx.profile(False)
     tv = ctx.tuned_variants()
+    resident = ctx.resident_sweeps() > 0
     para.close()
     del para
     ctx.close()
@@ -278,6 +279,10 @@ def throughput(name: str, steps: int, warmup: int, variant: int, particles: int 
     deg = 1 if all(c.a2 == 0.0 and c.a3 == 0.0 for c in all_coefs) else 3
     v = variant if variant >= 0 else (tv[0] if len(tv) == 1 else -1)
     kernel = f"k_em_step<{tname}, {deg}, {'true' if v & 1 else 'false'}, {'true' if v & 2 else 'false'}>"
+    if resident:
+        kernel = (f"resident sweep: k_sweep_normals<{tname}> (every step's normals) + "
+                  f"k_em_sweep_resident<{tname}, {deg}> (one block per ensemble through all the steps)")
+        v = -1
     if pr.coef.acdf != 0.0:
         kernel = (f"empirical-CDF step sequence (library radix sort on a sweep's first steps, then buckets: "
                   f"k_combine, k_em_step_sorted<{tname}, {deg}, false>, k_cdf_bscan, k_cdf_bsort<{tname}>)")

@@ -106,6 +106,9 @@ struct mcpr_ctx {
     int tune_cand[4] = {0, 1, 2, 3}; // variants of the trial, the first is the reference
     int tune_nc = 4;
     DevBuf mv; // per-item (mean, variance) of the separate-combine variant
+    DevBuf znorm;                 // resident sweeps: the normals of every step of the sweep
+    int resident = 1;             // 1: resident sweeps where every ensemble fits one block
+    int64_t resident_sweeps = 0;  // fine sweeps run resident so far
     // scratch sizing: buffers grow only inside mcpr_reserve (and the Parareal
     // driver's create); a hot-path call that needs more fails with
     // MCPR_E_NOT_RESERVED before launching anything
@@ -306,6 +309,8 @@ struct Tables {
     int total_sc = 0;
     int64_t total_dense = 0;  // dense sort positions, the sum of P (empirical-CDF drift)
     int nbuckets = 0;         // bucket engine: buckets of the launch
+    int64_t total_z = 0;      // resident sweep: normals of all steps (items' zoff)
+    int zm = 0;               // the steps per slice they are laid out for (-1: the items differ)
 };
 
 void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_t n_ens, Tables &t) {
@@ -313,6 +318,8 @@ void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_
     t.blocks.clear();
     t.total_dense = 0;
     t.nbuckets = 0;
+    t.total_z = 0;
+    t.zm = n_ens > 0 ? problems[ens[0].problem].steps_per_slice : 0;
     int off = 0;
     for (int e = 0; e < n_ens; ++e) {
         const mcpr_ensemble &E = ens[e];
@@ -345,6 +352,9 @@ void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_
             w.bbase = t.nbuckets;
             t.nbuckets += w.nbk;
         }
+        if (p.steps_per_slice != t.zm) t.zm = -1;
+        w.zoff = t.total_z;
+        t.total_z += (int64_t)p.steps_per_slice * 4 * ((E.n_particles + 3) / 4);
         w.dt = p.dt;
         w.sdt = std::sqrt(p.dt);
         w.p0[0] = p.p0_w;
@@ -473,9 +483,16 @@ mcpr_status records(mcpr_ctx *ctx, const Tables &t, int prec, int nreg, const mc
     return enqueue_records(ctx, ctx_bufs(ctx), t, prec, nreg, sp, shift, two_pass, mode, maps, out, s);
 }
 
+// Resident sweeps: the normals' scratch limit, and the step "variant" that
+// marks a resident sweep (in graph keys).
+constexpr size_t kResidentZBytes = (size_t)256 << 20;
+constexpr int kResidentVariant = 16;
+
 // The step sequence of the fine propagator on already uploaded tables:
 // step-0 sums, m Euler-Maruyama launches, the final moments (if traced) and
 // the restriction records (if wanted), into ctx-owned buffers.
+// variant == kResidentVariant: the resident sweep instead of the step-0 sums
+// and the m launches.
 // variant < 0: the first tune_steps steps run the candidate variants in turn,
 // each launch bracketed by events (the autotuner's trial; every variant gives
 // the same bits).
@@ -496,6 +513,17 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Bufs &bf, const Tables &t, int pre
     const bool trig = t.items[0].trig != 0; // the same for every item of a call
     const bool cdf = t.items[0].cdf != 0;
     const uint32_t ndense = (uint32_t)t.total_dense;
+    if (variant == kResidentVariant) {
+        // the whole sweep in two launches (normals, then one block per ensemble)
+        if (profile) HIP_TRY(hipEventRecord(ctx->prof0[ctx->prof_used], s));
+        HIP_TRY(mcpr::launch_em_sweep_resident(prec, deg, items, n, blocks, nb, m, ctx->znorm.p, part[m & 1],
+                                               shift[m & 1], trace, s));
+        if (profile) HIP_TRY(hipEventRecord(ctx->prof1[ctx->prof_used], s));
+        if (trace) HIP_TRY(mcpr::launch_finish(items, n, part[m & 1], shift[m & 1], trace, m, s));
+        if (want_stats)
+            return enqueue_records(ctx, bf, t, prec, nreg, sp, shift[m & 1], nreg > 1, 0, nullptr, bf.recs, s);
+        return MCPR_OK;
+    }
     if (j0 == 0) {
         if (cdf) HIP_TRY(mcpr::launch_cdf_start(prec, items, n, blocks, nb, ctx->cdfb, s));
         if (trig)
@@ -552,7 +580,7 @@ std::vector<char> graph_key(mcpr_ctx *ctx, const Tables &t, int prec, int deg, i
                             const mcpr::Splits &sp, bool want_stats, bool want_trace) {
     const void *ptrs[] = {ctx->items.p, ctx->blocks.p, ctx->part[0].p, ctx->part[1].p, ctx->shift[0].p,
                           ctx->shift[1].p, ctx->rpart.p, ctx->rshift[0].p, ctx->rshift[1].p, ctx->recs.p,
-                          ctx->trace.p,  ctx->mv.p};
+                          ctx->trace.p,  ctx->mv.p,       ctx->znorm.p};
     const int64_t ints[] = {(int64_t)t.items.size(), (int64_t)t.blocks.size(), t.total_sc, prec, deg, m, nreg,
                             want_stats, want_trace, variant, t.items[0].trig};
     std::vector<char> k(sizeof ptrs + sizeof ints + sizeof sp);
@@ -632,6 +660,19 @@ mcpr_status next_prof_slot(mcpr_ctx *ctx) {
     return MCPR_OK;
 }
 
+// Whether the fine sweep of t runs resident: every ensemble in place, at most
+// kResidentMaxP particles, no trigonometric or empirical-CDF term, and the
+// sweep's normals within kResidentZBytes.
+bool resident_ok(const mcpr_ctx *ctx, const Tables &t, int prec, int m) {
+    if (!ctx->resident || t.items.empty() || t.zm != m || m < 1 || m > 65535) return false;
+    if ((size_t)t.total_z * (prec == 0 ? sizeof(double) : sizeof(float)) > kResidentZBytes) return false;
+    for (const WorkItem &w : t.items)
+        if (w.trig || w.cdf || w.traj != 0 || w.src || w.R != 1 || w.P > mcpr::kResidentMaxP ||
+            w.nsc > mcpr::kResidentMaxSc)
+            return false;
+    return true;
+}
+
 // Buffers of a fine sweep of the tables t (records and trace if wanted).
 mcpr_status size_fine(mcpr_ctx *ctx, const Tables &t, int prec, int m, int nreg, bool stats, bool trace) {
     const int n = (int)t.items.size();
@@ -644,6 +685,11 @@ mcpr_status size_fine(mcpr_ctx *ctx, const Tables &t, int prec, int m, int nreg,
     if (trace && (st = ensure(ctx, ctx->trace, (size_t)n * (m + 1) * sizeof(double2))) != MCPR_OK) return st;
     if ((st = ensure(ctx, ctx->mv, (size_t)n * sizeof(double2))) != MCPR_OK) return st;
     if (t.items[0].cdf && (st = ensure_cdf(ctx, t, prec)) != MCPR_OK) return st;
+    // (the normals' scratch is sized only when reserving: a call it does not
+    // fit runs the per-step launches, which give the same bits)
+    if (ctx->growing && resident_ok(ctx, t, prec, m) &&
+        (st = ensure(ctx, ctx->znorm, (size_t)t.total_z * (prec == 0 ? sizeof(double) : sizeof(float)))) != MCPR_OK)
+        return st;
     return MCPR_OK;
 }
 
@@ -767,6 +813,8 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
     // the separate-combine variants are candidates then, and the default is
     // the plain one of those.
     const bool many = max_nsc > mcpr::kThreads;
+    const bool resident = resident_ok(ctx, t, prec, m) &&
+                          ctx->znorm.cap >= (size_t)t.total_z * (prec == 0 ? sizeof(double) : sizeof(float));
     // step-kernel variant: forced, tuned for this launch shape, or tuned now
     std::vector<char> tkey(6 * sizeof(int64_t));
     {
@@ -775,7 +823,10 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
     }
     int variant = many ? 2 : 0;
     bool tune_now = false;
-    if (ctx->tuning >= 0) {
+    if (resident) {
+        variant = kResidentVariant;
+        ctx->resident_sweeps++;
+    } else if (ctx->tuning >= 0) {
         variant = ctx->tuning & 3;
     } else {
         auto it = ctx->tuned.find(tkey);
@@ -1245,7 +1296,8 @@ void mcpr_destroy(mcpr_ctx *ctx) {
                       &ctx->adj_sums,      &ctx->adj_tables,  &ctx->trace,       &ctx->mv,
                       &ctx->cdf_keys[0],   &ctx->cdf_keys[1], &ctx->cdf_lab[0],  &ctx->cdf_lab[1],  &ctx->cdf_seg[0],
                       &ctx->cdf_seg[1],    &ctx->cdf_kl[0],   &ctx->cdf_kl[1],   &ctx->cdf_beg,     &ctx->cdf_tmp,
-                      &ctx->cdf_bcount,    &ctx->cdf_bmeta,   &ctx->cdf_stage,   &ctx->cdf_flag,    &ctx->cdf_defer};
+                      &ctx->cdf_bcount,    &ctx->cdf_bmeta,   &ctx->cdf_stage,   &ctx->cdf_flag,    &ctx->cdf_defer,
+                      &ctx->znorm};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->staging.p) (void)hipHostFree(ctx->staging.p);
@@ -1370,6 +1422,18 @@ mcpr_status mcpr_graph_stats(const mcpr_ctx *ctx, int64_t *builds, int64_t *laun
     if (!ctx) return MCPR_E_INVALID_ARG;
     if (builds) *builds = ctx->graph_builds;
     if (launches) *launches = ctx->graph_launches;
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_set_resident(mcpr_ctx *ctx, int32_t enable) {
+    if (!ctx || enable < 0 || enable > 1) return MCPR_E_INVALID_ARG;
+    ctx->resident = enable;
+    return MCPR_OK;
+}
+
+mcpr_status mcpr_resident_sweeps(const mcpr_ctx *ctx, int64_t *sweeps) {
+    if (!ctx || !sweeps) return MCPR_E_INVALID_ARG;
+    *sweeps = ctx->resident_sweeps;
     return MCPR_OK;
 }
 

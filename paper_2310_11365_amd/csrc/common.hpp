@@ -33,6 +33,12 @@ constexpr int kMaxRegions = 8;
 // have many superchunks, whose partials the step kernel's separate-combine
 // variant reduces once per step.
 constexpr int kMaxQuadsPerThread = 4;
+// Resident fine sweep (an ensemble held in one block's registers through all
+// the steps of a sweep): at most kResidentMaxSc superchunks of one quad per
+// thread, i.e. 12288 particles (the fp64 sweep keeps a step's state and the
+// next step's normals in registers without spilling).
+constexpr int kResidentMaxSc = 12;
+constexpr int64_t kResidentMaxP = (int64_t)kResidentMaxSc * kThreads * 4;
 constexpr int64_t kSmallEnsemble = 65536;
 inline int canonical_quads_per_thread(int64_t P) { return P < kSmallEnsemble ? 1 : kMaxQuadsPerThread; }
 
@@ -64,6 +70,7 @@ struct WorkItem {
     double p0[5];      // w, mu1, sd1, mu2, sd2
     int64_t traj;      // 0: steps work in place; else step j reads x + j*traj and writes x + (j+1)*traj
     const void *src;   // matching only: read from src instead of x (NULL: in place)
+    int64_t zoff;      // resident sweep: first normal of this item in the sweep's normal buffer
 };
 
 // Per-superchunk region partial: count, sum d, sum d^2, min, max (d = x - shift).

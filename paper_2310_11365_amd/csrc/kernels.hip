@@ -286,6 +286,25 @@ __device__ __forceinline__ T em_update(T xv, T z, T c0, T c1, T c2, T c3, T e0, 
     return fmaT(fmaT(e1, xv, e0), z, pol);
 }
 
+// Coefficients of step j from its mean field: p(x) = x + a(x) dt as a
+// polynomial (c0..c3), the diffusion times sqrt(dt) affine in x (e0, e1).
+template <typename T>
+struct StepCoef {
+    T c0, c1, c2, c3, e0, e1;
+};
+template <typename T>
+__device__ __forceinline__ StepCoef<T> step_coef(const WorkItem &W, double mean, double var) {
+    const double dt = W.dt, sdt = W.sdt;
+    StepCoef<T> k;
+    k.c0 = (T)((W.c[0] + W.c[4] * mean + W.c[5] * var) * dt);
+    k.c1 = (T)(1.0 + (W.c[1] + W.c[10] * (var + mean * mean)) * dt);
+    k.c2 = (T)(W.c[2] * dt);
+    k.c3 = (T)(W.c[3] * dt);
+    k.e0 = (T)((W.c[6] + W.c[8] * mean + W.c[9] * var) * sdt);
+    k.e1 = (T)(W.c[7] * sdt);
+    return k;
+}
+
 // Mean field of step j from the previous launch's partials: one block per item
 // (the variant of the step kernel that does not combine in every block).
 __global__ __launch_bounds__(kThreads) void k_combine(const WorkItem *__restrict__ items,
@@ -350,13 +369,8 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
         if (trace) trace[(int64_t)item * (m + 1) + j] = make_double2(mean, var);
     }
 
-    // step coefficients: p(x) = x + a(x) dt as a polynomial, diffusion * sqrt(dt) affine in x
-    const double dt = W.dt, sdt = W.sdt;
-    const T c0 = (T)((W.c[0] + W.c[4] * mean + W.c[5] * var) * dt);
-    const T c1 = (T)(1.0 + (W.c[1] + W.c[10] * (var + mean * mean)) * dt), c2 = (T)(W.c[2] * dt),
-            c3 = (T)(W.c[3] * dt);
-    const T e0 = (T)((W.c[6] + W.c[8] * mean + W.c[9] * var) * sdt);
-    const T e1 = (T)(W.c[7] * sdt);
+    const StepCoef<T> kc = step_coef<T>(W, mean, var);
+    const T c0 = kc.c0, c1 = kc.c1, c2 = kc.c2, c3 = kc.c3, e0 = kc.e0, e1 = kc.e1;
     const uint32_t step = (uint32_t)(W.step0 + j);
     const uint32_t inst = (uint32_t)W.inst;
     const uint32_t k0 = W.key0, k1 = W.key1;
@@ -364,7 +378,6 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
     double a1 = 0.0, a2 = 0.0;
     if (full) {
         // full superchunk: 32-bit quad offsets, no per-quad checks
-        const T *xs = x + base;
         T *ys = y + base;
         const uint32_t qb = (uint32_t)(base >> 2) + threadIdx.x;
 #pragma unroll
@@ -412,6 +425,232 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
     double sm[2] = {a1, a2};
     block_sum<2>(sm, lds);
     if (threadIdx.x == 0) part_out[W.part_off + sc] = make_double2(sm[0], sm[1]);
+}
+
+// ----------------------------------------------------------------------------
+// Resident fine sweep of small ensembles (at most kResidentMaxP particles,
+// one quad per thread and superchunk): one block of kResidentThreads per
+// ensemble keeps its particles in registers through all m steps of the sweep,
+// so a step costs a few block barriers instead of a launch.  The block's four
+// groups of kThreads threads stand for the superchunks g, g + 4, g + 8, ...
+// (thread t of group g holds quad (g + 4 i) kThreads + t), and every sum is
+// formed in the canonical order of the per-step launches: the same quad
+// leaves, the same tree inside each superchunk, the same ensemble tree, so the
+// sweep gives the per-step launches' bits.  The normals, which depend on the
+// particle, the step and the instance only, are drawn for the whole sweep
+// beforehand by k_sweep_normals (the transcendental work of every step in one
+// launch wide enough to fill the chip) into z: item i's normal e of quad q at
+// step j is z[zoff_i + 4 nq_i j + 4 q + e].
+// ----------------------------------------------------------------------------
+constexpr int kResidentGroups = 4;
+constexpr int kResidentThreads = kResidentGroups * kThreads;
+constexpr int kResidentPerThread = kResidentMaxSc / kResidentGroups;
+static_assert(kResidentMaxP < kSmallEnsemble, "one quad per thread and superchunk");
+
+// grid (superchunk blocks of the launch, m): one quad per thread
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sweep_normals(const WorkItem *__restrict__ items,
+                                                            const int2 *__restrict__ blocks, T *__restrict__ z) {
+    const int2 bt = blocks[blockIdx.x];
+    const WorkItem &W = items[bt.x];
+    const int32_t j = (int32_t)blockIdx.y;
+    const uint32_t nq = (uint32_t)((W.P + 3) / 4);
+    const uint32_t q = (uint32_t)bt.y * kThreads + threadIdx.x;
+    if (q >= nq) return;
+    const Words4 w = philox4x32_10(q, (uint32_t)(W.step0 + j), (uint32_t)W.inst, 0u, W.key0, W.key1);
+    T zz[4];
+    box_muller4(w, zz);
+    gstore_quad<false>(z + W.zoff + (int64_t)j * 4 * nq, q, zz);
+}
+
+// Lane 0's value of wave_sum with the same additions in the same order, from
+// DPP permutes, one swizzle and one readlane instead of LDS-crossbar shuffles
+// (sixteen wavefronts of one block on one CU would queue on the crossbar).
+// At each level lane 0 reads a lane whose partial equals that of its xor
+// partner: after the levels below o, the lanes of each aligned group of o
+// hold equal partials (every addition is commutative), so the half-row
+// mirror (lane 7 - i) stands for xor 4; row rotation by 8 is xor 8.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum_lane0(double v) {
+    v += dpp_f64<0xB1>(v);  // quad_perm [1,0,3,2]: xor 1
+    v += dpp_f64<0x4E>(v);  // quad_perm [2,3,0,1]: xor 2
+    v += dpp_f64<0x141>(v); // row_half_mirror: a lane of the partner quad
+    v += dpp_f64<0x128>(v); // row_ror:8: xor 8
+    {
+        const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F); // xor 16 within 32 lanes
+        const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+        v += __hiloint2double(hi, lo);
+    }
+    {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(v), 32);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 32);
+        v += __hiloint2double(hi, lo);
+    }
+    return v;
+}
+
+// The per-step exchange of the resident block.  Every wave sums its quad
+// leaves of each superchunk it holds (a1, a2; superchunks past nsc are
+// skipped, uniformly per wave); after the barrier wave 0 forms superchunk
+// t's sum in lane t (the tree over its four waves), the ensemble sums, the
+// mean field and the step coefficients, and publishes them; the other three
+// waves of the canonical ensemble tree hold only zeros (nsc <= 64), so their
+// contribution is the exact +0.0 of (w0 + 0) + (0 + 0).  p1, p2: superchunk
+// t's sums in lane t < nsc of wave 0.
+template <typename T>
+struct ResidentShared {
+    double mv[2];   // mean and variance at the start of the next step
+    T coef[6];      // its c0 c1 c2 c3 e0 e1
+};
+template <typename T, int NI>
+__device__ __forceinline__ void resident_exchange(const WorkItem &W, const double (&a1)[NI],
+                                                  const double (&a2)[NI], int nsc, double shd,
+                                                  double (*wsum)[NI][2], ResidentShared<T> &sh, double &p1,
+                                                  double &p2) {
+    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    const int g = (int)threadIdx.x / kThreads;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        if (g + kResidentGroups * i >= nsc) continue;
+        const double w1 = wave_sum_lane0(a1[i]), w2 = wave_sum_lane0(a2[i]);
+        if (lane == 0) {
+            wsum[wave][i][0] = w1;
+            wsum[wave][i][1] = w2;
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        double e1 = 0.0, e2 = 0.0;
+        if (lane < nsc) {
+            const int gs = lane % kResidentGroups, is = lane / kResidentGroups, w0 = 4 * gs;
+            p1 = (wsum[w0][is][0] + wsum[w0 + 1][is][0]) + (wsum[w0 + 2][is][0] + wsum[w0 + 3][is][0]);
+            p2 = (wsum[w0][is][1] + wsum[w0 + 1][is][1]) + (wsum[w0 + 2][is][1] + wsum[w0 + 3][is][1]);
+            e1 += p1;
+            e2 += p2;
+        }
+        e1 = wave_sum_lane0(e1);
+        e2 = wave_sum_lane0(e2);
+        if (lane == 0) {
+            const double S1 = (e1 + 0.0) + (0.0 + 0.0), S2 = (e2 + 0.0) + (0.0 + 0.0);
+            double mean, var;
+            finish_moments(S1, S2, shd, (double)W.P, mean, var);
+            const StepCoef<T> k = step_coef<T>(W, mean, var);
+            sh.mv[0] = mean;
+            sh.mv[1] = var;
+            sh.coef[0] = k.c0;
+            sh.coef[1] = k.c1;
+            sh.coef[2] = k.c2;
+            sh.coef[3] = k.c3;
+            sh.coef[4] = k.e0;
+            sh.coef[5] = k.e1;
+        }
+    }
+    __syncthreads();
+}
+
+// One block per item (in place, no trajectory).  Writes the final state, the
+// last step's superchunk partials and shift (as the per-step launches leave
+// them) and the trace entries 0..m-1.
+template <typename T, int DEG>
+__global__ __launch_bounds__(kResidentThreads) void k_em_sweep_resident(const WorkItem *__restrict__ items,
+                                                                        const T *__restrict__ z, int32_t m,
+                                                                        double2 *__restrict__ part_out,
+                                                                        double *__restrict__ shift_out,
+                                                                        double2 *__restrict__ trace) {
+    constexpr int NI = kResidentPerThread;
+    __shared__ double wsum[kResidentThreads / 64][NI][2];
+    __shared__ ResidentShared<T> sh;
+    const WorkItem &W = items[blockIdx.x];
+    T *__restrict__ x = reinterpret_cast<T *>(W.x);
+    const int64_t P = W.P;
+    const uint32_t nq = (uint32_t)((P + 3) / 4);
+    const int nsc = W.nsc;
+    const int g = (int)threadIdx.x / kThreads, t = (int)threadIdx.x % kThreads;
+    uint32_t qi[NI];
+    T v[NI][4];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        qi[i] = (uint32_t)(g + kResidentGroups * i) * kThreads + (uint32_t)t;
+        if (qi[i] < nq) {
+            load_quad(x, 4 * (int64_t)qi[i], P, v[i]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[i][e] = (T)0;
+        }
+    }
+    const T *__restrict__ zi = z + W.zoff;
+    // the step-0 sums, about x[0]
+    const T shift0 = x[0];
+    double a1[NI], a2[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        a1[i] = 0.0;
+        a2[i] = 0.0;
+        if (qi[i] < nq) {
+            const int64_t p = 4 * (int64_t)qi[i];
+            double d[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) d[e] = (p + e < P) ? leaf_diff(v[i][e], shift0) : 0.0;
+            double q1, q2;
+            quad_leaf(d, q1, q2);
+            a1[i] += q1;
+            a2[i] += q2;
+        }
+    }
+    double shd = (double)shift0, p1 = 0.0, p2 = 0.0;
+    T zn[NI][4];
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+        if (qi[i] < nq) gload_quad<false>(zi, qi[i], zn[i]);
+    resident_exchange<T, NI>(W, a1, a2, nsc, shd, wsum, sh, p1, p2);
+    for (int32_t j = 0; j < m; ++j) {
+        const double mean = sh.mv[0];
+        if (trace && threadIdx.x == 0) trace[(int64_t)blockIdx.x * (m + 1) + j] = make_double2(mean, sh.mv[1]);
+        const T shift = (T)mean;
+        const T c0 = sh.coef[0], c1 = sh.coef[1], c2 = sh.coef[2], c3 = sh.coef[3], e0 = sh.coef[4],
+                e1 = sh.coef[5];
+        T zc[NI][4];
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) zc[i][e] = zn[i][e];
+        if (j + 1 < m) { // the next step's normals, in flight through this step's barriers
+            const T *__restrict__ zr = zi + (int64_t)(j + 1) * 4 * nq;
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+                if (qi[i] < nq) gload_quad<false>(zr, qi[i], zn[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            a1[i] = 0.0;
+            a2[i] = 0.0;
+            if (qi[i] < nq) {
+                const int64_t p = 4 * (int64_t)qi[i];
+                double d[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    v[i][e] = em_update<T, DEG>(v[i][e], zc[i][e], c0, c1, c2, c3, e0, e1);
+                    d[e] = (p + e < P) ? leaf_diff(v[i][e], shift) : 0.0;
+                }
+                double q1, q2;
+                quad_leaf(d, q1, q2);
+                a1[i] += q1;
+                a2[i] += q2;
+            }
+        }
+        shd = (double)shift;
+        resident_exchange<T, NI>(W, a1, a2, nsc, shd, wsum, sh, p1, p2);
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+        if (qi[i] < nq) store_quad(x, 4 * (int64_t)qi[i], P, v[i]);
+    if (threadIdx.x < (unsigned)nsc) part_out[W.part_off + (int)threadIdx.x] = make_double2(p1, p2);
+    if (threadIdx.x == 0) shift_out[blockIdx.x] = shd;
 }
 
 // ----------------------------------------------------------------------------
@@ -1582,6 +1821,30 @@ hipError_t launch_em_step(int prec, int deg, int variant, const WorkItem *items,
         else
             em_step_variant<float, 3>(variant, items, blocks, nblocks, j, part_in, shift_in, mv, part_out, shift_out,
                                       trace, m, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_em_sweep_resident(int prec, int deg, const WorkItem *items, int n_items, const int2 *blocks,
+                                    int nblocks, int m, void *z, double2 *part_out, double *shift_out,
+                                    double2 *trace, hipStream_t s) {
+    const dim3 gz(nblocks, m);
+    if (prec == 0) {
+        hipLaunchKernelGGL(k_sweep_normals<double>, gz, dim3(kThreads), 0, s, items, blocks, (double *)z);
+        if (deg == 1)
+            hipLaunchKernelGGL((k_em_sweep_resident<double, 1>), dim3(n_items), dim3(kResidentThreads), 0, s, items,
+                               (const double *)z, m, part_out, shift_out, trace);
+        else
+            hipLaunchKernelGGL((k_em_sweep_resident<double, 3>), dim3(n_items), dim3(kResidentThreads), 0, s, items,
+                               (const double *)z, m, part_out, shift_out, trace);
+    } else {
+        hipLaunchKernelGGL(k_sweep_normals<float>, gz, dim3(kThreads), 0, s, items, blocks, (float *)z);
+        if (deg == 1)
+            hipLaunchKernelGGL((k_em_sweep_resident<float, 1>), dim3(n_items), dim3(kResidentThreads), 0, s, items,
+                               (const float *)z, m, part_out, shift_out, trace);
+        else
+            hipLaunchKernelGGL((k_em_sweep_resident<float, 3>), dim3(n_items), dim3(kResidentThreads), 0, s, items,
+                               (const float *)z, m, part_out, shift_out, trace);
     }
     return hipGetLastError();
 }

@@ -18,6 +18,14 @@ hipError_t launch_em_step(int prec, int deg, int variant, const WorkItem *items,
                           int nblocks, int j, const double2 *part_in, const double *shift_in, double2 *mv,
                           double2 *part_out, double *shift_out, double2 *trace, int m, hipStream_t s);
 // trace entry m of each item: moments of its final state from the last step's partials
+// Resident fine sweep of every item (each at most kResidentMaxP particles, in
+// place): the normals of all m steps into z (the items' zoff), then one
+// block per item through all the steps; leaves the last step's partials and
+// shift in part_out / shift_out and trace entries 0..m-1 as the per-step
+// launches do.
+hipError_t launch_em_sweep_resident(int prec, int deg, const WorkItem *items, int n_items, const int2 *blocks,
+                                    int nblocks, int m, void *z, double2 *part_out, double *shift_out,
+                                    double2 *trace, hipStream_t s);
 hipError_t launch_finish(const WorkItem *items, int n_items, const double2 *part_in, const double *shift_in,
                          double2 *trace, int m, hipStream_t s);
 hipError_t launch_adj_init(int prec, const WorkItem *items, const int2 *blocks, int nblocks, const void *xS,

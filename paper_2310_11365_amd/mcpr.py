@@ -115,6 +115,10 @@ def lib() -> ctypes.CDLL:
         L.mcpr_tuned_variant.restype = i32
         L.mcpr_graph_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.mcpr_graph_stats.restype = st
+        L.mcpr_set_resident.argtypes = [vp, i32]
+        L.mcpr_set_resident.restype = st
+        L.mcpr_resident_sweeps.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.mcpr_resident_sweeps.restype = st
         L.mcpr_set_cdf_sort.argtypes = [vp, i32]
         L.mcpr_set_cdf_sort.restype = st
         L.mcpr_cdf_stats.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int64)] * 3
@@ -266,6 +270,17 @@ class Context:
         b, n = ctypes.c_int64(), ctypes.c_int64()
         self._check(lib().mcpr_graph_stats(self._h, ctypes.byref(b), ctypes.byref(n)))
         return b.value, n.value
+
+    def set_resident(self, enable: bool):
+        """Resident fine sweeps of small ensembles (default on; the same bits
+        as the per-step launches)."""
+        self._check(lib().mcpr_set_resident(self._h, 1 if enable else 0))
+
+    def resident_sweeps(self) -> int:
+        """Fine sweeps run resident so far."""
+        v = ctypes.c_int64()
+        self._check(lib().mcpr_resident_sweeps(self._h, ctypes.byref(v)))
+        return v.value
 
     def set_cdf_sort(self, mode: int):
         """Sort of the empirical-CDF drift: 1 buckets after each sweep's first

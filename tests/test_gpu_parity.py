@@ -419,6 +419,66 @@ def test_batched_equals_single_bitwise(mc, ctx):
         assert batched[i].tobytes() == singles[i][1].tobytes()
 
 
+def _resident_case(mc, prec, cubic, sizes, slice_index=3, regions=(0.0,)):
+    """Ensembles of the given sizes (one problem each) propagated one slice
+    with records and the trace, on a fresh context with resident sweeps on and
+    on one with them off; returns both results and the contexts' resident
+    sweep counts."""
+    import torch
+    coef = W.dz_coef() if cubic else W.ou_coef(0.7, 0.4)
+    pr = W.make_problem(coef, W.P0(W.P0_MIXTURE, 0.5, -1.0, 0.3, 1.0, 0.3), 0.4, 8, 1e-3, regions,
+                        precision=prec, seed=11)
+    pcs = [mc.problem_c(pr) for _ in sizes]
+    dt = torch.float64 if prec == W.FP64 else torch.float32
+    nreg = len(regions) + 1
+    m = pr.steps_per_slice
+    out = []
+    for resident in (True, False):
+        c = mc.Context(0)
+        c.set_resident(resident)
+        xs = [torch.empty(P, dtype=dt, device="cuda") for P in sizes]
+        c.init_particles(pcs, [mc.ensemble(x, i, 0, i) for i, x in enumerate(xs)])
+        runs = []
+        for rep in range(2):  # the second call replays the captured sweep
+            ys = [x.clone() for x in xs]
+            buf = mc.stats_buffer(len(ys), nreg)
+            tr = torch.empty(len(ys) * (m + 1) * 2, dtype=torch.float64, device="cuda")
+            c.fine_propagate(pcs, [mc.ensemble(y, i, slice_index, i) for i, y in enumerate(ys)], buf, tr)
+            torch.cuda.synchronize()
+            runs.append(([y.clone() for y in ys], buf.clone(), tr.clone()))
+        out.append((runs, c.resident_sweeps()))
+        c.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32])
+@pytest.mark.parametrize("cubic", [False, True])
+def test_resident_sweep_equals_per_step_launches_bitwise(mc, prec, cubic):
+    """Resident sweeps (one block per ensemble through all the steps, normals
+    drawn beforehand) give bit for bit the per-step launches' particles,
+    records and trace: ragged ensembles from 1 to the 12288-particle limit in
+    one call (one, several and the most superchunks, tail quads), linear and
+    cubic drift, two regions; the second call replays its graph."""
+    import torch
+    sizes = [1, 5, 1023, 1024, 1027, 4096, 10_001, 12_288]
+    (res, n_res), (per, n_per) = _resident_case(mc, prec, cubic, sizes)
+    assert n_res == 2 and n_per == 0, (n_res, n_per)
+    for (xr, br, tr), (xp, bp, tp) in zip(res, per):
+        for a, b in zip(xr, xp):
+            assert torch.equal(a, b)
+        assert torch.equal(br, bp) and torch.equal(tr, tp)
+
+
+def test_resident_sweep_not_taken_above_its_limit(mc):
+    """One ensemble above 12288 particles in the call: the per-step launches
+    run (no resident sweep), with the same bits as alone."""
+    import torch
+    (res, n_res), (per, n_per) = _resident_case(mc, W.FP64, False, [100, 12_289])
+    assert n_res == 0 and n_per == 0
+    for a, b in zip(res[0][0], per[0][0]):
+        assert torch.equal(a, b)
+
+
 def test_run_to_run_bitwise(mc, ctx):
     import torch
     wl = W.dz_bimodal(P=300_000)
