@@ -479,6 +479,38 @@ def test_resident_sweep_not_taken_above_its_limit(mc):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32])
+def test_parareal_resident_equals_per_step_bitwise(mc, prec):
+    """The Parareal driver with resident sweeps (every iteration sweeps the
+    slices not yet exact, a smaller set each time) reproduces the per-step
+    launches' macro states, flags and slice states bit for bit: bimodal
+    workload with two regions and learning, P = 12288 (the resident limit);
+    the slice states still held after four iterations compared too."""
+    import torch
+    wl = W.dz_bimodal(P=12_288, N=8, T=2.0, precision=prec)
+    runs = []
+    for resident in (True, False):
+        c = mc.Context(0)
+        c.set_resident(resident)
+        para = mc.Parareal([wl.problem], [wl.P], c, learning=True, tol=0.0)
+        para.init()
+        out = [para.macro(0)]
+        for _ in range(4):
+            para.iterate()
+            out.append(para.macro(0) + (para.flags(0).copy(),))
+        slots = [para.slot(0, n).clone() for n in range(4, wl.problem.n_slices + 1)]  # (those still held)
+        runs.append((out, slots, c.resident_sweeps()))
+        para.close()
+        c.close()
+    (a, sa, na), (b, sb, nb) = runs
+    assert na >= 4 and nb == 0, (na, nb)
+    for x, y in zip(a, b):
+        for u, v in zip(x, y):
+            assert np.asarray(u).tobytes() == np.asarray(v).tobytes()
+    for u, v in zip(sa, sb):
+        assert torch.equal(u, v)
+
+
 def test_run_to_run_bitwise(mc, ctx):
     import torch
     wl = W.dz_bimodal(P=300_000)
