@@ -60,6 +60,55 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double *lds) {
     __syncthreads();
 }
 
+// Lane 0's value of wave_sum with the same additions in the same order, from
+// DPP permutes, one swizzle and one readlane instead of LDS-crossbar shuffles
+// (where many wavefronts reduce at once they queue on the crossbar: the
+// resident sweep's sixteen wavefronts on one CU, the restriction's million
+// blocks).
+// At each level lane 0 reads a lane whose partial equals that of its xor
+// partner: after the levels below o, the lanes of each aligned group of o
+// hold equal partials (every addition is commutative), so the half-row
+// mirror (lane 7 - i) stands for xor 4; row rotation by 8 is xor 8.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum_lane0(double v) {
+    v += dpp_f64<0xB1>(v);  // quad_perm [1,0,3,2]: xor 1
+    v += dpp_f64<0x4E>(v);  // quad_perm [2,3,0,1]: xor 2
+    v += dpp_f64<0x141>(v); // row_half_mirror: a lane of the partner quad
+    v += dpp_f64<0x128>(v); // row_ror:8: xor 8
+    {
+        const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F); // xor 16 within 32 lanes
+        const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+        v += __hiloint2double(hi, lo);
+    }
+    {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(v), 32);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 32);
+        v += __hiloint2double(hi, lo);
+    }
+    return v;
+}
+
+// block_sum with the lane-0 wave sums (the same bits).
+template <int N>
+__device__ __forceinline__ void block_sum_dpp(double (&v)[N], double *lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = wave_sum_lane0(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) lds[wave * N + k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = (lds[k] + lds[N + k]) + (lds[2 * N + k] + lds[3 * N + k]);
+    __syncthreads();
+}
+
 template <int N>
 __device__ __forceinline__ void block_minmax(double (&mn)[N], double (&mx)[N], double *lds) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -461,37 +510,6 @@ __global__ __launch_bounds__(kThreads) void k_sweep_normals(const WorkItem *__re
     T zz[4];
     box_muller4(w, zz);
     gstore_quad<false>(z + W.zoff + (int64_t)j * 4 * nq, q, zz);
-}
-
-// Lane 0's value of wave_sum with the same additions in the same order, from
-// DPP permutes, one swizzle and one readlane instead of LDS-crossbar shuffles
-// (sixteen wavefronts of one block on one CU would queue on the crossbar).
-// At each level lane 0 reads a lane whose partial equals that of its xor
-// partner: after the levels below o, the lanes of each aligned group of o
-// hold equal partials (every addition is commutative), so the half-row
-// mirror (lane 7 - i) stands for xor 4; row rotation by 8 is xor 8.
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double wave_sum_lane0(double v) {
-    v += dpp_f64<0xB1>(v);  // quad_perm [1,0,3,2]: xor 1
-    v += dpp_f64<0x4E>(v);  // quad_perm [2,3,0,1]: xor 2
-    v += dpp_f64<0x141>(v); // row_half_mirror: a lane of the partner quad
-    v += dpp_f64<0x128>(v); // row_ror:8: xor 8
-    {
-        const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F); // xor 16 within 32 lanes
-        const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
-        v += __hiloint2double(hi, lo);
-    }
-    {
-        const int lo = __builtin_amdgcn_readlane(__double2loint(v), 32);
-        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 32);
-        v += __hiloint2double(hi, lo);
-    }
-    return v;
 }
 
 // The per-step exchange of the resident block.  Every wave sums its quad
@@ -1533,13 +1551,17 @@ __global__ __launch_bounds__(kThreads) void k_region_partials(const WorkItem *__
     }
     const int64_t base = (int64_t)bt.y * 4 * kThreads * R;
     if (base + (int64_t)4 * kThreads * R <= P) {
+        // a full superchunk: every quad's load issued before the first is used
         const uint32_t qb = (uint32_t)(base >> 2) + threadIdx.x;
-        for (int r = 0; r < R; ++r) {
-            T v[4];
-            gload_quad<false>(x + base, (uint32_t)(r * kThreads + threadIdx.x), v);
-            region_accumulate<T, NREG, MODE, FULL>(v, 0, P, qb + (uint32_t)(r * kThreads), W, sp, mp, sh, acc, mn, mx,
-                                                   false);
-        }
+        T v[kMaxQuadsPerThread][4];
+#pragma unroll
+        for (int r = 0; r < kMaxQuadsPerThread; ++r)
+            if (r < R) gload_quad<false>(x + base, (uint32_t)(r * kThreads + threadIdx.x), v[r]);
+#pragma unroll
+        for (int r = 0; r < kMaxQuadsPerThread; ++r)
+            if (r < R)
+                region_accumulate<T, NREG, MODE, FULL>(v[r], 0, P, qb + (uint32_t)(r * kThreads), W, sp, mp, sh, acc,
+                                                       mn, mx, false);
     } else {
         for (int r = 0; r < R; ++r) {
             const int64_t Q = (base >> 2) + (int64_t)r * kThreads + threadIdx.x;
@@ -1551,7 +1573,7 @@ __global__ __launch_bounds__(kThreads) void k_region_partials(const WorkItem *__
             }
         }
     }
-    block_sum<3 * NREG>(acc, lds);
+    block_sum_dpp<3 * NREG>(acc, lds);
     if (FULL) block_minmax<NREG>(mn, mx, lds);
     if (threadIdx.x == 0) {
         RegionPartial *out = rpart + (int64_t)(W.part_off + bt.y) * NREG;
@@ -1702,6 +1724,32 @@ __global__ __launch_bounds__(kThreads) void k_match_apply(const WorkItem *__rest
     RegionMap mp[NREG];
 #pragma unroll
     for (int i = 0; i < NREG; ++i) mp[i] = maps[(int64_t)bt.x * NREG + i];
+    auto map_quad = [&](T (&v)[4], int64_t Q) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int g = region_of<NREG>((double)v[e], sp);
+            RegionMap m0 = mp[0];
+#pragma unroll
+            for (int i = 1; i < NREG; ++i)
+                if (g == i) m0 = mp[i];
+            v[e] = (T)apply_map<T>(m0, v[e], (uint32_t)Q, e, (uint32_t)W.inst, W.key0, W.key1);
+        }
+    };
+    const int64_t base = (int64_t)bt.y * 4 * kThreads * R; // first particle of the superchunk
+    if (base + (int64_t)4 * kThreads * R <= P) {
+        // a full superchunk: every quad's load issued before the first map
+        T v[kMaxQuadsPerThread][4];
+#pragma unroll
+        for (int g = 0; g < kMaxQuadsPerThread; ++g)
+            if (g < R) gload_quad<false>(xin + base, (uint32_t)(g * kThreads + threadIdx.x), v[g]);
+#pragma unroll
+        for (int g = 0; g < kMaxQuadsPerThread; ++g)
+            if (g < R) {
+                map_quad(v[g], (base >> 2) + g * kThreads + threadIdx.x);
+                gstore_quad<false>(x + base, (uint32_t)(g * kThreads + threadIdx.x), v[g]);
+            }
+        return;
+    }
     const int64_t qbase = (int64_t)bt.y * kThreads * R + threadIdx.x;
     for (int r = 0; r < R; ++r) {
         const int64_t Q = qbase + (int64_t)r * kThreads;
@@ -1709,15 +1757,7 @@ __global__ __launch_bounds__(kThreads) void k_match_apply(const WorkItem *__rest
         if (p < P) {
             T v[4];
             load_quad(xin, p, P, v);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int g = region_of<NREG>((double)v[e], sp);
-                RegionMap m0 = mp[0];
-#pragma unroll
-                for (int i = 1; i < NREG; ++i)
-                    if (g == i) m0 = mp[i];
-                v[e] = (T)apply_map<T>(m0, v[e], (uint32_t)Q, e, (uint32_t)W.inst, W.key0, W.key1);
-            }
+            map_quad(v, Q);
             store_quad(x, p, P, v);
         }
     }
