@@ -354,7 +354,7 @@ void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_
         }
         if (p.steps_per_slice != t.zm) t.zm = -1;
         w.zoff = t.total_z;
-        t.total_z += (int64_t)p.steps_per_slice * 4 * ((E.n_particles + 3) / 4);
+        t.total_z += (int64_t)p.steps_per_slice * 4 * mcpr::kThreads * w.R * w.nsc; // every quad of its superchunks
         w.dt = p.dt;
         w.sdt = std::sqrt(p.dt);
         w.p0[0] = p.p0_w;

@@ -75,11 +75,16 @@ __device__ __forceinline__ double dpp_f64(double v) {
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ double wave_sum_lane0(double v) {
+// Lane 0's sum over lanes 0..15 (the levels of the xor butterfly inside a row).
+__device__ __forceinline__ double row_sum_lane0(double v) {
     v += dpp_f64<0xB1>(v);  // quad_perm [1,0,3,2]: xor 1
     v += dpp_f64<0x4E>(v);  // quad_perm [2,3,0,1]: xor 2
     v += dpp_f64<0x141>(v); // row_half_mirror: a lane of the partner quad
     v += dpp_f64<0x128>(v); // row_ror:8: xor 8
+    return v;
+}
+__device__ __forceinline__ double wave_sum_lane0(double v) {
+    v = row_sum_lane0(v);
     {
         const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F); // xor 16 within 32 lanes
         const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
@@ -341,8 +346,22 @@ template <typename T>
 struct StepCoef {
     T c0, c1, c2, c3, e0, e1;
 };
+// The inputs of step_coef that stay fixed through a sweep (the item's
+// coefficients a0 a1 a2 a3 am av b0 b1 bm bv axs, dt and sqrt(dt)).
+struct StepIn {
+    double c[11];
+    double dt, sdt;
+};
+__device__ __forceinline__ StepIn step_in(const WorkItem &W) {
+    StepIn k;
+#pragma unroll
+    for (int i = 0; i < 11; ++i) k.c[i] = W.c[i];
+    k.dt = W.dt;
+    k.sdt = W.sdt;
+    return k;
+}
 template <typename T>
-__device__ __forceinline__ StepCoef<T> step_coef(const WorkItem &W, double mean, double var) {
+__device__ __forceinline__ StepCoef<T> step_coef(const StepIn &W, double mean, double var) {
     const double dt = W.dt, sdt = W.sdt;
     StepCoef<T> k;
     k.c0 = (T)((W.c[0] + W.c[4] * mean + W.c[5] * var) * dt);
@@ -352,6 +371,10 @@ __device__ __forceinline__ StepCoef<T> step_coef(const WorkItem &W, double mean,
     k.e0 = (T)((W.c[6] + W.c[8] * mean + W.c[9] * var) * sdt);
     k.e1 = (T)(W.c[7] * sdt);
     return k;
+}
+template <typename T>
+__device__ __forceinline__ StepCoef<T> step_coef(const WorkItem &W, double mean, double var) {
+    return step_coef<T>(step_in(W), mean, var);
 }
 
 // Mean field of step j from the previous launch's partials: one block per item
@@ -478,23 +501,32 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
 
 // ----------------------------------------------------------------------------
 // Resident fine sweep of small ensembles (at most kResidentMaxP particles,
-// one quad per thread and superchunk): one block of kResidentThreads per
-// ensemble keeps its particles in registers through all m steps of the sweep,
-// so a step costs a few block barriers instead of a launch.  The block's four
-// groups of kThreads threads stand for the superchunks g, g + 4, g + 8, ...
-// (thread t of group g holds quad (g + 4 i) kThreads + t), and every sum is
-// formed in the canonical order of the per-step launches: the same quad
-// leaves, the same tree inside each superchunk, the same ensemble tree, so the
-// sweep gives the per-step launches' bits.  The normals, which depend on the
-// particle, the step and the instance only, are drawn for the whole sweep
-// beforehand by k_sweep_normals (the transcendental work of every step in one
-// launch wide enough to fill the chip) into z: item i's normal e of quad q at
-// step j is z[zoff_i + 4 nq_i j + 4 q + e].
+// canonical superchunks of one quad per thread): one block of
+// kResidentThreads per ensemble keeps its particles in registers through all
+// m steps of the sweep, so a step costs two block barriers instead of a
+// launch.  Wavefront s of the block holds superchunk s, lane l its quads
+// 256 s + 4 l + r (r = 0..3): the lane's four quad leaves are the leaves
+// 4l .. 4l+3 of the superchunk's canonical tree, so the lane adds its two
+// lowest levels, (u0 + u1) + (u2 + u3), and the wave's lane-0 sum adds the
+// six above them -- the complete pairwise tree over the superchunk's 256
+// thread sums, as the per-step launches form it (every addition is
+// commutative, so the order of the two operands does not change a bit).
+// The ensemble tree follows in wavefront 0.  The sweep therefore gives the
+// per-step launches' bits with a quarter of their reduction work per quad.
+// The normals, which depend on the particle, the step and the instance only,
+// are drawn for the whole sweep beforehand by k_sweep_normals (the
+// transcendental work of every step in one launch wide enough to fill the
+// chip) into z, laid out so that every load of the sweep is coalesced: item
+// i's normal e of quad 256 s + 4 l + r at step j is
+//   z[zoff_i + 1024 nsc_i j + 4 (64 nsc_i r + 64 s + l) + e].
 // ----------------------------------------------------------------------------
-constexpr int kResidentGroups = 4;
-constexpr int kResidentThreads = kResidentGroups * kThreads;
-constexpr int kResidentPerThread = kResidentMaxSc / kResidentGroups;
+constexpr int kResidentThreads = 64 * kResidentMaxSc;
 static_assert(kResidentMaxP < kSmallEnsemble, "one quad per thread and superchunk");
+
+// Quad index of (r, s, l) in one step's normals of an item with nsc superchunks.
+__device__ __forceinline__ uint32_t resident_zquad(int r, int s, int l, int nsc) {
+    return (uint32_t)(64 * nsc * r + 64 * s + l);
+}
 
 // grid (superchunk blocks of the launch, m): one quad per thread
 template <typename T>
@@ -504,69 +536,118 @@ __global__ __launch_bounds__(kThreads) void k_sweep_normals(const WorkItem *__re
     const WorkItem &W = items[bt.x];
     const int32_t j = (int32_t)blockIdx.y;
     const uint32_t nq = (uint32_t)((W.P + 3) / 4);
-    const uint32_t q = (uint32_t)bt.y * kThreads + threadIdx.x;
+    const int r = (int)threadIdx.x >> 6, l = (int)threadIdx.x & 63;
+    const uint32_t q = (uint32_t)bt.y * kThreads + 4u * (uint32_t)l + (uint32_t)r;
     if (q >= nq) return;
     const Words4 w = philox4x32_10(q, (uint32_t)(W.step0 + j), (uint32_t)W.inst, 0u, W.key0, W.key1);
     T zz[4];
     box_muller4(w, zz);
-    gstore_quad<false>(z + W.zoff + (int64_t)j * 4 * nq, q, zz);
+    gstore_quad<false>(z + W.zoff + (int64_t)j * 4 * kThreads * W.nsc, resident_zquad(r, bt.y, l, W.nsc), zz);
 }
 
-// The per-step exchange of the resident block.  Every wave sums its quad
-// leaves of each superchunk it holds (a1, a2; superchunks past nsc are
-// skipped, uniformly per wave); after the barrier wave 0 forms superchunk
-// t's sum in lane t (the tree over its four waves), the ensemble sums, the
-// mean field and the step coefficients, and publishes them; the other three
-// waves of the canonical ensemble tree hold only zeros (nsc <= 64), so their
-// contribution is the exact +0.0 of (w0 + 0) + (0 + 0).  p1, p2: superchunk
-// t's sums in lane t < nsc of wave 0.
+// The lane's part of a superchunk's sums: the two lowest levels of the
+// canonical tree over the thread sums of its four quads, which are 0.0 + the
+// quad's leaf (0.0 past the ensemble).  The leaf q2 is never -0.0, so 0.0 + q2
+// = q2; a tree over the q1 themselves differs from the tree over 0.0 + q1 at
+// most by the sign of a zero result (a -0.0 where the canonical sum is +0.0),
+// which the lane's final + 0.0 removes, so a1 and a2 carry the canonical bits.
+// FULL: every particle of the lane's quads exists (all but the ensemble's
+// last wavefront), so no test is made.
+template <bool FULL, typename T>
+__device__ __forceinline__ void resident_leaves(const T (&v)[4][4], T shift, uint32_t q0, uint32_t nq, int64_t P,
+                                                double &a1, double &a2) {
+    double u1[4], u2[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t q = q0 + (uint32_t)r;
+        if (FULL || q < nq) {
+            double d[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) d[e] = leaf_diff(v[r][e], shift);
+            if (!FULL && 4 * (int64_t)q + 4 > P) { // the ensemble's ragged last quad
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (4 * (int64_t)q + e >= P) d[e] = 0.0;
+            }
+            quad_leaf(d, u1[r], u2[r]);
+        } else {
+            u1[r] = 0.0;
+            u2[r] = 0.0;
+        }
+    }
+    a1 = ((u1[0] + u1[1]) + (u1[2] + u1[3])) + 0.0;
+    a2 = (u2[0] + u2[1]) + (u2[2] + u2[3]);
+}
+
+// One step of the lane's quads with normals zc, then its part of the sums
+// (full: every particle of the wavefront's quads exists, which holds for all
+// but the ensemble's last wavefront).
+template <typename T, int DEG>
+__device__ __forceinline__ void resident_advance(T (&v)[4][4], const T (&zc)[4][4], const T (&k)[6], T shift,
+                                                 uint32_t q0, uint32_t nq, int64_t P, bool full, double &a1,
+                                                 double &a2) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (q0 + r < nq) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                v[r][e] = em_update<T, DEG>(v[r][e], zc[r][e], k[0], k[1], k[2], k[3], k[4], k[5]);
+        }
+    if (full)
+        resident_leaves<true>(v, shift, q0, nq, P, a1, a2);
+    else
+        resident_leaves<false>(v, shift, q0, nq, P, a1, a2);
+}
+
+// The per-step exchange of the resident block.  Wavefront s < nsc completes
+// superchunk s's sums into psum[s]; after the barrier lane 0 of wavefront 0
+// forms the ensemble sums, the mean field and the step coefficients, and
+// publishes them.  The ensemble sums follow the canonical tree: thread t of
+// the 256-thread ensemble tree holds 0.0 + superchunk t's sums (t < nsc <= 16)
+// and 0.0 beyond, so the wavefront tree over lanes 0..63 is the tree over
+// lanes 0..15 (row_sum_lane0) plus two all-zero subtrees, and the three other
+// wavefronts add (w0 + 0) + (0 + 0).
 template <typename T>
 struct ResidentShared {
     double mv[2];   // mean and variance at the start of the next step
     T coef[6];      // its c0 c1 c2 c3 e0 e1
 };
-template <typename T, int NI>
-__device__ __forceinline__ void resident_exchange(const WorkItem &W, const double (&a1)[NI],
-                                                  const double (&a2)[NI], int nsc, double shd,
-                                                  double (*wsum)[NI][2], ResidentShared<T> &sh, double &p1,
-                                                  double &p2) {
-    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
-    const int g = (int)threadIdx.x / kThreads;
-#pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        if (g + kResidentGroups * i >= nsc) continue;
-        const double w1 = wave_sum_lane0(a1[i]), w2 = wave_sum_lane0(a2[i]);
+static_assert(kResidentMaxSc <= 16, "the ensemble tree below covers 16 superchunks");
+template <typename T>
+__device__ __forceinline__ void resident_exchange(const StepIn &cin, double Pd, double a1, double a2, int nsc,
+                                                  double shd, double (*psum)[2], ResidentShared<T> &sh) {
+    const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = (int)threadIdx.x & 63;
+    if (s < nsc) {
+        const double w1 = wave_sum_lane0(a1), w2 = wave_sum_lane0(a2);
         if (lane == 0) {
-            wsum[wave][i][0] = w1;
-            wsum[wave][i][1] = w2;
+            psum[s][0] = w1;
+            psum[s][1] = w2;
         }
     }
     __syncthreads();
-    if (wave == 0) {
-        double e1 = 0.0, e2 = 0.0;
+    double t1 = 0.0, t2 = 0.0;
+    if (s == 0) {
         if (lane < nsc) {
-            const int gs = lane % kResidentGroups, is = lane / kResidentGroups, w0 = 4 * gs;
-            p1 = (wsum[w0][is][0] + wsum[w0 + 1][is][0]) + (wsum[w0 + 2][is][0] + wsum[w0 + 3][is][0]);
-            p2 = (wsum[w0][is][1] + wsum[w0 + 1][is][1]) + (wsum[w0 + 2][is][1] + wsum[w0 + 3][is][1]);
-            e1 += p1;
-            e2 += p2;
+            t1 += psum[lane][0];
+            t2 += psum[lane][1];
         }
-        e1 = wave_sum_lane0(e1);
-        e2 = wave_sum_lane0(e2);
-        if (lane == 0) {
-            const double S1 = (e1 + 0.0) + (0.0 + 0.0), S2 = (e2 + 0.0) + (0.0 + 0.0);
-            double mean, var;
-            finish_moments(S1, S2, shd, (double)W.P, mean, var);
-            const StepCoef<T> k = step_coef<T>(W, mean, var);
-            sh.mv[0] = mean;
-            sh.mv[1] = var;
-            sh.coef[0] = k.c0;
-            sh.coef[1] = k.c1;
-            sh.coef[2] = k.c2;
-            sh.coef[3] = k.c3;
-            sh.coef[4] = k.e0;
-            sh.coef[5] = k.e1;
-        }
+        t1 = row_sum_lane0(t1);
+        t2 = row_sum_lane0(t2);
+    }
+    if (threadIdx.x == 0) {
+        const double e1 = (t1 + 0.0) + 0.0, e2 = (t2 + 0.0) + 0.0; // lanes 16..31, then 32..63
+        const double S1 = (e1 + 0.0) + (0.0 + 0.0), S2 = (e2 + 0.0) + (0.0 + 0.0);
+        double mean, var;
+        finish_moments(S1, S2, shd, Pd, mean, var);
+        const StepCoef<T> k = step_coef<T>(cin, mean, var);
+        sh.mv[0] = mean;
+        sh.mv[1] = var;
+        sh.coef[0] = k.c0;
+        sh.coef[1] = k.c1;
+        sh.coef[2] = k.c2;
+        sh.coef[3] = k.c3;
+        sh.coef[4] = k.e0;
+        sh.coef[5] = k.e1;
     }
     __syncthreads();
 }
@@ -580,94 +661,87 @@ __global__ __launch_bounds__(kResidentThreads) void k_em_sweep_resident(const Wo
                                                                         double2 *__restrict__ part_out,
                                                                         double *__restrict__ shift_out,
                                                                         double2 *__restrict__ trace) {
-    constexpr int NI = kResidentPerThread;
-    __shared__ double wsum[kResidentThreads / 64][NI][2];
+    __shared__ double psum[kResidentMaxSc][2];
     __shared__ ResidentShared<T> sh;
     const WorkItem &W = items[blockIdx.x];
     T *__restrict__ x = reinterpret_cast<T *>(W.x);
     const int64_t P = W.P;
     const uint32_t nq = (uint32_t)((P + 3) / 4);
     const int nsc = W.nsc;
-    const int g = (int)threadIdx.x / kThreads, t = (int)threadIdx.x % kThreads;
-    uint32_t qi[NI];
-    T v[NI][4];
+    // s is uniform in the wavefront: scalar branches on it
+    const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), l = (int)threadIdx.x & 63;
+    const uint32_t q0 = (uint32_t)s * kThreads + 4u * (uint32_t)l;
+    const bool full = (int64_t)(s + 1) * 4 * kThreads <= P;
+    const StepIn cin = step_in(W);
+    const double Pd = (double)P;
+    T v[4][4];
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        qi[i] = (uint32_t)(g + kResidentGroups * i) * kThreads + (uint32_t)t;
-        if (qi[i] < nq) {
-            load_quad(x, 4 * (int64_t)qi[i], P, v[i]);
+    for (int r = 0; r < 4; ++r) {
+        if (q0 + r < nq) {
+            load_quad(x, 4 * (int64_t)(q0 + r), P, v[r]);
         } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[i][e] = (T)0;
+            for (int e = 0; e < 4; ++e) v[r][e] = (T)0;
         }
     }
     const T *__restrict__ zi = z + W.zoff;
+    const int64_t zstep = (int64_t)4 * kThreads * nsc;
     // the step-0 sums, about x[0]
     const T shift0 = x[0];
-    double a1[NI], a2[NI];
+    double a1, a2;
+    resident_leaves<false>(v, shift0, q0, nq, P, a1, a2);
+    double shd = (double)shift0;
+    // The normals' loads are issued unconditionally, whole steps ahead of
+    // their use, and no store is issued between them except every 64 steps,
+    // so that the wait for one step's normals does not also wait for the
+    // next step's (a conditional load or an interleaved store makes the
+    // compiler wait for every load in flight).  A quad past the ensemble
+    // reads an unused normal of its own superchunk, a wavefront past the
+    // last superchunk superchunk 0's, the last step its own normals again.
+    const int sz = s < nsc ? s : 0;
+    T za[4][4], zb[4][4];
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        a1[i] = 0.0;
-        a2[i] = 0.0;
-        if (qi[i] < nq) {
-            const int64_t p = 4 * (int64_t)qi[i];
-            double d[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) d[e] = (p + e < P) ? leaf_diff(v[i][e], shift0) : 0.0;
-            double q1, q2;
-            quad_leaf(d, q1, q2);
-            a1[i] += q1;
-            a2[i] += q2;
-        }
-    }
-    double shd = (double)shift0, p1 = 0.0, p2 = 0.0;
-    T zn[NI][4];
-#pragma unroll
-    for (int i = 0; i < NI; ++i)
-        if (qi[i] < nq) gload_quad<false>(zi, qi[i], zn[i]);
-    resident_exchange<T, NI>(W, a1, a2, nsc, shd, wsum, sh, p1, p2);
-    for (int32_t j = 0; j < m; ++j) {
+    for (int r = 0; r < 4; ++r) gload_quad<false>(zi, resident_zquad(r, sz, l, nsc), za[r]);
+    resident_exchange<T>(cin, Pd, a1, a2, nsc, shd, psum, sh);
+    // the trace entries of 64 steps, lane j % 64 of wavefront 0 holding step j's
+    double tm = 0.0, tv = 0.0;
+    // step j with its normals zc; the next step's normals go into zn, in
+    // flight through this step's barriers
+    auto step = [&](int32_t j, const T (&zc)[4][4], T (&zn)[4][4]) {
         const double mean = sh.mv[0];
-        if (trace && threadIdx.x == 0) trace[(int64_t)blockIdx.x * (m + 1) + j] = make_double2(mean, sh.mv[1]);
-        const T shift = (T)mean;
-        const T c0 = sh.coef[0], c1 = sh.coef[1], c2 = sh.coef[2], c3 = sh.coef[3], e0 = sh.coef[4],
-                e1 = sh.coef[5];
-        T zc[NI][4];
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) zc[i][e] = zn[i][e];
-        if (j + 1 < m) { // the next step's normals, in flight through this step's barriers
-            const T *__restrict__ zr = zi + (int64_t)(j + 1) * 4 * nq;
-#pragma unroll
-            for (int i = 0; i < NI; ++i)
-                if (qi[i] < nq) gload_quad<false>(zr, qi[i], zn[i]);
-        }
-#pragma unroll
-        for (int i = 0; i < NI; ++i) {
-            a1[i] = 0.0;
-            a2[i] = 0.0;
-            if (qi[i] < nq) {
-                const int64_t p = 4 * (int64_t)qi[i];
-                double d[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    v[i][e] = em_update<T, DEG>(v[i][e], zc[i][e], c0, c1, c2, c3, e0, e1);
-                    d[e] = (p + e < P) ? leaf_diff(v[i][e], shift) : 0.0;
-                }
-                double q1, q2;
-                quad_leaf(d, q1, q2);
-                a1[i] += q1;
-                a2[i] += q2;
+        if (trace && s == 0) {
+            if (l == (j & 63)) {
+                tm = mean;
+                tv = sh.mv[1];
+            }
+            if ((j & 63) == 63 || j + 1 == m) {
+                if (l <= (j & 63)) trace[(int64_t)blockIdx.x * (m + 1) + (j & ~63) + l] = make_double2(tm, tv);
             }
         }
-        shd = (double)shift;
-        resident_exchange<T, NI>(W, a1, a2, nsc, shd, wsum, sh, p1, p2);
-    }
+        const T shift = (T)mean;
+        T k[6];
 #pragma unroll
-    for (int i = 0; i < NI; ++i)
-        if (qi[i] < nq) store_quad(x, 4 * (int64_t)qi[i], P, v[i]);
-    if (threadIdx.x < (unsigned)nsc) part_out[W.part_off + (int)threadIdx.x] = make_double2(p1, p2);
+        for (int i = 0; i < 6; ++i) k[i] = sh.coef[i];
+        {
+            const T *__restrict__ zr = zi + (int64_t)(j + 1 < m ? j + 1 : j) * zstep;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) gload_quad<false>(zr, resident_zquad(r, sz, l, nsc), zn[r]);
+        }
+        resident_advance<T, DEG>(v, zc, k, shift, q0, nq, P, full, a1, a2);
+        shd = (double)shift;
+        resident_exchange<T>(cin, Pd, a1, a2, nsc, shd, psum, sh);
+    };
+    int32_t j = 0;
+    for (; j + 1 < m; j += 2) {
+        step(j, za, zb);
+        step(j + 1, zb, za);
+    }
+    if (j < m) step(j, za, zb);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (q0 + r < nq) store_quad(x, 4 * (int64_t)(q0 + r), P, v[r]);
+    if (threadIdx.x < (unsigned)nsc)
+        part_out[W.part_off + (int)threadIdx.x] = make_double2(psum[threadIdx.x][0], psum[threadIdx.x][1]);
     if (threadIdx.x == 0) shift_out[blockIdx.x] = shd;
 }
 
