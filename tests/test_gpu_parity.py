@@ -419,14 +419,14 @@ def test_batched_equals_single_bitwise(mc, ctx):
         assert batched[i].tobytes() == singles[i][1].tobytes()
 
 
-def _resident_case(mc, prec, cubic, sizes, slice_index=3, regions=(0.0,)):
+def _resident_case(mc, prec, cubic, sizes, slice_index=3, regions=(0.0,), T=0.4, N=8):
     """Ensembles of the given sizes (one problem each) propagated one slice
     with records and the trace, on a fresh context with resident sweeps on and
     on one with them off; returns both results and the contexts' resident
     sweep counts."""
     import torch
     coef = W.dz_coef() if cubic else W.ou_coef(0.7, 0.4)
-    pr = W.make_problem(coef, W.P0(W.P0_MIXTURE, 0.5, -1.0, 0.3, 1.0, 0.3), 0.4, 8, 1e-3, regions,
+    pr = W.make_problem(coef, W.P0(W.P0_MIXTURE, 0.5, -1.0, 0.3, 1.0, 0.3), T, N, 1e-3, regions,
                         precision=prec, seed=11)
     pcs = [mc.problem_c(pr) for _ in sizes]
     dt = torch.float64 if prec == W.FP64 else torch.float32
@@ -464,6 +464,22 @@ def test_resident_sweep_equals_per_step_launches_bitwise(mc, prec, cubic):
     (res, n_res), (per, n_per) = _resident_case(mc, prec, cubic, sizes)
     assert n_res == 2 and n_per == 0, (n_res, n_per)
     for (xr, br, tr), (xp, bp, tp) in zip(res, per):
+        for a, b in zip(xr, xp):
+            assert torch.equal(a, b)
+        assert torch.equal(br, bp) and torch.equal(tr, tp)
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32])
+def test_resident_sweep_odd_long_sweep_bitwise(mc, prec):
+    """A sweep of 131 steps (odd: the last step outside the two-step loop;
+    longer than two 64-step rounds of the trace) gives the per-step launches'
+    bits in particles, records and every trace entry."""
+    import torch
+    sizes = [7, 4096, 12_288]
+    (res, n_res), (per, n_per) = _resident_case(mc, prec, False, sizes, slice_index=1, T=0.393, N=3)
+    assert n_res == 2 and n_per == 0, (n_res, n_per)
+    for (xr, br, tr), (xp, bp, tp) in zip(res, per):
+        assert tr.numel() == len(sizes) * 132 * 2
         for a, b in zip(xr, xp):
             assert torch.equal(a, b)
         assert torch.equal(br, bp) and torch.equal(tr, tp)
