@@ -248,14 +248,15 @@ mcpr_status mcpr_graph_stats(const mcpr_ctx *ctx, int64_t *builds, int64_t *laun
 /* Resident fine sweeps (eq. Euler_Maruyama with the per-step mean field of
  * Sec. 2, the same arithmetic and the same bits as the per-step launches).
  * When every ensemble of an mcpr_fine_propagate call (or of a Parareal
- * iteration's sweep) has at most 16384 particles and neither the
+ * iteration's sweep) has at most 12288 particles and neither the
  * trigonometric nor the empirical-CDF term, the sweep runs in two launches:
  * the normals of all its steps (into library scratch of at most 256 MB,
  * sized by mcpr_reserve; a call whose normals do not fit what was reserved
- * runs the per-step launches instead), then one block per ensemble that keeps the particles in
- * registers through all the steps and reduces each step's mean field inside
- * the block in the canonical order.  A step then costs a few block barriers
- * instead of a launch (the latency-bound regime of small ensembles).
+ * runs the per-step launches instead), then one block per ensemble that
+ * keeps the particles in registers through all the steps and reduces each
+ * step's mean field inside the block in the canonical order.  A step then
+ * costs two block barriers instead of a launch (the latency-bound regime of
+ * small ensembles).
  * mcpr_set_resident: 1 (default) allows it, 0 always uses per-step launches.
  * mcpr_resident_sweeps: fine sweeps run resident so far.                    */
 mcpr_status mcpr_set_resident(mcpr_ctx *ctx, int32_t enable);
