@@ -255,7 +255,7 @@ mcpr_status mcpr_graph_stats(const mcpr_ctx *ctx, int64_t *builds, int64_t *laun
  * runs the per-step launches instead), then one block per ensemble that
  * keeps the particles in registers through all the steps and reduces each
  * step's mean field inside the block in the canonical order.  A step then
- * costs two block barriers instead of a launch (the latency-bound regime of
+ * costs one block barrier instead of a launch (the latency-bound regime of
  * small ensembles).
  * mcpr_set_resident: 1 (default) allows it, 0 always uses per-step launches.
  * mcpr_resident_sweeps: fine sweeps run resident so far.                    */

@@ -503,7 +503,7 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
 // Resident fine sweep of small ensembles (at most kResidentMaxP particles,
 // canonical superchunks of one quad per thread): one block of
 // kResidentThreads per ensemble keeps its particles in registers through all
-// m steps of the sweep, so a step costs two block barriers instead of a
+// m steps of the sweep, so a step costs one block barrier instead of a
 // launch.  Wavefront s of the block holds superchunk s, lane l its quads
 // 256 s + 4 l + r (r = 0..3): the lane's four quad leaves are the leaves
 // 4l .. 4l+3 of the superchunk's canonical tree, so the lane adds its two
@@ -600,56 +600,60 @@ __device__ __forceinline__ void resident_advance(T (&v)[4][4], const T (&zc)[4][
 }
 
 // The per-step exchange of the resident block.  Wavefront s < nsc completes
-// superchunk s's sums into psum[s]; after the barrier lane 0 of wavefront 0
-// forms the ensemble sums, the mean field and the step coefficients, and
-// publishes them.  The ensemble sums follow the canonical tree: thread t of
-// the 256-thread ensemble tree holds 0.0 + superchunk t's sums (t < nsc <= 16)
-// and 0.0 beyond, so the wavefront tree over lanes 0..63 is the tree over
-// lanes 0..15 (row_sum_lane0) plus two all-zero subtrees, and the three other
-// wavefronts add (w0 + 0) + (0 + 0).
+// superchunk s's sums into ps[s]; after the one barrier every wavefront that
+// holds a superchunk forms the ensemble sums, the mean field and the step
+// coefficients itself (the same operations on the same values in every
+// wavefront, so the same bits; no second barrier to publish them).  ps
+// alternates between two buffers from one exchange to the next: a wavefront
+// that starts writing exchange e + 1's sums may still find another reading
+// exchange e's, but none can reach exchange e + 2 before every wavefront has
+// passed the barrier of e + 1.  The ensemble sums follow the canonical tree:
+// thread t of the 256-thread ensemble tree holds 0.0 + superchunk t's sums
+// (t < nsc <= 16) and 0.0 beyond, so the wavefront tree over lanes 0..63 is
+// the tree over lanes 0..15 (row_sum_lane0) plus two all-zero subtrees, and
+// the three other wavefronts add (w0 + 0) + (0 + 0).
 template <typename T>
-struct ResidentShared {
-    double mv[2];   // mean and variance at the start of the next step
-    T coef[6];      // its c0 c1 c2 c3 e0 e1
+struct ResidentField {
+    double mean, var; // at the start of the next step
+    T k[6];           // its c0 c1 c2 c3 e0 e1
 };
 static_assert(kResidentMaxSc <= 16, "the ensemble tree below covers 16 superchunks");
+__device__ __forceinline__ double lane0_value(double v) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 0);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 0);
+    return __hiloint2double(hi, lo);
+}
 template <typename T>
 __device__ __forceinline__ void resident_exchange(const StepIn &cin, double Pd, double a1, double a2, int nsc,
-                                                  double shd, double (*psum)[2], ResidentShared<T> &sh) {
+                                                  double shd, double (*ps)[2], ResidentField<T> &f) {
     const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = (int)threadIdx.x & 63;
     if (s < nsc) {
         const double w1 = wave_sum_lane0(a1), w2 = wave_sum_lane0(a2);
         if (lane == 0) {
-            psum[s][0] = w1;
-            psum[s][1] = w2;
+            ps[s][0] = w1;
+            ps[s][1] = w2;
         }
     }
     __syncthreads();
-    double t1 = 0.0, t2 = 0.0;
-    if (s == 0) {
+    if (s < nsc) {
+        double t1 = 0.0, t2 = 0.0;
         if (lane < nsc) {
-            t1 += psum[lane][0];
-            t2 += psum[lane][1];
+            t1 += ps[lane][0];
+            t2 += ps[lane][1];
         }
-        t1 = row_sum_lane0(t1);
-        t2 = row_sum_lane0(t2);
-    }
-    if (threadIdx.x == 0) {
+        t1 = lane0_value(row_sum_lane0(t1));
+        t2 = lane0_value(row_sum_lane0(t2));
         const double e1 = (t1 + 0.0) + 0.0, e2 = (t2 + 0.0) + 0.0; // lanes 16..31, then 32..63
         const double S1 = (e1 + 0.0) + (0.0 + 0.0), S2 = (e2 + 0.0) + (0.0 + 0.0);
-        double mean, var;
-        finish_moments(S1, S2, shd, Pd, mean, var);
-        const StepCoef<T> k = step_coef<T>(cin, mean, var);
-        sh.mv[0] = mean;
-        sh.mv[1] = var;
-        sh.coef[0] = k.c0;
-        sh.coef[1] = k.c1;
-        sh.coef[2] = k.c2;
-        sh.coef[3] = k.c3;
-        sh.coef[4] = k.e0;
-        sh.coef[5] = k.e1;
+        finish_moments(S1, S2, shd, Pd, f.mean, f.var);
+        const StepCoef<T> k = step_coef<T>(cin, f.mean, f.var);
+        f.k[0] = k.c0;
+        f.k[1] = k.c1;
+        f.k[2] = k.c2;
+        f.k[3] = k.c3;
+        f.k[4] = k.e0;
+        f.k[5] = k.e1;
     }
-    __syncthreads();
 }
 
 // One block per item (in place, no trajectory).  Writes the final state, the
@@ -661,8 +665,7 @@ __global__ __launch_bounds__(kResidentThreads) void k_em_sweep_resident(const Wo
                                                                         double2 *__restrict__ part_out,
                                                                         double *__restrict__ shift_out,
                                                                         double2 *__restrict__ trace) {
-    __shared__ double psum[kResidentMaxSc][2];
-    __shared__ ResidentShared<T> sh;
+    __shared__ double psum[2][kResidentMaxSc][2];
     const WorkItem &W = items[blockIdx.x];
     T *__restrict__ x = reinterpret_cast<T *>(W.x);
     const int64_t P = W.P;
@@ -702,17 +705,18 @@ __global__ __launch_bounds__(kResidentThreads) void k_em_sweep_resident(const Wo
     T za[4][4], zb[4][4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) gload_quad<false>(zi, resident_zquad(r, sz, l, nsc), za[r]);
-    resident_exchange<T>(cin, Pd, a1, a2, nsc, shd, psum, sh);
+    ResidentField<T> f = {}; // (wavefronts past the last superchunk keep these zeros)
+    resident_exchange<T>(cin, Pd, a1, a2, nsc, shd, psum[0], f);
     // the trace entries of 64 steps, lane j % 64 of wavefront 0 holding step j's
     double tm = 0.0, tv = 0.0;
     // step j with its normals zc; the next step's normals go into zn, in
     // flight through this step's barriers
     auto step = [&](int32_t j, const T (&zc)[4][4], T (&zn)[4][4]) {
-        const double mean = sh.mv[0];
+        const double mean = f.mean;
         if (trace && s == 0) {
             if (l == (j & 63)) {
                 tm = mean;
-                tv = sh.mv[1];
+                tv = f.var;
             }
             if ((j & 63) == 63 || j + 1 == m) {
                 if (l <= (j & 63)) trace[(int64_t)blockIdx.x * (m + 1) + (j & ~63) + l] = make_double2(tm, tv);
@@ -721,7 +725,7 @@ __global__ __launch_bounds__(kResidentThreads) void k_em_sweep_resident(const Wo
         const T shift = (T)mean;
         T k[6];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) k[i] = sh.coef[i];
+        for (int i = 0; i < 6; ++i) k[i] = f.k[i];
         {
             const T *__restrict__ zr = zi + (int64_t)(j + 1 < m ? j + 1 : j) * zstep;
 #pragma unroll
@@ -729,7 +733,7 @@ __global__ __launch_bounds__(kResidentThreads) void k_em_sweep_resident(const Wo
         }
         resident_advance<T, DEG>(v, zc, k, shift, q0, nq, P, full, a1, a2);
         shd = (double)shift;
-        resident_exchange<T>(cin, Pd, a1, a2, nsc, shd, psum, sh);
+        resident_exchange<T>(cin, Pd, a1, a2, nsc, shd, psum[(j + 1) & 1], f);
     };
     int32_t j = 0;
     for (; j + 1 < m; j += 2) {
@@ -741,7 +745,7 @@ __global__ __launch_bounds__(kResidentThreads) void k_em_sweep_resident(const Wo
     for (int r = 0; r < 4; ++r)
         if (q0 + r < nq) store_quad(x, 4 * (int64_t)(q0 + r), P, v[r]);
     if (threadIdx.x < (unsigned)nsc)
-        part_out[W.part_off + (int)threadIdx.x] = make_double2(psum[threadIdx.x][0], psum[threadIdx.x][1]);
+        part_out[W.part_off + (int)threadIdx.x] = make_double2(psum[m & 1][threadIdx.x][0], psum[m & 1][threadIdx.x][1]);
     if (threadIdx.x == 0) shift_out[blockIdx.x] = shd;
 }
 
