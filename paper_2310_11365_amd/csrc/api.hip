@@ -54,7 +54,14 @@ constexpr int64_t kAdjointSmall = 262144;
 struct mcpr_ctx {
     int device = 0;
     std::string err;
-    DevBuf items, blocks, part[2], shift[2], rpart, rshift[2], maps, recs;
+    // the work table, block table and region maps of the last upload, one
+    // allocation (tables) so that an upload is one copy; items, blocks and
+    // maps point into it
+    DevBuf tables;
+    WorkItem *items = nullptr;
+    int2 *blocks = nullptr;
+    RegionMap *maps = nullptr;
+    DevBuf part[2], shift[2], rpart, rshift[2], recs;
     DevBuf adj_ckpt, adj_traj, adj_lam[2], adj_part[2], adj_acc, adj_trace, adj_grad, adj_sums; // adjoint scratch
     DevBuf adj_tables; // the adjoint's work tables (every slice's), block tables and upstream derivatives
     // empirical-CDF drift: states and labels in sorted order, the library
@@ -368,39 +375,36 @@ void build_tables(const mcpr_problem *problems, const mcpr_ensemble *ens, int32_
     t.total_sc = off;
 }
 
-// Upload items and blocks (and optionally maps) through the pinned staging
-// buffer, into the given device buffers.
-// Buffers of an upload of the tables t (and map_bytes of maps).
-mcpr_status size_upload(mcpr_ctx *ctx, const Tables &t, DevBuf &ditems, DevBuf &dblocks, size_t map_bytes) {
-    const size_t ib = t.items.size() * sizeof(WorkItem), bb = t.blocks.size() * sizeof(int2);
-    mcpr_status st;
-    if ((st = ensure(ctx, ditems, ib)) != MCPR_OK) return st;
-    if ((st = ensure(ctx, dblocks, bb)) != MCPR_OK) return st;
-    if (map_bytes && (st = ensure(ctx, ctx->maps, map_bytes)) != MCPR_OK) return st;
-    return ensure_host(ctx, ctx->staging, align256(ib) + align256(bb) + align256(map_bytes));
+// Upload the work and block tables (and optionally maps) through the pinned
+// staging buffer, in one copy into the tables buffer.
+// Bytes of an upload of the tables t and map_bytes of maps.
+size_t tables_bytes(const Tables &t, size_t map_bytes) {
+    return align256(t.items.size() * sizeof(WorkItem)) + align256(t.blocks.size() * sizeof(int2)) +
+           align256(map_bytes);
 }
-
-mcpr_status upload_into(mcpr_ctx *ctx, const Tables &t, DevBuf &ditems, DevBuf &dblocks, const void *maps,
-                        size_t map_bytes, hipStream_t s) {
-    const size_t ib = t.items.size() * sizeof(WorkItem), bb = t.blocks.size() * sizeof(int2);
+mcpr_status size_upload(mcpr_ctx *ctx, const Tables &t, size_t map_bytes) {
     mcpr_status st;
-    if ((st = size_upload(ctx, t, ditems, dblocks, map_bytes)) != MCPR_OK) return st;
-    char *h;
-    if ((st = stage(ctx, align256(ib) + align256(bb) + align256(map_bytes), &h)) != MCPR_OK) return st;
-    std::memcpy(h, t.items.data(), ib);
-    std::memcpy(h + align256(ib), t.blocks.data(), bb);
-    HIP_TRY(hipMemcpyAsync(ditems.p, h, ib, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(dblocks.p, h + align256(ib), bb, hipMemcpyHostToDevice, s));
-    if (map_bytes) {
-        std::memcpy(h + align256(ib) + align256(bb), maps, map_bytes);
-        HIP_TRY(hipMemcpyAsync(ctx->maps.p, h + align256(ib) + align256(bb), map_bytes, hipMemcpyHostToDevice, s));
-    }
-    HIP_TRY(hipEventRecord(ctx->staged, s));
-    return MCPR_OK;
+    if ((st = ensure(ctx, ctx->tables, tables_bytes(t, map_bytes))) != MCPR_OK) return st;
+    return ensure_host(ctx, ctx->staging, tables_bytes(t, map_bytes));
 }
 
 mcpr_status upload(mcpr_ctx *ctx, const Tables &t, const void *maps, size_t map_bytes, hipStream_t s) {
-    return upload_into(ctx, t, ctx->items, ctx->blocks, maps, map_bytes, s);
+    const size_t ib = t.items.size() * sizeof(WorkItem), bb = t.blocks.size() * sizeof(int2);
+    const size_t total = tables_bytes(t, map_bytes);
+    mcpr_status st;
+    if ((st = size_upload(ctx, t, map_bytes)) != MCPR_OK) return st;
+    char *h;
+    if ((st = stage(ctx, total, &h)) != MCPR_OK) return st;
+    std::memcpy(h, t.items.data(), ib);
+    std::memcpy(h + align256(ib), t.blocks.data(), bb);
+    if (map_bytes) std::memcpy(h + align256(ib) + align256(bb), maps, map_bytes);
+    HIP_TRY(hipMemcpyAsync(ctx->tables.p, h, total, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(ctx->staged, s));
+    char *d = (char *)ctx->tables.p;
+    ctx->items = (WorkItem *)d;
+    ctx->blocks = (int2 *)(d + align256(ib));
+    ctx->maps = map_bytes ? (RegionMap *)(d + align256(ib) + align256(bb)) : nullptr;
+    return MCPR_OK;
 }
 
 mcpr::Splits splits_of(const mcpr_problem &p) {
@@ -439,8 +443,8 @@ struct Bufs {
 
 Bufs ctx_bufs(mcpr_ctx *ctx) {
     Bufs b;
-    b.items = (const WorkItem *)ctx->items.p;
-    b.blocks = (const int2 *)ctx->blocks.p;
+    b.items = ctx->items;
+    b.blocks = ctx->blocks;
     for (int k = 0; k < 2; ++k) {
         b.part[k] = (double2 *)ctx->part[k].p;
         b.shift[k] = (double *)ctx->shift[k].p;
@@ -578,7 +582,7 @@ mcpr_status enqueue_fine(mcpr_ctx *ctx, const Bufs &bf, const Tables &t, int pre
 // Everything a captured fine sweep depends on besides the device tables.
 std::vector<char> graph_key(mcpr_ctx *ctx, const Tables &t, int prec, int deg, int variant, int m, int nreg,
                             const mcpr::Splits &sp, bool want_stats, bool want_trace) {
-    const void *ptrs[] = {ctx->items.p, ctx->blocks.p, ctx->part[0].p, ctx->part[1].p, ctx->shift[0].p,
+    const void *ptrs[] = {ctx->items, ctx->blocks, ctx->part[0].p, ctx->part[1].p, ctx->shift[0].p,
                           ctx->shift[1].p, ctx->rpart.p, ctx->rshift[0].p, ctx->rshift[1].p, ctx->recs.p,
                           ctx->trace.p,  ctx->mv.p,       ctx->znorm.p};
     const int64_t ints[] = {(int64_t)t.items.size(), (int64_t)t.blocks.size(), t.total_sc, prec, deg, m, nreg,
@@ -1191,7 +1195,7 @@ mcpr_status size_calls(mcpr_ctx *ctx, const Tables &t, const mcpr_problem *probl
                        int32_t calls, size_t map_bytes) {
     const mcpr_problem &p = problems[ens[0].problem];
     mcpr_status st;
-    if ((st = size_upload(ctx, t, ctx->items, ctx->blocks, map_bytes)) != MCPR_OK) return st;
+    if ((st = size_upload(ctx, t, map_bytes)) != MCPR_OK) return st;
     if ((calls & (MCPR_RESERVE_MOMENTS | MCPR_RESERVE_MATCH)) && (st = ensure_records(ctx, t, p.n_regions)) != MCPR_OK)
         return st;
     if ((calls & MCPR_RESERVE_QOI) &&
@@ -1289,8 +1293,8 @@ void mcpr_destroy(mcpr_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    DevBuf *bufs[] = {&ctx->items,       &ctx->blocks,      &ctx->part[0],     &ctx->part[1],     &ctx->shift[0],
-                      &ctx->shift[1],      &ctx->rpart,       &ctx->rshift[0],   &ctx->rshift[1],   &ctx->maps,
+    DevBuf *bufs[] = {&ctx->tables,      &ctx->part[0],     &ctx->part[1],     &ctx->shift[0],
+                      &ctx->shift[1],      &ctx->rpart,       &ctx->rshift[0],   &ctx->rshift[1],
                       &ctx->recs,          &ctx->adj_ckpt,    &ctx->adj_traj,    &ctx->adj_lam[0],  &ctx->adj_lam[1],
                       &ctx->adj_part[0],   &ctx->adj_part[1], &ctx->adj_acc,     &ctx->adj_trace,   &ctx->adj_grad,
                       &ctx->adj_sums,      &ctx->adj_tables,  &ctx->trace,       &ctx->mv,
@@ -1492,8 +1496,8 @@ mcpr_status mcpr_init_particles(mcpr_ctx *ctx, const mcpr_problem *problems, int
     Tables t;
     build_tables(problems, ens, n_ens, t);
     if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
-    HIP_TRY(mcpr::launch_init(problems[ens[0].problem].precision, (const WorkItem *)ctx->items.p,
-                              (const int2 *)ctx->blocks.p, (int)t.blocks.size(), s));
+    HIP_TRY(mcpr::launch_init(problems[ens[0].problem].precision, ctx->items,
+                              ctx->blocks, (int)t.blocks.size(), s));
     return MCPR_OK;
 }
 
@@ -1524,8 +1528,8 @@ mcpr_status mcpr_qoi(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_prob
     build_tables(problems, ens, n_ens, t);
     if ((st = ensure(ctx, ctx->part[0], (size_t)t.total_sc * sizeof(double2))) != MCPR_OK) return st;
     if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
-    HIP_TRY(mcpr::launch_qoi(problems[ens[0].problem].precision, kind, (const WorkItem *)ctx->items.p, n_ens,
-                             (const int2 *)ctx->blocks.p, (int)t.blocks.size(), (double2 *)ctx->part[0].p, out, s));
+    HIP_TRY(mcpr::launch_qoi(problems[ens[0].problem].precision, kind, ctx->items, n_ens,
+                             ctx->blocks, (int)t.blocks.size(), (double2 *)ctx->part[0].p, out, s));
     return MCPR_OK;
 }
 
@@ -1634,8 +1638,8 @@ mcpr_status mcpr_match(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_pr
     if (dry_run)
         return records(ctx, t, p.precision, p.n_regions, splits_of(p), nullptr, true, 1, (const RegionMap *)maps,
                        (RegionStats *)probe, s);
-    HIP_TRY(mcpr::launch_match_apply(p.precision, p.n_regions, (const WorkItem *)ctx->items.p,
-                                     (const int2 *)ctx->blocks.p, (int)t.blocks.size(), splits_of(p),
+    HIP_TRY(mcpr::launch_match_apply(p.precision, p.n_regions, ctx->items,
+                                     ctx->blocks, (int)t.blocks.size(), splits_of(p),
                                      (const RegionMap *)maps, s));
     return MCPR_OK;
 }
@@ -2200,9 +2204,9 @@ mcpr_status mcpr_parareal_init(mcpr_parareal *pr, int32_t sample_u0, mcpr_stream
         build_tables(lprobs.data(), lens.data(), (int)lens.size(), t);
         for (size_t e = 0; e < lens.size(); ++e) t.items[e].src = lsrc[e];
         if ((st = upload(ctx, t, maps.data(), maps.size() * sizeof(RegionMap), s)) != MCPR_OK) return st;
-        HIP_TRY(mcpr::launch_match_apply(pr->prec, I, (const WorkItem *)ctx->items.p, (const int2 *)ctx->blocks.p,
+        HIP_TRY(mcpr::launch_match_apply(pr->prec, I, ctx->items, ctx->blocks,
                                          (int)t.blocks.size(), splits_of(pr->inst[0].pb),
-                                         (const RegionMap *)ctx->maps.p, s));
+                                         ctx->maps, s));
     }
     // no final synchronisation: the lifting is ordered on the stream, and the
     // host has already taken everything it needs
