@@ -511,8 +511,9 @@ __global__ __launch_bounds__(kThreads) void k_em_step(const WorkItem *__restrict
 // six above them -- the complete pairwise tree over the superchunk's 256
 // thread sums, as the per-step launches form it (every addition is
 // commutative, so the order of the two operands does not change a bit).
-// The ensemble tree follows in wavefront 0.  The sweep therefore gives the
-// per-step launches' bits with a quarter of their reduction work per quad.
+// Every wavefront that holds a superchunk then adds the ensemble tree itself
+// (the same bits in each).  The sweep therefore gives the per-step launches'
+// bits with a quarter of their reduction work per quad.
 // The normals, which depend on the particle, the step and the instance only,
 // are drawn for the whole sweep beforehand by k_sweep_normals (the
 // transcendental work of every step in one launch wide enough to fill the
@@ -710,7 +711,7 @@ __global__ __launch_bounds__(kResidentThreads) void k_em_sweep_resident(const Wo
     // the trace entries of 64 steps, lane j % 64 of wavefront 0 holding step j's
     double tm = 0.0, tv = 0.0;
     // step j with its normals zc; the next step's normals go into zn, in
-    // flight through this step's barriers
+    // flight through this step's barrier
     auto step = [&](int32_t j, const T (&zc)[4][4], T (&zn)[4][4]) {
         const double mean = f.mean;
         if (trace && s == 0) {
@@ -744,8 +745,10 @@ __global__ __launch_bounds__(kResidentThreads) void k_em_sweep_resident(const Wo
 #pragma unroll
     for (int r = 0; r < 4; ++r)
         if (q0 + r < nq) store_quad(x, 4 * (int64_t)(q0 + r), P, v[r]);
-    if (threadIdx.x < (unsigned)nsc)
-        part_out[W.part_off + (int)threadIdx.x] = make_double2(psum[m & 1][threadIdx.x][0], psum[m & 1][threadIdx.x][1]);
+    if (threadIdx.x < (unsigned)nsc) {
+        const double *pl = psum[m & 1][threadIdx.x]; // the last exchange's
+        part_out[W.part_off + (int)threadIdx.x] = make_double2(pl[0], pl[1]);
+    }
     if (threadIdx.x == 0) shift_out[blockIdx.x] = shd;
 }
 
