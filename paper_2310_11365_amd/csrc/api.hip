@@ -742,10 +742,10 @@ mcpr_status replay(mcpr_ctx *ctx, const std::vector<char> &key, hipStream_t s, E
 }
 
 mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int nreg, const mcpr::Splits &sp,
-                          RegionStats *stats, double2 *trace, hipStream_t s) {
+                          bool want_stats, RegionStats *stats, double2 *trace, hipStream_t s) {
     const int n = (int)t.items.size();
     mcpr_status st;
-    if ((st = size_fine(ctx, t, prec, m, nreg, stats != nullptr, trace != nullptr)) != MCPR_OK) return st;
+    if ((st = size_fine(ctx, t, prec, m, nreg, want_stats, trace != nullptr)) != MCPR_OK) return st;
     const Bufs bf = ctx_bufs(ctx);
     int deg = 1, max_nsc = 0;
     int64_t ps = 0;
@@ -774,7 +774,7 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
             const int lib = std::min(tries[a], m);
             // (the profile events of a later attempt replace those of a failed one)
             if (lib >= m) {
-                if ((st = enqueue_fine(ctx, bf, t, prec, deg, 0, m, nreg, sp, stats != nullptr, trace != nullptr, s,
+                if ((st = enqueue_fine(ctx, bf, t, prec, deg, 0, m, nreg, sp, want_stats, trace != nullptr, s,
                                        ctx->profile, lib)) != MCPR_OK)
                     return st;
                 ctx->cdf_sweeps[1]++;
@@ -785,7 +785,7 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
             for (int part = 0; part < 2 && !over; ++part) {
                 const int j0 = part == 0 ? 0 : mid, j1 = part == 0 ? mid : m;
                 if (j0 >= j1) continue;
-                if ((st = enqueue_fine(ctx, bf, t, prec, deg, 0, m, nreg, sp, stats != nullptr, trace != nullptr, s,
+                if ((st = enqueue_fine(ctx, bf, t, prec, deg, 0, m, nreg, sp, want_stats, trace != nullptr, s,
                                        ctx->profile, lib, j0, j1)) != MCPR_OK)
                     return st;
                 HIP_TRY(hipMemcpyAsync(ctx->cdf_flag_host, ctx->cdfb.flag, sizeof(uint32_t), hipMemcpyDeviceToHost,
@@ -861,7 +861,7 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
         if (!ctx->tune_ev[0][0])
             for (int k = 0; k < 2; ++k)
                 for (int j = 0; j < kTuneSteps; ++j) HIP_TRY(hipEventCreate(&ctx->tune_ev[k][j]));
-        if ((st = enqueue_fine(ctx, bf, t, prec, deg, -1, m, nreg, sp, stats != nullptr, trace != nullptr, s,
+        if ((st = enqueue_fine(ctx, bf, t, prec, deg, -1, m, nreg, sp, want_stats, trace != nullptr, s,
                                false)) != MCPR_OK)
             return st;
         HIP_TRY(hipEventSynchronize(ctx->tune_ev[1][ctx->tune_steps - 1]));
@@ -881,21 +881,21 @@ mcpr_status fine_sequence(mcpr_ctx *ctx, const Tables &t, int prec, int m, int n
         if ((st = next_prof_slot(ctx)) != MCPR_OK) return st;
         ctx->prof_ps[ctx->prof_used] = ps * m;
         ctx->prof_launches += m;
-        if ((st = enqueue_fine(ctx, bf, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr, s,
+        if ((st = enqueue_fine(ctx, bf, t, prec, deg, variant, m, nreg, sp, want_stats, trace != nullptr, s,
                                true)) != MCPR_OK)
             return st;
         ctx->prof_used++;
     } else if (ctx->graphs && !t.items[0].cdf) {
         // (the empirical-CDF sweep runs the library sort eagerly: never captured)
-        std::vector<char> key = graph_key(ctx, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr);
+        std::vector<char> key = graph_key(ctx, t, prec, deg, variant, m, nreg, sp, want_stats, trace != nullptr);
         if ((st = replay(ctx, key, s,
                          [&](hipStream_t gs) {
-                             return enqueue_fine(ctx, bf, t, prec, deg, variant, m, nreg, sp, stats != nullptr,
+                             return enqueue_fine(ctx, bf, t, prec, deg, variant, m, nreg, sp, want_stats,
                                                  trace != nullptr, gs, false);
                          })) != MCPR_OK)
             return st;
     } else {
-        if ((st = enqueue_fine(ctx, bf, t, prec, deg, variant, m, nreg, sp, stats != nullptr, trace != nullptr, s,
+        if ((st = enqueue_fine(ctx, bf, t, prec, deg, variant, m, nreg, sp, want_stats, trace != nullptr, s,
                                false)) != MCPR_OK)
             return st;
     }
@@ -1256,6 +1256,31 @@ __global__ __launch_bounds__(mcpr::kThreads) void k_put_item(WorkItem w, int32_t
 
 } // namespace
 
+namespace {
+
+// The fine propagator of mcpr_fine_propagate.  want_stats: the restriction
+// records are formed; stats (may be NULL then) receives a copy of them, which
+// otherwise stay in the context's records buffer (ctx->recs) for the caller
+// inside the library to read.
+mcpr_status fine_propagate(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems,
+                           const mcpr_ensemble *ens, int32_t n_ens, bool want_stats, RegionStats *stats,
+                           double2 *trace, hipStream_t s) {
+    mcpr_status st = check_call(ctx, problems, n_problems, ens, n_ens);
+    if (st != MCPR_OK) return st;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const mcpr_problem &p = problems[ens[0].problem];
+    Tables t;
+    build_tables(problems, ens, n_ens, t);
+    if ((st = size_fine(ctx, t, p.precision, p.steps_per_slice, p.n_regions, want_stats, trace != nullptr)) !=
+        MCPR_OK)
+        return st;
+    if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
+    return fine_sequence(ctx, t, p.precision, p.steps_per_slice, p.n_regions, splits_of(p), want_stats, stats,
+                         trace, s);
+}
+
+} // namespace
+
 // ============================================================================
 // C ABI: context
 // ============================================================================
@@ -1536,19 +1561,8 @@ mcpr_status mcpr_qoi(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_prob
 mcpr_status mcpr_fine_propagate(mcpr_ctx *ctx, const mcpr_problem *problems, int32_t n_problems,
                                 const mcpr_ensemble *ens, int32_t n_ens, mcpr_region_stats *stats, double *trace,
                                 mcpr_stream stream) {
-    mcpr_status st = check_call(ctx, problems, n_problems, ens, n_ens);
-    if (st != MCPR_OK) return st;
-    HIP_TRY(hipSetDevice(ctx->device));
-    hipStream_t s = (hipStream_t)stream;
-    const mcpr_problem &p = problems[ens[0].problem];
-    Tables t;
-    build_tables(problems, ens, n_ens, t);
-    if ((st = size_fine(ctx, t, p.precision, p.steps_per_slice, p.n_regions, stats != nullptr, trace != nullptr)) !=
-        MCPR_OK)
-        return st;
-    if ((st = upload(ctx, t, nullptr, 0, s)) != MCPR_OK) return st;
-    return fine_sequence(ctx, t, p.precision, p.steps_per_slice, p.n_regions, splits_of(p), (RegionStats *)stats,
-                         (double2 *)trace, s);
+    return fine_propagate(ctx, problems, n_problems, ens, n_ens, stats != nullptr, (RegionStats *)stats,
+                          (double2 *)trace, (hipStream_t)stream);
 }
 
 mcpr_status mcpr_fine_propagate_static(const mcpr_problem *problems, int32_t n_problems, const mcpr_ensemble *ens,
@@ -1970,10 +1984,10 @@ char *slot_ptr(const mcpr_parareal *pr, const Instance &in, int n, int k) {
 
 
 // Fetch device records [n][I+1] into host memory (synchronises the stream).
-mcpr_status fetch(mcpr_parareal *pr, size_t count, std::vector<RegionStats> &out, hipStream_t s) {
+mcpr_status fetch(mcpr_parareal *pr, const void *src, size_t count, std::vector<RegionStats> &out, hipStream_t s) {
     mcpr_ctx *ctx = pr->ctx;
     out.resize(count);
-    HIP_TRY(hipMemcpyAsync(out.data(), pr->dstats.p, count * sizeof(RegionStats), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(out.data(), src, count * sizeof(RegionStats), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return MCPR_OK;
 }
@@ -2150,7 +2164,7 @@ mcpr_status mcpr_parareal_init(mcpr_parareal *pr, int32_t sample_u0, mcpr_stream
         MCPR_OK)
         return st;
     std::vector<RegionStats> h;
-    if ((st = fetch(pr, (size_t)n_inst * (I + 1), h, s)) != MCPR_OK) return st;
+    if ((st = fetch(pr, pr->dstats.p, (size_t)n_inst * (I + 1), h, s)) != MCPR_OK) return st;
 
     // coarse sweep and the lifting maps u^0_n = T(rho^0_n, u0), n = 1..N
     std::vector<mcpr_ensemble> lens;
@@ -2241,11 +2255,12 @@ mcpr_status mcpr_parareal_iterate(mcpr_parareal *pr, double *delta_out, mcpr_str
     if (ens.empty()) return MCPR_OK;
     mcpr_status st;
     if ((st = ensure(ctx, pr->dstats, ens.size() * (I + 1) * sizeof(RegionStats))) != MCPR_OK) return st;
-    if ((st = mcpr_fine_propagate(ctx, probs.data(), (int)probs.size(), ens.data(), (int)ens.size(),
-                                  (mcpr_region_stats *)pr->dstats.p, nullptr, stream)) != MCPR_OK)
+    // (the records stay in the context's buffer and come to the host from there)
+    if ((st = fine_propagate(ctx, probs.data(), (int)probs.size(), ens.data(), (int)ens.size(), true, nullptr,
+                             nullptr, s)) != MCPR_OK)
         return st;
     std::vector<RegionStats> h;
-    if ((st = fetch(pr, ens.size() * (I + 1), h, s)) != MCPR_OK) return st;
+    if ((st = fetch(pr, ctx->recs.p, ens.size() * (I + 1), h, s)) != MCPR_OK) return st;
     for (size_t e = 0; e < ens.size(); ++e) {
         Instance &in = pr->inst[who[e].first];
         const int n = who[e].second;
@@ -2342,7 +2357,7 @@ mcpr_status mcpr_parareal_iterate(mcpr_parareal *pr, double *delta_out, mcpr_str
                                              (mcpr_region_stats *)pr->dstats.p, stream)) != MCPR_OK)
                             return st;
                         std::vector<RegionStats> pr_h;
-                        if ((st = fetch(pr, (size_t)(I + 1), pr_h, s)) != MCPR_OK) return st;
+                        if ((st = fetch(pr, pr->dstats.p, (size_t)(I + 1), pr_h, s)) != MCPR_OK) return st;
                         inside = region_of(p, pr_h[r].min) == r && region_of(p, pr_h[r].max) == r;
                     }
                 } else {
